@@ -1,0 +1,154 @@
+/*
+ * urv.h -- C ABI of liburv, a gfx950 (MI355X) implementation of the PowerURV
+ * rank-revealing factorisation A = U R V^T of Gopal & Martinsson, "The
+ * PowerURV algorithm for computing rank-revealing full factorizations"
+ * (arXiv:1812.06007).
+ *
+ * Layout: every matrix is column-major; element (i,j) of a matrix with
+ * leading dimension ld lives at p[i + j*ld].  All matrix pointers are DEVICE
+ * pointers (memory from hipMalloc or a torch CUDA tensor) unless a comment
+ * says host.  The caller allocates and owns every buffer it passes; no
+ * pointer is kept after a call returns.  Calls taking a stream are
+ * asynchronous on that stream (NULL = the default stream): buffers must stay
+ * valid until the stream reaches the end of the call's work.
+ *
+ * Errors: every entry point returns an int status (urv_status).  Argument
+ * checks run on the host before any device work, so a call that returns
+ * URV_EINVAL has written nothing.  HIP failures return URV_EDEVICE; the text
+ * of the last failure on the calling thread is in urv_last_error().
+ * Non-finite inputs propagate (NaN in, NaN out).
+ */
+#ifndef URV_H
+#define URV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  URV_OK = 0,
+  URV_EINVAL = -1,   /* bad argument: null pointer, size, leading dimension, enum, workspace */
+  URV_ENOMEM = -2,   /* device allocation failed */
+  URV_EDEVICE = -3,  /* HIP runtime error, or a device-side bounded wait expired */
+  URV_ENOTSUP = -4   /* valid but unsupported combination */
+} urv_status;
+
+/* When the power iteration re-orthonormalises (Section 3, paragraph after
+ * eq. powerqr: re-orthonormalise after each application of A or A^T). */
+typedef enum {
+  URV_REORTH_FULL = 0, /* Qpos after every product with A and with A^T (default) */
+  URV_REORTH_HALF = 1, /* one Qpos per A^T A step */
+  URV_REORTH_NONE = 2  /* (A^T A)^q G then a single Qpos; only for small q and mild spectra */
+} urv_variant;
+
+/* Arithmetic of the factorisation.  A, U, R, V are FP64 in every mode. */
+typedef enum {
+  URV_FP64 = 0,       /* everything in FP64 */
+  URV_MIXED_BF16 = 2, /* power-step products on BF16 MFMA with FP32 accumulation, QR of the
+                         power iterates in FP32, V re-orthonormalised and the final
+                         A V = U R in FP64 */
+  URV_MIXED_FP16 = 3  /* as above with FP16 operands */
+} urv_precision;
+
+typedef struct {
+  int32_t variant;    /* urv_variant */
+  int32_t precision;  /* urv_precision */
+  int32_t orth_g;     /* nonzero: start the power iteration from Qpos(G) instead of G */
+  int32_t reserved;   /* must be 0 */
+  int64_t lda, ldu, ldr, ldv; /* leading dimensions; 0 selects the packed value (m, m, n, n) */
+  const double* G;    /* optional n x n starting matrix (device); NULL draws it from seed */
+  int64_t ldg;        /* leading dimension of G; 0 = n */
+  void* stream;       /* hipStream_t; NULL = default stream */
+  void* workspace;    /* optional device workspace; NULL = the library allocates on the stream */
+  size_t workspace_bytes;
+} urv_opts;
+
+/* Fills opts with the defaults: FULL, FP64, packed leading dimensions, drawn G,
+ * default stream, library-allocated workspace. */
+void urv_opts_init(urv_opts* opts);
+
+/*
+ * PowerURV (Section 3, eqs. power and powerqr).  A is m x n with m >= n
+ * (read only).  A Gaussian n x n G (eq. power) is drawn from seed (see
+ * urv_gaussian, stream id 2) unless opts->G is given.  Then q >= 0 power
+ * steps are taken on V (V starts as G, or Qpos(G) when q == 0 -- the DDH-URV
+ * case of Section 2.2 -- or when orth_g is set), and the final step factors
+ * A V = U R.  Qpos is an unpivoted blocked Householder QR whose R has a
+ * non-negative diagonal.
+ * Outputs: U m x n with orthonormal columns, R n x n upper triangular (its
+ * strictly lower part is written as 0), V n x n orthogonal; A = U R V^T.
+ * n == 0 is a no-op returning URV_OK.  m < n, q < 0, ld < rows, unknown
+ * enums, null pointers with n > 0 or a too-small workspace give URV_EINVAL.
+ * Asynchronous on opts->stream.
+ */
+int urv_factor_ex(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
+                  double* U, double* R, double* V, const urv_opts* opts);
+
+/* urv_factor_ex with default options (FULL, FP64, packed, default stream);
+ * returns after the device work has finished. */
+int urv_factor(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
+               double* U, double* R, double* V);
+
+/* Bytes of device workspace urv_factor_ex needs for these arguments (opts may
+ * be NULL for the defaults).  0 when n == 0. */
+size_t urv_workspace_size(int64_t m, int64_t n, int32_t q, const urv_opts* opts);
+
+/*
+ * The Gaussian matrix of eq. power (Section 3).  Element (i,j) is number
+ * l = i + j*rows of a counter-based stream: Philox4x64-10 (Salmon et al.,
+ * SC'11) with key (seed, 0) and counter (l/4, stream_id, 0, 0) gives four
+ * 64-bit words w; u = ((w >> 11) + 0.5) * 2^-53 in (0,1); Box-Muller maps
+ * (u0,u1) to sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1) and likewise (u2,u3);
+ * element l takes output l % 4.  G: rows x cols with leading dimension ld,
+ * FP64 (precision URV_FP64) or FP32 (any other value: the FP32 rounding of
+ * the FP64 value).  urv_factor_ex draws its G with stream_id 2.
+ */
+int urv_gaussian(void* G, int64_t rows, int64_t cols, int64_t ld, uint64_t seed,
+                 uint32_t stream_id, int32_t precision, void* stream);
+
+/*
+ * C = alpha * op(A) * op(B) + beta * C in FP64 on MFMA (the products A V and
+ * A^T W of Section 3 and the block-reflector updates of Section 2.2).
+ * op(X) = X when trans == 0, X^T otherwise; C is M x N, op(A) M x K,
+ * op(B) K x N.  beta == 0 never reads C.  C must not overlap A or B.
+ * Sums over k are split in a fixed order: results are bitwise reproducible.
+ */
+int urv_dgemm(int32_t transA, int32_t transB, int64_t M, int64_t N, int64_t K,
+              double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+              double beta, double* C, int64_t ldc, void* stream);
+
+/*
+ * Qpos: unpivoted blocked Householder QR of X (m x n, m >= n) with the
+ * diagonal of R made non-negative (the Q-factors of Section 2.2 and eqs.
+ * power / powerqr; the footnote on Haar matrices fixes the sign).  X is
+ * overwritten.  Q (m x n, explicit) and R (n x n, strictly lower part
+ * written as 0) may each be NULL when not wanted.  Asynchronous on stream;
+ * the workspace is allocated on the stream by the library.
+ */
+int urv_qr_pos(double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq,
+               double* R, int64_t ldr, void* stream);
+
+/*
+ * Checks of a factorisation, in FP64 on the device (rank-k errors of
+ * Section 5 and the partition of eq. blocks).  Blocking.  out (HOST, 4
+ * doubles): ||A - U R V^T||_F / ||A||_F, ||U^T U - I||_F, ||V^T V - I||_F,
+ * ||A||_F.  ek (HOST, n+1 doubles, may be NULL): ek[k] = ||R(k:n-1,k:n-1)||_F
+ * over the upper triangle, the Frobenius error of the rank-k truncation
+ * U(:,1:k) R(1:k,:) V^T when A = U R V^T.  Packed leading dimensions.
+ */
+int urv_metrics(const double* A, int64_t m, int64_t n, const double* U, const double* R,
+                const double* V, double* out, double* ek, void* stream);
+
+/* Static text for a status code. */
+const char* urv_strerror(int code);
+
+/* Detail text of the last error on the calling thread ("" if none). */
+const char* urv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* URV_H */

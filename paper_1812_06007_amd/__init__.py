@@ -1,0 +1,19 @@
+"""PowerURV (Gopal & Martinsson, arXiv:1812.06007) on AMD MI355X (gfx950).
+
+The factorisation A = U R V^T runs in the HIP kernels of ``liburv.so``
+behind the C ABI of ``include/urv.h``; this package is its Python binding.
+"""
+from .urv import (  # noqa: F401
+    UrvError,
+    dgemm,
+    empty_colmajor,
+    factor,
+    gaussian,
+    lib,
+    metrics,
+    qr_pos,
+    workspace_size,
+)
+
+__all__ = ["UrvError", "dgemm", "empty_colmajor", "factor", "gaussian", "lib", "metrics", "qr_pos",
+           "workspace_size"]

@@ -1,0 +1,266 @@
+// FP64 GEMM on CDNA4 matrix cores: C = alpha op(A) op(B) + beta C.
+//
+// This is the level-3 kernel behind the products A V and A^T W of the power
+// iteration (Section 3, eq. power) and behind the compact-WY block-reflector
+// updates of the Householder QR (Section 2.2: reflectors accumulated and
+// applied to the trailing matrix with a matrix-matrix multiply).
+//
+// Design for gfx950:
+//  * v_mfma_f64_16x16x4_f64 tiles; a workgroup of 4 waves owns a BM x BN tile
+//    of C, each wave a (BM/2) x (BN/2) sub-tile held in registers.
+//  * K is walked in steps of BK = 16 through double-buffered LDS tiles (one
+//    barrier per step); the next step's global loads are in flight while the
+//    current step's MFMAs run.
+//  * The MFMA is fed (op(B) fragment, op(A) fragment) so that each lane ends
+//    with 16 consecutive rows of one column of C: column-major stores of C
+//    are 128-byte segments.
+//  * Workgroups are mapped to tiles XCD by XCD (the dispatcher deals
+//    workgroups round-robin to the 8 XCDs) and in groups of tile rows, so
+//    tiles that share rows of op(A) / columns of op(B) share an L2.
+//  * When the tile grid alone cannot fill 256 CUs and K is long, K is split
+//    into chunks whose partial sums go to scratch and are added in a fixed
+//    order by a second kernel: results do not depend on scheduling.
+#include "common.hpp"
+
+namespace urv {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 16;
+constexpr int PAD = 1;  // LDS row padding (doubles): spreads transposed LDS writes over banks
+
+template <bool TA, bool TB, int BM, int BN>
+__global__ __launch_bounds__(256) void dgemm_kernel(
+    int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
+    const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
+    double* __restrict__ partial, int64_t k_chunk, int tiles_m, int tiles_n) {
+  constexpr int WM = BM / 2, WN = BN / 2;       // wave tile
+  constexpr int FM = WM / 16, FN = WN / 16;     // MFMA blocks per wave
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;  // loads per thread per step
+  __shared__ double As[2][BK][BM + PAD];
+  __shared__ double Bs[2][BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // ---- workgroup -> tile, XCD-major then grouped rows
+  const int ntiles = tiles_m * tiles_n;
+  int wg = blockIdx.x;
+  if ((ntiles & 7) == 0) wg = (wg & 7) * (ntiles >> 3) + (wg >> 3);
+  constexpr int GROUP = 8;
+  const int group = wg / (GROUP * tiles_n);
+  const int first_m = group * GROUP;
+  const int gsize = min(tiles_m - first_m, GROUP);
+  const int tm = first_m + (wg % (GROUP * tiles_n)) % gsize;
+  const int tn = (wg % (GROUP * tiles_n)) / gsize;
+  const int64_t m0 = static_cast<int64_t>(tm) * BM;
+  const int64_t n0 = static_cast<int64_t>(tn) * BN;
+
+  const int64_t kb = static_cast<int64_t>(blockIdx.y) * k_chunk;
+  const int64_t ke = min(K, kb + k_chunk);
+  const int nk = static_cast<int>(ceil_div(ke - kb, BK));
+
+  double ra[LA], rb[LB];
+
+  auto load_global = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int q = tid + 256 * r;
+      int i, k;
+      if (!TA) { i = q % BM; k = q / BM; } else { k = q % BK; i = q / BK; }
+      const int64_t gi = m0 + i, gk = k0 + k;
+      double v = 0.0;
+      if (gi < M && gk < ke) v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int q = tid + 256 * r;
+      int j, k;
+      if (TB) { j = q % BN; k = q / BN; } else { k = q % BK; j = q / BK; }
+      const int64_t gj = n0 + j, gk = k0 + k;
+      double v = 0.0;
+      if (gj < N && gk < ke) v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
+      rb[r] = v;
+    }
+  };
+  auto store_lds = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int q = tid + 256 * r;
+      int i, k;
+      if (!TA) { i = q % BM; k = q / BM; } else { k = q % BK; i = q / BK; }
+      As[buf][k][i] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int q = tid + 256 * r;
+      int j, k;
+      if (TB) { j = q % BN; k = q / BN; } else { k = q % BK; j = q / BK; }
+      Bs[buf][k][j] = rb[r];
+    }
+  };
+
+  d4 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+  if (nk > 0) {
+    load_global(kb);
+    store_lds(0);
+  }
+  __syncthreads();
+
+  const int lrow = lane & 15;  // index within a 16-block
+  const int lk = lane >> 4;    // k within a 4-step
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load_global(kb + static_cast<int64_t>(kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      double fa[FM], fb[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) fa[a] = As[cur][kk * 4 + lk][wm * WM + a * 16 + lrow];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) fb[b] = Bs[cur][kk * 4 + lk][wn * WN + b * 16 + lrow];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[b], fa[a], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store_lds(cur ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue: lane holds C(m0 + .. + lrow, n0 + .. + lk + 4r)
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+    const int64_t gm = m0 + wm * WM + a * 16 + lrow;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gn = n0 + wn * WN + b * 16 + lk + 4 * r;
+        if (gn >= N) continue;
+        const double v = acc[a][b][r];
+        if (partial) {
+          partial[(static_cast<int64_t>(blockIdx.y) * N + gn) * M + gm] = v;
+        } else {
+          double* c = C + gm + gn * ldc;
+          *c = (beta == 0.0) ? alpha * v : alpha * v + beta * *c;
+        }
+      }
+    }
+  }
+}
+
+// C = alpha * sum_z P[z] + beta * C, z ascending.
+__global__ void splitk_reduce_kernel(int64_t M, int64_t N, int splits, double alpha,
+                                     const double* __restrict__ P, double beta,
+                                     double* __restrict__ C, int64_t ldc) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t i = idx % M, j = idx / M;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += P[z * M * N + idx];
+  double* c = C + i + j * ldc;
+  *c = (beta == 0.0) ? alpha * s : alpha * s + beta * *c;
+}
+
+__global__ void scale_kernel(int64_t M, int64_t N, double beta, double* __restrict__ C,
+                             int64_t ldc) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= M * N) return;
+  double* c = C + idx % M + (idx / M) * ldc;
+  *c = (beta == 0.0) ? 0.0 : beta * *c;
+}
+
+struct Plan {
+  int bm, bn, tiles_m, tiles_n, splits;
+  int64_t k_chunk;
+};
+
+Plan make_plan(int64_t M, int64_t N, int64_t K) {
+  Plan p;
+  p.bm = (M <= 64) ? 64 : 128;
+  p.bn = (N <= 64) ? 64 : 128;
+  p.tiles_m = static_cast<int>(ceil_div(M, p.bm));
+  p.tiles_n = static_cast<int>(ceil_div(N, p.bn));
+  const int64_t tiles = static_cast<int64_t>(p.tiles_m) * p.tiles_n;
+  p.splits = 1;
+  const int64_t target = 512;  // workgroups wanted in flight (256 CUs, 2 per CU)
+  if (tiles > 0 && tiles < 256 && K >= 512) {
+    int64_t s = ceil_div(target, tiles);
+    s = std::min<int64_t>(s, K / 256);
+    s = std::min<int64_t>(s, 64);
+    p.splits = static_cast<int>(std::max<int64_t>(s, 1));
+  }
+  p.k_chunk = ceil_div(ceil_div(K, p.splits), BK) * BK;
+  if (K > 0) p.splits = static_cast<int>(ceil_div(K, p.k_chunk));
+  return p;
+}
+
+template <bool TA, bool TB>
+void launch_tiles(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                  int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                  double* partial, hipStream_t s) {
+  const dim3 grid(p.tiles_m * p.tiles_n, p.splits);
+#define URV_GEMM_CASE(TBM, TBN)                                                                \
+  if (p.bm == TBM && p.bn == TBN) {                                                           \
+    dgemm_kernel<TA, TB, TBM, TBN><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, \
+                                                      ldc, partial, p.k_chunk, p.tiles_m,     \
+                                                      p.tiles_n);                             \
+    return;                                                                                   \
+  }
+  URV_GEMM_CASE(128, 128)
+  URV_GEMM_CASE(64, 128)
+  URV_GEMM_CASE(128, 64)
+  URV_GEMM_CASE(64, 64)
+#undef URV_GEMM_CASE
+}
+
+}  // namespace
+
+size_t dgemm_work_elems(int64_t M, int64_t N, int64_t K) {
+  const Plan p = make_plan(M, N, K);
+  return p.splits > 1 ? static_cast<size_t>(p.splits) * M * N : 0;
+}
+
+int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+          int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+          double* work, size_t work_elems, hipStream_t s) {
+  if (M == 0 || N == 0) return URV_OK;
+  if (K == 0 || alpha == 0.0) {
+    const int64_t total = M * N;
+    scale_kernel<<<static_cast<unsigned>(ceil_div(total, 256)), 256, 0, s>>>(M, N, beta, C, ldc);
+    URV_LAUNCHED("scale_kernel");
+    return URV_OK;
+  }
+  Plan p = make_plan(M, N, K);
+  if (p.splits > 1 && (work == nullptr || work_elems < static_cast<size_t>(p.splits) * M * N)) {
+    p.splits = 1;
+    p.k_chunk = ceil_div(K, BK) * BK;
+  }
+  double* partial = p.splits > 1 ? work : nullptr;
+  if (!ta && !tb) launch_tiles<false, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
+  else if (ta && !tb) launch_tiles<true, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
+  else if (!ta && tb) launch_tiles<false, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
+  else launch_tiles<true, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
+  URV_LAUNCHED("dgemm_kernel");
+  if (partial) {
+    const int64_t total = M * N;
+    splitk_reduce_kernel<<<static_cast<unsigned>(ceil_div(total, 256)), 256, 0, s>>>(
+        M, N, p.splits, alpha, partial, beta, C, ldc);
+    URV_LAUNCHED("splitk_reduce_kernel");
+  }
+  return URV_OK;
+}
+
+}  // namespace urv

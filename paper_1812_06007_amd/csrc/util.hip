@@ -1,0 +1,152 @@
+// Strided copies and the FP64 checks of a factorisation: relative
+// reconstruction error, orthogonality of U and V, and the Frobenius norms of
+// the trailing blocks R22 of eq. (blocks) for every k -- the rank-k errors
+// plotted in Section 5.  Reductions are two-pass with a fixed assignment of
+// elements to threads, so the checks are bitwise reproducible.
+#include "common.hpp"
+
+#include <vector>
+
+namespace urv {
+namespace {
+
+__global__ void copy_kernel(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                            int64_t ldd, int64_t rows, int64_t cols) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx % rows, j = idx / rows;
+  dst[i + j * ldd] = src[i + j * lds];
+}
+
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+
+// partial[b] = sum of (X(i,j) - [i==j] * diag)^2 over elements idx = b*T + t + k*B*T.
+__global__ __launch_bounds__(kRedThreads) void sumsq_partial_kernel(
+    const double* __restrict__ X, int64_t ld, int64_t rows, int64_t cols, double diag,
+    double* __restrict__ partial) {
+  __shared__ double red[kRedThreads];
+  const int64_t total = rows * cols;
+  double s = 0.0;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(kRedThreads) + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(kRedBlocks) * kRedThreads) {
+    const int64_t i = idx % rows, j = idx / rows;
+    double v = X[i + j * ld];
+    if (i == j) v -= diag;
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void sum_final_kernel(const double* __restrict__ partial,
+                                                                 int count, double* __restrict__ out) {
+  __shared__ double red[kRedThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += kRedThreads) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// rowsq[i] = sum_{j >= i} R(i,j)^2
+__global__ void upper_row_sumsq_kernel(const double* __restrict__ R, int64_t ld, int64_t n,
+                                       double* __restrict__ rowsq) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t j = i; j < n; ++j) s += R[i + j * ld] * R[i + j * ld];
+  rowsq[i] = s;
+}
+
+// ek[k] = sqrt(sum_{i >= k} rowsq[i]), ek[n] = 0 (one thread: sequential suffix sum).
+__global__ void suffix_sqrt_kernel(const double* __restrict__ rowsq, int64_t n, double* __restrict__ ek) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double acc = 0.0;
+  ek[n] = 0.0;
+  for (int64_t k = n - 1; k >= 0; --k) {
+    acc += rowsq[k];
+    ek[k] = sqrt(acc);
+  }
+}
+
+// out[0] = sqrt(s0/s1), out[1] = sqrt(s2), out[2] = sqrt(s3), out[3] = sqrt(s1)
+__global__ void finalize_metrics_kernel(const double* __restrict__ sums, double* __restrict__ out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  out[3] = sqrt(sums[1]);
+  out[0] = sqrt(sums[0]) / out[3];
+  out[1] = sqrt(sums[2]);
+  out[2] = sqrt(sums[3]);
+}
+
+int sumsq(const double* X, int64_t ld, int64_t rows, int64_t cols, double diag, double* partial,
+          double* out, hipStream_t s) {
+  sumsq_partial_kernel<<<kRedBlocks, kRedThreads, 0, s>>>(X, ld, rows, cols, diag, partial);
+  URV_LAUNCHED("sumsq_partial_kernel");
+  sum_final_kernel<<<1, kRedThreads, 0, s>>>(partial, kRedBlocks, out);
+  URV_LAUNCHED("sum_final_kernel");
+  return URV_OK;
+}
+
+}  // namespace
+
+int copy_matrix(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                int64_t cols, hipStream_t s) {
+  if (rows == 0 || cols == 0) return URV_OK;
+  copy_kernel<<<static_cast<unsigned>(ceil_div(rows * cols, 256)), 256, 0, s>>>(src, lds, dst, ldd,
+                                                                                 rows, cols);
+  URV_LAUNCHED("copy_kernel");
+  return URV_OK;
+}
+
+int metrics(const double* A, int64_t m, int64_t n, const double* U, const double* R,
+            const double* V, double* out_host, double* ek_host, hipStream_t s) {
+  // Workspace: UR (m x n), E (m x n), Gram (n x n), partials, scalars, rowsq, ek.
+  const size_t mn = static_cast<size_t>(m) * n, nn = static_cast<size_t>(n) * n;
+  const size_t gw = std::max({dgemm_work_elems(m, n, n), dgemm_work_elems(n, n, m),
+                              dgemm_work_elems(n, n, n)});
+  const size_t total = 2 * mn + nn + kRedBlocks + 8 + 2 * (n + 1) + gw;
+  double* buf = nullptr;
+  URV_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), total * sizeof(double), s));
+  double* UR = buf;
+  double* E = UR + mn;
+  double* Gm = E + mn;
+  double* part = Gm + nn;
+  double* scal = part + kRedBlocks;
+  double* rowsq = scal + 8;
+  double* ek = rowsq + (n + 1);
+  double* gwork = ek + (n + 1);
+  int rc = URV_OK;
+  do {
+    if ((rc = dgemm(false, false, m, n, n, 1.0, U, m, R, n, 0.0, UR, m, gwork, gw, s))) break;
+    if ((rc = copy_matrix(A, m, E, m, m, n, s))) break;
+    if ((rc = dgemm(false, true, m, n, n, -1.0, UR, m, V, n, 1.0, E, m, gwork, gw, s))) break;
+    if ((rc = sumsq(E, m, m, n, 0.0, part, scal + 0, s))) break;
+    if ((rc = sumsq(A, m, m, n, 0.0, part, scal + 1, s))) break;
+    if ((rc = dgemm(true, false, n, n, m, 1.0, U, m, U, m, 0.0, Gm, n, gwork, gw, s))) break;
+    if ((rc = sumsq(Gm, n, n, n, 1.0, part, scal + 2, s))) break;
+    if ((rc = dgemm(true, false, n, n, n, 1.0, V, n, V, n, 0.0, Gm, n, gwork, gw, s))) break;
+    if ((rc = sumsq(Gm, n, n, n, 1.0, part, scal + 3, s))) break;
+    upper_row_sumsq_kernel<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(R, n, n, rowsq);
+    suffix_sqrt_kernel<<<1, 1, 0, s>>>(rowsq, n, ek);
+    finalize_metrics_kernel<<<1, 1, 0, s>>>(scal, scal + 4);
+    if (hipGetLastError() != hipSuccess) { rc = URV_EDEVICE; break; }
+    if (hipMemcpyAsync(out_host, scal + 4, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) { rc = URV_EDEVICE; break; }
+    if (ek_host && hipMemcpyAsync(ek_host, ek, (n + 1) * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) { rc = URV_EDEVICE; break; }
+    if (hipStreamSynchronize(s) != hipSuccess) { rc = URV_EDEVICE; break; }
+  } while (false);
+  hipFreeAsync(buf, s);
+  if (rc == URV_EDEVICE) set_last_error("metrics: HIP error");
+  return rc;
+}
+
+}  // namespace urv

@@ -1,0 +1,253 @@
+"""Python binding of liburv (include/urv.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of liburv.so; this module turns
+torch CUDA tensors into column-major device pointers and the current HIP
+stream, and maps status codes to exceptions.  There is no fallback: if the
+library is missing or no GPU is present, calls raise.
+
+Matrices are torch tensors of shape (rows, cols).  Column-major storage
+(stride (1, ld), ld >= rows) is passed through without a copy; anything else
+is copied to column-major first.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liburv.so")
+
+URV_OK, URV_EINVAL, URV_ENOMEM, URV_EDEVICE, URV_ENOTSUP = 0, -1, -2, -3, -4
+VARIANTS = {"full": 0, "half": 1, "none": 2}
+PRECISIONS = {"fp64": 0, "mixed_bf16": 2, "mixed_fp16": 3}
+
+
+class UrvError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__("liburv status %d (%s): %s" % (status, _strerror(status), detail))
+        self.status = status
+        self.detail = detail
+
+
+class UrvOpts(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("orth_g", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("lda", ctypes.c_int64),
+        ("ldu", ctypes.c_int64),
+        ("ldr", ctypes.c_int64),
+        ("ldv", ctypes.c_int64),
+        ("G", ctypes.c_void_p),
+        ("ldg", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+EXPORTS = ["urv_opts_init", "urv_factor_ex", "urv_factor", "urv_workspace_size", "urv_gaussian",
+           "urv_dgemm", "urv_qr_pos", "urv_metrics", "urv_strerror", "urv_last_error"]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load liburv.so (built by ``python -m paper_1812_06007_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liburv.so is not built (%s); run python -m paper_1812_06007_amd.build" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32, U64, D, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                    ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
+    L.urv_opts_init.argtypes = [ctypes.POINTER(UrvOpts)]
+    L.urv_opts_init.restype = None
+    L.urv_factor_ex.argtypes = [P, I64, I64, I32, U64, P, P, P, ctypes.POINTER(UrvOpts)]
+    L.urv_factor.argtypes = [P, I64, I64, I32, U64, P, P, P]
+    L.urv_workspace_size.argtypes = [I64, I64, I32, ctypes.POINTER(UrvOpts)]
+    L.urv_workspace_size.restype = SZ
+    L.urv_gaussian.argtypes = [P, I64, I64, I64, U64, U32, I32, P]
+    L.urv_dgemm.argtypes = [I32, I32, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P]
+    L.urv_qr_pos.argtypes = [P, I64, I64, I64, P, I64, P, I64, P]
+    L.urv_metrics.argtypes = [P, I64, I64, P, P, P, P, P, P]
+    L.urv_strerror.argtypes = [ctypes.c_int]
+    L.urv_strerror.restype = ctypes.c_char_p
+    L.urv_last_error.argtypes = []
+    L.urv_last_error.restype = ctypes.c_char_p
+    for name in ("urv_factor_ex", "urv_factor", "urv_gaussian", "urv_dgemm", "urv_qr_pos", "urv_metrics"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _strerror(status: int) -> str:
+    try:
+        return lib().urv_strerror(status).decode()
+    except Exception:  # pragma: no cover - only when the library cannot load
+        return "?"
+
+
+def _check(status: int) -> None:
+    if status != URV_OK:
+        raise UrvError(status, lib().urv_last_error().decode())
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_ptr():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _colmajor(t, dtype=None):
+    """(tensor, ld): t itself if it is column-major on the GPU, else a column-major copy."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if not t.is_cuda:
+        raise ValueError("liburv works on GPU tensors; got a tensor on %s" % t.device)
+    dtype = dtype or torch.float64
+    rows, cols = t.shape
+    if t.dtype == dtype and (t.stride(0) == 1 or rows <= 1) and (t.stride(1) >= max(rows, 1) or cols <= 1):
+        return t, max(t.stride(1) if cols > 1 else rows, rows, 1)
+    c = empty_colmajor(rows, cols, dtype=dtype, device=t.device)
+    c.copy_(t)
+    return c, max(rows, 1)
+
+
+def _packed(t):
+    """Column-major with leading dimension == rows (copy if needed)."""
+    c, ld = _colmajor(t)
+    if ld == max(c.shape[0], 1) or c.shape[1] <= 1:
+        return c
+    p = empty_colmajor(*c.shape, device=c.device)
+    p.copy_(c)
+    return p
+
+
+def empty_colmajor(rows: int, cols: int, dtype=None, device=None):
+    """Uninitialised (rows, cols) tensor with column-major strides (1, rows)."""
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=dtype or torch.float64, device=device or "cuda").t()
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() > 0 else 0)
+
+
+def workspace_size(m: int, n: int, q: int = 0, variant: str = "full", precision: str = "fp64") -> int:
+    o = UrvOpts()
+    lib().urv_opts_init(ctypes.byref(o))
+    o.variant = VARIANTS[variant]
+    o.precision = PRECISIONS[precision]
+    return int(lib().urv_workspace_size(m, n, q, ctypes.byref(o)))
+
+
+def factor(A, q: int, seed: int = 0, variant: str = "full", precision: str = "fp64", G=None,
+           orth_g: bool = False, workspace=None, out=None):
+    """PowerURV A = U R V^T (Section 3).  Returns (U, R, V) as column-major FP64 tensors.
+
+    Asynchronous on the current stream.  ``workspace`` may be a uint8 CUDA
+    tensor of at least ``workspace_size(...)`` bytes; ``out`` may be a
+    (U, R, V) triple of column-major tensors to write into.
+    """
+    torch = _torch()
+    A, lda = _colmajor(A)
+    m, n = A.shape
+    if out is None:
+        U = empty_colmajor(m, n, device=A.device)
+        R = empty_colmajor(n, n, device=A.device)
+        V = empty_colmajor(n, n, device=A.device)
+    else:
+        U, R, V = out
+    o = UrvOpts()
+    lib().urv_opts_init(ctypes.byref(o))
+    o.variant = VARIANTS[variant]
+    o.precision = PRECISIONS[precision]
+    o.orth_g = int(bool(orth_g))
+    o.lda = lda
+    o.ldu = max(U.stride(1), m) if n > 1 else max(m, 1)
+    o.ldr = max(R.stride(1), n) if n > 1 else max(n, 1)
+    o.ldv = max(V.stride(1), n) if n > 1 else max(n, 1)
+    Gk = None
+    if G is not None:
+        Gk, ldg = _colmajor(G)
+        if tuple(Gk.shape) != (n, n):
+            raise ValueError("G must be n x n")
+        o.G = Gk.data_ptr()
+        o.ldg = ldg
+    o.stream = _stream_ptr().value
+    if workspace is not None:
+        if workspace.dtype != torch.uint8 or not workspace.is_cuda:
+            raise ValueError("workspace must be a uint8 CUDA tensor")
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel()
+    for t in (U, R, V):
+        if t.stride(0) != 1 and t.shape[0] > 1:
+            raise ValueError("outputs must be column-major")
+    _check(lib().urv_factor_ex(_ptr(A), m, n, q, seed & (2**64 - 1), _ptr(U), _ptr(R), _ptr(V), ctypes.byref(o)))
+    return U, R, V
+
+
+def gaussian(rows: int, cols: int, seed: int, stream_id: int = 2, dtype=None, device=None):
+    """The Gaussian of eq. power drawn on the GPU (Philox4x64-10 + Box-Muller)."""
+    torch = _torch()
+    dtype = dtype or torch.float64
+    G = empty_colmajor(rows, cols, dtype=dtype, device=device)
+    prec = 0 if dtype == torch.float64 else 1
+    _check(lib().urv_gaussian(_ptr(G), rows, cols, max(rows, 1), seed & (2**64 - 1), stream_id, prec, _stream_ptr()))
+    return G
+
+
+def dgemm(A, B, transA: bool = False, transB: bool = False, alpha: float = 1.0, beta: float = 0.0, C=None):
+    """C = alpha op(A) op(B) + beta C in FP64 (C column-major, written in place if given)."""
+    A, lda = _colmajor(A)
+    B, ldb = _colmajor(B)
+    M = A.shape[1] if transA else A.shape[0]
+    K = A.shape[0] if transA else A.shape[1]
+    N = B.shape[0] if transB else B.shape[1]
+    if (B.shape[1] if transB else B.shape[0]) != K:
+        raise ValueError("inner dimensions differ")
+    if C is None:
+        C = empty_colmajor(M, N, device=A.device)
+        beta = 0.0
+    elif C.stride(0) != 1 and C.shape[0] > 1:
+        raise ValueError("C must be column-major")
+    ldc = max(C.stride(1), M, 1) if N > 1 else max(M, 1)
+    _check(lib().urv_dgemm(int(transA), int(transB), M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta,
+                           _ptr(C), ldc, _stream_ptr()))
+    return C
+
+
+def qr_pos(X, want_q: bool = True, want_r: bool = True):
+    """Blocked Householder QR with diag(R) >= 0.  Returns (Q, R) (None where not wanted)."""
+    Xw = empty_colmajor(*X.shape, device=X.device)
+    Xw.copy_(X)
+    m, n = Xw.shape
+    Q = empty_colmajor(m, n, device=X.device) if want_q else None
+    R = empty_colmajor(n, n, device=X.device) if want_r else None
+    _check(lib().urv_qr_pos(_ptr(Xw), m, n, max(m, 1), _ptr(Q), max(m, 1), _ptr(R), max(n, 1), _stream_ptr()))
+    return Q, R
+
+
+def metrics(A, U, R, V) -> dict:
+    """Device checks: recon, orthU, orthV, normA and ek (rank-k errors, length n+1). Blocking."""
+    import numpy as np
+
+    A, U, R, V = (_packed(t) for t in (A, U, R, V))
+    m, n = A.shape
+    out = np.zeros(4)
+    ek = np.zeros(n + 1)
+    _check(lib().urv_metrics(_ptr(A), m, n, _ptr(U), _ptr(R), _ptr(V),
+                             out.ctypes.data_as(ctypes.c_void_p), ek.ctypes.data_as(ctypes.c_void_p),
+                             _stream_ptr()))
+    return {"recon": out[0], "orthU": out[1], "orthV": out[2], "normA": out[3], "ek": ek}

@@ -1,0 +1,127 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/urv.h, and rejects bad arguments with
+URV_EINVAL before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1812_06007_amd import urv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "urv.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(urv_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("urv_factor", "urv_factor_ex", "urv_workspace_size", "urv_gaussian",
+                     "urv_strerror", "urv_last_error"):
+        assert required in names
+    assert sorted(urv.EXPORTS) == names
+
+
+def test_library_exports_every_declared_symbol():
+    L = urv.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_opts_struct_matches_header_layout():
+    # int32 x4, int64 x4, ptr, int64, ptr, ptr, size_t
+    assert ctypes.sizeof(urv.UrvOpts) == 4 * 4 + 8 * 4 + 8 + 8 + 8 + 8 + 8
+    o = urv.UrvOpts()
+    urv.lib().urv_opts_init(ctypes.byref(o))
+    assert (o.variant, o.precision, o.orth_g, o.reserved, o.lda, o.G, o.stream, o.workspace) == (
+        0, 0, 0, 0, 0, None, None, None)
+
+
+def test_strerror_and_last_error():
+    L = urv.lib()
+    assert L.urv_strerror(0) == b"success"
+    assert L.urv_strerror(-1) == b"invalid argument"
+    assert L.urv_strerror(12345) == b"unknown status"
+    assert isinstance(L.urv_last_error(), bytes)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def _factor(m, n, q, ptrs=True, **fields):
+    o = urv.UrvOpts()
+    urv.lib().urv_opts_init(ctypes.byref(o))
+    for k, v in fields.items():
+        setattr(o, k, v)
+    p = FAKE if ptrs else None
+    return urv.lib().urv_factor_ex(p, m, n, q, 0, p, p, p, ctypes.byref(o))
+
+
+@pytest.mark.parametrize("m,n,q,fields", [
+    (3, 5, 1, {}),                      # m < n
+    (5, -1, 1, {}),                     # n < 0
+    (5, 3, -1, {}),                     # q < 0
+    (5, 3, 1, {"variant": 3}),          # unknown variant
+    (5, 3, 1, {"precision": 1}),        # unknown precision
+    (5, 3, 1, {"reserved": 7}),
+    (5, 3, 1, {"lda": 4}),              # ld < rows
+    (5, 3, 1, {"ldu": 2}),
+    (5, 3, 1, {"ldr": 2}),
+    (5, 3, 1, {"ldv": 2}),
+    (5, 3, 1, {"ldg": 2}),
+    (5, 3, 1, {"lda": -5}),
+    (5, 3, 1, {"workspace_bytes": 64}),  # bytes without a buffer
+    (5, 3, 1, {"workspace": 0x2000, "workspace_bytes": 64}),  # too small
+])
+def test_factor_rejects_bad_arguments(m, n, q, fields):
+    assert _factor(m, n, q, **fields) == urv.URV_EINVAL
+    assert urv.lib().urv_last_error() != b""
+
+
+def test_factor_null_pointers_rejected():
+    assert _factor(5, 3, 1, ptrs=False) == urv.URV_EINVAL
+
+
+def test_factor_empty_is_noop():
+    assert _factor(5, 0, 2, ptrs=False) == urv.URV_OK
+    assert _factor(0, 0, 0, ptrs=False) == urv.URV_OK
+
+
+def test_too_many_rows_is_unsupported():
+    assert _factor(1 << 20, 8, 1) == urv.URV_ENOTSUP
+
+
+def test_workspace_size_monotone():
+    small = urv.workspace_size(100, 50)
+    big = urv.workspace_size(1000, 500)
+    assert 0 < small < big
+    assert urv.workspace_size(10, 0) == 0
+    assert urv.workspace_size(3, 5) == 0
+    # the FP64 workspace of the 8000 x 8000 case stays far below 288 GB of HBM
+    assert urv.workspace_size(8000, 8000, 2) < 4 * 2**30
+
+
+def test_other_entry_points_validate():
+    L = urv.lib()
+    assert L.urv_gaussian(FAKE, 4, 3, 2, 0, 2, 0, None) == urv.URV_EINVAL   # ld < rows
+    assert L.urv_gaussian(None, 4, 3, 4, 0, 2, 0, None) == urv.URV_EINVAL   # null
+    assert L.urv_gaussian(None, 0, 3, 1, 0, 2, 0, None) == urv.URV_OK       # empty
+    assert L.urv_dgemm(0, 0, 4, 4, 4, 1.0, FAKE, 3, FAKE, 4, 0.0, FAKE, 4, None) == urv.URV_EINVAL
+    assert L.urv_dgemm(1, 0, 4, 4, 5, 1.0, FAKE, 4, FAKE, 5, 0.0, FAKE, 4, None) == urv.URV_EINVAL
+    assert L.urv_dgemm(0, 0, -1, 4, 4, 1.0, FAKE, 4, FAKE, 4, 0.0, FAKE, 4, None) == urv.URV_EINVAL
+    assert L.urv_dgemm(0, 0, 0, 4, 4, 1.0, None, 1, None, 4, 0.0, None, 1, None) == urv.URV_OK
+    assert L.urv_qr_pos(FAKE, 3, 5, 3, None, 3, None, 5, None) == urv.URV_EINVAL
+    assert L.urv_qr_pos(FAKE, 5, 3, 4, None, 5, None, 3, None) == urv.URV_EINVAL
+    assert L.urv_qr_pos(None, 5, 0, 5, None, 5, None, 1, None) == urv.URV_OK
+    assert L.urv_metrics(None, 5, 3, None, None, None, None, None, None) == urv.URV_EINVAL
+
+
+def test_binding_refuses_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        urv.factor(torch.zeros(4, 3, dtype=torch.float64), 1)
