@@ -84,11 +84,10 @@ struct QrWork {
   double* Y = nullptr;      // m x n explicit unit-lower reflector blocks (ld = m)
   double* T = nullptr;      // kPanelNB x n: T of each block (ld = kPanelNB)
   double* tau = nullptr;    // n
-  double* S = nullptr;      // kPanelNB x kPanelNB Gram Y^T Y of a block
   double* W1 = nullptr;     // kPanelNB x n
   double* W2 = nullptr;     // kPanelNB x n
-  double* part = nullptr;   // panel partial sums
-  double* rowj = nullptr;   // panel pivot rows
+  uint64_t* xch = nullptr;  // panel exchange slots (tagged partial sums, pivot rows)
+  size_t xch_words = 0;
   unsigned* sync = nullptr; // panel barrier counters (one per block) + error flag
   double* gemm_work = nullptr;
   size_t gemm_work_elems = 0;

@@ -15,8 +15,8 @@
 //                    action follow.  Workgroups meet at a counter barrier;
 //                    partial sums are added in a fixed order, so every
 //                    workgroup derives bitwise-identical reflectors.
-//   S = Y^T Y        FP64 MFMA GEMM
-//   build_t_kernel   T (upper triangular) from tau and S, in LDS
+//                    The same reductions carry the Gram matrix S = Y^T Y,
+//                    from which workgroup 0 forms T (upper triangular).
 //   trailing update  C <- (I - Y T^T Y^T) C by three GEMMs.
 // Q is formed afterwards from the stored blocks, last block first, starting
 // from [D; 0] with D = sign(diag R), which makes diag(R) >= 0 at no cost.
@@ -26,160 +26,318 @@ namespace urv {
 namespace {
 
 constexpr int NB = kPanelNB;        // columns per panel (one lane per column)
-constexpr int PANEL_WAVES = 4;      // row groups per workgroup
-constexpr int RPT = 64;             // rows per lane
+constexpr int PANEL_WAVES = 8;      // row groups (waves) per workgroup
+constexpr int RPT = 32;             // rows per lane
 constexpr int RPW = PANEL_WAVES * RPT;  // rows per workgroup
+constexpr int PANEL_THREADS = 64 * PANEL_WAVES;
 constexpr int kMaxPanelWgs = 240;   // all panel workgroups must be co-resident
 constexpr long kSpinLimit = 1L << 23;   // bounded wait: ~seconds, then give up
 
-__device__ inline bool grid_barrier(unsigned* counter, unsigned target, unsigned* err) {
-  // Release our writes, count in, poll (relaxed, so the loop does not keep
-  // invalidating caches), then acquire everybody's writes once.
-  __threadfence();
-  __syncthreads();
-  __shared__ int failed;
-  if (threadIdx.x == 0) {
-    failed = 0;
-    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    long spins = 0;
-    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-          ++spins > kSpinLimit) {
-        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        failed = 1;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-  }
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return failed == 0;
+// Cross-workgroup exchange of the panel.  A value is published as two
+// 64-bit words (tag << 32 | high half) and (tag << 32 | low half) with
+// agent-scope atomic stores, which bypass the per-XCD caches; a reader polls
+// with agent-scope atomic loads until both words carry the tag it expects.
+// Each word is self-validating, so no fences or counters are needed, and a
+// round costs one trip to the coherence point.  Tags (block * 64 + column + 1)
+// grow through a factorisation, and the buffer is zeroed when it starts.
+__device__ inline void tagged_store(uint64_t* p, uint32_t tag, double v) {
+  const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(v));
+  const uint64_t t = static_cast<uint64_t>(tag) << 32;
+  __hip_atomic_store(p, t | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 1, t | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Panel rows [0, mp) x columns [0, jb) at X (ld ldx); the panel's first row is
-// the diagonal row of its first column.  Writes the factored panel back in
-// place (R above / beta on the diagonal / v below), the explicit unit-lower
-// reflector block to Y (ld ldy, same row origin), and tau[0..jb).
-__global__ __launch_bounds__(256) void panel_kernel(double* __restrict__ X, int64_t ldx,
+// Waits for K tagged values (word pairs at p[k*stride], p[k*stride+1]) and
+// returns them in out[].  Gives up (returns false, raises *err) after a bounded
+// number of polls, or as soon as another workgroup has raised *err.
+template <int K>
+__device__ inline bool tagged_load_all(const uint64_t* const* ptr, int count, uint32_t tag,
+                                       double* out, unsigned* err) {
+  long spins = 0;
+  for (;;) {
+    uint64_t w0[K], w1[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (k < count) {
+        w0[k] = __hip_atomic_load(ptr[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        w1[k] = __hip_atomic_load(ptr[k] + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    bool ready = true;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < count) ready = ready && (w0[k] >> 32) == tag && (w1[k] >> 32) == tag;
+    if (ready) {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (k < count)
+          out[k] = __longlong_as_double(static_cast<long long>((w0[k] << 32) | (w1[k] & 0xffffffffull)));
+      return true;
+    }
+    if (++spins > kSpinLimit ||
+        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Makes one lane's LDS writes visible to the other lanes of its wave: the
+// lanes run in lockstep, so only the compiler must be kept from moving LDS
+// accesses across this point (and the LDS queue drained).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Lane `lane`'s value of v (uniform result).
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), lane);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// sum over the waves of a workgroup, in a fixed order
+__device__ inline double sum_waves(const double (*red)[NB], int c) {
+  double a = 0.0, b = 0.0;
+#pragma unroll
+  for (int w = 0; w < PANEL_WAVES; w += 2) {
+    a += red[w][c];
+    b += red[w + 1][c];
+  }
+  return a + b;
+}
+
+// Column jj of T (lane i computes T(i, jj)):
+// T(jj,jj) = tau_jj,  T(i,jj) = -tau_jj sum_{k<jj} T(i,k) S(k,jj) for i < jj (T(i,k) = 0 for k < i).
+__device__ inline void t_column(double (*Tsh)[NB + 2], const double (*Ssh)[NB + 2],
+                                const double* tau_sh, int jj, int i) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int k = 0;
+  for (; k + 1 < jj; k += 2) {
+    const double2 tk = *reinterpret_cast<const double2*>(&Tsh[i][k]);
+    const double2 sk = *reinterpret_cast<const double2*>(&Ssh[jj][k]);
+    acc[k & 2] += tk.x * sk.x;
+    acc[(k & 2) + 1] += tk.y * sk.y;
+  }
+  if (k < jj) acc[0] += Tsh[i][k] * Ssh[jj][k];
+  const double tj = tau_sh[jj];
+  const double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  Tsh[i][jj] = (i < jj) ? -tj * sum : (i == jj ? tj : 0.0);
+}
+
+// Householder panel.  Rows [0, mp) x columns [0, jb) at X (ld ldx); the
+// panel's first row is the diagonal row of its first column.  Writes back in
+// place (R above the diagonal, beta on it, v below), the explicit unit-lower
+// reflector block to Y (ld ldy), tau[0..jb), and from workgroup 0 the
+// triangular factor T (ld ldt) of H_0 ... H_{jb-1} = I - Y T Y^T.
+//
+// Layout: workgroup w owns panel rows [w*RPW, (w+1)*RPW); wave g of it owns
+// RPT consecutive rows of those, lane c holds column c of them in registers.
+//
+// Column j takes one device-wide reduction of q_c = sum_{rows > j} x_j x_c
+// for every column c (x_j before the step).  For c >= j these give the norm
+// of the pivot column and v^T x_c; for c < j, where x_c already holds the
+// reflector y_c, they give the Gram entries S(c,j) = y_c^T y_j =
+// x_c(j) + q_c / (alpha - beta), from which workgroup 0 builds T column by
+// column (T(j,j) = tau_j, T(0:j,j) = -tau_j T(0:j,0:j) S(0:j,j)).
+// Partial sums of a round are added over workgroups in one fixed order, so
+// every workgroup derives bitwise-identical reflectors.
+__global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict__ X, int64_t ldx,
                                                      int64_t mp, int jb, double* __restrict__ Y,
                                                      int64_t ldy, double* __restrict__ tau,
-                                                     double* __restrict__ part,
-                                                     double* __restrict__ rowj,
-                                                     unsigned* __restrict__ counter,
+                                                     double* __restrict__ T, int ldt,
+                                                     uint64_t* __restrict__ xch, uint32_t tag0,
                                                      unsigned* __restrict__ err) {
   __shared__ double stage[64][NB + 1];
-  __shared__ double colj[RPW];
+  __shared__ __attribute__((aligned(16))) double bc[PANEL_WAVES][RPT];  // pivot column, per wave
   __shared__ double red[PANEL_WAVES][NB];
+  __shared__ double pivrow[NB];
+  __shared__ __attribute__((aligned(16))) double Ssh[NB][NB + 2];  // Ssh[j][c] = S(c, j), c < j
+  __shared__ __attribute__((aligned(16))) double Tsh[NB][NB + 2];  // Tsh[i][k] = T(i, k)
+  __shared__ double tau_sh[NB];
 
   const int P = gridDim.x;
   const int wg = blockIdx.x;
-  const int c = threadIdx.x & 63;       // column owned by this lane
-  const int g = threadIdx.x >> 6;       // row group (wave)
+  const int c = threadIdx.x & 63;                                   // column of this lane
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // row group (wave)
   const int64_t row0 = static_cast<int64_t>(wg) * RPW;
-  const int64_t myrow0 = row0 + g * RPT;  // first panel row of this lane
+  const int64_t myrow0 = row0 + static_cast<int64_t>(g) * RPT;     // first panel row of the wave
+  const int myrow0i = static_cast<int>(myrow0);                      // panels have < 2^31 rows
+  // exchange slots: [parity][P + 1][NB][2 words]; slot P carries the pivot row
+  auto slot = [&](int par, int w, int col) {
+    return xch + ((static_cast<int64_t>(par) * (P + 1) + w) * NB + col) * 2;
+  };
 
-  // ---- load: chunk k (64 rows) of the workgroup belongs to wave k
+  // ---- load through LDS, 64 rows at a time (coalesced along columns)
+  constexpr int WAVES_PER_CHUNK = 64 / RPT;
   double x[RPT];
-  for (int k = 0; k < PANEL_WAVES; ++k) {
-    for (int e = threadIdx.x; e < 64 * NB; e += 256) {
+  for (int k = 0; k < RPW / 64; ++k) {
+    for (int e = threadIdx.x; e < 64 * NB; e += PANEL_THREADS) {
       const int r = e & 63, col = e >> 6;
       const int64_t gi = row0 + k * 64 + r;
       stage[r][col] = (gi < mp && col < jb) ? X[gi + col * ldx] : 0.0;
     }
     __syncthreads();
-    if (g == k) {
+    if (g / WAVES_PER_CHUNK == k) {
+      const int r0 = (g % WAVES_PER_CHUNK) * RPT;
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) x[r] = stage[r][c];
+      for (int r = 0; r < RPT; ++r) x[r] = stage[r0 + r][c];
     }
     __syncthreads();
   }
+  if (wg == 0)
+    for (int e = threadIdx.x; e < NB * (NB + 2); e += PANEL_THREADS) (&Tsh[0][0])[e] = 0.0;
 
   bool ok = true;
-  for (int j = 0; j < jb && ok; ++j) {
-    const int buf = j & 1;
-    double* pj = part + static_cast<int64_t>(buf) * P * NB;
-    double* rj = rowj + buf * NB;
-    // 1. pivot column of this workgroup's rows into LDS; pivot row to global
+  for (int j = 0; j < jb; ++j) {
+    const int par = j & 1;
+    const uint32_t tag = tag0 + static_cast<uint32_t>(j) + 1u;
+    // lo: local index of the pivot row in this wave (uniform); rows r > lo lie below it
+    const int lo = min(max(j - myrow0i, -1), RPT);  // 32-bit, wave-uniform
+    const bool owner = lo >= 0 && lo < RPT;
+
+    // 1. lane j puts its column, zeroed on and above the pivot row, into LDS
     if (c == j) {
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) colj[g * RPT + r] = x[r];
+      for (int r = 0; r < RPT; r += 2)
+        *reinterpret_cast<double2*>(&bc[g][r]) = make_double2(r > lo ? x[r] : 0.0, r + 1 > lo ? x[r + 1] : 0.0);
     }
-    if (j >= myrow0 && j < myrow0 + RPT && c >= j && c < jb) {
-      const int rr = static_cast<int>(j - myrow0);
+    wave_lds_sync();
+    // 2. q_c over this wave's rows below the pivot
+    double qa[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < RPT; r += 2) {
+      const double2 xj = *reinterpret_cast<const double2*>(&bc[g][r]);
+      qa[r & 2] += xj.x * x[r];
+      qa[(r & 2) + 1] += xj.y * x[r + 1];
+    }
+    if (owner) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
-        if (r == rr) rj[c] = x[r];
+        if (r == lo) pivrow[c] = x[r];
+    }
+    red[g][c] = (qa[0] + qa[1]) + (qa[2] + qa[3]);
+    __syncthreads();
+    if (g == 0) {
+      tagged_store(slot(par, wg, c), tag, sum_waves(red, c));
+      if (j >= row0 && j < row0 + RPW) tagged_store(slot(par, P, c), tag, pivrow[c]);
+      // Workgroup 0 finishes column j-1 of T while the others catch up.
+      if (wg == 0 && j > 0) t_column(Tsh, Ssh, tau_sh, j - 1, c);
+    }
+    // 3. gather, in one batch where possible: pivot row entries c and j, and this
+    //    wave's share (w = g, g + PANEL_WAVES, ...) of the partial sums
+    double piv[2];
+    double sacc = 0.0;
+    {
+      const uint64_t* ptrs[6] = {slot(par, P, c), slot(par, P, j)};
+      int cnt = 2;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int w = g + PANEL_WAVES * u;
+        ptrs[2 + u] = slot(par, w < P ? w : 0, c);
+        cnt += (w < P) ? 1 : 0;
+      }
+      double vals[6];
+      ok = tagged_load_all<6>(ptrs, cnt, tag, vals, err);
+      piv[0] = vals[0];
+      piv[1] = vals[1];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (2 + u < cnt) sacc += vals[2 + u];
+    }
+    for (int w0 = g + 4 * PANEL_WAVES; w0 < P && ok; w0 += 4 * PANEL_WAVES) {
+      const uint64_t* ptrs[4];
+      int cnt = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int w = w0 + PANEL_WAVES * u;
+        ptrs[u] = slot(par, w < P ? w : 0, c);
+        cnt += (w < P) ? 1 : 0;
+      }
+      double vals[4];
+      ok = tagged_load_all<4>(ptrs, cnt, tag, vals, err);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (u < cnt) sacc += vals[u];
+    }
+    red[g][c] = sacc;
+    // every wave failing to gather gives up together
+    if (__syncthreads_or(ok ? 0 : 1)) {
+      ok = false;
+      break;
+    }
+    const double xcj = piv[0];
+    const double alpha = piv[1];
+    const double qc = sum_waves(red, c);
+    const double sigma2 = sum_waves(red, j);
+    // 4. reflector of column j
+    double t = 0.0, beta = alpha, rinv = 0.0;
+    if (sigma2 != 0.0) {
+      const double norm = sqrt(alpha * alpha + sigma2);
+      beta = (alpha >= 0.0) ? -norm : norm;
+      rinv = 1.0 / (alpha - beta);
+      t = (beta - alpha) / beta;
+    }
+    if (g == 0) {
+      if (c < j) Ssh[j][c] = xcj + qc * rinv;
+      if (c == 0) tau_sh[j] = t;
+    }
+    // its action, one instruction stream for all lanes (lane j's column from LDS):
+    //   c > j:  x_c -= tau (v^T x_c) v, with v = x_j / (alpha - beta) below the pivot
+    //   c == j: x_j becomes v below the pivot and beta on it
+    const bool upd = c > j && t != 0.0;
+    const double tw = upd ? t * (xcj + qc * rinv) : 0.0;  // tau * (v^T x_c)
+    const double coef = tw * rinv;
+    const double scale = (c == j) ? rinv : 1.0;
+#pragma unroll
+    for (int r = 0; r < RPT; r += 2) {
+      const double2 xj = *reinterpret_cast<const double2*>(&bc[g][r]);
+      const double n0 = x[r] * scale - coef * xj.x;
+      const double n1 = x[r + 1] * scale - coef * xj.y;
+      x[r] = (r > lo) ? n0 : x[r];
+      x[r + 1] = (r + 1 > lo) ? n1 : x[r + 1];
+    }
+    if (owner) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (r == lo) x[r] = (c == j) ? beta : x[r] - tw;
     }
     __syncthreads();
-    // 2. partial inner products over rows below the pivot
-    double p = 0.0;
-    if (c >= j && c < jb) {
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int64_t gi = myrow0 + r;
-        if (gi > j && gi < mp) p += colj[g * RPT + r] * x[r];
-      }
-    }
-    red[g][c] = p;
-    __syncthreads();
-    if (g == 0 && c >= j && c < jb) pj[static_cast<int64_t>(wg) * NB + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
-    // 3. all workgroups
-    ok = grid_barrier(counter, static_cast<unsigned>(P) * (j + 1), err);
-    if (!ok) break;
-    // 4. reflector of column j and its action on columns c >= j
-    if (c >= j && c < jb) {
-      double sigma2 = 0.0, d = 0.0;
-      for (int w = 0; w < P; ++w) {
-        sigma2 += pj[static_cast<int64_t>(w) * NB + j];
-        d += pj[static_cast<int64_t>(w) * NB + c];
-      }
-      const double alpha = rj[j];
-      if (sigma2 != 0.0) {
-        const double norm = sqrt(alpha * alpha + sigma2);
-        const double beta = (alpha >= 0.0) ? -norm : norm;
-        const double denom = alpha - beta;
-        const double t = (beta - alpha) / beta;
-        if (c == j) {
-#pragma unroll
-          for (int r = 0; r < RPT; ++r) {
-            const int64_t gi = myrow0 + r;
-            if (gi > j) x[r] = x[r] / denom;
-            else if (gi == j) x[r] = beta;
-          }
-          if (wg == 0 && g == 0) tau[j] = t;
-        } else {
-          const double xcj = rj[c];
-          const double tw = t * (xcj + d / denom);  // tau * (v^T x_c)
-#pragma unroll
-          for (int r = 0; r < RPT; ++r) {
-            const int64_t gi = myrow0 + r;
-            if (gi > j) x[r] -= tw * (colj[g * RPT + r] / denom);
-            else if (gi == j) x[r] -= tw;
-          }
-        }
-      } else if (c == j && wg == 0 && g == 0) {
-        tau[j] = 0.0;
-      }
-    }
   }
 
   if (!ok) {
-    // Device-side wait gave up: poison the outputs so the failure is visible.
+    // A device-side wait gave up: poison the outputs so the failure is visible.
     const double nan = __builtin_nan("");
-    if (wg == 0 && threadIdx.x < jb) tau[threadIdx.x] = nan;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) x[r] = nan;
+    if (g == 0) tau_sh[c] = nan;
+  }
+  __syncthreads();
+
+  // ---- last column of T, then T and tau out
+  if (wg == 0) {
+    if (ok && g == 0 && jb > 0) t_column(Tsh, Ssh, tau_sh, jb - 1, c);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+      const int i = e % NB, k = e / NB;
+      if (i < jb && k < jb) T[i + static_cast<int64_t>(k) * ldt] = ok ? Tsh[i][k] : __builtin_nan("");
+    }
+    if (threadIdx.x < jb) tau[threadIdx.x] = tau_sh[threadIdx.x];
   }
 
   // ---- store: panel in place, and explicit Y (0 above, 1 on the diagonal)
-  for (int k = 0; k < PANEL_WAVES; ++k) {
-    if (g == k) {
+  for (int k = 0; k < RPW / 64; ++k) {
+    if (g / WAVES_PER_CHUNK == k) {
+      const int r0 = (g % WAVES_PER_CHUNK) * RPT;
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) stage[r][c] = x[r];
+      for (int r = 0; r < RPT; ++r) stage[r0 + r][c] = x[r];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * NB; e += 256) {
+    for (int e = threadIdx.x; e < 64 * NB; e += PANEL_THREADS) {
       const int r = e & 63, col = e >> 6;
       const int64_t gi = row0 + k * 64 + r;
       if (gi < mp && col < jb) {
@@ -189,38 +347,6 @@ __global__ __launch_bounds__(256) void panel_kernel(double* __restrict__ X, int6
       }
     }
     __syncthreads();
-  }
-}
-
-// T (jb x jb, upper) with H_0 ... H_{jb-1} = I - Y T Y^T from tau and the
-// Gram matrix S = Y^T Y:  T(j,j) = tau_j,  T(0:j, j) = -tau_j T(0:j,0:j) S(0:j, j).
-__global__ __launch_bounds__(256) void build_t_kernel(const double* __restrict__ S, int lds,
-                                                       const double* __restrict__ tau, int jb,
-                                                       double* __restrict__ T, int ldt) {
-  __shared__ double Ts[NB][NB + 1];
-  __shared__ double Ss[NB][NB + 1];
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int i = e % NB, j = e / NB;
-    Ss[i][j] = (i < jb && j < jb) ? S[i + j * lds] : 0.0;
-    Ts[i][j] = 0.0;
-  }
-  __syncthreads();
-  for (int j = 0; j < jb; ++j) {
-    const double t = tau[j];
-    const int i = threadIdx.x;
-    double v = 0.0;
-    if (i < j) {
-      for (int k = i; k < j; ++k) v += Ts[i][k] * Ss[k][j];
-      v = -t * v;
-    }
-    __syncthreads();
-    if (i < j) Ts[i][j] = v;
-    if (i == j) Ts[j][j] = t;
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int i = e % NB, j = e / NB;
-    if (i < jb && j < jb) T[i + j * ldt] = Ts[i][j];
   }
 }
 
@@ -249,6 +375,11 @@ __global__ void init_q_kernel(const double* __restrict__ X, int64_t ldx, int64_t
   Q[i + c * ldq] = v;
 }
 
+__global__ void fill_u64_kernel(uint64_t* p, int64_t count) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx < count) p[idx] = 0;
+}
+
 __global__ void fill_u32_kernel(unsigned* p, int64_t count, unsigned v) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx < count) p[idx] = v;
@@ -257,7 +388,7 @@ __global__ void fill_u32_kernel(unsigned* p, int64_t count, unsigned v) {
 int64_t panel_wgs(int64_t mp) { return ceil_div(mp, RPW); }
 
 struct QrSizes {
-  size_t y, t, tau, s, w, part, rowj, sync, gemm_work;
+  size_t y, t, tau, w, xch, sync, gemm_work;
 };
 
 QrSizes qr_sizes(int64_t m, int64_t n) {
@@ -266,15 +397,12 @@ QrSizes qr_sizes(int64_t m, int64_t n) {
   z.y = static_cast<size_t>(m) * n;
   z.t = static_cast<size_t>(NB) * n;
   z.tau = n;
-  z.s = NB * NB;
   z.w = static_cast<size_t>(NB) * n;
-  z.part = 2 * static_cast<size_t>(panel_wgs(m)) * NB;
-  z.rowj = 2 * NB;
+  z.xch = 2 * (static_cast<size_t>(panel_wgs(m)) + 1) * NB * 2;
   z.sync = nblocks + 2;
   size_t gw = 0;
   for (int64_t j0 = 0; j0 < n; j0 += NB) {
     const int64_t jb = std::min<int64_t>(NB, n - j0), mp = m - j0;
-    gw = std::max(gw, dgemm_work_elems(jb, jb, mp));
     gw = std::max(gw, dgemm_work_elems(jb, n - j0 - jb, mp));
     gw = std::max(gw, dgemm_work_elems(jb, n - j0, mp));
   }
@@ -296,11 +424,10 @@ void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWork& w) {
   w.Y = a.take<double>(z.y);
   w.T = a.take<double>(z.t);
   w.tau = a.take<double>(z.tau);
-  w.S = a.take<double>(z.s);
   w.W1 = a.take<double>(z.w);
   w.W2 = a.take<double>(z.w);
-  w.part = a.take<double>(z.part);
-  w.rowj = a.take<double>(z.rowj);
+  w.xch = a.take<uint64_t>(z.xch);
+  w.xch_words = z.xch;
   w.sync = a.take<unsigned>(z.sync);
   w.gemm_work = a.take<double>(z.gemm_work);
   w.gemm_work_elems = z.gemm_work;
@@ -317,6 +444,9 @@ int qr_pos(double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq,
   unsigned* err = w.sync + nblocks;
   fill_u32_kernel<<<static_cast<unsigned>(ceil_div(nblocks + 2, 256)), 256, 0, s>>>(w.sync, nblocks + 2, 0u);
   URV_LAUNCHED("fill_u32_kernel");
+  fill_u64_kernel<<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(w.xch_words), 256)), 256, 0, s>>>(
+      w.xch, static_cast<int64_t>(w.xch_words));
+  URV_LAUNCHED("fill_u64_kernel");
 
   for (int64_t j0 = 0, blk = 0; j0 < n; j0 += NB, ++blk) {
     const int jb = static_cast<int>(std::min<int64_t>(NB, n - j0));
@@ -325,13 +455,9 @@ int qr_pos(double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq,
     double* Yb = w.Y + j0 + j0 * m;
     double* Tb = w.T + j0 * NB;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
-    panel_kernel<<<P, 256, 0, s>>>(Xp, ldx, mp, jb, Yb, m, w.tau + j0, w.part, w.rowj,
-                                   w.sync + blk, err);
+    panel_kernel<<<P, PANEL_THREADS, 0, s>>>(Xp, ldx, mp, jb, Yb, m, w.tau + j0, Tb, NB, w.xch,
+                                   static_cast<uint32_t>(blk * NB), err);
     URV_LAUNCHED("panel_kernel");
-    URV_TRY(dgemm(true, false, jb, jb, mp, 1.0, Yb, m, Yb, m, 0.0, w.S, NB, w.gemm_work,
-                  w.gemm_work_elems, s));
-    build_t_kernel<<<1, 256, 0, s>>>(w.S, NB, w.tau + j0, jb, Tb, NB);
-    URV_LAUNCHED("build_t_kernel");
     const int64_t nc = n - j0 - jb;
     if (nc > 0) {
       double* Cb = X + j0 + (j0 + jb) * ldx;
