@@ -22,6 +22,9 @@
 //    order by a second kernel: results do not depend on scheduling.
 #include "common.hpp"
 
+#include <cstdio>
+#include <cstdlib>
+
 namespace urv {
 namespace {
 
@@ -30,21 +33,22 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int BK = 16;
 constexpr int PAD = 1;  // LDS row padding (doubles): spreads transposed LDS writes over banks
 
-template <bool TA, bool TB, int BM, int BN>
-__global__ __launch_bounds__(256) void dgemm_kernel(
+template <bool TA, bool TB, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
     int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
     const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
     double* __restrict__ partial, int64_t k_chunk, int tiles_m, int tiles_n) {
-  constexpr int WM = BM / 2, WN = BN / 2;       // wave tile
+  constexpr int NT = 64 * WGM * WGN;             // threads
+  constexpr int WM = BM / WGM, WN = BN / WGN;    // wave tile
   constexpr int FM = WM / 16, FN = WN / 16;     // MFMA blocks per wave
-  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;  // loads per thread per step
+  constexpr int LA = BM * BK / NT, LB = BN * BK / NT;  // loads per thread per step
   __shared__ double As[2][BK][BM + PAD];
   __shared__ double Bs[2][BK][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
 
   // ---- workgroup -> tile, XCD-major then grouped rows
   const int ntiles = tiles_m * tiles_n;
@@ -65,10 +69,31 @@ __global__ __launch_bounds__(256) void dgemm_kernel(
 
   double ra[LA], rb[LB];
 
+  // tiles entirely inside C, and K steps entirely inside the chunk, skip all bounds checks
+  const bool full_mn = (m0 + BM <= M) && (n0 + BN <= N);
   auto load_global = [&](int64_t k0) {
+    if (full_mn && k0 + BK <= ke) {
+#pragma unroll
+      for (int r = 0; r < LA; ++r) {
+        const int q = tid + NT * r;
+        int i, k;
+        if (!TA) { i = q % BM; k = q / BM; } else { k = q % BK; i = q / BK; }
+        const int64_t gi = m0 + i, gk = k0 + k;
+        ra[r] = TA ? A[gk + gi * lda] : A[gi + gk * lda];
+      }
+#pragma unroll
+      for (int r = 0; r < LB; ++r) {
+        const int q = tid + NT * r;
+        int j, k;
+        if (TB) { j = q % BN; k = q / BN; } else { k = q % BK; j = q / BK; }
+        const int64_t gj = n0 + j, gk = k0 + k;
+        rb[r] = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
+      }
+      return;
+    }
 #pragma unroll
     for (int r = 0; r < LA; ++r) {
-      const int q = tid + 256 * r;
+      const int q = tid + NT * r;
       int i, k;
       if (!TA) { i = q % BM; k = q / BM; } else { k = q % BK; i = q / BK; }
       const int64_t gi = m0 + i, gk = k0 + k;
@@ -78,7 +103,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
-      const int q = tid + 256 * r;
+      const int q = tid + NT * r;
       int j, k;
       if (TB) { j = q % BN; k = q / BN; } else { k = q % BK; j = q / BK; }
       const int64_t gj = n0 + j, gk = k0 + k;
@@ -90,14 +115,14 @@ __global__ __launch_bounds__(256) void dgemm_kernel(
   auto store_lds = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < LA; ++r) {
-      const int q = tid + 256 * r;
+      const int q = tid + NT * r;
       int i, k;
       if (!TA) { i = q % BM; k = q / BM; } else { k = q % BK; i = q / BK; }
       As[buf][k][i] = ra[r];
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
-      const int q = tid + 256 * r;
+      const int q = tid + NT * r;
       int j, k;
       if (TB) { j = q % BN; k = q / BN; } else { k = q % BK; j = q / BK; }
       Bs[buf][k][j] = rb[r];
@@ -138,25 +163,84 @@ __global__ __launch_bounds__(256) void dgemm_kernel(
     __syncthreads();
   }
 
-  // ---- epilogue: lane holds C(m0 + .. + lrow, n0 + .. + lk + 4r)
+  // ---- epilogue: lane holds C(m0 + .. + lrow, n0 + .. + lk + 4r).  All loads of C
+  // are issued before any store, so the read-modify-write costs one round trip.
+  if (partial) {
 #pragma unroll
-  for (int a = 0; a < FM; ++a) {
-    const int64_t gm = m0 + wm * WM + a * 16 + lrow;
-    if (gm >= M) continue;
+    for (int a = 0; a < FM; ++a) {
+      const int64_t gm = m0 + wm * WM + a * 16 + lrow;
 #pragma unroll
-    for (int b = 0; b < FN; ++b) {
+      for (int b = 0; b < FN; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gn = n0 + wn * WN + b * 16 + lk + 4 * r;
-        if (gn >= N) continue;
-        const double v = acc[a][b][r];
-        if (partial) {
-          partial[(static_cast<int64_t>(blockIdx.y) * N + gn) * M + gm] = v;
-        } else {
-          double* c = C + gm + gn * ldc;
-          *c = (beta == 0.0) ? alpha * v : alpha * v + beta * *c;
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gn = n0 + wn * WN + b * 16 + lk + 4 * r;
+          if (gm < M && gn < N) partial[(static_cast<int64_t>(blockIdx.y) * N + gn) * M + gm] = acc[a][b][r];
         }
-      }
+    }
+    return;
+  }
+  if (full_mn) {
+    double* cbase = C + (m0 + wm * WM + lrow) + (n0 + wn * WN + lk) * ldc;
+    if (beta != 0.0) {
+      d4 cv[FM][FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cv[a][b][r] = cbase[a * 16 + (b * 16 + 4 * r) * ldc];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            cbase[a * 16 + (b * 16 + 4 * r) * ldc] = alpha * acc[a][b][r] + beta * cv[a][b][r];
+    } else {
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cbase[a * 16 + (b * 16 + 4 * r) * ldc] = alpha * acc[a][b][r];
+    }
+    return;
+  }
+  if (beta != 0.0) {
+    d4 cv[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      const int64_t gm = m0 + wm * WM + a * 16 + lrow;
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gn = n0 + wn * WN + b * 16 + lk + 4 * r;
+          cv[a][b][r] = (gm < M && gn < N) ? C[gm + gn * ldc] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      const int64_t gm = m0 + wm * WM + a * 16 + lrow;
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gn = n0 + wn * WN + b * 16 + lk + 4 * r;
+          if (gm < M && gn < N) C[gm + gn * ldc] = alpha * acc[a][b][r] + beta * cv[a][b][r];
+        }
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      const int64_t gm = m0 + wm * WM + a * 16 + lrow;
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gn = n0 + wn * WN + b * 16 + lk + 4 * r;
+          if (gm < M && gn < N) C[gm + gn * ldc] = alpha * acc[a][b][r];
+        }
     }
   }
 }
@@ -183,7 +267,7 @@ __global__ void scale_kernel(int64_t M, int64_t N, double beta, double* __restri
 }
 
 struct Plan {
-  int bm, bn, tiles_m, tiles_n, splits;
+  int bm, bn, wgm, wgn, tiles_m, tiles_n, splits;
   int64_t k_chunk;
 };
 
@@ -191,6 +275,17 @@ Plan make_plan(int64_t M, int64_t N, int64_t K) {
   Plan p;
   p.bm = (M <= 64) ? 64 : 128;
   p.bn = (N <= 64) ? 64 : 128;
+  // waves per workgroup: 16 for full 128 x 128 tiles, 8 otherwise (measured best on MI355X)
+  p.wgm = (p.bm == 128) ? 4 : 2;
+  p.wgn = (p.bn == 128) ? 4 : 2;
+  if (p.bm == 64 && p.bn == 128) p.wgn = 4;
+  if (const char* e = std::getenv("URV_GEMM_WAVES")) {  // tuning only: "WGMxWGN"
+    int a = 0, b = 0;
+    if (std::sscanf(e, "%dx%d", &a, &b) == 2 && (a == 2 || a == 4) && (b == 2 || b == 4)) {
+      p.wgm = a;
+      p.wgn = b;
+    }
+  }
   p.tiles_m = static_cast<int>(ceil_div(M, p.bm));
   p.tiles_n = static_cast<int>(ceil_div(N, p.bn));
   const int64_t tiles = static_cast<int64_t>(p.tiles_m) * p.tiles_n;
@@ -212,18 +307,26 @@ void launch_tiles(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, 
                   int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                   double* partial, hipStream_t s) {
   const dim3 grid(p.tiles_m * p.tiles_n, p.splits);
-#define URV_GEMM_CASE(TBM, TBN)                                                                \
-  if (p.bm == TBM && p.bn == TBN) {                                                           \
-    dgemm_kernel<TA, TB, TBM, TBN><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, \
-                                                      ldc, partial, p.k_chunk, p.tiles_m,     \
-                                                      p.tiles_n);                             \
-    return;                                                                                   \
+#define URV_GEMM_CASE(TBM, TBN, GM, GN)                                                          \
+  if (p.bm == TBM && p.bn == TBN && p.wgm == GM && p.wgn == GN) {                               \
+    dgemm_kernel<TA, TB, TBM, TBN, GM, GN><<<grid, 64 * GM * GN, 0, s>>>(                       \
+        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, p.k_chunk, p.tiles_m, p.tiles_n); \
+    return;                                                                                     \
   }
-  URV_GEMM_CASE(128, 128)
-  URV_GEMM_CASE(64, 128)
-  URV_GEMM_CASE(128, 64)
-  URV_GEMM_CASE(64, 64)
+  URV_GEMM_CASE(128, 128, 2, 2)
+  URV_GEMM_CASE(128, 128, 2, 4)
+  URV_GEMM_CASE(128, 128, 4, 2)
+  URV_GEMM_CASE(128, 128, 4, 4)
+  URV_GEMM_CASE(64, 128, 2, 2)
+  URV_GEMM_CASE(64, 128, 2, 4)
+  URV_GEMM_CASE(128, 64, 2, 2)
+  URV_GEMM_CASE(128, 64, 4, 2)
+  URV_GEMM_CASE(64, 64, 2, 2)
 #undef URV_GEMM_CASE
+  // any other combination (only reachable through the tuning variable): 2 x 2 waves
+  Plan q = p;
+  q.wgm = q.wgn = 2;
+  launch_tiles<TA, TB>(q, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
 }
 
 }  // namespace
