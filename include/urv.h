@@ -131,6 +131,11 @@ int urv_dgemm(int32_t transA, int32_t transB, int64_t M, int64_t N, int64_t K,
 int urv_qr_pos(double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq,
                double* R, int64_t ldr, void* stream);
 
+/* urv_qr_pos in FP32 (the QR of the power iterates in the mixed-precision
+ * form): same layout, ownership and errors, FP32 matrices. */
+int urv_qr_pos_f32(float* X, int64_t m, int64_t n, int64_t ldx, float* Q, int64_t ldq,
+                   float* R, int64_t ldr, void* stream);
+
 /*
  * Checks of a factorisation, in FP64 on the device (rank-k errors of
  * Section 5 and the partition of eq. blocks).  Blocking.  out (HOST, 4

@@ -6,6 +6,12 @@
 //   NONE, q > 0: V = Qpos(V)                 ((A^T A)^q G = V Z, eq. power)
 //   X = A V;  (U, R) = Qpos(X)               (eq. powerqr)
 //
+// Mixed precision (not in the paper): the power-step products run on BF16 or
+// FP16 matrix cores with FP32 accumulation and the QRs of the iterates in
+// FP32; V is then re-orthonormalised once in FP64 (an FP32 QR leaves
+// ||V^T V - I|| near 1e-6, which would bound the reconstruction error), and the
+// final A V = U R is FP64, so A = U R V^T holds to FP64 accuracy.
+//
 // Every step is a kernel launch on the caller's stream; the host only
 // validates arguments, carves the workspace and sequences launches.
 #include "common.hpp"
@@ -17,30 +23,57 @@ namespace urv {
 namespace {
 thread_local std::string g_last_error;
 
+struct MixedWork {
+  void* A16 = nullptr;   // A rounded to 16 bits, m x n, ld lda16
+  void* At16 = nullptr;  // A^T rounded to 16 bits, n x m, ld ldat16
+  void* B16 = nullptr;   // second operand of a 16-bit product (V, W or X)
+  int64_t lda16 = 0, ldat16 = 0;
+  float* V32 = nullptr;  // n x n
+  float* X32 = nullptr;  // m x n
+  float* W32 = nullptr;  // m x n
+  float* Y32 = nullptr;  // n x n
+  QrWorkT<float> qr;
+};
+
 struct FactorWork {
   double* X = nullptr;   // m x n (ld m): A V, factored in place
   double* Xs = nullptr;  // n x n (ld n): A^T W, factored in place
   double* gemm_work = nullptr;
   size_t gemm_work_elems = 0;
   QrWork qr;
+  bool mixed = false;
+  MixedWork mx;
 };
 
 size_t driver_gemm_work(int64_t m, int64_t n) {
   return std::max(dgemm_work_elems(m, n, n), dgemm_work_elems(n, n, m));
 }
 
-void carve_factor(Arena& a, int64_t m, int64_t n, FactorWork& w) {
+void carve_factor(Arena& a, int64_t m, int64_t n, bool mixed, FactorWork& w) {
   w.X = a.take<double>(static_cast<size_t>(m) * n);
   w.Xs = a.take<double>(static_cast<size_t>(n) * n);
   w.gemm_work_elems = driver_gemm_work(m, n);
   w.gemm_work = a.take<double>(w.gemm_work_elems);
   qr_work_carve(a, m, n, w.qr);
+  w.mixed = mixed;
+  if (!mixed) return;
+  MixedWork& x = w.mx;
+  x.lda16 = lowp_ld(m);
+  x.ldat16 = lowp_ld(n);
+  x.A16 = a.take<uint16_t>(static_cast<size_t>(x.lda16) * n);
+  x.At16 = a.take<uint16_t>(static_cast<size_t>(x.ldat16) * m);
+  x.B16 = a.take<uint16_t>(static_cast<size_t>(std::max(x.lda16, x.ldat16)) * n);
+  x.V32 = a.take<float>(static_cast<size_t>(n) * n);
+  x.X32 = a.take<float>(static_cast<size_t>(m) * n);
+  x.W32 = a.take<float>(static_cast<size_t>(m) * n);
+  x.Y32 = a.take<float>(static_cast<size_t>(n) * n);
+  qr_work_carve(a, m, n, x.qr);
 }
 
-size_t factor_bytes(int64_t m, int64_t n) {
+size_t factor_bytes(int64_t m, int64_t n, bool mixed) {
   Arena a;
   FactorWork w;
-  carve_factor(a, m, n, w);
+  carve_factor(a, m, n, mixed, w);
   return a.used;
 }
 
@@ -80,16 +113,12 @@ int validate_factor(const double* A, int64_t m, int64_t n, int32_t q, const doub
     set_last_error("urv_factor: workspace_bytes given without a workspace");
     return URV_EINVAL;
   }
-  if (o.workspace != nullptr && o.workspace_bytes < factor_bytes(m, n)) {
+  if (o.workspace != nullptr && o.workspace_bytes < factor_bytes(m, n, o.precision != URV_FP64)) {
     set_last_error("urv_factor: workspace too small (see urv_workspace_size)");
     return URV_EINVAL;
   }
   if (m > kMaxRows) {
     set_last_error("urv_factor: more rows than the panel kernel supports");
-    return URV_ENOTSUP;
-  }
-  if (o.precision != URV_FP64) {
-    set_last_error("urv_factor: mixed precision is not available in this build");
     return URV_ENOTSUP;
   }
   return URV_OK;
@@ -108,32 +137,78 @@ int run_factor(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, 
     URV_TRY(launch_gaussian(V, n, n, ldv, seed, 2u, false, s));
   if (q == 0 || o.orth_g) {
     URV_TRY(copy_matrix(V, ldv, w.Xs, n, n, n, s));
-    URV_TRY(qr_pos(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));
+    URV_TRY(qr_pos<double>(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));
   }
   for (int32_t t = 0; t < q; ++t) {
     URV_TRY(dgemm(false, false, m, n, n, 1.0, A, lda, V, ldv, 0.0, w.X, m, w.gemm_work,
                   w.gemm_work_elems, s));                                   // X = A V
     if (full) {
-      URV_TRY(qr_pos(w.X, m, n, m, U, ldu, nullptr, 0, w.qr, s));          // W = Qpos(X), in U
+      URV_TRY(qr_pos<double>(w.X, m, n, m, U, ldu, nullptr, 0, w.qr, s));          // W = Qpos(X), in U
       URV_TRY(dgemm(true, false, n, n, m, 1.0, A, lda, U, ldu, 0.0, w.Xs, n, w.gemm_work,
                     w.gemm_work_elems, s));                                 // A^T W
-      URV_TRY(qr_pos(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));         // V = Qpos(A^T W)
+      URV_TRY(qr_pos<double>(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));         // V = Qpos(A^T W)
     } else if (none) {
       URV_TRY(dgemm(true, false, n, n, m, 1.0, A, lda, w.X, m, 0.0, V, ldv, w.gemm_work,
                     w.gemm_work_elems, s));                                 // V = A^T A V
     } else {
       URV_TRY(dgemm(true, false, n, n, m, 1.0, A, lda, w.X, m, 0.0, w.Xs, n, w.gemm_work,
                     w.gemm_work_elems, s));                                 // A^T X
-      URV_TRY(qr_pos(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));         // V = Qpos(A^T X)
+      URV_TRY(qr_pos<double>(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));         // V = Qpos(A^T X)
     }
   }
   if (none && q > 0) {
     URV_TRY(copy_matrix(V, ldv, w.Xs, n, n, n, s));
-    URV_TRY(qr_pos(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));
+    URV_TRY(qr_pos<double>(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));
   }
   URV_TRY(dgemm(false, false, m, n, n, 1.0, A, lda, V, ldv, 0.0, w.X, m, w.gemm_work,
                 w.gemm_work_elems, s));                                     // X = A V
-  URV_TRY(qr_pos(w.X, m, n, m, U, ldu, R, ldr, w.qr, s));                  // A V = U R
+  URV_TRY(qr_pos<double>(w.X, m, n, m, U, ldu, R, ldr, w.qr, s));                  // A V = U R
+  return URV_OK;
+}
+
+// The power iteration in 16-bit products / FP32 QRs, then the FP64 tail.
+int run_factor_mixed(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, double* U,
+                     double* R, double* V, const urv_opts& o, const FactorWork& w, hipStream_t s) {
+  const int64_t lda = o.lda ? o.lda : m, ldu = o.ldu ? o.ldu : m;
+  const int64_t ldr = o.ldr ? o.ldr : n, ldv = o.ldv ? o.ldv : n, ldg = o.ldg ? o.ldg : n;
+  const bool full = o.variant == URV_REORTH_FULL, none = o.variant == URV_REORTH_NONE;
+  const bool bf16 = o.precision == URV_MIXED_BF16;
+  const MixedWork& x = w.mx;
+  const int64_t ldv16 = lowp_ld(n);
+
+  URV_TRY(to_lowp<double>(bf16, A, lda, m, n, x.A16, x.lda16, s));           // A^T W operand
+  URV_TRY(to_lowp_transposed(bf16, A, lda, m, n, x.At16, x.ldat16, s));      // A V operand
+  if (o.G)
+    URV_TRY((convert<double, float>(o.G, ldg, n, n, x.V32, n, s)));
+  else
+    URV_TRY(launch_gaussian(x.V32, n, n, n, seed, 2u, true, s));
+  if (o.orth_g) {
+    URV_TRY(copy_matrix_f32(x.V32, n, x.Y32, n, n, n, s));
+    URV_TRY(qr_pos<float>(x.Y32, n, n, n, x.V32, n, nullptr, 0, x.qr, s));
+  }
+  for (int32_t t = 0; t < q; ++t) {
+    URV_TRY(to_lowp<float>(bf16, x.V32, n, n, n, x.B16, ldv16, s));
+    URV_TRY(gemm_lowp(bf16, m, n, n, 1.f, x.At16, x.ldat16, x.B16, ldv16, 0.f, x.X32, m, s));  // X = A V
+    const float* rhs = x.X32;
+    if (full) {
+      URV_TRY(qr_pos<float>(x.X32, m, n, m, x.W32, m, nullptr, 0, x.qr, s));               // W = Qpos(X)
+      rhs = x.W32;
+    }
+    URV_TRY(to_lowp<float>(bf16, rhs, m, m, n, x.B16, x.lda16, s));
+    float* out = none ? x.V32 : x.Y32;
+    URV_TRY(gemm_lowp(bf16, n, n, m, 1.f, x.A16, x.lda16, x.B16, x.lda16, 0.f, out, n, s));   // A^T W
+    if (!none) URV_TRY(qr_pos<float>(x.Y32, n, n, n, x.V32, n, nullptr, 0, x.qr, s));        // V = Qpos
+  }
+  if (none && q > 0) {
+    URV_TRY(copy_matrix_f32(x.V32, n, x.Y32, n, n, n, s));
+    URV_TRY(qr_pos<float>(x.Y32, n, n, n, x.V32, n, nullptr, 0, x.qr, s));
+  }
+  // FP64 re-orthonormalisation of V, then the FP64 tail A V = U R.
+  URV_TRY((convert<float, double>(x.V32, n, n, n, w.Xs, n, s)));
+  URV_TRY(qr_pos<double>(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));
+  URV_TRY(dgemm(false, false, m, n, n, 1.0, A, lda, V, ldv, 0.0, w.X, m, w.gemm_work,
+                w.gemm_work_elems, s));
+  URV_TRY(qr_pos<double>(w.X, m, n, m, U, ldu, R, ldr, w.qr, s));
   return URV_OK;
 }
 
@@ -145,7 +220,8 @@ int factor_impl(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
   URV_TRY(validate_factor(A, m, n, q, U, R, V, o));
   if (n == 0) return URV_OK;
   hipStream_t s = static_cast<hipStream_t>(o.stream);
-  const size_t need = factor_bytes(m, n);
+  const bool mixed = o.precision != URV_FP64 && q > 0;
+  const size_t need = factor_bytes(m, n, mixed);
   Arena a;
   bool owned = false;
   if (o.workspace) {
@@ -164,16 +240,21 @@ int factor_impl(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
     owned = true;
   }
   FactorWork w;
-  carve_factor(a, m, n, w);
-  int rc = a.overflow ? URV_EINVAL : run_factor(A, m, n, q, seed, U, R, V, o, w, s);
+  carve_factor(a, m, n, mixed, w);
+  int rc = a.overflow ? URV_EINVAL
+           : mixed    ? run_factor_mixed(A, m, n, q, seed, U, R, V, o, w, s)
+                      : run_factor(A, m, n, q, seed, U, R, V, o, w, s);
   if (rc == URV_OK && check_flag) {
     unsigned flag = 0;
+    unsigned flag32 = 0;
     if (hipMemcpyAsync(&flag, qr_error_flag(w.qr, n), sizeof(flag), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
+        (mixed && hipMemcpyAsync(&flag32, qr_error_flag(w.mx.qr, n), sizeof(flag32),
+                                 hipMemcpyDeviceToHost, s) != hipSuccess) ||
         hipStreamSynchronize(s) != hipSuccess) {
       rc = hip_status(hipGetLastError(), "urv_factor: synchronize");
       if (rc == URV_OK) rc = URV_EDEVICE;
-    } else if (flag != 0) {
+    } else if (flag != 0 || flag32 != 0) {
       set_last_error("urv_factor: a panel's device-wide wait expired");
       rc = URV_EDEVICE;
     }
@@ -193,6 +274,41 @@ int hip_status(hipError_t e, const char* what) {
   return (e == hipErrorOutOfMemory) ? URV_ENOMEM : URV_EDEVICE;
 }
 
+}  // namespace urv
+
+namespace urv {
+namespace {
+template <class T>
+int qr_entry(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int64_t ldr,
+             void* stream) {
+  clear_last_error();
+  if (n < 0 || m < n) {
+    set_last_error("urv_qr_pos: need 0 <= n <= m");
+    return URV_EINVAL;
+  }
+  if (n == 0) return URV_OK;
+  if (!X || ldx < m || (Q && ldq < m) || (R && ldr < n)) {
+    set_last_error("urv_qr_pos: null pointer or leading dimension smaller than the row count");
+    return URV_EINVAL;
+  }
+  if (m > kMaxRows) {
+    set_last_error("urv_qr_pos: more rows than the panel kernel supports");
+    return URV_ENOTSUP;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = qr_work_bytes<T>(m, n);
+  void* p = nullptr;
+  URV_HIP(hipMallocAsync(&p, need, s));
+  Arena a;
+  a.base = static_cast<char*>(p);
+  a.size = need;
+  QrWorkT<T> w;
+  qr_work_carve(a, m, n, w);
+  const int rc = qr_pos<T>(X, m, n, ldx, Q, ldq, R, ldr, w, s);
+  hipFreeAsync(p, s);
+  return rc;
+}
+}  // namespace
 }  // namespace urv
 
 using namespace urv;
@@ -222,10 +338,9 @@ int urv_factor(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, 
 }
 
 size_t urv_workspace_size(int64_t m, int64_t n, int32_t q, const urv_opts* opts) {
-  (void)q;
-  (void)opts;
   if (n <= 0 || m < n) return 0;
-  return factor_bytes(m, n);
+  const bool mixed = opts && opts->precision != URV_FP64 && q > 0;
+  return factor_bytes(m, n, mixed);
 }
 
 int urv_gaussian(void* G, int64_t rows, int64_t cols, int64_t ld, uint64_t seed,
@@ -275,32 +390,12 @@ int urv_dgemm(int32_t transA, int32_t transB, int64_t M, int64_t N, int64_t K, d
 
 int urv_qr_pos(double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq, double* R,
                int64_t ldr, void* stream) {
-  clear_last_error();
-  if (n < 0 || m < n) {
-    set_last_error("urv_qr_pos: need 0 <= n <= m");
-    return URV_EINVAL;
-  }
-  if (n == 0) return URV_OK;
-  if (!X || ldx < m || (Q && ldq < m) || (R && ldr < n)) {
-    set_last_error("urv_qr_pos: null pointer or leading dimension smaller than the row count");
-    return URV_EINVAL;
-  }
-  if (m > kMaxRows) {
-    set_last_error("urv_qr_pos: more rows than the panel kernel supports");
-    return URV_ENOTSUP;
-  }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t need = qr_work_bytes(m, n);
-  void* p = nullptr;
-  URV_HIP(hipMallocAsync(&p, need, s));
-  Arena a;
-  a.base = static_cast<char*>(p);
-  a.size = need;
-  QrWork w;
-  qr_work_carve(a, m, n, w);
-  const int rc = qr_pos(X, m, n, ldx, Q, ldq, R, ldr, w, s);
-  hipFreeAsync(p, s);
-  return rc;
+  return qr_entry<double>(X, m, n, ldx, Q, ldq, R, ldr, stream);
+}
+
+int urv_qr_pos_f32(float* X, int64_t m, int64_t n, int64_t ldx, float* Q, int64_t ldq, float* R,
+                   int64_t ldr, void* stream) {
+  return qr_entry<float>(X, m, n, ldx, Q, ldq, R, ldr, stream);
 }
 
 int urv_metrics(const double* A, int64_t m, int64_t n, const double* U, const double* R,

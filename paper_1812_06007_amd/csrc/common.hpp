@@ -65,13 +65,20 @@ struct Arena {
 int launch_gaussian(void* G, int64_t rows, int64_t cols, int64_t ld, uint64_t seed,
                     uint32_t stream_id, bool out_f32, hipStream_t s);
 
-// FP64 GEMM.  work: device scratch for split-K partial sums (may be null:
-// then no split-K is used); work_elems its capacity in doubles.
-int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
-          int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
-          double* work, size_t work_elems, hipStream_t s);
-// Scratch doubles dgemm may use for the given shape (0 if it never splits K).
-size_t dgemm_work_elems(int64_t M, int64_t N, int64_t K);
+// FP64 / FP32 GEMM on MFMA.  work: device scratch for split-K partial sums
+// (may be null: then no split-K is used); work_elems its capacity in elements.
+template <class T>
+int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, const T* A, int64_t lda,
+         const T* B, int64_t ldb, T beta, T* C, int64_t ldc, T* work, size_t work_elems,
+         hipStream_t s);
+inline int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                 double* C, int64_t ldc, double* work, size_t work_elems, hipStream_t s) {
+  return gemm<double>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work, work_elems, s);
+}
+// Scratch elements gemm may use for the given shape (0 if it never splits K).
+size_t gemm_work_elems(int64_t M, int64_t N, int64_t K);
+inline size_t dgemm_work_elems(int64_t M, int64_t N, int64_t K) { return gemm_work_elems(M, N, K); }
 
 // 2-D copies / fills.
 int copy_matrix(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
@@ -80,27 +87,52 @@ int copy_matrix(const double* src, int64_t lds, double* dst, int64_t ldd, int64_
 // ---------------------------------------------------------------- QR
 constexpr int kPanelNB = 64;  // block width of the Householder QR
 
-struct QrWork {
-  double* Y = nullptr;      // m x n explicit unit-lower reflector blocks (ld = m)
-  double* T = nullptr;      // kPanelNB x n: T of each block (ld = kPanelNB)
-  double* tau = nullptr;    // n
-  double* W1 = nullptr;     // kPanelNB x n
-  double* W2 = nullptr;     // kPanelNB x n
+template <class T>
+struct QrWorkT {
+  T* Y = nullptr;           // m x n explicit unit-lower reflector blocks (ld = m)
+  T* Tm = nullptr;          // kPanelNB x n: T of each block (ld = kPanelNB)
+  T* tau = nullptr;         // n
+  T* W1 = nullptr;          // kPanelNB x n
+  T* W2 = nullptr;          // kPanelNB x n
   uint64_t* xch = nullptr;  // panel exchange slots (tagged partial sums, pivot rows)
   size_t xch_words = 0;
-  unsigned* sync = nullptr; // panel barrier counters (one per block) + error flag
-  double* gemm_work = nullptr;
+  unsigned* sync = nullptr; // panel error flag area
+  T* gemm_work = nullptr;
   size_t gemm_work_elems = 0;
 };
+using QrWork = QrWorkT<double>;
 
+template <class T>
 size_t qr_work_bytes(int64_t m, int64_t n);
-void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWork& w);
+template <class T>
+void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w);
 // Device flag set by a panel whose bounded device-wide wait expired.
-unsigned* qr_error_flag(const QrWork& w, int64_t n);
+template <class T>
+unsigned* qr_error_flag(const QrWorkT<T>& w, int64_t n);
 
-// X (m x n, ldx) overwritten; Q (m x n) / R (n x n) optional.
-int qr_pos(double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq, double* R,
-           int64_t ldr, const QrWork& w, hipStream_t s);
+// X (m x n, ldx) overwritten; Q (m x n) / R (n x n) optional.  T = double or float.
+template <class T>
+int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int64_t ldr,
+           const QrWorkT<T>& w, hipStream_t s);
+
+// ---------------------------------------------------------------- mixed precision
+// Leading dimension of a 16-bit operand with `rows` rows (multiple of 32).
+int64_t lowp_ld(int64_t rows);
+// C (FP32, M x N) = alpha A^T B + beta C for 16-bit (BF16 if bf16, else FP16) A (K x M) and
+// B (K x N), column-major, leading dimensions multiples of 32 with zero padding below K.
+int gemm_lowp(bool bf16, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
+              const void* B, int64_t ldb, float beta, float* C, int64_t ldc, hipStream_t s);
+// dst (ldd x cols, 16-bit, RNE) = src (rows x cols), zero in rows [rows, ldd).
+template <class S>
+int to_lowp(bool bf16, const S* src, int64_t lds, int64_t rows, int64_t cols, void* dst, int64_t ldd,
+            hipStream_t s);
+// dst (ldd x rows, 16-bit) = src^T for src rows x cols (FP64), zero in rows [cols, ldd).
+int to_lowp_transposed(bool bf16, const double* src, int64_t lds, int64_t rows, int64_t cols,
+                       void* dst, int64_t ldd, hipStream_t s);
+template <class S, class D>
+int convert(const S* src, int64_t lds, int64_t rows, int64_t cols, D* dst, int64_t ldd, hipStream_t s);
+int copy_matrix_f32(const float* src, int64_t lds, float* dst, int64_t ldd, int64_t rows, int64_t cols,
+                    hipStream_t s);
 
 // ---------------------------------------------------------------- metrics
 int metrics(const double* A, int64_t m, int64_t n, const double* U, const double* R,

@@ -1,4 +1,4 @@
-// FP64 GEMM on CDNA4 matrix cores: C = alpha op(A) op(B) + beta C.
+// FP64 and FP32 GEMM on CDNA4 matrix cores: C = alpha op(A) op(B) + beta C.
 //
 // This is the level-3 kernel behind the products A V and A^T W of the power
 // iteration (Section 3, eq. power) and behind the compact-WY block-reflector
@@ -6,8 +6,9 @@
 // applied to the trailing matrix with a matrix-matrix multiply).
 //
 // Design for gfx950:
-//  * v_mfma_f64_16x16x4_f64 tiles; a workgroup of 4 waves owns a BM x BN tile
-//    of C, each wave a (BM/2) x (BN/2) sub-tile held in registers.
+//  * v_mfma_f64_16x16x4_f64 (FP64) / v_mfma_f32_16x16x4_f32 (FP32) tiles; a
+//    workgroup of WGM x WGN waves owns a BM x BN tile of C, each wave a
+//    (BM/WGM) x (BN/WGN) sub-tile held in registers.
 //  * K is walked in steps of BK = 16 through double-buffered LDS tiles (one
 //    barrier per step); the next step's global loads are in flight while the
 //    current step's MFMAs run.
@@ -29,21 +30,44 @@ namespace urv {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// One 16x16x4 MFMA per element type.  The result layouts differ: lane l, entry
+// r holds output row l/16 + 4r for FP64 and row 4(l/16) + r for FP32.
+template <class T>
+struct Mma;
+template <>
+struct Mma<double> {
+  using acc = d4;
+  static __device__ inline acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct Mma<float> {
+  using acc = f4;
+  static __device__ inline acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int r) { return 4 * lk + r; }
+};
 
 constexpr int BK = 16;
-constexpr int PAD = 1;  // LDS row padding (doubles): spreads transposed LDS writes over banks
+constexpr int PAD = 1;  // LDS row padding (elements): spreads transposed LDS writes over banks
 
-template <bool TA, bool TB, int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
-    int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
-    const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
-    double* __restrict__ partial, int64_t k_chunk, int tiles_m, int tiles_n) {
+template <class T, bool TA, bool TB, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(
+    int64_t M, int64_t N, int64_t K, T alpha, const T* __restrict__ A, int64_t lda,
+    const T* __restrict__ B, int64_t ldb, T beta, T* __restrict__ C, int64_t ldc,
+    T* __restrict__ partial, int64_t k_chunk, int tiles_m, int tiles_n) {
+  using acc_t = typename Mma<T>::acc;
   constexpr int NT = 64 * WGM * WGN;             // threads
   constexpr int WM = BM / WGM, WN = BN / WGN;    // wave tile
   constexpr int FM = WM / 16, FN = WN / 16;     // MFMA blocks per wave
   constexpr int LA = BM * BK / NT, LB = BN * BK / NT;  // loads per thread per step
-  __shared__ double As[2][BK][BM + PAD];
-  __shared__ double Bs[2][BK][BN + PAD];
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -67,7 +91,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
   const int64_t ke = min(K, kb + k_chunk);
   const int nk = static_cast<int>(ceil_div(ke - kb, BK));
 
-  double ra[LA], rb[LB];
+  T ra[LA], rb[LB];
 
   // tiles entirely inside C, and K steps entirely inside the chunk, skip all bounds checks
   const bool full_mn = (m0 + BM <= M) && (n0 + BN <= N);
@@ -97,7 +121,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
       int i, k;
       if (!TA) { i = q % BM; k = q / BM; } else { k = q % BK; i = q / BK; }
       const int64_t gi = m0 + i, gk = k0 + k;
-      double v = 0.0;
+      T v = 0;
       if (gi < M && gk < ke) v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
       ra[r] = v;
     }
@@ -107,7 +131,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
       int j, k;
       if (TB) { j = q % BN; k = q / BN; } else { k = q % BK; j = q / BK; }
       const int64_t gj = n0 + j, gk = k0 + k;
-      double v = 0.0;
+      T v = 0;
       if (gj < N && gk < ke) v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
       rb[r] = v;
     }
@@ -129,11 +153,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
     }
   };
 
-  d4 acc[FM][FN];
+  acc_t acc[FM][FN];
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < FN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
   if (nk > 0) {
     load_global(kb);
@@ -148,7 +172,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
     if (kt + 1 < nk) load_global(kb + static_cast<int64_t>(kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
-      double fa[FM], fb[FN];
+      T fa[FM], fb[FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a) fa[a] = As[cur][kk * 4 + lk][wm * WM + a * 16 + lrow];
 #pragma unroll
@@ -157,7 +181,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
       for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[b], fa[a], acc[a][b], 0, 0, 0);
+          acc[a][b] = Mma<T>::run(fb[b], fa[a], acc[a][b]);
     }
     if (kt + 1 < nk) store_lds(cur ^ 1);
     __syncthreads();
@@ -173,41 +197,41 @@ __global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
       for (int b = 0; b < FN; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t gn = n0 + wn * WN + b * 16 + lk + 4 * r;
+          const int64_t gn = n0 + wn * WN + b * 16 + Mma<T>::row(lk, r);
           if (gm < M && gn < N) partial[(static_cast<int64_t>(blockIdx.y) * N + gn) * M + gm] = acc[a][b][r];
         }
     }
     return;
   }
   if (full_mn) {
-    double* cbase = C + (m0 + wm * WM + lrow) + (n0 + wn * WN + lk) * ldc;
-    if (beta != 0.0) {
-      d4 cv[FM][FN];
+    T* cbase = C + (m0 + wm * WM + lrow) + (n0 + wn * WN) * ldc;
+    if (beta != T(0)) {
+      acc_t cv[FM][FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) cv[a][b][r] = cbase[a * 16 + (b * 16 + 4 * r) * ldc];
+          for (int r = 0; r < 4; ++r) cv[a][b][r] = cbase[a * 16 + (b * 16 + Mma<T>::row(lk, r)) * ldc];
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            cbase[a * 16 + (b * 16 + 4 * r) * ldc] = alpha * acc[a][b][r] + beta * cv[a][b][r];
+            cbase[a * 16 + (b * 16 + Mma<T>::row(lk, r)) * ldc] = alpha * acc[a][b][r] + beta * cv[a][b][r];
     } else {
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) cbase[a * 16 + (b * 16 + 4 * r) * ldc] = alpha * acc[a][b][r];
+          for (int r = 0; r < 4; ++r) cbase[a * 16 + (b * 16 + Mma<T>::row(lk, r)) * ldc] = alpha * acc[a][b][r];
     }
     return;
   }
-  if (beta != 0.0) {
-    d4 cv[FM][FN];
+  if (beta != T(0)) {
+    acc_t cv[FM][FN];
 #pragma unroll
     for (int a = 0; a < FM; ++a) {
       const int64_t gm = m0 + wm * WM + a * 16 + lrow;
@@ -215,7 +239,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
       for (int b = 0; b < FN; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t gn = n0 + wn * WN + b * 16 + lk + 4 * r;
+          const int64_t gn = n0 + wn * WN + b * 16 + Mma<T>::row(lk, r);
           cv[a][b][r] = (gm < M && gn < N) ? C[gm + gn * ldc] : 0.0;
         }
     }
@@ -226,7 +250,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
       for (int b = 0; b < FN; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t gn = n0 + wn * WN + b * 16 + lk + 4 * r;
+          const int64_t gn = n0 + wn * WN + b * 16 + Mma<T>::row(lk, r);
           if (gm < M && gn < N) C[gm + gn * ldc] = alpha * acc[a][b][r] + beta * cv[a][b][r];
         }
     }
@@ -238,7 +262,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
       for (int b = 0; b < FN; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t gn = n0 + wn * WN + b * 16 + lk + 4 * r;
+          const int64_t gn = n0 + wn * WN + b * 16 + Mma<T>::row(lk, r);
           if (gm < M && gn < N) C[gm + gn * ldc] = alpha * acc[a][b][r];
         }
     }
@@ -246,24 +270,26 @@ __global__ __launch_bounds__(64 * WGM * WGN) void dgemm_kernel(
 }
 
 // C = alpha * sum_z P[z] + beta * C, z ascending.
-__global__ void splitk_reduce_kernel(int64_t M, int64_t N, int splits, double alpha,
-                                     const double* __restrict__ P, double beta,
-                                     double* __restrict__ C, int64_t ldc) {
+template <class T>
+__global__ void splitk_reduce_kernel(int64_t M, int64_t N, int splits, T alpha,
+                                     const T* __restrict__ P, T beta,
+                                     T* __restrict__ C, int64_t ldc) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx >= M * N) return;
   const int64_t i = idx % M, j = idx / M;
-  double s = 0.0;
+  T s = 0;
   for (int z = 0; z < splits; ++z) s += P[z * M * N + idx];
-  double* c = C + i + j * ldc;
-  *c = (beta == 0.0) ? alpha * s : alpha * s + beta * *c;
+  T* c = C + i + j * ldc;
+  *c = (beta == T(0)) ? alpha * s : alpha * s + beta * *c;
 }
 
-__global__ void scale_kernel(int64_t M, int64_t N, double beta, double* __restrict__ C,
+template <class T>
+__global__ void scale_kernel(int64_t M, int64_t N, T beta, T* __restrict__ C,
                              int64_t ldc) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx >= M * N) return;
-  double* c = C + idx % M + (idx / M) * ldc;
-  *c = (beta == 0.0) ? 0.0 : beta * *c;
+  T* c = C + idx % M + (idx / M) * ldc;
+  *c = (beta == T(0)) ? T(0) : beta * *c;
 }
 
 struct Plan {
@@ -302,14 +328,14 @@ Plan make_plan(int64_t M, int64_t N, int64_t K) {
   return p;
 }
 
-template <bool TA, bool TB>
-void launch_tiles(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
-                  int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
-                  double* partial, hipStream_t s) {
+template <class T, bool TA, bool TB>
+void launch_tiles(const Plan& p, int64_t M, int64_t N, int64_t K, T alpha, const T* A,
+                  int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc,
+                  T* partial, hipStream_t s) {
   const dim3 grid(p.tiles_m * p.tiles_n, p.splits);
 #define URV_GEMM_CASE(TBM, TBN, GM, GN)                                                          \
   if (p.bm == TBM && p.bn == TBN && p.wgm == GM && p.wgn == GN) {                               \
-    dgemm_kernel<TA, TB, TBM, TBN, GM, GN><<<grid, 64 * GM * GN, 0, s>>>(                       \
+    gemm_kernel<T, TA, TB, TBM, TBN, GM, GN><<<grid, 64 * GM * GN, 0, s>>>(                       \
         M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, p.k_chunk, p.tiles_m, p.tiles_n); \
     return;                                                                                     \
   }
@@ -326,21 +352,22 @@ void launch_tiles(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, 
   // any other combination (only reachable through the tuning variable): 2 x 2 waves
   Plan q = p;
   q.wgm = q.wgn = 2;
-  launch_tiles<TA, TB>(q, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
+  launch_tiles<T, TA, TB>(q, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
 }
 
 }  // namespace
 
-size_t dgemm_work_elems(int64_t M, int64_t N, int64_t K) {
+size_t gemm_work_elems(int64_t M, int64_t N, int64_t K) {
   const Plan p = make_plan(M, N, K);
   return p.splits > 1 ? static_cast<size_t>(p.splits) * M * N : 0;
 }
 
-int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
-          int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
-          double* work, size_t work_elems, hipStream_t s) {
+template <class T>
+int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, const T* A, int64_t lda,
+         const T* B, int64_t ldb, T beta, T* C, int64_t ldc, T* work, size_t work_elems,
+         hipStream_t s) {
   if (M == 0 || N == 0) return URV_OK;
-  if (K == 0 || alpha == 0.0) {
+  if (K == 0 || alpha == T(0)) {
     const int64_t total = M * N;
     scale_kernel<<<static_cast<unsigned>(ceil_div(total, 256)), 256, 0, s>>>(M, N, beta, C, ldc);
     URV_LAUNCHED("scale_kernel");
@@ -351,12 +378,12 @@ int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const
     p.splits = 1;
     p.k_chunk = ceil_div(K, BK) * BK;
   }
-  double* partial = p.splits > 1 ? work : nullptr;
-  if (!ta && !tb) launch_tiles<false, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
-  else if (ta && !tb) launch_tiles<true, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
-  else if (!ta && tb) launch_tiles<false, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
-  else launch_tiles<true, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
-  URV_LAUNCHED("dgemm_kernel");
+  T* partial = p.splits > 1 ? work : nullptr;
+  if (!ta && !tb) launch_tiles<T, false, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
+  else if (ta && !tb) launch_tiles<T, true, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
+  else if (!ta && tb) launch_tiles<T, false, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
+  else launch_tiles<T, true, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
+  URV_LAUNCHED("gemm_kernel");
   if (partial) {
     const int64_t total = M * N;
     splitk_reduce_kernel<<<static_cast<unsigned>(ceil_div(total, 256)), 256, 0, s>>>(
@@ -365,5 +392,12 @@ int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const
   }
   return URV_OK;
 }
+
+template int gemm<double>(bool, bool, int64_t, int64_t, int64_t, double, const double*, int64_t,
+                          const double*, int64_t, double, double*, int64_t, double*, size_t,
+                          hipStream_t);
+template int gemm<float>(bool, bool, int64_t, int64_t, int64_t, float, const float*, int64_t,
+                         const float*, int64_t, float, float*, int64_t, float*, size_t,
+                         hipStream_t);
 
 }  // namespace urv

@@ -1,0 +1,244 @@
+// Kernels of the mixed-precision form: the products of the power iteration
+// (A V and A^T W of Section 3, eq. power) on BF16 / FP16 matrix cores with
+// FP32 accumulation, and the precision conversions around them.
+//
+// gemm_lowp computes C = alpha A^T B + beta C for 16-bit A (K x M) and B
+// (K x N), both column-major with K contiguous, so one lane's MFMA operand (8
+// consecutive k) is one 16-byte load.  A V is computed as (A^T)^T V from a
+// transposed 16-bit copy of A made once, A^T W directly from the 16-bit A.
+// The 16-bit buffers have leading dimensions padded to a multiple of 32 and
+// zero padding, so every K step of 32 is a full, unguarded load.
+#include "common.hpp"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+namespace urv {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+template <bool BF16>
+struct Lowp;
+template <>
+struct Lowp<true> {
+  using elem = __bf16;
+  using vec8 = bf8;
+  static __device__ inline f4 mma(vec8 a, vec8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Lowp<false> {
+  using elem = _Float16;
+  using vec8 = h8;
+  static __device__ inline f4 mma(vec8 a, vec8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int LBM = 128, LBN = 128, LBK = 32;
+constexpr int LPAD = 8;  // 16-byte row padding in LDS
+
+// v_mfma_f32_16x16x32_{bf16,f16}: lane l holds A(i = l%16, k = 8(l/16) + e), e = 0..7,
+// B(k = 8(l/16) + e, j = l%16); result entry r of lane l is D(4(l/16) + r, l%16).
+// The MFMA is fed (B fragment, A fragment), so lane l ends with C(m = l%16, n = 4(l/16)+r):
+// sixteen consecutive rows of C per column.
+template <bool BF16>
+__global__ __launch_bounds__(256) void gemm_lowp_kernel(int64_t M, int64_t N, int64_t K, float alpha,
+                                                        const void* __restrict__ Av, int64_t lda,
+                                                        const void* __restrict__ Bv, int64_t ldb,
+                                                        float beta, float* __restrict__ C,
+                                                        int64_t ldc, int tiles_m, int tiles_n) {
+  using E = typename Lowp<BF16>::elem;
+  using V8 = typename Lowp<BF16>::vec8;
+  const E* A = static_cast<const E*>(Av);
+  const E* B = static_cast<const E*>(Bv);
+  __shared__ __attribute__((aligned(16))) E As[2][LBM][LBK + LPAD];
+  __shared__ __attribute__((aligned(16))) E Bs[2][LBN][LBK + LPAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int ntiles = tiles_m * tiles_n;
+  int wg = blockIdx.x;
+  if ((ntiles & 7) == 0) wg = (wg & 7) * (ntiles >> 3) + (wg >> 3);
+  const int tm = wg % tiles_m, tn = wg / tiles_m;
+  const int64_t m0 = static_cast<int64_t>(tm) * LBM, n0 = static_cast<int64_t>(tn) * LBN;
+  const int nk = static_cast<int>(ceil_div(K, LBK));
+
+  // each thread moves two 16-byte chunks of A and two of B per K step
+  uint4 ra[2], rb[2];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int q = tid + 256 * r;
+      const int row = q >> 2, ch = q & 3;
+      const int64_t gi = m0 + row, gj = n0 + row;
+      ra[r] = (gi < M) ? *reinterpret_cast<const uint4*>(A + gi * lda + k0 + 8 * ch) : make_uint4(0, 0, 0, 0);
+      rb[r] = (gj < N) ? *reinterpret_cast<const uint4*>(B + gj * ldb + k0 + 8 * ch) : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int q = tid + 256 * r;
+      const int row = q >> 2, ch = q & 3;
+      *reinterpret_cast<uint4*>(&As[buf][row][8 * ch]) = ra[r];
+      *reinterpret_cast<uint4*>(&Bs[buf][row][8 * ch]) = rb[r];
+    }
+  };
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+  if (nk > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  const int lrow = lane & 15, lk = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load(static_cast<int64_t>(kt + 1) * LBK);
+    V8 fa[4], fb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) fa[a] = *reinterpret_cast<const V8*>(&As[cur][wm * 64 + a * 16 + lrow][8 * lk]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) fb[b] = *reinterpret_cast<const V8*>(&Bs[cur][wn * 64 + b * 16 + lrow][8 * lk]);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = Lowp<BF16>::mma(fb[b], fa[a], acc[a][b]);
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int64_t gm = m0 + wm * 64 + a * 16 + lrow;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gn = n0 + wn * 64 + b * 16 + 4 * lk + r;
+        if (gm < M && gn < N) {
+          float* c = C + gm + gn * ldc;
+          *c = (beta == 0.f) ? alpha * acc[a][b][r] : alpha * acc[a][b][r] + beta * *c;
+        }
+      }
+  }
+}
+
+// dst (rows_pad x cols, ld ldd) = 16-bit RNE rounding of src (rows x cols), zero in rows >= rows.
+template <bool BF16, class S>
+__global__ void to_lowp_kernel(const S* __restrict__ src, int64_t lds, int64_t rows, int64_t cols,
+                               void* __restrict__ dstv, int64_t ldd) {
+  using E = typename Lowp<BF16>::elem;
+  E* dst = static_cast<E*>(dstv);
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= ldd * cols) return;
+  const int64_t i = idx % ldd, j = idx / ldd;
+  const float v = (i < rows) ? static_cast<float>(src[i + j * lds]) : 0.f;
+  dst[i + j * ldd] = static_cast<E>(v);
+}
+
+// dst = 16-bit rounding of src^T: src rows x cols (ld lds), dst cols x rows (ld ldd, padded
+// with zeros in rows >= cols), through 32 x 32 LDS tiles so both sides are coalesced.
+template <bool BF16>
+__global__ __launch_bounds__(256) void to_lowp_transposed_kernel(const double* __restrict__ src,
+                                                                  int64_t lds, int64_t rows,
+                                                                  int64_t cols, void* __restrict__ dstv,
+                                                                  int64_t ldd) {
+  using E = typename Lowp<BF16>::elem;
+  E* dst = static_cast<E*>(dstv);
+  __shared__ float tile[32][33];
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 32;  // src row block
+  const int64_t j0 = static_cast<int64_t>(blockIdx.y) * 32;  // src column block
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;    // 32 x 8
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t i = i0 + tx, j = j0 + y;
+    tile[y][tx] = (i < rows && j < cols) ? static_cast<float>(src[i + j * lds]) : 0.f;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t di = j0 + tx, dj = i0 + y;  // dst(di, dj) = src(dj, di)
+    if (di < ldd && dj < rows) dst[di + dj * ldd] = static_cast<E>(tile[tx][y]);
+  }
+}
+
+template <class S, class D>
+__global__ void convert_kernel(const S* __restrict__ src, int64_t lds, int64_t rows, int64_t cols,
+                               D* __restrict__ dst, int64_t ldd) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx % rows, j = idx / rows;
+  dst[i + j * ldd] = static_cast<D>(src[i + j * lds]);
+}
+
+}  // namespace
+
+int64_t lowp_ld(int64_t rows) { return ceil_div(std::max<int64_t>(rows, 1), 32) * 32; }
+
+int gemm_lowp(bool bf16, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
+              const void* B, int64_t ldb, float beta, float* C, int64_t ldc, hipStream_t s) {
+  if (M == 0 || N == 0) return URV_OK;
+  if (lda % 32 != 0 || ldb % 32 != 0 || lda < lowp_ld(K) || ldb < lowp_ld(K)) {
+    set_last_error("gemm_lowp: 16-bit operands need padded leading dimensions");
+    return URV_EINVAL;
+  }
+  const int tiles_m = static_cast<int>(ceil_div(M, LBM)), tiles_n = static_cast<int>(ceil_div(N, LBN));
+  const dim3 grid(tiles_m * tiles_n);
+  if (bf16)
+    gemm_lowp_kernel<true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n);
+  else
+    gemm_lowp_kernel<false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n);
+  URV_LAUNCHED("gemm_lowp_kernel");
+  return URV_OK;
+}
+
+template <class S>
+int to_lowp(bool bf16, const S* src, int64_t lds, int64_t rows, int64_t cols, void* dst, int64_t ldd,
+            hipStream_t s) {
+  if (rows == 0 || cols == 0) return URV_OK;
+  const unsigned blocks = static_cast<unsigned>(ceil_div(ldd * cols, 256));
+  if (bf16)
+    to_lowp_kernel<true, S><<<blocks, 256, 0, s>>>(src, lds, rows, cols, dst, ldd);
+  else
+    to_lowp_kernel<false, S><<<blocks, 256, 0, s>>>(src, lds, rows, cols, dst, ldd);
+  URV_LAUNCHED("to_lowp_kernel");
+  return URV_OK;
+}
+template int to_lowp<double>(bool, const double*, int64_t, int64_t, int64_t, void*, int64_t, hipStream_t);
+template int to_lowp<float>(bool, const float*, int64_t, int64_t, int64_t, void*, int64_t, hipStream_t);
+
+int to_lowp_transposed(bool bf16, const double* src, int64_t lds, int64_t rows, int64_t cols,
+                       void* dst, int64_t ldd, hipStream_t s) {
+  if (rows == 0 || cols == 0) return URV_OK;
+  // cover dst rows [0, ldd) (zero padding included) and dst columns [0, rows)
+  const dim3 grid(static_cast<unsigned>(ceil_div(rows, 32)), static_cast<unsigned>(ceil_div(ldd, 32)));
+  if (bf16)
+    to_lowp_transposed_kernel<true><<<grid, 256, 0, s>>>(src, lds, rows, cols, dst, ldd);
+  else
+    to_lowp_transposed_kernel<false><<<grid, 256, 0, s>>>(src, lds, rows, cols, dst, ldd);
+  URV_LAUNCHED("to_lowp_transposed_kernel");
+  return URV_OK;
+}
+
+template <class S, class D>
+int convert(const S* src, int64_t lds, int64_t rows, int64_t cols, D* dst, int64_t ldd, hipStream_t s) {
+  if (rows == 0 || cols == 0) return URV_OK;
+  convert_kernel<S, D><<<static_cast<unsigned>(ceil_div(rows * cols, 256)), 256, 0, s>>>(src, lds, rows, cols,
+                                                                                        dst, ldd);
+  URV_LAUNCHED("convert_kernel");
+  return URV_OK;
+}
+template int convert<float, double>(const float*, int64_t, int64_t, int64_t, double*, int64_t, hipStream_t);
+template int convert<double, float>(const double*, int64_t, int64_t, int64_t, float*, int64_t, hipStream_t);
+
+}  // namespace urv

@@ -33,26 +33,34 @@ constexpr int PANEL_THREADS = 64 * PANEL_WAVES;
 constexpr int kMaxPanelWgs = 240;   // all panel workgroups must be co-resident
 constexpr long kSpinLimit = 1L << 23;   // bounded wait: ~seconds, then give up
 
-// Cross-workgroup exchange of the panel.  A value is published as two
-// 64-bit words (tag << 32 | high half) and (tag << 32 | low half) with
-// agent-scope atomic stores, which bypass the per-XCD caches; a reader polls
-// with agent-scope atomic loads until both words carry the tag it expects.
-// Each word is self-validating, so no fences or counters are needed, and a
-// round costs one trip to the coherence point.  Tags (block * 64 + column + 1)
-// grow through a factorisation, and the buffer is zeroed when it starts.
+// Cross-workgroup exchange of the panel.  An FP64 value is published as two
+// 64-bit words (tag << 32 | high half) and (tag << 32 | low half), an FP32
+// value as one word (tag << 32 | bits), with agent-scope atomic stores, which
+// bypass the per-XCD caches; a reader polls with agent-scope atomic loads
+// until every word carries the tag it expects.  Each word is self-validating,
+// so no fences or counters are needed, and a round costs one trip to the
+// coherence point.  Tags (block * 64 + column + 1) grow through a
+// factorisation, and the buffer is zeroed when it starts.  A slot is two
+// words for either type.
 __device__ inline void tagged_store(uint64_t* p, uint32_t tag, double v) {
   const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(v));
   const uint64_t t = static_cast<uint64_t>(tag) << 32;
   __hip_atomic_store(p, t | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(p + 1, t | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ inline void tagged_store(uint64_t* p, uint32_t tag, float v) {
+  const uint64_t bits = static_cast<uint64_t>(__float_as_uint(v));
+  __hip_atomic_store(p, (static_cast<uint64_t>(tag) << 32) | bits, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
 
-// Waits for K tagged values (word pairs at p[k*stride], p[k*stride+1]) and
-// returns them in out[].  Gives up (returns false, raises *err) after a bounded
-// number of polls, or as soon as another workgroup has raised *err.
-template <int K>
+// Waits for K tagged values and returns them in out[].  Gives up (returns
+// false, raises *err) after a bounded number of polls, or as soon as another
+// workgroup has raised *err.
+template <class T, int K>
 __device__ inline bool tagged_load_all(const uint64_t* const* ptr, int count, uint32_t tag,
-                                       double* out, unsigned* err) {
+                                       T* out, unsigned* err) {
+  constexpr bool kTwo = sizeof(T) == 8;
   long spins = 0;
   for (;;) {
     uint64_t w0[K], w1[K];
@@ -60,7 +68,8 @@ __device__ inline bool tagged_load_all(const uint64_t* const* ptr, int count, ui
     for (int k = 0; k < K; ++k) {
       if (k < count) {
         w0[k] = __hip_atomic_load(ptr[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        w1[k] = __hip_atomic_load(ptr[k] + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        w1[k] = kTwo ? __hip_atomic_load(ptr[k] + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : w0[k];
       }
     }
     bool ready = true;
@@ -69,9 +78,14 @@ __device__ inline bool tagged_load_all(const uint64_t* const* ptr, int count, ui
       if (k < count) ready = ready && (w0[k] >> 32) == tag && (w1[k] >> 32) == tag;
     if (ready) {
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (k < count)
-          out[k] = __longlong_as_double(static_cast<long long>((w0[k] << 32) | (w1[k] & 0xffffffffull)));
+      for (int k = 0; k < K; ++k) {
+        if (k < count) {
+          if constexpr (kTwo)
+            out[k] = __longlong_as_double(static_cast<long long>((w0[k] << 32) | (w1[k] & 0xffffffffull)));
+          else
+            out[k] = __uint_as_float(static_cast<unsigned>(w0[k] & 0xffffffffull));
+        }
+      }
       return true;
     }
     if (++spins > kSpinLimit ||
@@ -83,6 +97,19 @@ __device__ inline bool tagged_load_all(const uint64_t* const* ptr, int count, ui
   }
 }
 
+template <class T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+  static __device__ inline double2 make(double a, double b) { return make_double2(a, b); }
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+  static __device__ inline float2 make(float a, float b) { return make_float2(a, b); }
+};
+
 // Makes one lane's LDS writes visible to the other lanes of its wave: the
 // lanes run in lockstep, so only the compiler must be kept from moving LDS
 // accesses across this point (and the LDS queue drained).
@@ -92,17 +119,10 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Lane `lane`'s value of v (uniform result).
-__device__ inline double readlane_f64(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), lane);
-  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
 // sum over the waves of a workgroup, in a fixed order
-__device__ inline double sum_waves(const double (*red)[NB], int c) {
-  double a = 0.0, b = 0.0;
+template <class T>
+__device__ inline T sum_waves(const T (*red)[NB], int c) {
+  T a = 0, b = 0;
 #pragma unroll
   for (int w = 0; w < PANEL_WAVES; w += 2) {
     a += red[w][c];
@@ -113,20 +133,22 @@ __device__ inline double sum_waves(const double (*red)[NB], int c) {
 
 // Column jj of T (lane i computes T(i, jj)):
 // T(jj,jj) = tau_jj,  T(i,jj) = -tau_jj sum_{k<jj} T(i,k) S(k,jj) for i < jj (T(i,k) = 0 for k < i).
-__device__ inline void t_column(double (*Tsh)[NB + 2], const double (*Ssh)[NB + 2],
-                                const double* tau_sh, int jj, int i) {
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+template <class T>
+__device__ inline void t_column(T (*Tsh)[NB + 2], const T (*Ssh)[NB + 2], const T* tau_sh,
+                                int jj, int i) {
+  using V2 = typename Vec2<T>::type;
+  T acc[4] = {0, 0, 0, 0};
   int k = 0;
   for (; k + 1 < jj; k += 2) {
-    const double2 tk = *reinterpret_cast<const double2*>(&Tsh[i][k]);
-    const double2 sk = *reinterpret_cast<const double2*>(&Ssh[jj][k]);
+    const V2 tk = *reinterpret_cast<const V2*>(&Tsh[i][k]);
+    const V2 sk = *reinterpret_cast<const V2*>(&Ssh[jj][k]);
     acc[k & 2] += tk.x * sk.x;
     acc[(k & 2) + 1] += tk.y * sk.y;
   }
   if (k < jj) acc[0] += Tsh[i][k] * Ssh[jj][k];
-  const double tj = tau_sh[jj];
-  const double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-  Tsh[i][jj] = (i < jj) ? -tj * sum : (i == jj ? tj : 0.0);
+  const T tj = tau_sh[jj];
+  const T sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  Tsh[i][jj] = (i < jj) ? -tj * sum : (i == jj ? tj : T(0));
 }
 
 // Householder panel.  Rows [0, mp) x columns [0, jb) at X (ld ldx); the
@@ -146,19 +168,21 @@ __device__ inline void t_column(double (*Tsh)[NB + 2], const double (*Ssh)[NB + 
 // column (T(j,j) = tau_j, T(0:j,j) = -tau_j T(0:j,0:j) S(0:j,j)).
 // Partial sums of a round are added over workgroups in one fixed order, so
 // every workgroup derives bitwise-identical reflectors.
-__global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict__ X, int64_t ldx,
-                                                     int64_t mp, int jb, double* __restrict__ Y,
-                                                     int64_t ldy, double* __restrict__ tau,
-                                                     double* __restrict__ T, int ldt,
+template <class T>
+__global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X, int64_t ldx,
+                                                     int64_t mp, int jb, T* __restrict__ Y,
+                                                     int64_t ldy, T* __restrict__ tau,
+                                                     T* __restrict__ Tout, int ldt,
                                                      uint64_t* __restrict__ xch, uint32_t tag0,
                                                      unsigned* __restrict__ err) {
-  __shared__ double stage[64][NB + 1];
-  __shared__ __attribute__((aligned(16))) double bc[PANEL_WAVES][RPT];  // pivot column, per wave
-  __shared__ double red[PANEL_WAVES][NB];
-  __shared__ double pivrow[NB];
-  __shared__ __attribute__((aligned(16))) double Ssh[NB][NB + 2];  // Ssh[j][c] = S(c, j), c < j
-  __shared__ __attribute__((aligned(16))) double Tsh[NB][NB + 2];  // Tsh[i][k] = T(i, k)
-  __shared__ double tau_sh[NB];
+  using V2 = typename Vec2<T>::type;
+  __shared__ T stage[64][NB + 1];
+  __shared__ __attribute__((aligned(16))) T bc[PANEL_WAVES][RPT];  // pivot column, per wave
+  __shared__ T red[PANEL_WAVES][NB];
+  __shared__ T pivrow[NB];
+  __shared__ __attribute__((aligned(16))) T Ssh[NB][NB + 2];  // Ssh[j][c] = S(c, j), c < j
+  __shared__ __attribute__((aligned(16))) T Tsh[NB][NB + 2];  // Tsh[i][k] = T(i, k)
+  __shared__ T tau_sh[NB];
 
   const int P = gridDim.x;
   const int wg = blockIdx.x;
@@ -174,12 +198,12 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
 
   // ---- load through LDS, 64 rows at a time (coalesced along columns)
   constexpr int WAVES_PER_CHUNK = 64 / RPT;
-  double x[RPT];
+  T x[RPT];
   for (int k = 0; k < RPW / 64; ++k) {
     for (int e = threadIdx.x; e < 64 * NB; e += PANEL_THREADS) {
       const int r = e & 63, col = e >> 6;
       const int64_t gi = row0 + k * 64 + r;
-      stage[r][col] = (gi < mp && col < jb) ? X[gi + col * ldx] : 0.0;
+      stage[r][col] = (gi < mp && col < jb) ? X[gi + col * ldx] : T(0);
     }
     __syncthreads();
     if (g / WAVES_PER_CHUNK == k) {
@@ -190,7 +214,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
     __syncthreads();
   }
   if (wg == 0)
-    for (int e = threadIdx.x; e < NB * (NB + 2); e += PANEL_THREADS) (&Tsh[0][0])[e] = 0.0;
+    for (int e = threadIdx.x; e < NB * (NB + 2); e += PANEL_THREADS) (&Tsh[0][0])[e] = T(0);
 
   bool ok = true;
   for (int j = 0; j < jb; ++j) {
@@ -204,14 +228,14 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
     if (c == j) {
 #pragma unroll
       for (int r = 0; r < RPT; r += 2)
-        *reinterpret_cast<double2*>(&bc[g][r]) = make_double2(r > lo ? x[r] : 0.0, r + 1 > lo ? x[r + 1] : 0.0);
+        *reinterpret_cast<V2*>(&bc[g][r]) = Vec2<T>::make(r > lo ? x[r] : T(0), r + 1 > lo ? x[r + 1] : T(0));
     }
     wave_lds_sync();
     // 2. q_c over this wave's rows below the pivot
-    double qa[4] = {0.0, 0.0, 0.0, 0.0};
+    T qa[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int r = 0; r < RPT; r += 2) {
-      const double2 xj = *reinterpret_cast<const double2*>(&bc[g][r]);
+      const V2 xj = *reinterpret_cast<const V2*>(&bc[g][r]);
       qa[r & 2] += xj.x * x[r];
       qa[(r & 2) + 1] += xj.y * x[r + 1];
     }
@@ -230,8 +254,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
     }
     // 3. gather, in one batch where possible: pivot row entries c and j, and this
     //    wave's share (w = g, g + PANEL_WAVES, ...) of the partial sums
-    double piv[2];
-    double sacc = 0.0;
+    T piv[2];
+    T sacc = T(0);
     {
       const uint64_t* ptrs[6] = {slot(par, P, c), slot(par, P, j)};
       int cnt = 2;
@@ -241,8 +265,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
         ptrs[2 + u] = slot(par, w < P ? w : 0, c);
         cnt += (w < P) ? 1 : 0;
       }
-      double vals[6];
-      ok = tagged_load_all<6>(ptrs, cnt, tag, vals, err);
+      T vals[6];
+      ok = tagged_load_all<T, 6>(ptrs, cnt, tag, vals, err);
       piv[0] = vals[0];
       piv[1] = vals[1];
 #pragma unroll
@@ -258,8 +282,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
         ptrs[u] = slot(par, w < P ? w : 0, c);
         cnt += (w < P) ? 1 : 0;
       }
-      double vals[4];
-      ok = tagged_load_all<4>(ptrs, cnt, tag, vals, err);
+      T vals[4];
+      ok = tagged_load_all<T, 4>(ptrs, cnt, tag, vals, err);
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         if (u < cnt) sacc += vals[u];
@@ -270,16 +294,16 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
       ok = false;
       break;
     }
-    const double xcj = piv[0];
-    const double alpha = piv[1];
-    const double qc = sum_waves(red, c);
-    const double sigma2 = sum_waves(red, j);
+    const T xcj = piv[0];
+    const T alpha = piv[1];
+    const T qc = sum_waves(red, c);
+    const T sigma2 = sum_waves(red, j);
     // 4. reflector of column j
-    double t = 0.0, beta = alpha, rinv = 0.0;
-    if (sigma2 != 0.0) {
-      const double norm = sqrt(alpha * alpha + sigma2);
-      beta = (alpha >= 0.0) ? -norm : norm;
-      rinv = 1.0 / (alpha - beta);
+    T t = T(0), beta = alpha, rinv = T(0);
+    if (sigma2 != T(0)) {
+      const T norm = sqrt(alpha * alpha + sigma2);
+      beta = (alpha >= T(0)) ? -norm : norm;
+      rinv = T(1) / (alpha - beta);
       t = (beta - alpha) / beta;
     }
     if (g == 0) {
@@ -289,15 +313,15 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
     // its action, one instruction stream for all lanes (lane j's column from LDS):
     //   c > j:  x_c -= tau (v^T x_c) v, with v = x_j / (alpha - beta) below the pivot
     //   c == j: x_j becomes v below the pivot and beta on it
-    const bool upd = c > j && t != 0.0;
-    const double tw = upd ? t * (xcj + qc * rinv) : 0.0;  // tau * (v^T x_c)
-    const double coef = tw * rinv;
-    const double scale = (c == j) ? rinv : 1.0;
+    const bool upd = c > j && t != T(0);
+    const T tw = upd ? t * (xcj + qc * rinv) : T(0);  // tau * (v^T x_c)
+    const T coef = tw * rinv;
+    const T scale = (c == j) ? rinv : T(1);
 #pragma unroll
     for (int r = 0; r < RPT; r += 2) {
-      const double2 xj = *reinterpret_cast<const double2*>(&bc[g][r]);
-      const double n0 = x[r] * scale - coef * xj.x;
-      const double n1 = x[r + 1] * scale - coef * xj.y;
+      const V2 xj = *reinterpret_cast<const V2*>(&bc[g][r]);
+      const T n0 = x[r] * scale - coef * xj.x;
+      const T n1 = x[r + 1] * scale - coef * xj.y;
       x[r] = (r > lo) ? n0 : x[r];
       x[r + 1] = (r + 1 > lo) ? n1 : x[r + 1];
     }
@@ -311,7 +335,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
 
   if (!ok) {
     // A device-side wait gave up: poison the outputs so the failure is visible.
-    const double nan = __builtin_nan("");
+    const T nan = static_cast<T>(__builtin_nan(""));
 #pragma unroll
     for (int r = 0; r < RPT; ++r) x[r] = nan;
     if (g == 0) tau_sh[c] = nan;
@@ -324,7 +348,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
     __syncthreads();
     for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
       const int i = e % NB, k = e / NB;
-      if (i < jb && k < jb) T[i + static_cast<int64_t>(k) * ldt] = ok ? Tsh[i][k] : __builtin_nan("");
+      if (i < jb && k < jb) Tout[i + static_cast<int64_t>(k) * ldt] = ok ? Tsh[i][k] : static_cast<T>(__builtin_nan(""));
     }
     if (threadIdx.x < jb) tau[threadIdx.x] = tau_sh[threadIdx.x];
   }
@@ -341,9 +365,9 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
       const int r = e & 63, col = e >> 6;
       const int64_t gi = row0 + k * 64 + r;
       if (gi < mp && col < jb) {
-        const double v = stage[r][col];
+        const T v = stage[r][col];
         X[gi + col * ldx] = v;
-        Y[gi + col * ldy] = (gi > col) ? v : (gi == col ? 1.0 : 0.0);
+        Y[gi + col * ldy] = (gi > col) ? v : (gi == col ? T(1) : T(0));
       }
     }
     __syncthreads();
@@ -351,27 +375,29 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(double* __restrict
 }
 
 // R(i,c) = d_i X(i,c) for i <= c, 0 below; d_i = sign(X(i,i)), sign(0) = +1.
-__global__ void extract_r_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
-                                 double* __restrict__ R, int64_t ldr) {
+template <class T>
+__global__ void extract_r_kernel(const T* __restrict__ X, int64_t ldx, int64_t n,
+                                 T* __restrict__ R, int64_t ldr) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx >= n * n) return;
   const int64_t i = idx % n, c = idx / n;
-  double v = 0.0;
+  T v = 0;
   if (i <= c) {
-    const double d = (X[i + i * ldx] < 0.0) ? -1.0 : 1.0;
+    const T d = (X[i + i * ldx] < T(0)) ? T(-1) : T(1);
     v = d * X[i + c * ldx];
   }
   R[i + c * ldr] = v;
 }
 
 // Q = [D; 0], D = diag(sign(X(c,c))).
-__global__ void init_q_kernel(const double* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
-                              double* __restrict__ Q, int64_t ldq) {
+template <class T>
+__global__ void init_q_kernel(const T* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                              T* __restrict__ Q, int64_t ldq) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx >= m * n) return;
   const int64_t i = idx % m, c = idx / m;
-  double v = 0.0;
-  if (i == c) v = (X[c + c * ldx] < 0.0) ? -1.0 : 1.0;
+  T v = 0;
+  if (i == c) v = (X[c + c * ldx] < T(0)) ? T(-1) : T(1);
   Q[i + c * ldq] = v;
 }
 
@@ -412,29 +438,32 @@ QrSizes qr_sizes(int64_t m, int64_t n) {
 
 }  // namespace
 
+template <class T>
 size_t qr_work_bytes(int64_t m, int64_t n) {
   Arena a;
-  QrWork w;
+  QrWorkT<T> w;
   qr_work_carve(a, m, n, w);
   return a.used;
 }
 
-void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWork& w) {
+template <class T>
+void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w) {
   const QrSizes z = qr_sizes(m, n);
-  w.Y = a.take<double>(z.y);
-  w.T = a.take<double>(z.t);
-  w.tau = a.take<double>(z.tau);
-  w.W1 = a.take<double>(z.w);
-  w.W2 = a.take<double>(z.w);
+  w.Y = a.take<T>(z.y);
+  w.Tm = a.take<T>(z.t);
+  w.tau = a.take<T>(z.tau);
+  w.W1 = a.take<T>(z.w);
+  w.W2 = a.take<T>(z.w);
   w.xch = a.take<uint64_t>(z.xch);
   w.xch_words = z.xch;
   w.sync = a.take<unsigned>(z.sync);
-  w.gemm_work = a.take<double>(z.gemm_work);
+  w.gemm_work = a.take<T>(z.gemm_work);
   w.gemm_work_elems = z.gemm_work;
 }
 
-int qr_pos(double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq, double* R,
-           int64_t ldr, const QrWork& w, hipStream_t s) {
+template <class T>
+int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int64_t ldr,
+           const QrWorkT<T>& w, hipStream_t s) {
   if (n == 0) return URV_OK;
   const int64_t nblocks = ceil_div(n, NB);
   if (panel_wgs(m) > kMaxPanelWgs) {
@@ -451,46 +480,59 @@ int qr_pos(double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq,
   for (int64_t j0 = 0, blk = 0; j0 < n; j0 += NB, ++blk) {
     const int jb = static_cast<int>(std::min<int64_t>(NB, n - j0));
     const int64_t mp = m - j0;
-    double* Xp = X + j0 + j0 * ldx;
-    double* Yb = w.Y + j0 + j0 * m;
-    double* Tb = w.T + j0 * NB;
+    T* Xp = X + j0 + j0 * ldx;
+    T* Yb = w.Y + j0 + j0 * m;
+    T* Tb = w.Tm + j0 * NB;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
-    panel_kernel<<<P, PANEL_THREADS, 0, s>>>(Xp, ldx, mp, jb, Yb, m, w.tau + j0, Tb, NB, w.xch,
+    panel_kernel<T><<<P, PANEL_THREADS, 0, s>>>(Xp, ldx, mp, jb, Yb, m, w.tau + j0, Tb, NB, w.xch,
                                    static_cast<uint32_t>(blk * NB), err);
     URV_LAUNCHED("panel_kernel");
     const int64_t nc = n - j0 - jb;
     if (nc > 0) {
-      double* Cb = X + j0 + (j0 + jb) * ldx;
-      URV_TRY(dgemm(true, false, jb, nc, mp, 1.0, Yb, m, Cb, ldx, 0.0, w.W1, NB, w.gemm_work,
-                    w.gemm_work_elems, s));
-      URV_TRY(dgemm(true, false, jb, nc, jb, 1.0, Tb, NB, w.W1, NB, 0.0, w.W2, NB, nullptr, 0, s));
-      URV_TRY(dgemm(false, false, mp, nc, jb, -1.0, Yb, m, w.W2, NB, 1.0, Cb, ldx, nullptr, 0, s));
+      T* Cb = X + j0 + (j0 + jb) * ldx;
+      URV_TRY(gemm<T>(true, false, jb, nc, mp, T(1), Yb, m, Cb, ldx, T(0), w.W1, NB, w.gemm_work,
+                      w.gemm_work_elems, s));
+      URV_TRY(gemm<T>(true, false, jb, nc, jb, T(1), Tb, NB, w.W1, NB, T(0), w.W2, NB, nullptr, 0, s));
+      URV_TRY(gemm<T>(false, false, mp, nc, jb, T(-1), Yb, m, w.W2, NB, T(1), Cb, ldx, nullptr, 0, s));
     }
   }
 
   if (R) {
-    extract_r_kernel<<<static_cast<unsigned>(ceil_div(n * n, 256)), 256, 0, s>>>(X, ldx, n, R, ldr);
+    extract_r_kernel<T><<<static_cast<unsigned>(ceil_div(n * n, 256)), 256, 0, s>>>(X, ldx, n, R, ldr);
     URV_LAUNCHED("extract_r_kernel");
   }
   if (Q) {
-    init_q_kernel<<<static_cast<unsigned>(ceil_div(m * n, 256)), 256, 0, s>>>(X, ldx, m, n, Q, ldq);
+    init_q_kernel<T><<<static_cast<unsigned>(ceil_div(m * n, 256)), 256, 0, s>>>(X, ldx, m, n, Q, ldq);
     URV_LAUNCHED("init_q_kernel");
     for (int64_t blk = nblocks - 1; blk >= 0; --blk) {
       const int64_t j0 = blk * NB;
       const int jb = static_cast<int>(std::min<int64_t>(NB, n - j0));
       const int64_t mp = m - j0, nq = n - j0;
-      const double* Yb = w.Y + j0 + j0 * m;
-      const double* Tb = w.T + j0 * NB;
-      double* Qb = Q + j0 + j0 * ldq;
-      URV_TRY(dgemm(true, false, jb, nq, mp, 1.0, Yb, m, Qb, ldq, 0.0, w.W1, NB, w.gemm_work,
-                    w.gemm_work_elems, s));
-      URV_TRY(dgemm(false, false, jb, nq, jb, 1.0, Tb, NB, w.W1, NB, 0.0, w.W2, NB, nullptr, 0, s));
-      URV_TRY(dgemm(false, false, mp, nq, jb, -1.0, Yb, m, w.W2, NB, 1.0, Qb, ldq, nullptr, 0, s));
+      const T* Yb = w.Y + j0 + j0 * m;
+      const T* Tb = w.Tm + j0 * NB;
+      T* Qb = Q + j0 + j0 * ldq;
+      URV_TRY(gemm<T>(true, false, jb, nq, mp, T(1), Yb, m, Qb, ldq, T(0), w.W1, NB, w.gemm_work,
+                      w.gemm_work_elems, s));
+      URV_TRY(gemm<T>(false, false, jb, nq, jb, T(1), Tb, NB, w.W1, NB, T(0), w.W2, NB, nullptr, 0, s));
+      URV_TRY(gemm<T>(false, false, mp, nq, jb, T(-1), Yb, m, w.W2, NB, T(1), Qb, ldq, nullptr, 0, s));
     }
   }
   return URV_OK;
 }
 
-unsigned* qr_error_flag(const QrWork& w, int64_t n) { return w.sync + ceil_div(n, NB); }
+template <class T>
+unsigned* qr_error_flag(const QrWorkT<T>& w, int64_t n) {
+  return w.sync + ceil_div(n, NB);
+}
+
+#define URV_QR_INSTANTIATE(T)                                                                 \
+  template size_t qr_work_bytes<T>(int64_t, int64_t);                                         \
+  template void qr_work_carve<T>(Arena&, int64_t, int64_t, QrWorkT<T>&);                     \
+  template int qr_pos<T>(T*, int64_t, int64_t, int64_t, T*, int64_t, T*, int64_t,             \
+                         const QrWorkT<T>&, hipStream_t);                                     \
+  template unsigned* qr_error_flag<T>(const QrWorkT<T>&, int64_t);
+URV_QR_INSTANTIATE(double)
+URV_QR_INSTANTIATE(float)
+#undef URV_QR_INSTANTIATE
 
 }  // namespace urv

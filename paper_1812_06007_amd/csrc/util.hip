@@ -10,7 +10,8 @@
 namespace urv {
 namespace {
 
-__global__ void copy_kernel(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+template <class T>
+__global__ void copy_kernel(const T* __restrict__ src, int64_t lds, T* __restrict__ dst,
                             int64_t ldd, int64_t rows, int64_t cols) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx >= rows * cols) return;
@@ -102,8 +103,17 @@ int sumsq(const double* X, int64_t ld, int64_t rows, int64_t cols, double diag, 
 int copy_matrix(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
                 int64_t cols, hipStream_t s) {
   if (rows == 0 || cols == 0) return URV_OK;
-  copy_kernel<<<static_cast<unsigned>(ceil_div(rows * cols, 256)), 256, 0, s>>>(src, lds, dst, ldd,
-                                                                                 rows, cols);
+  copy_kernel<double><<<static_cast<unsigned>(ceil_div(rows * cols, 256)), 256, 0, s>>>(src, lds, dst,
+                                                                                         ldd, rows, cols);
+  URV_LAUNCHED("copy_kernel");
+  return URV_OK;
+}
+
+int copy_matrix_f32(const float* src, int64_t lds, float* dst, int64_t ldd, int64_t rows, int64_t cols,
+                    hipStream_t s) {
+  if (rows == 0 || cols == 0) return URV_OK;
+  copy_kernel<float><<<static_cast<unsigned>(ceil_div(rows * cols, 256)), 256, 0, s>>>(src, lds, dst,
+                                                                                        ldd, rows, cols);
   URV_LAUNCHED("copy_kernel");
   return URV_OK;
 }

@@ -48,7 +48,7 @@ class UrvOpts(ctypes.Structure):
 
 
 EXPORTS = ["urv_opts_init", "urv_factor_ex", "urv_factor", "urv_workspace_size", "urv_gaussian",
-           "urv_dgemm", "urv_qr_pos", "urv_metrics", "urv_strerror", "urv_last_error"]
+           "urv_dgemm", "urv_qr_pos", "urv_qr_pos_f32", "urv_metrics", "urv_strerror", "urv_last_error"]
 
 _lib = None
 
@@ -72,12 +72,14 @@ def lib() -> ctypes.CDLL:
     L.urv_gaussian.argtypes = [P, I64, I64, I64, U64, U32, I32, P]
     L.urv_dgemm.argtypes = [I32, I32, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P]
     L.urv_qr_pos.argtypes = [P, I64, I64, I64, P, I64, P, I64, P]
+    L.urv_qr_pos_f32.argtypes = [P, I64, I64, I64, P, I64, P, I64, P]
     L.urv_metrics.argtypes = [P, I64, I64, P, P, P, P, P, P]
     L.urv_strerror.argtypes = [ctypes.c_int]
     L.urv_strerror.restype = ctypes.c_char_p
     L.urv_last_error.argtypes = []
     L.urv_last_error.restype = ctypes.c_char_p
-    for name in ("urv_factor_ex", "urv_factor", "urv_gaussian", "urv_dgemm", "urv_qr_pos", "urv_metrics"):
+    for name in ("urv_factor_ex", "urv_factor", "urv_gaussian", "urv_dgemm", "urv_qr_pos", "urv_qr_pos_f32",
+                 "urv_metrics"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -228,14 +230,18 @@ def dgemm(A, B, transA: bool = False, transB: bool = False, alpha: float = 1.0, 
     return C
 
 
-def qr_pos(X, want_q: bool = True, want_r: bool = True):
-    """Blocked Householder QR with diag(R) >= 0.  Returns (Q, R) (None where not wanted)."""
-    Xw = empty_colmajor(*X.shape, device=X.device)
+def qr_pos(X, want_q: bool = True, want_r: bool = True, fp32: bool = False):
+    """Blocked Householder QR with diag(R) >= 0 (FP64, or FP32 with fp32=True).
+    Returns (Q, R) (None where not wanted)."""
+    torch = _torch()
+    dt = torch.float32 if fp32 else torch.float64
+    Xw = empty_colmajor(*X.shape, dtype=dt, device=X.device)
     Xw.copy_(X)
     m, n = Xw.shape
-    Q = empty_colmajor(m, n, device=X.device) if want_q else None
-    R = empty_colmajor(n, n, device=X.device) if want_r else None
-    _check(lib().urv_qr_pos(_ptr(Xw), m, n, max(m, 1), _ptr(Q), max(m, 1), _ptr(R), max(n, 1), _stream_ptr()))
+    Q = empty_colmajor(m, n, dtype=dt, device=X.device) if want_q else None
+    R = empty_colmajor(n, n, dtype=dt, device=X.device) if want_r else None
+    fn = lib().urv_qr_pos_f32 if fp32 else lib().urv_qr_pos
+    _check(fn(_ptr(Xw), m, n, max(m, 1), _ptr(Q), max(m, 1), _ptr(R), max(n, 1), _stream_ptr()))
     return Q, R
 
 

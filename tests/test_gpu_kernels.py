@@ -158,3 +158,28 @@ def test_qr_power_of_two_scaling_bitwise(urv):
     Q2, R2 = urv.qr_pos(to_gpu(X * 2.0**-9))
     np.testing.assert_array_equal(to_np(Q1), to_np(Q2))
     np.testing.assert_array_equal(to_np(R1) * 2.0**-9, to_np(R2))
+
+
+# ---------------------------------------------------------------- Qpos in FP32 (mixed-precision form)
+@pytest.mark.parametrize("m,n", [(1, 1), (7, 3), (65, 64), (300, 300), (1000, 257), (2000, 130)])
+def test_qr_fp32_matches_oracle(urv, orc, m, n):
+    announce("qr fp32", m, n)
+    rng = np.random.default_rng(m * 17 + n)
+    X = rng.standard_normal((m, n)).astype(np.float32).astype(np.float64)  # exactly representable
+    Q, R = urv.qr_pos(to_gpu(X), fp32=True)
+    Q, R = to_np(Q), to_np(R)
+    Qo, Ro = orc.qr_pos(X)
+    eps32 = float(np.finfo(np.float32).eps)
+    nx = np.linalg.norm(X)
+    assert np.linalg.norm(R - Ro) <= 50 * max(n, 4) * eps32 * nx
+    assert np.all(np.diag(R) >= 0) and np.array_equal(R, np.triu(R))
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 20 * max(n, 4) * eps32
+    assert np.linalg.norm(Q @ R - X) <= 20 * max(n, 4) * eps32 * nx
+
+
+def test_qr_fp32_kahan_exact(urv):
+    announce("qr fp32 kahan")
+    K = gen.kahan(100).astype(np.float32).astype(np.float64)
+    Q, R = urv.qr_pos(to_gpu(K), fp32=True)
+    np.testing.assert_array_equal(to_np(Q), np.eye(100))
+    np.testing.assert_array_equal(to_np(R), K)

@@ -234,3 +234,33 @@ def test_full_size_kahan_4000(urv):
         met = urv.metrics(K, U, R, V)
         assert met["recon"] < 1e-12 and met["orthU"] < 1e-10 and met["orthV"] < 1e-10, (q, met)
         assert np.linalg.norm(R.cpu().numpy()) == pytest.approx(np.sqrt(n), rel=1e-12)
+
+
+# ------------------------------------------------ mixed precision (BF16 / FP16 products, FP32 QR, FP64 tail)
+@pytest.mark.parametrize("prec", ["mixed_bf16", "mixed_fp16"])
+@pytest.mark.parametrize("variant", ["full", "half"])
+def test_mixed_precision_against_fp64_oracle(urv, orc, prec, variant):
+    """Reconstruction and orthogonality stay at FP64 level (the FP64 re-orthonormalisation and
+    tail); the rank-k errors stay close to the FP64 oracle's where sigma_k is well above the
+    16-bit rounding level, and never beat the Eckart-Young bound."""
+    announce("mixed", prec, variant)
+    m, n = 1200, 600
+    sigma = np.exp(-10.0 * np.arange(1, n + 1) / n)  # the same decay range as exp(-j/800), j <= 8000
+    A = gen.noisy_spectral_matrix(m, n, sigma, seed=7, noise_var=1e-6)
+    A = A.astype(np.float32).astype(np.float64)  # the input is an FP32 matrix
+    G = gen.gaussian(n, n, 8)
+    U, R, V = _gpu_factor(urv, A, 2, G=to_gpu(G), precision=prec, variant=variant)
+    met = _assert_invariants(urv, A, (U, R, V), 1e-10)
+    assert met["recon"] <= 1e-6
+    Uo, Ro, Vo = orc.urv(A, 2, G=G, variant="full")
+    eko = orc.metrics(A, Uo, Ro, Vo)["ek"]
+    ek = met["ek"]
+    na = np.linalg.norm(A)
+    s = np.linalg.svd(A, compute_uv=False)
+    tail = np.sqrt(np.concatenate([np.cumsum((s * s)[::-1])[::-1], [0.0]]))
+    assert np.all(ek >= tail * (1 - 1e-9) - 1e-13 * na)
+    sel = eko >= 0.05 * na
+    ratio = ek[sel] / eko[sel]
+    print("[mixed] %s %s: max ek ratio (ek >= 5%% ||A||) %.4f, ||R-R64||/||A|| %.3e"
+          % (prec, variant, ratio.max(), np.linalg.norm(R - Ro) / na))
+    assert ratio.max() <= 1.25
