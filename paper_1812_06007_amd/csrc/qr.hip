@@ -406,12 +406,69 @@ __global__ void fill_u64_kernel(uint64_t* p, int64_t count) {
   if (idx < count) p[idx] = 0;
 }
 
+// Zeroes a rows x cols block (ld ld).
+template <class T>
+__global__ void zero_block_kernel(T* __restrict__ p, int64_t rows, int64_t cols, int64_t ld) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= rows * cols) return;
+  p[idx % rows + (idx / rows) * ld] = T(0);
+}
+
+// Joins the T factors of two consecutive panels into the T of their union:
+// for H = (I - Y1 T1 Y1^T)(I - Y2 T2 Y2^T) = I - [Y1 Y2] T [Y1 Y2]^T,
+// T = [[T1, -T1 (Y1^T Y2) T2], [0, T2]].  T1 and T2 are already in place in
+// the (ld ldt) block at Tb; S12 = Y1^T Y2 (jb1 x jb2, ld lds).  One workgroup.
+template <class T>
+__global__ __launch_bounds__(1024) void t_join_kernel(T* __restrict__ Tb, int ldt, int jb1, int jb2,
+                                                      const T* __restrict__ S12, int lds) {
+  __shared__ T t1[NB][NB + 1];
+  __shared__ T t2[NB][NB + 1];
+  __shared__ T u[NB][NB + 1];
+  constexpr int PER = NB * NB / 1024;
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int i = e % NB, j = e / NB;
+    t1[i][j] = (i < jb1 && j < jb1) ? Tb[i + static_cast<int64_t>(j) * ldt] : T(0);
+    t2[i][j] = (i < jb2 && j < jb2) ? Tb[jb1 + i + static_cast<int64_t>(jb1 + j) * ldt] : T(0);
+    u[i][j] = (i < jb1 && j < jb2) ? S12[i + static_cast<int64_t>(j) * lds] : T(0);
+  }
+  __syncthreads();
+  // u <- S12 T2 (T2 upper triangular: only k <= j contributes)
+  T acc[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int e = threadIdx.x + r * 1024, i = e % NB, j = e / NB;
+    T a = 0;
+    for (int k = 0; k <= j; ++k) a += u[i][k] * t2[k][j];
+    acc[r] = a;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int e = threadIdx.x + r * 1024;
+    u[e % NB][e / NB] = acc[r];
+  }
+  __syncthreads();
+  // T12 = -T1 u (T1 upper triangular: only k >= i contributes); lower-left block is zero
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int e = threadIdx.x + r * 1024, i = e % NB, j = e / NB;
+    T a = 0;
+    for (int k = i; k < NB; ++k) a += t1[i][k] * u[k][j];
+    if (i < jb1 && j < jb2) Tb[i + static_cast<int64_t>(jb1 + j) * ldt] = -a;
+    if (i < jb2 && j < jb1) Tb[jb1 + i + static_cast<int64_t>(j) * ldt] = T(0);
+  }
+}
+
 __global__ void fill_u32_kernel(unsigned* p, int64_t count, unsigned v) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx < count) p[idx] = v;
 }
 
 int64_t panel_wgs(int64_t mp) { return ceil_div(mp, RPW); }
+
+// Outer block: two consecutive panels share one trailing update of width NB2,
+// which halves the passes over the trailing matrix.
+constexpr int NB2 = 2 * NB;
 
 struct QrSizes {
   size_t y, t, tau, w, xch, sync, gemm_work;
@@ -421,16 +478,18 @@ QrSizes qr_sizes(int64_t m, int64_t n) {
   QrSizes z;
   const int64_t nblocks = ceil_div(n, NB);
   z.y = static_cast<size_t>(m) * n;
-  z.t = static_cast<size_t>(NB) * n;
+  z.t = static_cast<size_t>(NB2) * n;
   z.tau = n;
-  z.w = static_cast<size_t>(NB) * n;
+  z.w = static_cast<size_t>(NB2) * n;
   z.xch = 2 * (static_cast<size_t>(panel_wgs(m)) + 1) * NB * 2;
   z.sync = nblocks + 2;
   size_t gw = 0;
-  for (int64_t j0 = 0; j0 < n; j0 += NB) {
-    const int64_t jb = std::min<int64_t>(NB, n - j0), mp = m - j0;
-    gw = std::max(gw, dgemm_work_elems(jb, n - j0 - jb, mp));
-    gw = std::max(gw, dgemm_work_elems(jb, n - j0, mp));
+  for (int64_t j0 = 0; j0 < n; j0 += NB2) {
+    const int64_t jb = std::min<int64_t>(NB2, n - j0), mp = m - j0;
+    const int64_t jb1 = std::min<int64_t>(NB, jb), jb2 = jb - jb1;
+    gw = std::max(gw, gemm_work_elems(jb1, jb2, mp));
+    gw = std::max(gw, gemm_work_elems(jb, n - j0 - jb, mp));
+    gw = std::max(gw, gemm_work_elems(jb, n - j0, mp));
   }
   z.gemm_work = gw;
   return z;
@@ -477,23 +536,47 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       w.xch, static_cast<int64_t>(w.xch_words));
   URV_LAUNCHED("fill_u64_kernel");
 
-  for (int64_t j0 = 0, blk = 0; j0 < n; j0 += NB, ++blk) {
-    const int jb = static_cast<int>(std::min<int64_t>(NB, n - j0));
-    const int64_t mp = m - j0;
-    T* Xp = X + j0 + j0 * ldx;
-    T* Yb = w.Y + j0 + j0 * m;
-    T* Tb = w.Tm + j0 * NB;
+  uint32_t panels = 0;  // panel launches so far: exchange tags stay distinct
+  auto panel = [&](int64_t r0, int jbp, T* Tp) -> int {
+    const int64_t mp = m - r0;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
-    panel_kernel<T><<<P, PANEL_THREADS, 0, s>>>(Xp, ldx, mp, jb, Yb, m, w.tau + j0, Tb, NB, w.xch,
-                                   static_cast<uint32_t>(blk * NB), err);
+    panel_kernel<T><<<P, PANEL_THREADS, 0, s>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
+                                                w.tau + r0, Tp, NB2, w.xch, panels * NB, err);
+    ++panels;
     URV_LAUNCHED("panel_kernel");
+    return URV_OK;
+  };
+  for (int64_t j0 = 0; j0 < n; j0 += NB2) {
+    const int jb = static_cast<int>(std::min<int64_t>(NB2, n - j0));
+    const int jb1 = std::min(jb, NB), jb2 = jb - jb1;
+    const int64_t mp = m - j0;
+    T* Yb = w.Y + j0 + j0 * m;
+    T* Tb = w.Tm + j0 * NB2;
+    URV_TRY(panel(j0, jb1, Tb));
+    if (jb2 > 0) {
+      // first panel's reflectors applied to the second panel's columns
+      T* C2 = X + j0 + (j0 + jb1) * ldx;
+      URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, C2, ldx, T(0), w.W1, NB2, w.gemm_work,
+                      w.gemm_work_elems, s));
+      URV_TRY(gemm<T>(true, false, jb1, jb2, jb1, T(1), Tb, NB2, w.W1, NB2, T(0), w.W2, NB2, nullptr, 0, s));
+      URV_TRY(gemm<T>(false, false, mp, jb2, jb1, T(-1), Yb, m, w.W2, NB2, T(1), C2, ldx, nullptr, 0, s));
+      // Y2 is zero above its panel; then the second panel and the joined T
+      zero_block_kernel<T><<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(jb1) * jb2, 256)), 256, 0, s>>>(
+          w.Y + j0 + (j0 + jb1) * m, jb1, jb2, m);
+      URV_LAUNCHED("zero_block_kernel");
+      URV_TRY(panel(j0 + jb1, jb2, Tb + jb1 + static_cast<int64_t>(jb1) * NB2));
+      URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, Yb + static_cast<int64_t>(jb1) * m, m, T(0),
+                      w.W1, NB2, w.gemm_work, w.gemm_work_elems, s));
+      t_join_kernel<T><<<1, 1024, 0, s>>>(Tb, NB2, jb1, jb2, w.W1, NB2);
+      URV_LAUNCHED("t_join_kernel");
+    }
     const int64_t nc = n - j0 - jb;
     if (nc > 0) {
       T* Cb = X + j0 + (j0 + jb) * ldx;
-      URV_TRY(gemm<T>(true, false, jb, nc, mp, T(1), Yb, m, Cb, ldx, T(0), w.W1, NB, w.gemm_work,
+      URV_TRY(gemm<T>(true, false, jb, nc, mp, T(1), Yb, m, Cb, ldx, T(0), w.W1, NB2, w.gemm_work,
                       w.gemm_work_elems, s));
-      URV_TRY(gemm<T>(true, false, jb, nc, jb, T(1), Tb, NB, w.W1, NB, T(0), w.W2, NB, nullptr, 0, s));
-      URV_TRY(gemm<T>(false, false, mp, nc, jb, T(-1), Yb, m, w.W2, NB, T(1), Cb, ldx, nullptr, 0, s));
+      URV_TRY(gemm<T>(true, false, jb, nc, jb, T(1), Tb, NB2, w.W1, NB2, T(0), w.W2, NB2, nullptr, 0, s));
+      URV_TRY(gemm<T>(false, false, mp, nc, jb, T(-1), Yb, m, w.W2, NB2, T(1), Cb, ldx, nullptr, 0, s));
     }
   }
 
@@ -504,17 +587,18 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   if (Q) {
     init_q_kernel<T><<<static_cast<unsigned>(ceil_div(m * n, 256)), 256, 0, s>>>(X, ldx, m, n, Q, ldq);
     URV_LAUNCHED("init_q_kernel");
-    for (int64_t blk = nblocks - 1; blk >= 0; --blk) {
-      const int64_t j0 = blk * NB;
-      const int jb = static_cast<int>(std::min<int64_t>(NB, n - j0));
+    const int64_t nouter = ceil_div(n, NB2);
+    for (int64_t blk = nouter - 1; blk >= 0; --blk) {
+      const int64_t j0 = blk * NB2;
+      const int jb = static_cast<int>(std::min<int64_t>(NB2, n - j0));
       const int64_t mp = m - j0, nq = n - j0;
       const T* Yb = w.Y + j0 + j0 * m;
-      const T* Tb = w.Tm + j0 * NB;
+      const T* Tb = w.Tm + j0 * NB2;
       T* Qb = Q + j0 + j0 * ldq;
-      URV_TRY(gemm<T>(true, false, jb, nq, mp, T(1), Yb, m, Qb, ldq, T(0), w.W1, NB, w.gemm_work,
+      URV_TRY(gemm<T>(true, false, jb, nq, mp, T(1), Yb, m, Qb, ldq, T(0), w.W1, NB2, w.gemm_work,
                       w.gemm_work_elems, s));
-      URV_TRY(gemm<T>(false, false, jb, nq, jb, T(1), Tb, NB, w.W1, NB, T(0), w.W2, NB, nullptr, 0, s));
-      URV_TRY(gemm<T>(false, false, mp, nq, jb, T(-1), Yb, m, w.W2, NB, T(1), Qb, ldq, nullptr, 0, s));
+      URV_TRY(gemm<T>(false, false, jb, nq, jb, T(1), Tb, NB2, w.W1, NB2, T(0), w.W2, NB2, nullptr, 0, s));
+      URV_TRY(gemm<T>(false, false, mp, nq, jb, T(-1), Yb, m, w.W2, NB2, T(1), Qb, ldq, nullptr, 0, s));
     }
   }
   return URV_OK;
