@@ -79,7 +79,7 @@ def main() -> int:
     ap.add_argument("--m", type=int, default=0, help="rows (default n)")
     ap.add_argument("--q", type=int, default=2)
     ap.add_argument("--variant", default="full", choices=["full", "half", "none"])
-    ap.add_argument("--cpu-sample", type=int, default=1200, help="n of the oracle sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=1600, help="n of the oracle sample (0: skip)")
     ap.add_argument("--gemm-reps", type=int, default=5)
     args = ap.parse_args()
 

@@ -301,6 +301,11 @@ Plan make_plan(int64_t M, int64_t N, int64_t K) {
   Plan p;
   p.bm = (M <= 64) ? 64 : 128;
   p.bn = (N <= 64) ? 64 : 128;
+  // Short sums cannot be split over k: use smaller tiles to fill more CUs instead.
+  if (K < 512) {
+    if (p.bm == 128 && ceil_div(M, 128) * ceil_div(N, p.bn) < 256) p.bm = 64;
+    if (p.bn == 128 && ceil_div(M, p.bm) * ceil_div(N, 128) < 256) p.bn = 64;
+  }
   // waves per workgroup: 16 for full 128 x 128 tiles, 8 otherwise (measured best on MI355X)
   p.wgm = (p.bm == 128) ? 4 : 2;
   p.wgn = (p.bn == 128) ? 4 : 2;

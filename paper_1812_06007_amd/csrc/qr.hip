@@ -178,7 +178,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
   using V2 = typename Vec2<T>::type;
   __shared__ T stage[64][NB + 1];
   __shared__ __attribute__((aligned(16))) T bc[PANEL_WAVES][RPT];  // pivot column, per wave
-  __shared__ T red[PANEL_WAVES][NB];
+  __shared__ T red[PANEL_WAVES][NB];   // partial q of this workgroup, per wave
+  __shared__ T red2[PANEL_WAVES][NB];  // gathered partial sums, per wave
   __shared__ T pivrow[NB];
   __shared__ __attribute__((aligned(16))) T Ssh[NB][NB + 2];  // Ssh[j][c] = S(c, j), c < j
   __shared__ __attribute__((aligned(16))) T Tsh[NB][NB + 2];  // Tsh[i][k] = T(i, k)
@@ -215,6 +216,11 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
   }
   if (wg == 0)
     for (int e = threadIdx.x; e < NB * (NB + 2); e += PANEL_THREADS) (&Tsh[0][0])[e] = T(0);
+  __syncthreads();  // stage is reused below for the rows of R
+  // Column c keeps its reflector unscaled (u_c = (alpha_c - beta_c) y_c below the
+  // pivot) until the panel is done; my_rinv = 1 / (alpha_c - beta_c).
+  T my_rinv = T(0);
+  constexpr int TW = PANEL_WAVES - 1;  // wave of workgroup 0 that builds T
 
   bool ok = true;
   for (int j = 0; j < jb; ++j) {
@@ -226,9 +232,14 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
 
     // 1. lane j puts its column, zeroed on and above the pivot row, into LDS
     if (c == j) {
+      if (lo < 0) {
 #pragma unroll
-      for (int r = 0; r < RPT; r += 2)
-        *reinterpret_cast<V2*>(&bc[g][r]) = Vec2<T>::make(r > lo ? x[r] : T(0), r + 1 > lo ? x[r + 1] : T(0));
+        for (int r = 0; r < RPT; r += 2) *reinterpret_cast<V2*>(&bc[g][r]) = Vec2<T>::make(x[r], x[r + 1]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < RPT; r += 2)
+          *reinterpret_cast<V2*>(&bc[g][r]) = Vec2<T>::make(r > lo ? x[r] : T(0), r + 1 > lo ? x[r + 1] : T(0));
+      }
     }
     wave_lds_sync();
     // 2. q_c over this wave's rows below the pivot
@@ -240,18 +251,19 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
       qa[(r & 2) + 1] += xj.y * x[r + 1];
     }
     if (owner) {
+      T v = x[0];
 #pragma unroll
-      for (int r = 0; r < RPT; ++r)
-        if (r == lo) pivrow[c] = x[r];
+      for (int r = 1; r < RPT; ++r) v = (r == lo) ? x[r] : v;
+      pivrow[c] = v;
     }
     red[g][c] = (qa[0] + qa[1]) + (qa[2] + qa[3]);
     __syncthreads();
     if (g == 0) {
       tagged_store(slot(par, wg, c), tag, sum_waves(red, c));
       if (j >= row0 && j < row0 + RPW) tagged_store(slot(par, P, c), tag, pivrow[c]);
-      // Workgroup 0 finishes column j-1 of T while the others catch up.
-      if (wg == 0 && j > 0) t_column(Tsh, Ssh, tau_sh, j - 1, c);
     }
+    // One wave of workgroup 0 finishes column j-1 of T while the exchange is in flight.
+    if (wg == 0 && g == TW && j > 0) t_column(Tsh, Ssh, tau_sh, j - 1, c);
     // 3. gather, in one batch where possible: pivot row entries c and j, and this
     //    wave's share (w = g, g + PANEL_WAVES, ...) of the partial sums
     T piv[2];
@@ -288,7 +300,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
       for (int u = 0; u < 4; ++u)
         if (u < cnt) sacc += vals[u];
     }
-    red[g][c] = sacc;
+    red2[g][c] = sacc;
     // every wave failing to gather gives up together
     if (__syncthreads_or(ok ? 0 : 1)) {
       ok = false;
@@ -296,8 +308,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
     }
     const T xcj = piv[0];
     const T alpha = piv[1];
-    const T qc = sum_waves(red, c);
-    const T sigma2 = sum_waves(red, j);
+    const T qc = sum_waves(red2, c);
+    const T sigma2 = sum_waves(red2, j);
     // 4. reflector of column j
     T t = T(0), beta = alpha, rinv = T(0);
     if (sigma2 != T(0)) {
@@ -306,31 +318,43 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
       rinv = T(1) / (alpha - beta);
       t = (beta - alpha) / beta;
     }
+    if (c == j) my_rinv = rinv;
     if (g == 0) {
-      if (c < j) Ssh[j][c] = xcj + qc * rinv;
+      // S(c,j) = y_c^T y_j with y_c = my_rinv u_c
+      if (c < j) Ssh[j][c] = my_rinv * (xcj + qc * rinv);
       if (c == 0) tau_sh[j] = t;
+      // row j of R is final after this step: R(j,c) for c >= j, kept for the end
+      if (wg == 0) stage[j][c] = (c == j) ? beta : xcj - t * (xcj + qc * rinv);
     }
-    // its action, one instruction stream for all lanes (lane j's column from LDS):
-    //   c > j:  x_c -= tau (v^T x_c) v, with v = x_j / (alpha - beta) below the pivot
-    //   c == j: x_j becomes v below the pivot and beta on it
+    // its action on the columns right of j, below the pivot:
+    //   x_c -= tau (v^T x_c) v  with v = u_j / (alpha - beta),
+    // one FMA per element for every lane: the broadcast column is zero on and
+    // above the pivot row, and coef is zero for c <= j.
     const bool upd = c > j && t != T(0);
-    const T tw = upd ? t * (xcj + qc * rinv) : T(0);  // tau * (v^T x_c)
-    const T coef = tw * rinv;
-    const T scale = (c == j) ? rinv : T(1);
+    const T coef = upd ? t * (xcj + qc * rinv) * rinv : T(0);
 #pragma unroll
     for (int r = 0; r < RPT; r += 2) {
       const V2 xj = *reinterpret_cast<const V2*>(&bc[g][r]);
-      const T n0 = x[r] * scale - coef * xj.x;
-      const T n1 = x[r + 1] * scale - coef * xj.y;
-      x[r] = (r > lo) ? n0 : x[r];
-      x[r + 1] = (r + 1 > lo) ? n1 : x[r + 1];
+      x[r] = fma(-coef, xj.x, x[r]);
+      x[r + 1] = fma(-coef, xj.y, x[r + 1]);
     }
-    if (owner) {
+  }
+  __syncthreads();
+
+  if (ok) {
+    // scale each reflector below its pivot, and put the rows of R (kept in
+    // stage) back on and above the diagonal
+    const int loc = c - myrow0i;
 #pragma unroll
-      for (int r = 0; r < RPT; ++r)
-        if (r == lo) x[r] = (c == j) ? beta : x[r] - tw;
+    for (int r = 0; r < RPT; ++r)
+      if (c < jb && r > loc) x[r] *= my_rinv;
+    if (wg == 0 && myrow0i < jb) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int row = myrow0i + r;
+        if (row < jb && c >= row) x[r] = stage[row][c];
+      }
     }
-    __syncthreads();
   }
 
   if (!ok) {
@@ -344,7 +368,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
 
   // ---- last column of T, then T and tau out
   if (wg == 0) {
-    if (ok && g == 0 && jb > 0) t_column(Tsh, Ssh, tau_sh, jb - 1, c);
+    if (ok && g == TW && jb > 0) t_column(Tsh, Ssh, tau_sh, jb - 1, c);
     __syncthreads();
     for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
       const int i = e % NB, k = e / NB;
