@@ -88,8 +88,9 @@ __device__ inline bool tagged_load_all(const uint64_t* const* ptr, int count, ui
       }
       return true;
     }
-    if (++spins > kSpinLimit ||
-        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+    // the error flag is looked at every 64th poll only: each look is a round trip
+    if ((++spins & 63) == 0 &&
+        (spins > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
       __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
