@@ -7,12 +7,15 @@ final QR) of the 8000 x 8000 FP64 matrix A = Q1 diag(1/j^2) Q2^T with Haar
 Q1, Q2, inputs and workspace resident in HBM.  The printed JSON line carries
 TFLOP/s at the executed operation count (standard LAPACK counts, explicit Q
 included), the reconstruction error, the MFMA roofline of the dominant
-kernel (the FP64 GEMM A V, timed with HIP events on the stream it runs on)
-and the FP64 CPU oracle timed on a small sample of the same workload.
+kernel (the FP64 GEMM A V, timed with HIP events on the stream it runs on),
+the mixed-precision forms (BF16 / FP16 power steps) against plain FP64 on the
+same input and on the 16000 x 8000 noisy exp(-j/800) matrix, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +27,36 @@ if ROOT not in sys.path:
 
 METRIC = "PowerURV TFLOP/s & time (n=8000,q=2) mixed vs FP64; ||A−URV||/||A||"
 FP64_MFMA_PEAK_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_nn_av_8000_traffic.txt")
+GEMM_SOURCES = [os.path.join(ROOT, "paper_1812_06007_amd", "csrc", f) for f in ("gemm.hip", "common.hpp")]
+
+
+def gemm_source_hash() -> str:
+    """sha256 over the sources the GEMM kernel is built from."""
+    h = hashlib.sha256()
+    for path in GEMM_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def gemm_traffic(m: int, n: int):
+    """HBM bytes per launch of the A V GEMM from the committed rocprofv3 PMC
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when that
+    summary is for another shape or for an older gemm.hip."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("gemm_source_sha256") != gemm_source_hash() or kv.get("shape") != "%dx%dx%d" % (m, n, n):
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
 
 
 def executed_flops(m: int, n: int, q: int, variant: str, orth_g: bool = False) -> float:
@@ -63,11 +96,64 @@ def cpu_baseline(q: int, variant: str, sample_n: int) -> dict:
     oracle.urv(A, q, seed=1812, variant=variant)
     dt = time.perf_counter() - t0
     fl = executed_flops(sample_n, sample_n, q, variant)
-    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)) or 1)
     return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
             "sample": "oracle PowerURV %s q=%d on %dx%d, sigma_j=1/j^2: %.2f s for %.3e flop"
                       % (variant.upper(), q, sample_n, sample_n, dt, fl),
             "seconds": dt}
+
+
+def time_factor(A, q: int, variant: str, precision: str, steps: int, warmup: int, out) -> float:
+    """Mean milliseconds of urv.factor over `steps` runs (HIP events on the current stream)."""
+    import torch
+
+    from paper_1812_06007_amd import urv
+
+    m, n = A.shape
+    ws = torch.empty(urv.workspace_size(m, n, q, variant, precision), dtype=torch.uint8, device=A.device)
+    for _ in range(warmup):
+        urv.factor(A, q, seed=1812, variant=variant, precision=precision, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        urv.factor(A, q, seed=1812, variant=variant, precision=precision, workspace=ws, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def compare_precisions(A, q: int, variant: str, ms64: float, met64: dict, steps: int, out64) -> dict:
+    """The mixed-precision forms against the FP64 run (time, reconstruction,
+    orthogonality, rank-k errors and the diagonal of R) on the same A and G."""
+    import numpy as np
+    import torch
+
+    from paper_1812_06007_amd import urv
+
+    m, n = A.shape
+    na = met64["normA"]
+    ek64 = met64["ek"]
+    d64 = torch.diagonal(out64[1]).abs().cpu().numpy()
+    keep = ek64[:-1] > 1e-3 * na  # rank-k errors that rise above FP32-level noise
+    res = {"fp64": {"ms": ms64, "recon": met64["recon"], "orthU": met64["orthU"], "orthV": met64["orthV"]}}
+    for prec in ("mixed_bf16", "mixed_fp16"):
+        out = (urv.empty_colmajor(m, n, device=A.device), urv.empty_colmajor(n, n, device=A.device),
+               urv.empty_colmajor(n, n, device=A.device))
+        ms = time_factor(A, q, variant, prec, steps, 1, out)
+        met = urv.metrics(A, *out)
+        ek = met["ek"]
+        ratio = ek[:-1][keep] / ek64[:-1][keep]
+        d = torch.diagonal(out[1]).abs().cpu().numpy()
+        res[prec] = {"ms": ms, "speedup_vs_fp64": ms64 / ms, "recon": met["recon"], "orthU": met["orthU"],
+                     "orthV": met["orthV"],
+                     "ek_ratio_max": float(ratio.max()) if ratio.size else None,
+                     "ek_ratio_at_k_n8": float(ek[n // 8] / ek64[n // 8]) if ek64[n // 8] > 0 else None,
+                     "diagR_maxdiff_rel_normA": float(np.max(np.abs(d - d64)) / na)}
+        del out
+    return res
 
 
 def main() -> int:
@@ -79,9 +165,19 @@ def main() -> int:
     ap.add_argument("--m", type=int, default=0, help="rows (default n)")
     ap.add_argument("--q", type=int, default=2)
     ap.add_argument("--variant", default="full", choices=["full", "half", "none"])
-    ap.add_argument("--cpu-sample", type=int, default=1600, help="n of the oracle sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=3600, help="n of the oracle sample (0: skip)")
     ap.add_argument("--gemm-reps", type=int, default=5)
+    ap.add_argument("--mixed-steps", type=int, default=3, help="timed steps per mixed comparison (0: skip)")
+    ap.add_argument("--gemm-only", action="store_true",
+                    help="run only the A V GEMM launches (for counter collection) and exit")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only plain 1 GiB device copies (counter calibration) and exit")
+    ap.add_argument("--gemm-source-hash", action="store_true",
+                    help="print the hash the traffic summary is keyed on and exit")
     args = ap.parse_args()
+    if args.gemm_source_hash:
+        print(gemm_source_hash())
+        return 0
 
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU layout is described "
@@ -100,6 +196,27 @@ def main() -> int:
     q = args.q
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] 3 copies of 1 GiB done", file=sys.stderr, flush=True)
+        return 0
+
+    if args.gemm_only:
+        # any A of the shape will do for the counters; torch's own QR is kept out of the profiled run
+        A = urv.gaussian(m, n, seed=1812, stream_id=5)
+        X = urv.empty_colmajor(m, n, device=dev)
+        Vg = urv.gaussian(n, n, seed=1812)
+        for _ in range(args.gemm_reps):
+            urv.dgemm(A, Vg, C=X)
+        torch.cuda.synchronize()
+        print("[bench] %d launches of the %dx%dx%d FP64 GEMM done" % (args.gemm_reps, m, n, n),
+              file=sys.stderr, flush=True)
+        return 0
 
     print("[bench] generating A %dx%d (sigma_j = 1/j^2) on the GPU" % (m, n), file=sys.stderr, flush=True)
     sigma = gen.spectrum("poly2", n)
@@ -152,6 +269,25 @@ def main() -> int:
     gemm_tf = 2.0 * m * n * n / (gemm_ms * 1e-3) / 1e12
     del X
 
+    mixed = None
+    if args.mixed_steps > 0:
+        mixed = {"n8000": compare_precisions(A, q, args.variant, ms, met, args.mixed_steps, (U, R, V)),
+                 "c3": None}
+        del ws
+        print("[bench] mixed vs FP64 on the 16000x8000 noisy exp(-j/800) matrix", file=sys.stderr, flush=True)
+        m3, n3 = 16000, 8000
+        A3 = gen.noisy_spectral_matrix(m3, n3, gen.spectrum("exp800", n3), seed=1812, noise_var=1e-6,
+                                       device=dev).float().double()
+        out3 = (urv.empty_colmajor(m3, n3, device=dev), urv.empty_colmajor(n3, n3, device=dev),
+                urv.empty_colmajor(n3, n3, device=dev))
+        ms3 = time_factor(A3, q, args.variant, "fp64", max(1, args.mixed_steps - 1), 1, out3)
+        met3 = urv.metrics(A3, *out3)
+        mixed["c3"] = compare_precisions(A3, q, args.variant, ms3, met3, max(1, args.mixed_steps - 1), out3)
+        mixed["c3"]["workload"] = ("A 16000x8000 = Q1 diag(exp(-j/800)) Q2^T + N(0, 1e-6) noise, "
+                                   "rounded to FP32 values")
+        del A3, out3
+        torch.cuda.empty_cache()
+
     cpu = None
     if args.cpu_sample > 0:
         print("[bench] oracle CPU baseline on a %dx%d sample" % (args.cpu_sample, args.cpu_sample),
@@ -182,10 +318,11 @@ def main() -> int:
         "orthU": met["orthU"],
         "orthV": met["orthV"],
         "wall_s_timed": wall,
-        "roofline": {"bound": "mfma", "kernel": "dgemm_kernel<NN,128x128> (X = A V)",
+        "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double,NN,128x128,4x4 waves> (X = A V)",
                      "achieved": gemm_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": gemm_tf / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "frac": gemm_tf / FP64_MFMA_PEAK_TFLOPS, "traffic": gemm_traffic(m, n),
                      "launch_ms": gemm_ms, "flop_per_launch": 2.0 * m * n * n},
+        "mixed_vs_fp64": mixed,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
     }
     print(json.dumps(out))

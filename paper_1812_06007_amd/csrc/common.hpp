@@ -36,6 +36,16 @@ int hip_status(hipError_t e, const char* what);
 #define URV_LAUNCHED(what) URV_HIP(hipGetLastError())
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// The dispatcher deals the workgroups of a launch to the 8 XCDs of MI355X
+// round-robin (workgroup b runs on XCD b % 8), and each XCD has its own L2.
+// Returns the logical tile index of workgroup b such that every XCD works
+// through one contiguous range of the tile sequence (a bijection on
+// [0, ntiles) for any ntiles), so neighbouring tiles share an L2.
+__device__ inline int xcd_tile_order(int b, int ntiles) {
+  const int q = ntiles >> 3, r = ntiles & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ---------------------------------------------------------------- workspace

@@ -76,8 +76,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(
 
   // ---- workgroup -> tile, XCD-major then grouped rows
   const int ntiles = tiles_m * tiles_n;
-  int wg = blockIdx.x;
-  if ((ntiles & 7) == 0) wg = (wg & 7) * (ntiles >> 3) + (wg >> 3);
+  const int wg = xcd_tile_order(static_cast<int>(blockIdx.x), ntiles);
   constexpr int GROUP = 8;
   const int group = wg / (GROUP * tiles_n);
   const int first_m = group * GROUP;

@@ -63,9 +63,13 @@ __global__ __launch_bounds__(256) void gemm_lowp_kernel(int64_t M, int64_t N, in
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int ntiles = tiles_m * tiles_n;
-  int wg = blockIdx.x;
-  if ((ntiles & 7) == 0) wg = (wg & 7) * (ntiles >> 3) + (wg >> 3);
-  const int tm = wg % tiles_m, tn = wg / tiles_m;
+  // XCD-contiguous ranges of the tile sequence, walked in groups of 8 tile rows
+  const int wg = xcd_tile_order(static_cast<int>(blockIdx.x), ntiles);
+  constexpr int GROUP = 8;
+  const int first_m = (wg / (GROUP * tiles_n)) * GROUP;
+  const int gsize = min(tiles_m - first_m, GROUP);
+  const int tm = first_m + (wg % (GROUP * tiles_n)) % gsize;
+  const int tn = (wg % (GROUP * tiles_n)) / gsize;
   const int64_t m0 = static_cast<int64_t>(tm) * LBM, n0 = static_cast<int64_t>(tn) * LBN;
   const int nk = static_cast<int>(ceil_div(K, LBK));
 
