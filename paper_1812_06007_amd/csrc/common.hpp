@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "urv.h"
@@ -100,15 +101,20 @@ constexpr int kPanelNB = 64;  // block width of the Householder QR
 template <class T>
 struct QrWorkT {
   T* Y = nullptr;           // m x n explicit unit-lower reflector blocks (ld = m)
-  T* Tm = nullptr;          // kPanelNB x n: T of each block (ld = kPanelNB)
+  T* Tm = nullptr;          // 2 kPanelNB x n: T of each 128-column block (ld = 2 kPanelNB)
   T* tau = nullptr;         // n
-  T* W1 = nullptr;          // kPanelNB x n
-  T* W2 = nullptr;          // kPanelNB x n
+  T* W1 = nullptr;          // 2 kPanelNB x n, trailing updates
+  T* W2 = nullptr;          // 2 kPanelNB x n
   uint64_t* xch = nullptr;  // panel exchange slots (tagged partial sums, pivot rows)
   size_t xch_words = 0;
   unsigned* sync = nullptr; // panel error flag area
-  T* gemm_work = nullptr;
+  T* gemm_work = nullptr;   // split-K partial sums of the trailing updates
   size_t gemm_work_elems = 0;
+  // scratch of the block factorisations, which run on a second stream
+  T* W1b = nullptr;         // kPanelNB x kPanelNB
+  T* W2b = nullptr;         // kPanelNB x kPanelNB
+  T* gemm_work_b = nullptr;
+  size_t gemm_work_b_elems = 0;
 };
 using QrWork = QrWorkT<double>;
 
@@ -119,6 +125,18 @@ void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w);
 // Device flag set by a panel whose bounded device-wide wait expired.
 template <class T>
 unsigned* qr_error_flag(const QrWorkT<T>& w, int64_t n);
+
+// A second stream of the current device, created on first use and kept for the
+// life of the process (default priority, non-blocking), with two events.  Work
+// is enqueued on it only while *mu is held, so calls from several host threads
+// keep their event records and waits paired.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_next = nullptr;
+  hipEvent_t ev_fact = nullptr;
+  std::mutex* mu = nullptr;
+};
+int side_stream(SideStream* out);
 
 // X (m x n, ldx) overwritten; Q (m x n) / R (n x n) optional.  T = double or float.
 template <class T>

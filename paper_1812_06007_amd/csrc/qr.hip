@@ -496,7 +496,7 @@ int64_t panel_wgs(int64_t mp) { return ceil_div(mp, RPW); }
 constexpr int NB2 = 2 * NB;
 
 struct QrSizes {
-  size_t y, t, tau, w, xch, sync, gemm_work;
+  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b;
 };
 
 QrSizes qr_sizes(int64_t m, int64_t n) {
@@ -508,15 +508,19 @@ QrSizes qr_sizes(int64_t m, int64_t n) {
   z.w = static_cast<size_t>(NB2) * n;
   z.xch = 2 * (static_cast<size_t>(panel_wgs(m)) + 1) * NB * 2;
   z.sync = nblocks + 2;
-  size_t gw = 0;
+  size_t gw = 0, gwb = 0;
   for (int64_t j0 = 0; j0 < n; j0 += NB2) {
     const int64_t jb = std::min<int64_t>(NB2, n - j0), mp = m - j0;
     const int64_t jb1 = std::min<int64_t>(NB, jb), jb2 = jb - jb1;
-    gw = std::max(gw, gemm_work_elems(jb1, jb2, mp));
-    gw = std::max(gw, gemm_work_elems(jb, n - j0 - jb, mp));
+    const int64_t nc = n - j0 - jb, nn = std::min<int64_t>(NB2, nc);
+    gwb = std::max(gwb, gemm_work_elems(jb1, jb2, mp));
+    gw = std::max(gw, gemm_work_elems(jb, nn, mp));
+    gw = std::max(gw, gemm_work_elems(jb, nc - nn, mp));
     gw = std::max(gw, gemm_work_elems(jb, n - j0, mp));
   }
   z.gemm_work = gw;
+  z.wb = static_cast<size_t>(NB) * NB;
+  z.gemm_work_b = gwb;
   return z;
 }
 
@@ -543,6 +547,10 @@ void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w) {
   w.sync = a.take<unsigned>(z.sync);
   w.gemm_work = a.take<T>(z.gemm_work);
   w.gemm_work_elems = z.gemm_work;
+  w.W1b = a.take<T>(z.wb);
+  w.W2b = a.take<T>(z.wb);
+  w.gemm_work_b = a.take<T>(z.gemm_work_b);
+  w.gemm_work_b_elems = z.gemm_work_b;
 }
 
 template <class T>
@@ -561,17 +569,26 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       w.xch, static_cast<int64_t>(w.xch_words));
   URV_LAUNCHED("fill_u64_kernel");
 
+  // Look-ahead: 128-column blocks are factored on a second stream while the
+  // caller's stream applies the previous block to the rest of the matrix.
+  // The panels occupy a few dozen CUs; the trailing update fills the others.
+  SideStream side;
+  URV_TRY(side_stream(&side));
+  std::lock_guard<std::mutex> side_lock(*side.mu);
+  const hipStream_t s2 = side.stream;
+
   uint32_t panels = 0;  // panel launches so far: exchange tags stay distinct
   auto panel = [&](int64_t r0, int jbp, T* Tp) -> int {
     const int64_t mp = m - r0;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
-    panel_kernel<T><<<P, PANEL_THREADS, 0, s>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
-                                                w.tau + r0, Tp, NB2, w.xch, panels * NB, err);
+    panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
+                                                 w.tau + r0, Tp, NB2, w.xch, panels * NB, err);
     ++panels;
     URV_LAUNCHED("panel_kernel");
     return URV_OK;
   };
-  for (int64_t j0 = 0; j0 < n; j0 += NB2) {
+  // Householder vectors, tau and T of the block at column j0, on the side stream.
+  auto factor_block = [&](int64_t j0) -> int {
     const int jb = static_cast<int>(std::min<int64_t>(NB2, n - j0));
     const int jb1 = std::min(jb, NB), jb2 = jb - jb1;
     const int64_t mp = m - j0;
@@ -581,28 +598,52 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     if (jb2 > 0) {
       // first panel's reflectors applied to the second panel's columns
       T* C2 = X + j0 + (j0 + jb1) * ldx;
-      URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, C2, ldx, T(0), w.W1, NB2, w.gemm_work,
-                      w.gemm_work_elems, s));
-      URV_TRY(gemm<T>(true, false, jb1, jb2, jb1, T(1), Tb, NB2, w.W1, NB2, T(0), w.W2, NB2, nullptr, 0, s));
-      URV_TRY(gemm<T>(false, false, mp, jb2, jb1, T(-1), Yb, m, w.W2, NB2, T(1), C2, ldx, nullptr, 0, s));
+      URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, C2, ldx, T(0), w.W1b, NB, w.gemm_work_b,
+                      w.gemm_work_b_elems, s2));
+      URV_TRY(gemm<T>(true, false, jb1, jb2, jb1, T(1), Tb, NB2, w.W1b, NB, T(0), w.W2b, NB, nullptr, 0, s2));
+      URV_TRY(gemm<T>(false, false, mp, jb2, jb1, T(-1), Yb, m, w.W2b, NB, T(1), C2, ldx, nullptr, 0, s2));
       // Y2 is zero above its panel; then the second panel and the joined T
-      zero_block_kernel<T><<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(jb1) * jb2, 256)), 256, 0, s>>>(
+      zero_block_kernel<T><<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(jb1) * jb2, 256)), 256, 0, s2>>>(
           w.Y + j0 + (j0 + jb1) * m, jb1, jb2, m);
       URV_LAUNCHED("zero_block_kernel");
       URV_TRY(panel(j0 + jb1, jb2, Tb + jb1 + static_cast<int64_t>(jb1) * NB2));
       URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, Yb + static_cast<int64_t>(jb1) * m, m, T(0),
-                      w.W1, NB2, w.gemm_work, w.gemm_work_elems, s));
-      t_join_kernel<T><<<1, 1024, 0, s>>>(Tb, NB2, jb1, jb2, w.W1, NB2);
+                      w.W1b, NB, w.gemm_work_b, w.gemm_work_b_elems, s2));
+      t_join_kernel<T><<<1, 1024, 0, s2>>>(Tb, NB2, jb1, jb2, w.W1b, NB);
       URV_LAUNCHED("t_join_kernel");
     }
-    const int64_t nc = n - j0 - jb;
-    if (nc > 0) {
-      T* Cb = X + j0 + (j0 + jb) * ldx;
-      URV_TRY(gemm<T>(true, false, jb, nc, mp, T(1), Yb, m, Cb, ldx, T(0), w.W1, NB2, w.gemm_work,
-                      w.gemm_work_elems, s));
-      URV_TRY(gemm<T>(true, false, jb, nc, jb, T(1), Tb, NB2, w.W1, NB2, T(0), w.W2, NB2, nullptr, 0, s));
-      URV_TRY(gemm<T>(false, false, mp, nc, jb, T(-1), Yb, m, w.W2, NB2, T(1), Cb, ldx, nullptr, 0, s));
-    }
+    return URV_OK;
+  };
+  // C <- (I - Y T^T Y^T) C for the block at j0 and columns [c0, c0 + nc), on the caller's stream.
+  auto apply_block = [&](int64_t j0, int64_t c0, int64_t nc) -> int {
+    if (nc <= 0) return URV_OK;
+    const int jb = static_cast<int>(std::min<int64_t>(NB2, n - j0));
+    const int64_t mp = m - j0;
+    const T* Yb = w.Y + j0 + j0 * m;
+    const T* Tb = w.Tm + j0 * NB2;
+    T* Cb = X + j0 + c0 * ldx;
+    URV_TRY(gemm<T>(true, false, jb, nc, mp, T(1), Yb, m, Cb, ldx, T(0), w.W1, NB2, w.gemm_work,
+                    w.gemm_work_elems, s));
+    URV_TRY(gemm<T>(true, false, jb, nc, jb, T(1), Tb, NB2, w.W1, NB2, T(0), w.W2, NB2, nullptr, 0, s));
+    URV_TRY(gemm<T>(false, false, mp, nc, jb, T(-1), Yb, m, w.W2, NB2, T(1), Cb, ldx, nullptr, 0, s));
+    return URV_OK;
+  };
+
+  URV_HIP(hipEventRecord(side.ev_next, s));      // the cleared flags and slots
+  URV_HIP(hipStreamWaitEvent(s2, side.ev_next, 0));
+  URV_TRY(factor_block(0));
+  URV_HIP(hipEventRecord(side.ev_fact, s2));
+  for (int64_t j0 = 0; j0 < n; j0 += NB2) {
+    URV_HIP(hipStreamWaitEvent(s, side.ev_fact, 0));  // block j0 is factored
+    const int64_t j1 = j0 + NB2;
+    if (j1 >= n) break;
+    const int64_t nn = std::min<int64_t>(NB2, n - j1);
+    URV_TRY(apply_block(j0, j1, nn));                 // the next block's columns first
+    URV_HIP(hipEventRecord(side.ev_next, s));
+    URV_HIP(hipStreamWaitEvent(s2, side.ev_next, 0));
+    URV_TRY(factor_block(j1));
+    URV_HIP(hipEventRecord(side.ev_fact, s2));
+    URV_TRY(apply_block(j0, j1 + nn, n - j1 - nn));   // the rest, beside the next factorisation
   }
 
   if (R) {

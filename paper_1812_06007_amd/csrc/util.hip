@@ -100,6 +100,34 @@ int sumsq(const double* X, int64_t ld, int64_t rows, int64_t cols, double diag, 
 
 }  // namespace
 
+int side_stream(SideStream* out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex init_mu;
+  static SideStream table[kMaxDevices];
+  static std::mutex use_mu[kMaxDevices];
+  int dev = 0;
+  URV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_last_error("side_stream: device index out of range");
+    return URV_EDEVICE;
+  }
+  std::lock_guard<std::mutex> g(init_mu);
+  SideStream& e = table[dev];
+  if (e.stream == nullptr) {
+    hipStream_t st = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    URV_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    URV_HIP(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+    URV_HIP(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+    e.ev_next = a;
+    e.ev_fact = b;
+    e.mu = &use_mu[dev];
+    e.stream = st;
+  }
+  *out = e;
+  return URV_OK;
+}
+
 int copy_matrix(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
                 int64_t cols, hipStream_t s) {
   if (rows == 0 || cols == 0) return URV_OK;
