@@ -38,6 +38,7 @@ struct MixedWork {
 struct FactorWork {
   double* X = nullptr;   // m x n (ld m): A V, factored in place
   double* Xs = nullptr;  // n x n (ld n): A^T W, factored in place
+  double* At = nullptr;  // n x m (ld n): A^T, turned into A^T W by the reflectors of W
   double* gemm_work = nullptr;
   size_t gemm_work_elems = 0;
   QrWork qr;
@@ -52,9 +53,10 @@ size_t driver_gemm_work(int64_t m, int64_t n) {
 void carve_factor(Arena& a, int64_t m, int64_t n, bool mixed, FactorWork& w) {
   w.X = a.take<double>(static_cast<size_t>(m) * n);
   w.Xs = a.take<double>(static_cast<size_t>(n) * n);
+  w.At = a.take<double>(static_cast<size_t>(n) * m);
   w.gemm_work_elems = driver_gemm_work(m, n);
   w.gemm_work = a.take<double>(w.gemm_work_elems);
-  qr_work_carve(a, m, n, w.qr);
+  qr_work_carve(a, m, n, w.qr, m);
   w.mixed = mixed;
   if (!mixed) return;
   MixedWork& x = w.mx;
@@ -124,6 +126,33 @@ int validate_factor(const double* A, int64_t m, int64_t n, int32_t q, const doub
   return URV_OK;
 }
 
+// V = Qpos(Y) for Y n x n (ld n, overwritten), delivered as X = A V in w.X
+// and, when wanted, explicitly in V: the reflectors of Y are applied to a copy
+// of A (and to I) block by block while Y is being factored.
+int qpos_times_a(const double* A, int64_t lda, int64_t m, int64_t n, double* Y, double* V, int64_t ldv,
+                 bool want_v, const FactorWork& w, hipStream_t s) {
+  QrTarget<double> t[2];
+  int nt = 0;
+  URV_TRY(copy_matrix(A, lda, w.X, m, m, n, s));
+  t[nt++] = QrTarget<double>{w.X, m, m};
+  if (want_v) {
+    URV_TRY(set_identity<double>(V, n, n, ldv, s));
+    t[nt++] = QrTarget<double>{V, n, ldv};
+  }
+  return qr_pos<double>(Y, n, n, n, nullptr, 0, nullptr, 0, w.qr, s, t, nt);
+}
+
+// The final step of eq. (powerqr): A V = U R with X = A V in w.X.
+int final_qr(int64_t m, int64_t n, double* U, int64_t ldu, double* R, int64_t ldr, const FactorWork& w,
+             hipStream_t s) {
+  if (m == n) {  // U formed from I alongside the factorisation
+    URV_TRY(set_identity<double>(U, m, n, ldu, s));
+    const QrTarget<double> t{U, m, ldu};
+    return qr_pos<double>(w.X, m, n, m, nullptr, 0, R, ldr, w.qr, s, &t, 1);
+  }
+  return qr_pos<double>(w.X, m, n, m, U, ldu, R, ldr, w.qr, s);
+}
+
 int run_factor(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, double* U,
                double* R, double* V, const urv_opts& o, const FactorWork& w, hipStream_t s) {
   const int64_t lda = o.lda ? o.lda : m, ldu = o.ldu ? o.ldu : m;
@@ -135,35 +164,45 @@ int run_factor(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, 
     URV_TRY(copy_matrix(o.G, ldg, V, ldv, n, n, s));
   else
     URV_TRY(launch_gaussian(V, n, n, ldv, seed, 2u, false, s));
-  if (q == 0 || o.orth_g) {
-    URV_TRY(copy_matrix(V, ldv, w.Xs, n, n, n, s));
-    URV_TRY(qr_pos<double>(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));
-  }
-  for (int32_t t = 0; t < q; ++t) {
-    URV_TRY(dgemm(false, false, m, n, n, 1.0, A, lda, V, ldv, 0.0, w.X, m, w.gemm_work,
-                  w.gemm_work_elems, s));                                   // X = A V
-    if (full) {
-      URV_TRY(qr_pos<double>(w.X, m, n, m, U, ldu, nullptr, 0, w.qr, s));          // W = Qpos(X), in U
-      URV_TRY(dgemm(true, false, n, n, m, 1.0, A, lda, U, ldu, 0.0, w.Xs, n, w.gemm_work,
-                    w.gemm_work_elems, s));                                 // A^T W
-      URV_TRY(qr_pos<double>(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));         // V = Qpos(A^T W)
-    } else if (none) {
+  if (none) {
+    // (A^T A)^q G (or (A^T A)^q Qpos(G)), then one Qpos
+    if (o.orth_g && q > 0) {
+      URV_TRY(copy_matrix(V, ldv, w.Xs, n, n, n, s));
+      URV_TRY(qr_pos<double>(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));
+    }
+    for (int32_t t = 0; t < q; ++t) {
+      URV_TRY(dgemm(false, false, m, n, n, 1.0, A, lda, V, ldv, 0.0, w.X, m, w.gemm_work,
+                    w.gemm_work_elems, s));                                 // X = A V
       URV_TRY(dgemm(true, false, n, n, m, 1.0, A, lda, w.X, m, 0.0, V, ldv, w.gemm_work,
                     w.gemm_work_elems, s));                                 // V = A^T A V
+    }
+    URV_TRY(copy_matrix(V, ldv, w.Xs, n, n, n, s));
+    URV_TRY(qpos_times_a(A, lda, m, n, w.Xs, V, ldv, true, w, s));          // V = Qpos, X = A V
+    return final_qr(m, n, U, ldu, R, ldr, w, s);
+  }
+  if (q == 0 || o.orth_g) {
+    URV_TRY(copy_matrix(V, ldv, w.Xs, n, n, n, s));
+    URV_TRY(qpos_times_a(A, lda, m, n, w.Xs, V, ldv, q == 0, w, s));       // V = Qpos(G), X = A V
+  } else {
+    URV_TRY(dgemm(false, false, m, n, n, 1.0, A, lda, V, ldv, 0.0, w.X, m, w.gemm_work,
+                  w.gemm_work_elems, s));                                   // X = A G
+  }
+  for (int32_t t = 0; t < q; ++t) {
+    const bool last = t == q - 1;
+    double* Y = w.Xs;
+    if (full) {
+      // W = Qpos(X) is needed only as A^T W: its reflectors are applied to A^T
+      URV_TRY(transpose_matrix(A, lda, m, n, w.At, n, s));
+      const QrTarget<double> tt{w.At, n, n};
+      URV_TRY(qr_pos<double>(w.X, m, n, m, nullptr, 0, nullptr, 0, w.qr, s, &tt, 1));
+      Y = w.At;                                                             // A^T W, n x n
     } else {
       URV_TRY(dgemm(true, false, n, n, m, 1.0, A, lda, w.X, m, 0.0, w.Xs, n, w.gemm_work,
                     w.gemm_work_elems, s));                                 // A^T X
-      URV_TRY(qr_pos<double>(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));         // V = Qpos(A^T X)
     }
+    URV_TRY(qpos_times_a(A, lda, m, n, Y, V, ldv, last, w, s));             // V = Qpos(Y), X = A V
   }
-  if (none && q > 0) {
-    URV_TRY(copy_matrix(V, ldv, w.Xs, n, n, n, s));
-    URV_TRY(qr_pos<double>(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));
-  }
-  URV_TRY(dgemm(false, false, m, n, n, 1.0, A, lda, V, ldv, 0.0, w.X, m, w.gemm_work,
-                w.gemm_work_elems, s));                                     // X = A V
-  URV_TRY(qr_pos<double>(w.X, m, n, m, U, ldu, R, ldr, w.qr, s));                  // A V = U R
-  return URV_OK;
+  return final_qr(m, n, U, ldu, R, ldr, w, s);
 }
 
 // The power iteration in 16-bit products / FP32 QRs, then the FP64 tail.
@@ -203,13 +242,10 @@ int run_factor_mixed(const double* A, int64_t m, int64_t n, int32_t q, uint64_t 
     URV_TRY(copy_matrix_f32(x.V32, n, x.Y32, n, n, n, s));
     URV_TRY(qr_pos<float>(x.Y32, n, n, n, x.V32, n, nullptr, 0, x.qr, s));
   }
-  // FP64 re-orthonormalisation of V, then the FP64 tail A V = U R.
+  // FP64 re-orthonormalisation of V (delivering X = A V alongside), then the FP64 tail A V = U R.
   URV_TRY((convert<float, double>(x.V32, n, n, n, w.Xs, n, s)));
-  URV_TRY(qr_pos<double>(w.Xs, n, n, n, V, ldv, nullptr, 0, w.qr, s));
-  URV_TRY(dgemm(false, false, m, n, n, 1.0, A, lda, V, ldv, 0.0, w.X, m, w.gemm_work,
-                w.gemm_work_elems, s));
-  URV_TRY(qr_pos<double>(w.X, m, n, m, U, ldu, R, ldr, w.qr, s));
-  return URV_OK;
+  URV_TRY(qpos_times_a(A, lda, m, n, w.Xs, V, ldv, true, w, s));
+  return final_qr(m, n, U, ldu, R, ldr, w, s);
 }
 
 // Runs the factorisation; when check_flag, waits for the stream and reports a

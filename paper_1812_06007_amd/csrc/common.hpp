@@ -115,13 +115,20 @@ struct QrWorkT {
   T* W2b = nullptr;         // kPanelNB x kPanelNB
   T* gemm_work_b = nullptr;
   size_t gemm_work_b_elems = 0;
+  // scratch of the reflectors applied to targets (third stream)
+  int64_t target_rows = 0;  // largest target row count the workspace covers
+  T* W1f = nullptr;         // target_rows x 2 kPanelNB
+  T* W2f = nullptr;         // target_rows x 2 kPanelNB
+  T* gemm_work_f = nullptr;
+  size_t gemm_work_f_elems = 0;
 };
 using QrWork = QrWorkT<double>;
 
+// Workspace of qr_pos for an m x n matrix and targets of up to target_rows rows.
 template <class T>
-size_t qr_work_bytes(int64_t m, int64_t n);
+size_t qr_work_bytes(int64_t m, int64_t n, int64_t target_rows = 0);
 template <class T>
-void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w);
+void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w, int64_t target_rows = 0);
 // Device flag set by a panel whose bounded device-wide wait expired.
 template <class T>
 unsigned* qr_error_flag(const QrWorkT<T>& w, int64_t n);
@@ -131,17 +138,40 @@ unsigned* qr_error_flag(const QrWorkT<T>& w, int64_t n);
 // is enqueued on it only while *mu is held, so calls from several host threads
 // keep their event records and waits paired.
 struct SideStream {
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // block factorisations
+  hipStream_t stream3 = nullptr;  // reflectors applied to the targets of a QR
   hipEvent_t ev_next = nullptr;
   hipEvent_t ev_fact = nullptr;
+  hipEvent_t ev_tgt = nullptr;
   std::mutex* mu = nullptr;
 };
 int side_stream(SideStream* out);
 
+// A matrix Z (rows x m, ld ldz) to be multiplied on the right by the Q factor
+// of a QR of an m x n matrix: on return Z(:, 0:n) = Z Q, where
+// Q = H_1 ... H_n [D; 0] is the Q of qr_pos; columns n..m-1 are scratch.
+template <class T>
+struct QrTarget {
+  T* Z = nullptr;
+  int64_t rows = 0;
+  int64_t ldz = 0;
+};
+
+// dst (cols x rows, ldd) = src^T for src rows x cols.
+int transpose_matrix(const double* src, int64_t lds, int64_t rows, int64_t cols, double* dst, int64_t ldd,
+                     hipStream_t s);
+template <class T>
+int set_identity(T* Z, int64_t rows, int64_t cols, int64_t ld, hipStream_t s);
+// Z(:, j) *= sign(X(j, j)) for j < n (sign(0) = +1).
+template <class T>
+int scale_cols_sign(T* Z, int64_t rows, int64_t n, int64_t ldz, const T* X, int64_t ldx, hipStream_t s);
+
 // X (m x n, ldx) overwritten; Q (m x n) / R (n x n) optional.  T = double or float.
+// Targets (optional) get Z <- Z Q as above, applied block by block while the
+// factorisation proceeds.
 template <class T>
 int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int64_t ldr,
-           const QrWorkT<T>& w, hipStream_t s);
+           const QrWorkT<T>& w, hipStream_t s, const QrTarget<T>* targets = nullptr, int ntargets = 0);
 
 // ---------------------------------------------------------------- mixed precision
 // Leading dimension of a 16-bit operand with `rows` rows (multiple of 32).

@@ -496,10 +496,10 @@ int64_t panel_wgs(int64_t mp) { return ceil_div(mp, RPW); }
 constexpr int NB2 = 2 * NB;
 
 struct QrSizes {
-  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b;
+  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f;
 };
 
-QrSizes qr_sizes(int64_t m, int64_t n) {
+QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   QrSizes z;
   const int64_t nblocks = ceil_div(n, NB);
   z.y = static_cast<size_t>(m) * n;
@@ -508,7 +508,7 @@ QrSizes qr_sizes(int64_t m, int64_t n) {
   z.w = static_cast<size_t>(NB2) * n;
   z.xch = 2 * (static_cast<size_t>(panel_wgs(m)) + 1) * NB * 2;
   z.sync = nblocks + 2;
-  size_t gw = 0, gwb = 0;
+  size_t gw = 0, gwb = 0, gwf = 0;
   for (int64_t j0 = 0; j0 < n; j0 += NB2) {
     const int64_t jb = std::min<int64_t>(NB2, n - j0), mp = m - j0;
     const int64_t jb1 = std::min<int64_t>(NB, jb), jb2 = jb - jb1;
@@ -517,26 +517,29 @@ QrSizes qr_sizes(int64_t m, int64_t n) {
     gw = std::max(gw, gemm_work_elems(jb, nn, mp));
     gw = std::max(gw, gemm_work_elems(jb, nc - nn, mp));
     gw = std::max(gw, gemm_work_elems(jb, n - j0, mp));
+    if (target_rows > 0) gwf = std::max(gwf, gemm_work_elems(target_rows, jb, mp));
   }
   z.gemm_work = gw;
   z.wb = static_cast<size_t>(NB) * NB;
   z.gemm_work_b = gwb;
+  z.wf = static_cast<size_t>(std::max<int64_t>(target_rows, 0)) * NB2;
+  z.gemm_work_f = gwf;
   return z;
 }
 
 }  // namespace
 
 template <class T>
-size_t qr_work_bytes(int64_t m, int64_t n) {
+size_t qr_work_bytes(int64_t m, int64_t n, int64_t target_rows) {
   Arena a;
   QrWorkT<T> w;
-  qr_work_carve(a, m, n, w);
+  qr_work_carve(a, m, n, w, target_rows);
   return a.used;
 }
 
 template <class T>
-void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w) {
-  const QrSizes z = qr_sizes(m, n);
+void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w, int64_t target_rows) {
+  const QrSizes z = qr_sizes(m, n, target_rows);
   w.Y = a.take<T>(z.y);
   w.Tm = a.take<T>(z.t);
   w.tau = a.take<T>(z.tau);
@@ -551,12 +554,23 @@ void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w) {
   w.W2b = a.take<T>(z.wb);
   w.gemm_work_b = a.take<T>(z.gemm_work_b);
   w.gemm_work_b_elems = z.gemm_work_b;
+  w.target_rows = std::max<int64_t>(target_rows, 0);
+  w.W1f = a.take<T>(z.wf);
+  w.W2f = a.take<T>(z.wf);
+  w.gemm_work_f = a.take<T>(z.gemm_work_f);
+  w.gemm_work_f_elems = z.gemm_work_f;
 }
 
 template <class T>
 int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int64_t ldr,
-           const QrWorkT<T>& w, hipStream_t s) {
+           const QrWorkT<T>& w, hipStream_t s, const QrTarget<T>* targets, int ntargets) {
   if (n == 0) return URV_OK;
+  for (int i = 0; i < ntargets; ++i) {
+    if (targets[i].rows > w.target_rows || targets[i].ldz < targets[i].rows) {
+      set_last_error("qr_pos: target larger than the workspace covers");
+      return URV_EINVAL;
+    }
+  }
   const int64_t nblocks = ceil_div(n, NB);
   if (panel_wgs(m) > kMaxPanelWgs) {
     set_last_error("qr_pos: too many rows for the panel kernel");
@@ -629,12 +643,37 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     return URV_OK;
   };
 
+  // Z <- Z (I - Y T Y^T) for the block at j0 and every target, on the third stream.
+  const hipStream_t s3 = side.stream3;
+  auto apply_targets = [&](int64_t j0) -> int {
+    const int jb = static_cast<int>(std::min<int64_t>(NB2, n - j0));
+    const int64_t mp = m - j0;
+    const T* Yb = w.Y + j0 + j0 * m;
+    const T* Tb = w.Tm + j0 * NB2;
+    for (int i = 0; i < ntargets; ++i) {
+      const QrTarget<T>& z = targets[i];
+      T* Zb = z.Z + j0 * z.ldz;
+      URV_TRY(gemm<T>(false, false, z.rows, jb, mp, T(1), Zb, z.ldz, Yb, m, T(0), w.W1f, z.rows,
+                      w.gemm_work_f, w.gemm_work_f_elems, s3));               // Z Y
+      URV_TRY(gemm<T>(false, false, z.rows, jb, jb, T(1), w.W1f, z.rows, Tb, NB2, T(0), w.W2f, z.rows,
+                      nullptr, 0, s3));                                       // (Z Y) T
+      URV_TRY(gemm<T>(false, true, z.rows, mp, jb, T(-1), w.W2f, z.rows, Yb, m, T(1), Zb, z.ldz, nullptr,
+                      0, s3));                                                // Z -= (Z Y T) Y^T
+    }
+    return URV_OK;
+  };
+
   URV_HIP(hipEventRecord(side.ev_next, s));      // the cleared flags and slots
   URV_HIP(hipStreamWaitEvent(s2, side.ev_next, 0));
+  if (ntargets > 0) URV_HIP(hipStreamWaitEvent(s3, side.ev_next, 0));  // targets written before the call
   URV_TRY(factor_block(0));
   URV_HIP(hipEventRecord(side.ev_fact, s2));
   for (int64_t j0 = 0; j0 < n; j0 += NB2) {
     URV_HIP(hipStreamWaitEvent(s, side.ev_fact, 0));  // block j0 is factored
+    if (ntargets > 0) {
+      URV_HIP(hipStreamWaitEvent(s3, side.ev_fact, 0));
+      URV_TRY(apply_targets(j0));
+    }
     const int64_t j1 = j0 + NB2;
     if (j1 >= n) break;
     const int64_t nn = std::min<int64_t>(NB2, n - j1);
@@ -644,6 +683,13 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     URV_TRY(factor_block(j1));
     URV_HIP(hipEventRecord(side.ev_fact, s2));
     URV_TRY(apply_block(j0, j1 + nn, n - j1 - nn));   // the rest, beside the next factorisation
+  }
+  if (ntargets > 0) {
+    // Q = H_1 ... H_n [D; 0]: the sign fix D on the first n columns, then join
+    for (int i = 0; i < ntargets; ++i)
+      URV_TRY(scale_cols_sign<T>(targets[i].Z, targets[i].rows, n, targets[i].ldz, X, ldx, s3));
+    URV_HIP(hipEventRecord(side.ev_tgt, s3));
+    URV_HIP(hipStreamWaitEvent(s, side.ev_tgt, 0));
   }
 
   if (R) {
@@ -676,10 +722,10 @@ unsigned* qr_error_flag(const QrWorkT<T>& w, int64_t n) {
 }
 
 #define URV_QR_INSTANTIATE(T)                                                                 \
-  template size_t qr_work_bytes<T>(int64_t, int64_t);                                         \
-  template void qr_work_carve<T>(Arena&, int64_t, int64_t, QrWorkT<T>&);                     \
+  template size_t qr_work_bytes<T>(int64_t, int64_t, int64_t);                                \
+  template void qr_work_carve<T>(Arena&, int64_t, int64_t, QrWorkT<T>&, int64_t);            \
   template int qr_pos<T>(T*, int64_t, int64_t, int64_t, T*, int64_t, T*, int64_t,             \
-                         const QrWorkT<T>&, hipStream_t);                                     \
+                         const QrWorkT<T>&, hipStream_t, const QrTarget<T>*, int);            \
   template unsigned* qr_error_flag<T>(const QrWorkT<T>&, int64_t);
 URV_QR_INSTANTIATE(double)
 URV_QR_INSTANTIATE(float)

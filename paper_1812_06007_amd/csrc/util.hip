@@ -19,6 +19,42 @@ __global__ void copy_kernel(const T* __restrict__ src, int64_t lds, T* __restric
   dst[i + j * ldd] = src[i + j * lds];
 }
 
+// dst (cols x rows) = src^T, through 32 x 32 LDS tiles (both sides coalesced).
+__global__ __launch_bounds__(256) void transpose_kernel(const double* __restrict__ src, int64_t lds,
+                                                        int64_t rows, int64_t cols,
+                                                        double* __restrict__ dst, int64_t ldd) {
+  __shared__ double tile[32][33];
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 32, j0 = static_cast<int64_t>(blockIdx.y) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + tx, j = j0 + r;
+    if (i < rows && j < cols) tile[r][tx] = src[i + j * lds];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = j0 + tx, i = i0 + r;  // dst(j, i) = src(i, j)
+    if (i < rows && j < cols) dst[j + i * ldd] = tile[tx][r];
+  }
+}
+
+template <class T>
+__global__ void identity_kernel(T* __restrict__ Z, int64_t rows, int64_t cols, int64_t ld) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx % rows, j = idx / rows;
+  Z[i + j * ld] = (i == j) ? T(1) : T(0);
+}
+
+// Z(:, j) *= sign(X(j, j)) for j < n, sign(0) = +1.
+template <class T>
+__global__ void scale_cols_sign_kernel(T* __restrict__ Z, int64_t rows, int64_t n, int64_t ldz,
+                                       const T* __restrict__ X, int64_t ldx) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= rows * n) return;
+  const int64_t i = idx % rows, j = idx / rows;
+  if (X[j + j * ldx] < T(0)) Z[i + j * ldz] = -Z[i + j * ldz];
+}
+
 constexpr int kRedBlocks = 1024;
 constexpr int kRedThreads = 256;
 
@@ -114,19 +150,53 @@ int side_stream(SideStream* out) {
   std::lock_guard<std::mutex> g(init_mu);
   SideStream& e = table[dev];
   if (e.stream == nullptr) {
-    hipStream_t st = nullptr;
-    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t st = nullptr, st3 = nullptr;
+    hipEvent_t a = nullptr, b = nullptr, c = nullptr;
     URV_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    URV_HIP(hipStreamCreateWithFlags(&st3, hipStreamNonBlocking));
     URV_HIP(hipEventCreateWithFlags(&a, hipEventDisableTiming));
     URV_HIP(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+    URV_HIP(hipEventCreateWithFlags(&c, hipEventDisableTiming));
     e.ev_next = a;
     e.ev_fact = b;
+    e.ev_tgt = c;
+    e.stream3 = st3;
     e.mu = &use_mu[dev];
     e.stream = st;
   }
   *out = e;
   return URV_OK;
 }
+
+int transpose_matrix(const double* src, int64_t lds, int64_t rows, int64_t cols, double* dst, int64_t ldd,
+                     hipStream_t s) {
+  if (rows == 0 || cols == 0) return URV_OK;
+  const dim3 grid(static_cast<unsigned>(ceil_div(rows, 32)), static_cast<unsigned>(ceil_div(cols, 32)));
+  transpose_kernel<<<grid, 256, 0, s>>>(src, lds, rows, cols, dst, ldd);
+  URV_LAUNCHED("transpose_kernel");
+  return URV_OK;
+}
+
+template <class T>
+int set_identity(T* Z, int64_t rows, int64_t cols, int64_t ld, hipStream_t s) {
+  if (rows == 0 || cols == 0) return URV_OK;
+  identity_kernel<T><<<static_cast<unsigned>(ceil_div(rows * cols, 256)), 256, 0, s>>>(Z, rows, cols, ld);
+  URV_LAUNCHED("identity_kernel");
+  return URV_OK;
+}
+template int set_identity<double>(double*, int64_t, int64_t, int64_t, hipStream_t);
+template int set_identity<float>(float*, int64_t, int64_t, int64_t, hipStream_t);
+
+template <class T>
+int scale_cols_sign(T* Z, int64_t rows, int64_t n, int64_t ldz, const T* X, int64_t ldx, hipStream_t s) {
+  if (rows == 0 || n == 0) return URV_OK;
+  scale_cols_sign_kernel<T><<<static_cast<unsigned>(ceil_div(rows * n, 256)), 256, 0, s>>>(Z, rows, n, ldz, X,
+                                                                                           ldx);
+  URV_LAUNCHED("scale_cols_sign_kernel");
+  return URV_OK;
+}
+template int scale_cols_sign<double>(double*, int64_t, int64_t, int64_t, const double*, int64_t, hipStream_t);
+template int scale_cols_sign<float>(float*, int64_t, int64_t, int64_t, const float*, int64_t, hipStream_t);
 
 int copy_matrix(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
                 int64_t cols, hipStream_t s) {
