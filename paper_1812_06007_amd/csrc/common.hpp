@@ -103,13 +103,18 @@ struct QrWorkT {
   T* Y = nullptr;           // m x n explicit unit-lower reflector blocks (ld = m)
   T* Tm = nullptr;          // 2 kPanelNB x n: T of each 128-column block (ld = 2 kPanelNB)
   T* tau = nullptr;         // n
-  T* W1 = nullptr;          // 2 kPanelNB x n, trailing updates
+  T* W1 = nullptr;          // 2 kPanelNB x n, bulk trailing updates (fourth stream)
   T* W2 = nullptr;          // 2 kPanelNB x n
   uint64_t* xch = nullptr;  // panel exchange slots (tagged partial sums, pivot rows)
   size_t xch_words = 0;
   unsigned* sync = nullptr; // panel error flag area
-  T* gemm_work = nullptr;   // split-K partial sums of the trailing updates
+  T* gemm_work = nullptr;   // split-K partial sums of the bulk trailing updates
   size_t gemm_work_elems = 0;
+  // updates of the next two column blocks (caller's stream)
+  T* W1n = nullptr;         // 2 kPanelNB x 2 kPanelNB
+  T* W2n = nullptr;         // 2 kPanelNB x 2 kPanelNB
+  T* gemm_work_n = nullptr;
+  size_t gemm_work_n_elems = 0;
   // scratch of the block factorisations, which run on a second stream
   T* W1b = nullptr;         // kPanelNB x kPanelNB
   T* W2b = nullptr;         // kPanelNB x kPanelNB
@@ -140,9 +145,12 @@ unsigned* qr_error_flag(const QrWorkT<T>& w, int64_t n);
 struct SideStream {
   hipStream_t stream = nullptr;   // block factorisations
   hipStream_t stream3 = nullptr;  // reflectors applied to the targets of a QR
+  hipStream_t stream4 = nullptr;  // bulk of the trailing updates
   hipEvent_t ev_next = nullptr;
   hipEvent_t ev_fact = nullptr;
   hipEvent_t ev_tgt = nullptr;
+  hipEvent_t ev_near = nullptr;
+  hipEvent_t ev_bulk = nullptr;
   std::mutex* mu = nullptr;
 };
 int side_stream(SideStream* out);

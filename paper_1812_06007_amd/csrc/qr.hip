@@ -496,7 +496,7 @@ int64_t panel_wgs(int64_t mp) { return ceil_div(mp, RPW); }
 constexpr int NB2 = 2 * NB;
 
 struct QrSizes {
-  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f;
+  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f, wn, gemm_work_n;
 };
 
 QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
@@ -508,13 +508,16 @@ QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   z.w = static_cast<size_t>(NB2) * n;
   z.xch = 2 * (static_cast<size_t>(panel_wgs(m)) + 1) * NB * 2;
   z.sync = nblocks + 2;
-  size_t gw = 0, gwb = 0, gwf = 0;
+  size_t gw = 0, gwb = 0, gwf = 0, gwn = 0;
   for (int64_t j0 = 0; j0 < n; j0 += NB2) {
     const int64_t jb = std::min<int64_t>(NB2, n - j0), mp = m - j0;
     const int64_t jb1 = std::min<int64_t>(NB, jb), jb2 = jb - jb1;
     const int64_t nc = n - j0 - jb, nn = std::min<int64_t>(NB2, nc);
     gwb = std::max(gwb, gemm_work_elems(jb1, jb2, mp));
-    gw = std::max(gw, gemm_work_elems(jb, nn, mp));
+    const int64_t nn2 = std::min<int64_t>(NB2, std::max<int64_t>(nc - nn, 0));
+    gwn = std::max(gwn, gemm_work_elems(jb, nn, mp));
+    gwn = std::max(gwn, gemm_work_elems(jb, nn2, mp));
+    gw = std::max(gw, gemm_work_elems(jb, std::max<int64_t>(nc - nn - nn2, 0), mp));
     gw = std::max(gw, gemm_work_elems(jb, nc - nn, mp));
     gw = std::max(gw, gemm_work_elems(jb, n - j0, mp));
     if (target_rows > 0) gwf = std::max(gwf, gemm_work_elems(target_rows, jb, mp));
@@ -524,6 +527,8 @@ QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   z.gemm_work_b = gwb;
   z.wf = static_cast<size_t>(std::max<int64_t>(target_rows, 0)) * NB2;
   z.gemm_work_f = gwf;
+  z.wn = static_cast<size_t>(NB2) * NB2;
+  z.gemm_work_n = gwn;
   return z;
 }
 
@@ -559,6 +564,10 @@ void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w, int64_t target
   w.W2f = a.take<T>(z.wf);
   w.gemm_work_f = a.take<T>(z.gemm_work_f);
   w.gemm_work_f_elems = z.gemm_work_f;
+  w.W1n = a.take<T>(z.wn);
+  w.W2n = a.take<T>(z.wn);
+  w.gemm_work_n = a.take<T>(z.gemm_work_n);
+  w.gemm_work_n_elems = z.gemm_work_n;
 }
 
 template <class T>
@@ -628,18 +637,24 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     }
     return URV_OK;
   };
-  // C <- (I - Y T^T Y^T) C for the block at j0 and columns [c0, c0 + nc), on the caller's stream.
-  auto apply_block = [&](int64_t j0, int64_t c0, int64_t nc) -> int {
+  // C <- (I - Y T^T Y^T) C for the block at j0 and columns [c0, c0 + nc): the next two
+  // column blocks on the caller's stream, the bulk on the fourth stream (own scratch each).
+  const hipStream_t s4 = side.stream4;
+  auto apply_block = [&](int64_t j0, int64_t c0, int64_t nc, bool bulk) -> int {
     if (nc <= 0) return URV_OK;
     const int jb = static_cast<int>(std::min<int64_t>(NB2, n - j0));
     const int64_t mp = m - j0;
     const T* Yb = w.Y + j0 + j0 * m;
     const T* Tb = w.Tm + j0 * NB2;
     T* Cb = X + j0 + c0 * ldx;
-    URV_TRY(gemm<T>(true, false, jb, nc, mp, T(1), Yb, m, Cb, ldx, T(0), w.W1, NB2, w.gemm_work,
-                    w.gemm_work_elems, s));
-    URV_TRY(gemm<T>(true, false, jb, nc, jb, T(1), Tb, NB2, w.W1, NB2, T(0), w.W2, NB2, nullptr, 0, s));
-    URV_TRY(gemm<T>(false, false, mp, nc, jb, T(-1), Yb, m, w.W2, NB2, T(1), Cb, ldx, nullptr, 0, s));
+    const hipStream_t st = bulk ? s4 : s;
+    T* W1 = bulk ? w.W1 : w.W1n;
+    T* W2 = bulk ? w.W2 : w.W2n;
+    T* gw = bulk ? w.gemm_work : w.gemm_work_n;
+    const size_t gwe = bulk ? w.gemm_work_elems : w.gemm_work_n_elems;
+    URV_TRY(gemm<T>(true, false, jb, nc, mp, T(1), Yb, m, Cb, ldx, T(0), W1, NB2, gw, gwe, st));
+    URV_TRY(gemm<T>(true, false, jb, nc, jb, T(1), Tb, NB2, W1, NB2, T(0), W2, NB2, nullptr, 0, st));
+    URV_TRY(gemm<T>(false, false, mp, nc, jb, T(-1), Yb, m, W2, NB2, T(1), Cb, ldx, nullptr, 0, st));
     return URV_OK;
   };
 
@@ -668,6 +683,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   if (ntargets > 0) URV_HIP(hipStreamWaitEvent(s3, side.ev_next, 0));  // targets written before the call
   URV_TRY(factor_block(0));
   URV_HIP(hipEventRecord(side.ev_fact, s2));
+  bool bulk_pending = false;
   for (int64_t j0 = 0; j0 < n; j0 += NB2) {
     URV_HIP(hipStreamWaitEvent(s, side.ev_fact, 0));  // block j0 is factored
     if (ntargets > 0) {
@@ -677,13 +693,26 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     const int64_t j1 = j0 + NB2;
     if (j1 >= n) break;
     const int64_t nn = std::min<int64_t>(NB2, n - j1);
-    URV_TRY(apply_block(j0, j1, nn));                 // the next block's columns first
+    URV_TRY(apply_block(j0, j1, nn, false));          // the next block's columns first
     URV_HIP(hipEventRecord(side.ev_next, s));
     URV_HIP(hipStreamWaitEvent(s2, side.ev_next, 0));
     URV_TRY(factor_block(j1));
     URV_HIP(hipEventRecord(side.ev_fact, s2));
-    URV_TRY(apply_block(j0, j1 + nn, n - j1 - nn));   // the rest, beside the next factorisation
+    const int64_t j2 = j1 + nn;
+    if (j2 >= n) continue;
+    // the block after next: its columns need the bulk update of the previous block
+    const int64_t nn2 = std::min<int64_t>(NB2, n - j2);
+    if (bulk_pending) URV_HIP(hipStreamWaitEvent(s, side.ev_bulk, 0));
+    URV_TRY(apply_block(j0, j2, nn2, false));
+    const int64_t j3 = j2 + nn2;
+    if (j3 >= n) continue;
+    URV_HIP(hipEventRecord(side.ev_near, s));
+    URV_HIP(hipStreamWaitEvent(s4, side.ev_near, 0));
+    URV_TRY(apply_block(j0, j3, n - j3, true));       // the rest, beside the next factorisations
+    URV_HIP(hipEventRecord(side.ev_bulk, s4));
+    bulk_pending = true;
   }
+  if (bulk_pending) URV_HIP(hipStreamWaitEvent(s, side.ev_bulk, 0));
   if (ntargets > 0) {
     // Q = H_1 ... H_n [D; 0]: the sign fix D on the first n columns, then join
     for (int i = 0; i < ntargets; ++i)
