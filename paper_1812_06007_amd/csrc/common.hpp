@@ -89,6 +89,14 @@ inline int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha
 }
 // Scratch elements gemm may use for the given shape (0 if it never splits K).
 size_t gemm_work_elems(int64_t M, int64_t N, int64_t K);
+// op(A) op(B) as `splits` partial sums over consecutive k chunks, each M x N
+// packed (ld M) one after the other in `partial`, to be added in order by the
+// consumer.  *splits is at least 1 and at most work_elems / (M N).
+template <class T>
+int gemm_partials(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
+                  int64_t ldb, T* partial, size_t work_elems, int* splits, hipStream_t s);
+// Scratch elements gemm_partials uses for this shape when given enough.
+size_t gemm_partials_elems(int64_t M, int64_t N, int64_t K);
 inline size_t dgemm_work_elems(int64_t M, int64_t N, int64_t K) { return gemm_work_elems(M, N, K); }
 
 // 2-D copies / fills.
@@ -138,10 +146,11 @@ void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w, int64_t target
 template <class T>
 unsigned* qr_error_flag(const QrWorkT<T>& w, int64_t n);
 
-// A second stream of the current device, created on first use and kept for the
-// life of the process (default priority, non-blocking), with two events.  Work
-// is enqueued on it only while *mu is held, so calls from several host threads
-// keep their event records and waits paired.
+// Streams of the current device for the QR pipeline beside the caller's,
+// created on first use and kept for the life of the process (non-blocking,
+// default priority), with their events.  Work is enqueued on them only while
+// *mu is held, so calls from several host threads keep their event records and
+// waits paired.
 struct SideStream {
   hipStream_t stream = nullptr;   // block factorisations
   hipStream_t stream3 = nullptr;  // reflectors applied to the targets of a QR

@@ -366,6 +366,47 @@ size_t gemm_work_elems(int64_t M, int64_t N, int64_t K) {
   return p.splits > 1 ? static_cast<size_t>(p.splits) * M * N : 0;
 }
 
+size_t gemm_partials_elems(int64_t M, int64_t N, int64_t K) {
+  const Plan p = make_plan(M, N, K);
+  return static_cast<size_t>(std::max(p.splits, 1)) * M * N;
+}
+
+template <class T>
+int gemm_partials(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
+                  int64_t ldb, T* partial, size_t work_elems, int* splits, hipStream_t s) {
+  *splits = 0;
+  if (M == 0 || N == 0) return URV_OK;
+  const size_t mn = static_cast<size_t>(M) * N;
+  if (partial == nullptr || work_elems < mn) {
+    set_last_error("gemm_partials: scratch smaller than one M x N slice");
+    return URV_EINVAL;
+  }
+  if (K == 0) {
+    scale_kernel<<<static_cast<unsigned>(ceil_div(M * N, 256)), 256, 0, s>>>(M, N, T(0), partial, M);
+    URV_LAUNCHED("scale_kernel");
+    *splits = 1;
+    return URV_OK;
+  }
+  Plan p = make_plan(M, N, K);
+  const int64_t cap = static_cast<int64_t>(work_elems / mn);
+  if (p.splits > cap) {
+    p.k_chunk = ceil_div(ceil_div(K, cap), BK) * BK;
+    p.splits = static_cast<int>(ceil_div(K, p.k_chunk));
+  }
+  if (!ta && !tb) launch_tiles<T, false, false>(p, M, N, K, T(1), A, lda, B, ldb, T(0), nullptr, M, partial, s);
+  else if (ta && !tb) launch_tiles<T, true, false>(p, M, N, K, T(1), A, lda, B, ldb, T(0), nullptr, M, partial, s);
+  else if (!ta && tb) launch_tiles<T, false, true>(p, M, N, K, T(1), A, lda, B, ldb, T(0), nullptr, M, partial, s);
+  else launch_tiles<T, true, true>(p, M, N, K, T(1), A, lda, B, ldb, T(0), nullptr, M, partial, s);
+  URV_LAUNCHED("gemm_kernel");
+  *splits = p.splits;
+  return URV_OK;
+}
+
+template int gemm_partials<double>(bool, bool, int64_t, int64_t, int64_t, const double*, int64_t, const double*,
+                                   int64_t, double*, size_t, int*, hipStream_t);
+template int gemm_partials<float>(bool, bool, int64_t, int64_t, int64_t, const float*, int64_t, const float*,
+                                  int64_t, float*, size_t, int*, hipStream_t);
+
 template <class T>
 int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, const T* A, int64_t lda,
          const T* B, int64_t ldb, T beta, T* C, int64_t ldc, T* work, size_t work_elems,

@@ -22,6 +22,8 @@
 // from [D; 0] with D = sign(diag R), which makes diag(R) >= 0 at no cost.
 #include "common.hpp"
 
+#include <cstdlib>
+
 namespace urv {
 namespace {
 
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
                                                      int64_t ldy, T* __restrict__ tau,
                                                      T* __restrict__ Tout, int ldt,
                                                      uint64_t* __restrict__ xch, uint32_t tag0,
-                                                     unsigned* __restrict__ err) {
+                                                     unsigned* __restrict__ err, int zero_above) {
   using V2 = typename Vec2<T>::type;
   __shared__ T stage[64][NB + 1];
   __shared__ __attribute__((aligned(16))) T bc[PANEL_WAVES][RPT];  // pivot column, per wave
@@ -378,6 +380,11 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
     if (threadIdx.x < jb) tau[threadIdx.x] = tau_sh[threadIdx.x];
   }
 
+  // ---- Y is zero in the zero_above rows above the panel (an earlier panel of the same block)
+  if (wg == 0)
+    for (int e = threadIdx.x; e < zero_above * jb; e += PANEL_THREADS)
+      Y[(e % zero_above) - zero_above + static_cast<int64_t>(e / zero_above) * ldy] = T(0);
+
   // ---- store: panel in place, and explicit Y (0 above, 1 on the diagonal)
   for (int k = 0; k < RPW / 64; ++k) {
     if (g / WAVES_PER_CHUNK == k) {
@@ -431,21 +438,31 @@ __global__ void fill_u64_kernel(uint64_t* p, int64_t count) {
   if (idx < count) p[idx] = 0;
 }
 
-// Zeroes a rows x cols block (ld ld).
+// Sum of `splits` partial values spaced `slice` apart, in ascending order
+// (four independent loads in flight, added in the same order as one loop).
 template <class T>
-__global__ void zero_block_kernel(T* __restrict__ p, int64_t rows, int64_t cols, int64_t ld) {
-  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (idx >= rows * cols) return;
-  p[idx % rows + (idx / rows) * ld] = T(0);
+__device__ inline T sum_splits(const T* __restrict__ src, int splits, int64_t slice) {
+  T a = 0;
+  int z = 0;
+  for (; z + 4 <= splits; z += 4) {
+    const T v0 = src[z * slice], v1 = src[(z + 1) * slice], v2 = src[(z + 2) * slice], v3 = src[(z + 3) * slice];
+    a += v0;
+    a += v1;
+    a += v2;
+    a += v3;
+  }
+  for (; z < splits; ++z) a += src[z * slice];
+  return a;
 }
 
 // Joins the T factors of two consecutive panels into the T of their union:
 // for H = (I - Y1 T1 Y1^T)(I - Y2 T2 Y2^T) = I - [Y1 Y2] T [Y1 Y2]^T,
 // T = [[T1, -T1 (Y1^T Y2) T2], [0, T2]].  T1 and T2 are already in place in
-// the (ld ldt) block at Tb; S12 = Y1^T Y2 (jb1 x jb2, ld lds).  One workgroup.
+// the (ld ldt) block at Tb; S12 = Y1^T Y2 arrives as `splits` partial sums
+// (jb1 x jb2 each, packed), added in order.  One workgroup.
 template <class T>
 __global__ __launch_bounds__(1024) void t_join_kernel(T* __restrict__ Tb, int ldt, int jb1, int jb2,
-                                                      const T* __restrict__ S12, int lds) {
+                                                      const T* __restrict__ S12, int splits) {
   __shared__ T t1[NB][NB + 1];
   __shared__ T t2[NB][NB + 1];
   __shared__ T u[NB][NB + 1];
@@ -454,7 +471,9 @@ __global__ __launch_bounds__(1024) void t_join_kernel(T* __restrict__ Tb, int ld
     const int i = e % NB, j = e / NB;
     t1[i][j] = (i < jb1 && j < jb1) ? Tb[i + static_cast<int64_t>(j) * ldt] : T(0);
     t2[i][j] = (i < jb2 && j < jb2) ? Tb[jb1 + i + static_cast<int64_t>(jb1 + j) * ldt] : T(0);
-    u[i][j] = (i < jb1 && j < jb2) ? S12[i + static_cast<int64_t>(j) * lds] : T(0);
+    u[i][j] = (i < jb1 && j < jb2)
+                  ? sum_splits(S12 + static_cast<int64_t>(j) * jb1 + i, splits, static_cast<int64_t>(jb1) * jb2)
+                  : T(0);
   }
   __syncthreads();
   // u <- S12 T2 (T2 upper triangular: only k <= j contributes)
@@ -484,6 +503,37 @@ __global__ __launch_bounds__(1024) void t_join_kernel(T* __restrict__ Tb, int ld
   }
 }
 
+// W2 = T^T W1 with W1 = sum_z P[z] (jb x N each, packed, z ascending) and T
+// upper triangular (ld ldt): the middle factor of (I - Y T^T Y^T) C, fused with
+// the split-K reduction of W1 = Y^T C.  Four columns per workgroup.
+template <class T>
+__global__ __launch_bounds__(256) void reduce_tmul_kernel(int jb, int64_t N, int splits, const T* __restrict__ P,
+                                                          const T* __restrict__ Tm, int ldt, T* __restrict__ W2,
+                                                          int64_t ldw2) {
+  constexpr int CW = 4;
+  __shared__ T w1[CW][4 * NB + 1];
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CW;
+  const int cols = static_cast<int>(min<int64_t>(CW, N - c0));
+  const int64_t slice = static_cast<int64_t>(jb) * N;
+  for (int e = threadIdx.x; e < jb * cols; e += blockDim.x) {
+    const int k = e % jb, jj = e / jb;
+    w1[jj][k] = sum_splits(P + (c0 + jj) * jb + k, splits, slice);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < jb * cols; e += blockDim.x) {
+    const int i = e % jb, jj = e / jb;
+    const T* tcol = Tm + static_cast<int64_t>(i) * ldt;
+    T a0 = 0, a1 = 0;
+    int k = 0;
+    for (; k + 1 <= i; k += 2) {
+      a0 += tcol[k] * w1[jj][k];
+      a1 += tcol[k + 1] * w1[jj][k + 1];
+    }
+    if (k <= i) a0 += tcol[k] * w1[jj][k];
+    W2[i + (c0 + jj) * ldw2] = a0 + a1;
+  }
+}
+
 __global__ void fill_u32_kernel(unsigned* p, int64_t count, unsigned v) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx < count) p[idx] = v;
@@ -491,9 +541,20 @@ __global__ void fill_u32_kernel(unsigned* p, int64_t count, unsigned v) {
 
 int64_t panel_wgs(int64_t mp) { return ceil_div(mp, RPW); }
 
-// Outer block: two consecutive panels share one trailing update of width NB2,
-// which halves the passes over the trailing matrix.
+// Sub-block: two consecutive panels joined (NB2 columns).  Outer block: two
+// sub-blocks joined (NBO columns); the trailing matrix and the targets are
+// updated once per outer block, so their GEMMs have k = NBO.
 constexpr int NB2 = 2 * NB;
+constexpr int NBO = 4 * NB;  // widest outer block; T is stored with this leading dimension
+
+// Outer block width used by qr_pos: NB2 or NBO (URV_QR_BLOCK, for tuning).
+int outer_block() {
+  static const int nb = [] {
+    const char* e = std::getenv("URV_QR_BLOCK");
+    return (e && std::atoi(e) == NBO) ? NBO : NB2;
+  }();
+  return nb;
+}
 
 struct QrSizes {
   size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f, wn, gemm_work_n;
@@ -503,31 +564,41 @@ QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   QrSizes z;
   const int64_t nblocks = ceil_div(n, NB);
   z.y = static_cast<size_t>(m) * n;
-  z.t = static_cast<size_t>(NB2) * n;
+  z.t = static_cast<size_t>(NBO) * n;
   z.tau = n;
-  z.w = static_cast<size_t>(NB2) * n;
+  z.w = static_cast<size_t>(NBO) * n;
   z.xch = 2 * (static_cast<size_t>(panel_wgs(m)) + 1) * NB * 2;
   z.sync = nblocks + 2;
   size_t gw = 0, gwb = 0, gwf = 0, gwn = 0;
-  for (int64_t j0 = 0; j0 < n; j0 += NB2) {
-    const int64_t jb = std::min<int64_t>(NB2, n - j0), mp = m - j0;
-    const int64_t jb1 = std::min<int64_t>(NB, jb), jb2 = jb - jb1;
-    const int64_t nc = n - j0 - jb, nn = std::min<int64_t>(NB2, nc);
-    gwb = std::max(gwb, gemm_work_elems(jb1, jb2, mp));
-    const int64_t nn2 = std::min<int64_t>(NB2, std::max<int64_t>(nc - nn, 0));
-    gwn = std::max(gwn, gemm_work_elems(jb, nn, mp));
-    gwn = std::max(gwn, gemm_work_elems(jb, nn2, mp));
-    gw = std::max(gw, gemm_work_elems(jb, std::max<int64_t>(nc - nn - nn2, 0), mp));
-    gw = std::max(gw, gemm_work_elems(jb, nc - nn, mp));
-    gw = std::max(gw, gemm_work_elems(jb, n - j0, mp));
-    if (target_rows > 0) gwf = std::max(gwf, gemm_work_elems(target_rows, jb, mp));
+  for (const int64_t nbo : {static_cast<int64_t>(NB2), static_cast<int64_t>(NBO)}) {
+    for (int64_t j0 = 0; j0 < n; j0 += nbo) {
+      const int64_t jb = std::min<int64_t>(nbo, n - j0), mp = m - j0;
+      const int64_t ja = std::min<int64_t>(NB2, jb), jbb = jb - ja;
+      const int64_t nc = n - j0 - jb, nn = std::min<int64_t>(nbo, nc);
+      // the block factorisation (side stream): panel pairs, A applied to B, S_AB, the next block
+      for (int64_t r0 = j0; r0 < j0 + jb; r0 += NB2) {
+        const int64_t js = std::min<int64_t>(NB2, j0 + jb - r0);
+        const int64_t jb1 = std::min<int64_t>(NB, js), jb2 = js - jb1;
+        gwb = std::max(gwb, gemm_partials_elems(jb1, jb2, m - r0));
+      }
+      gwb = std::max(gwb, gemm_partials_elems(ja, jbb, mp));
+      gwb = std::max(gwb, gemm_work_elems(ja, jbb, mp));
+      gwb = std::max(gwb, gemm_partials_elems(jb, nn, mp));
+      const int64_t nn2 = std::min<int64_t>(nbo, std::max<int64_t>(nc - nn, 0));
+      gwn = std::max(gwn, gemm_partials_elems(jb, nn, mp));
+      gwn = std::max(gwn, gemm_partials_elems(jb, nn2, mp));
+      gw = std::max(gw, gemm_partials_elems(jb, std::max<int64_t>(nc - nn - nn2, 0), mp));
+      gw = std::max(gw, gemm_work_elems(jb, nc - nn, mp));
+      gw = std::max(gw, gemm_work_elems(jb, n - j0, mp));
+      if (target_rows > 0) gwf = std::max(gwf, gemm_work_elems(target_rows, jb, mp));
+    }
   }
   z.gemm_work = gw;
-  z.wb = static_cast<size_t>(NB) * NB;
+  z.wb = static_cast<size_t>(NBO) * NBO;
   z.gemm_work_b = gwb;
-  z.wf = static_cast<size_t>(std::max<int64_t>(target_rows, 0)) * NB2;
+  z.wf = static_cast<size_t>(std::max<int64_t>(target_rows, 0)) * NBO;
   z.gemm_work_f = gwf;
-  z.wn = static_cast<size_t>(NB2) * NB2;
+  z.wn = static_cast<size_t>(NBO) * NBO;
   z.gemm_work_n = gwn;
   return z;
 }
@@ -585,6 +656,10 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     set_last_error("qr_pos: too many rows for the panel kernel");
     return URV_ENOTSUP;
   }
+  SideStream side;
+  URV_TRY(side_stream(&side));
+  std::lock_guard<std::mutex> side_lock(*side.mu);
+
   unsigned* err = w.sync + nblocks;
   fill_u32_kernel<<<static_cast<unsigned>(ceil_div(nblocks + 2, 256)), 256, 0, s>>>(w.sync, nblocks + 2, 0u);
   URV_LAUNCHED("fill_u32_kernel");
@@ -593,84 +668,118 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   URV_LAUNCHED("fill_u64_kernel");
 
   // Look-ahead: 128-column blocks are factored on a second stream while the
-  // caller's stream applies the previous block to the rest of the matrix.
+  // other streams apply the previous blocks to the rest of the matrix.
   // The panels occupy a few dozen CUs; the trailing update fills the others.
-  SideStream side;
-  URV_TRY(side_stream(&side));
-  std::lock_guard<std::mutex> side_lock(*side.mu);
   const hipStream_t s2 = side.stream;
+  const int nbo = outer_block();
 
   uint32_t panels = 0;  // panel launches so far: exchange tags stay distinct
-  auto panel = [&](int64_t r0, int jbp, T* Tp) -> int {
+  auto panel = [&](int64_t r0, int jbp, T* Tp, int zero_above) -> int {
     const int64_t mp = m - r0;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
     panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
-                                                 w.tau + r0, Tp, NB2, w.xch, panels * NB, err);
+                                                 w.tau + r0, Tp, NBO, w.xch, panels * NB, err, zero_above);
     ++panels;
     URV_LAUNCHED("panel_kernel");
     return URV_OK;
   };
-  // Householder vectors, tau and T of the block at column j0, on the side stream.
-  auto factor_block = [&](int64_t j0) -> int {
-    const int jb = static_cast<int>(std::min<int64_t>(NB2, n - j0));
-    const int jb1 = std::min(jb, NB), jb2 = jb - jb1;
-    const int64_t mp = m - j0;
-    T* Yb = w.Y + j0 + j0 * m;
-    T* Tb = w.Tm + j0 * NB2;
-    URV_TRY(panel(j0, jb1, Tb));
+  // Householder vectors, tau and T (at Tp, ld NBO) of the sub-block of width
+  // jbs at row/column r0 of the outer block starting at j0, on the side stream.
+  auto factor_sub = [&](int64_t j0, int64_t r0, int jbs, T* Tp) -> int {
+    const int jb1 = std::min(jbs, NB), jb2 = jbs - jb1;
+    const int64_t mp = m - r0;
+    T* Yb = w.Y + r0 + r0 * m;
+    URV_TRY(panel(r0, jb1, Tp, static_cast<int>(r0 - j0)));
     if (jb2 > 0) {
-      // first panel's reflectors applied to the second panel's columns
-      T* C2 = X + j0 + (j0 + jb1) * ldx;
-      URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, C2, ldx, T(0), w.W1b, NB, w.gemm_work_b,
-                      w.gemm_work_b_elems, s2));
-      URV_TRY(gemm<T>(true, false, jb1, jb2, jb1, T(1), Tb, NB2, w.W1b, NB, T(0), w.W2b, NB, nullptr, 0, s2));
-      URV_TRY(gemm<T>(false, false, mp, jb2, jb1, T(-1), Yb, m, w.W2b, NB, T(1), C2, ldx, nullptr, 0, s2));
-      // Y2 is zero above its panel; then the second panel and the joined T
-      zero_block_kernel<T><<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(jb1) * jb2, 256)), 256, 0, s2>>>(
-          w.Y + j0 + (j0 + jb1) * m, jb1, jb2, m);
-      URV_LAUNCHED("zero_block_kernel");
-      URV_TRY(panel(j0 + jb1, jb2, Tb + jb1 + static_cast<int64_t>(jb1) * NB2));
-      URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, Yb + static_cast<int64_t>(jb1) * m, m, T(0),
-                      w.W1b, NB, w.gemm_work_b, w.gemm_work_b_elems, s2));
-      t_join_kernel<T><<<1, 1024, 0, s2>>>(Tb, NB2, jb1, jb2, w.W1b, NB);
+      // first panel's reflectors applied to the second panel's columns:
+      // C2 -= Y1 (T1^T (Y1^T C2)), the reduction of Y1^T C2 fused with T1^T
+      T* C2 = X + r0 + (r0 + jb1) * ldx;
+      int splits = 0;
+      URV_TRY(gemm_partials<T>(true, false, jb1, jb2, mp, Yb, m, C2, ldx, w.gemm_work_b, w.gemm_work_b_elems,
+                               &splits, s2));
+      reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(jb2, 4)), 256, 0, s2>>>(
+          jb1, jb2, splits, w.gemm_work_b, Tp, NBO, w.W2b, NBO);
+      URV_LAUNCHED("reduce_tmul_kernel");
+      URV_TRY(gemm<T>(false, false, mp, jb2, jb1, T(-1), Yb, m, w.W2b, NBO, T(1), C2, ldx, nullptr, 0, s2));
+      // the second panel (Y2 zero above it), then the joined T from S12 = Y1^T Y2
+      URV_TRY(panel(r0 + jb1, jb2, Tp + jb1 + static_cast<int64_t>(jb1) * NBO, static_cast<int>(r0 + jb1 - j0)));
+      URV_TRY(gemm_partials<T>(true, false, jb1, jb2, mp, Yb, m, Yb + static_cast<int64_t>(jb1) * m, m,
+                               w.gemm_work_b, w.gemm_work_b_elems, &splits, s2));
+      t_join_kernel<T><<<1, 1024, 0, s2>>>(Tp, NBO, jb1, jb2, w.gemm_work_b, splits);
       URV_LAUNCHED("t_join_kernel");
+    }
+    return URV_OK;
+  };
+  // The outer block at column j0: sub-blocks A and B, B updated by A in
+  // between, and T = [[T_A, -T_A (Y_A^T Y_B) T_B], [0, T_B]].
+  auto factor_block = [&](int64_t j0) -> int {
+    const int jbo = static_cast<int>(std::min<int64_t>(nbo, n - j0));
+    const int ja = std::min(jbo, NB2), jbb = jbo - ja;
+    const int64_t mp = m - j0;
+    T* Tb = w.Tm + j0 * NBO;
+    URV_TRY(factor_sub(j0, j0, ja, Tb));
+    if (jbb > 0) {
+      const T* Ya = w.Y + j0 + j0 * m;
+      T* CB = X + j0 + (j0 + ja) * ldx;
+      int splits = 0;
+      URV_TRY(gemm_partials<T>(true, false, ja, jbb, mp, Ya, m, CB, ldx, w.gemm_work_b, w.gemm_work_b_elems,
+                               &splits, s2));
+      reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(jbb, 4)), 256, 0, s2>>>(
+          ja, jbb, splits, w.gemm_work_b, Tb, NBO, w.W2b, NBO);
+      URV_LAUNCHED("reduce_tmul_kernel");
+      URV_TRY(gemm<T>(false, false, mp, jbb, ja, T(-1), Ya, m, w.W2b, NBO, T(1), CB, ldx, nullptr, 0, s2));
+      T* TB = Tb + ja + static_cast<int64_t>(ja) * NBO;
+      URV_TRY(factor_sub(j0, j0 + ja, jbb, TB));
+      // Y_B is zero in the rows of A, so S_AB = Y_A^T Y_B over all mp rows
+      URV_TRY(gemm<T>(true, false, ja, jbb, mp, T(1), Ya, m, Ya + static_cast<int64_t>(ja) * m, m, T(0),
+                      w.W1b, NBO, w.gemm_work_b, w.gemm_work_b_elems, s2));
+      URV_TRY(gemm<T>(false, false, ja, jbb, jbb, T(1), w.W1b, NBO, TB, NBO, T(0), w.W2b, NBO, nullptr, 0, s2));
+      URV_TRY(gemm<T>(false, false, ja, jbb, ja, T(-1), Tb, NBO, w.W2b, NBO, T(0), Tb + static_cast<int64_t>(ja) * NBO,
+                      NBO, nullptr, 0, s2));
+      URV_TRY(gemm<T>(false, false, jbb, ja, 0, T(0), Tb, NBO, Tb, NBO, T(0), Tb + ja, NBO, nullptr, 0, s2));
     }
     return URV_OK;
   };
   // C <- (I - Y T^T Y^T) C for the block at j0 and columns [c0, c0 + nc): the next two
   // column blocks on the caller's stream, the bulk on the fourth stream (own scratch each).
   const hipStream_t s4 = side.stream4;
-  auto apply_block = [&](int64_t j0, int64_t c0, int64_t nc, bool bulk) -> int {
+  enum { kOnPanelStream, kOnCallerStream, kOnBulkStream };
+  auto apply_block = [&](int64_t j0, int64_t c0, int64_t nc, int where) -> int {
     if (nc <= 0) return URV_OK;
-    const int jb = static_cast<int>(std::min<int64_t>(NB2, n - j0));
+    const int jb = static_cast<int>(std::min<int64_t>(nbo, n - j0));
     const int64_t mp = m - j0;
     const T* Yb = w.Y + j0 + j0 * m;
-    const T* Tb = w.Tm + j0 * NB2;
+    const T* Tb = w.Tm + j0 * NBO;
     T* Cb = X + j0 + c0 * ldx;
-    const hipStream_t st = bulk ? s4 : s;
-    T* W1 = bulk ? w.W1 : w.W1n;
-    T* W2 = bulk ? w.W2 : w.W2n;
-    T* gw = bulk ? w.gemm_work : w.gemm_work_n;
-    const size_t gwe = bulk ? w.gemm_work_elems : w.gemm_work_n_elems;
-    URV_TRY(gemm<T>(true, false, jb, nc, mp, T(1), Yb, m, Cb, ldx, T(0), W1, NB2, gw, gwe, st));
-    URV_TRY(gemm<T>(true, false, jb, nc, jb, T(1), Tb, NB2, W1, NB2, T(0), W2, NB2, nullptr, 0, st));
-    URV_TRY(gemm<T>(false, false, mp, nc, jb, T(-1), Yb, m, W2, NB2, T(1), Cb, ldx, nullptr, 0, st));
+    const bool bulk = where == kOnBulkStream, panel_side = where == kOnPanelStream;
+    const hipStream_t st = bulk ? s4 : (panel_side ? s2 : s);
+    T* W1 = bulk ? w.W1 : (panel_side ? w.W1b : w.W1n);
+    T* W2 = bulk ? w.W2 : (panel_side ? w.W2b : w.W2n);
+    T* gw = bulk ? w.gemm_work : (panel_side ? w.gemm_work_b : w.gemm_work_n);
+    const size_t gwe = bulk ? w.gemm_work_elems : (panel_side ? w.gemm_work_b_elems : w.gemm_work_n_elems);
+    (void)W1;
+    int splits = 0;
+    URV_TRY(gemm_partials<T>(true, false, jb, nc, mp, Yb, m, Cb, ldx, gw, gwe, &splits, st));   // Y^T C
+    reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(nc, 4)), 256, 0, st>>>(jb, nc, splits, gw, Tb, NBO,
+                                                                                   W2, NBO);  // T^T (Y^T C)
+    URV_LAUNCHED("reduce_tmul_kernel");
+    URV_TRY(gemm<T>(false, false, mp, nc, jb, T(-1), Yb, m, W2, NBO, T(1), Cb, ldx, nullptr, 0, st));
     return URV_OK;
   };
 
   // Z <- Z (I - Y T Y^T) for the block at j0 and every target, on the third stream.
   const hipStream_t s3 = side.stream3;
   auto apply_targets = [&](int64_t j0) -> int {
-    const int jb = static_cast<int>(std::min<int64_t>(NB2, n - j0));
+    const int jb = static_cast<int>(std::min<int64_t>(nbo, n - j0));
     const int64_t mp = m - j0;
     const T* Yb = w.Y + j0 + j0 * m;
-    const T* Tb = w.Tm + j0 * NB2;
+    const T* Tb = w.Tm + j0 * NBO;
     for (int i = 0; i < ntargets; ++i) {
       const QrTarget<T>& z = targets[i];
       T* Zb = z.Z + j0 * z.ldz;
       URV_TRY(gemm<T>(false, false, z.rows, jb, mp, T(1), Zb, z.ldz, Yb, m, T(0), w.W1f, z.rows,
                       w.gemm_work_f, w.gemm_work_f_elems, s3));               // Z Y
-      URV_TRY(gemm<T>(false, false, z.rows, jb, jb, T(1), w.W1f, z.rows, Tb, NB2, T(0), w.W2f, z.rows,
+      URV_TRY(gemm<T>(false, false, z.rows, jb, jb, T(1), w.W1f, z.rows, Tb, NBO, T(0), w.W2f, z.rows,
                       nullptr, 0, s3));                                       // (Z Y) T
       URV_TRY(gemm<T>(false, true, z.rows, mp, jb, T(-1), w.W2f, z.rows, Yb, m, T(1), Zb, z.ldz, nullptr,
                       0, s3));                                                // Z -= (Z Y T) Y^T
@@ -678,37 +787,43 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     return URV_OK;
   };
 
+  // Streams: s2 factors block k, then updates block k+1's columns and factors
+  // it (the critical chain); s updates block k+2's columns once block k is
+  // factored; s4 updates the rest; s3 applies block k to the targets.  A
+  // stream waits only on events recorded at least one block earlier, except
+  // the chain itself.
   URV_HIP(hipEventRecord(side.ev_next, s));      // the cleared flags and slots
   URV_HIP(hipStreamWaitEvent(s2, side.ev_next, 0));
   if (ntargets > 0) URV_HIP(hipStreamWaitEvent(s3, side.ev_next, 0));  // targets written before the call
   URV_TRY(factor_block(0));
   URV_HIP(hipEventRecord(side.ev_fact, s2));
-  bool bulk_pending = false;
-  for (int64_t j0 = 0; j0 < n; j0 += NB2) {
+  bool near_pending = false, bulk_pending = false;
+  for (int64_t j0 = 0; j0 < n; j0 += nbo) {
     URV_HIP(hipStreamWaitEvent(s, side.ev_fact, 0));  // block j0 is factored
     if (ntargets > 0) {
       URV_HIP(hipStreamWaitEvent(s3, side.ev_fact, 0));
       URV_TRY(apply_targets(j0));
     }
-    const int64_t j1 = j0 + NB2;
+    const int64_t j1 = j0 + nbo;
     if (j1 >= n) break;
-    const int64_t nn = std::min<int64_t>(NB2, n - j1);
-    URV_TRY(apply_block(j0, j1, nn, false));          // the next block's columns first
-    URV_HIP(hipEventRecord(side.ev_next, s));
-    URV_HIP(hipStreamWaitEvent(s2, side.ev_next, 0));
+    const int64_t nn = std::min<int64_t>(nbo, n - j1);
+    // the chain: block j1's columns (the previous block's share came from s), then its factorisation
+    if (near_pending) URV_HIP(hipStreamWaitEvent(s2, side.ev_near, 0));
+    URV_TRY(apply_block(j0, j1, nn, kOnPanelStream));
     URV_TRY(factor_block(j1));
     URV_HIP(hipEventRecord(side.ev_fact, s2));
     const int64_t j2 = j1 + nn;
     if (j2 >= n) continue;
-    // the block after next: its columns need the bulk update of the previous block
-    const int64_t nn2 = std::min<int64_t>(NB2, n - j2);
+    // the block after next, which needs the previous bulk update first
+    const int64_t nn2 = std::min<int64_t>(nbo, n - j2);
     if (bulk_pending) URV_HIP(hipStreamWaitEvent(s, side.ev_bulk, 0));
-    URV_TRY(apply_block(j0, j2, nn2, false));
+    URV_TRY(apply_block(j0, j2, nn2, kOnCallerStream));
+    URV_HIP(hipEventRecord(side.ev_near, s));
+    near_pending = true;
     const int64_t j3 = j2 + nn2;
     if (j3 >= n) continue;
-    URV_HIP(hipEventRecord(side.ev_near, s));
     URV_HIP(hipStreamWaitEvent(s4, side.ev_near, 0));
-    URV_TRY(apply_block(j0, j3, n - j3, true));       // the rest, beside the next factorisations
+    URV_TRY(apply_block(j0, j3, n - j3, kOnBulkStream));  // the rest, beside the chain
     URV_HIP(hipEventRecord(side.ev_bulk, s4));
     bulk_pending = true;
   }
@@ -728,18 +843,18 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   if (Q) {
     init_q_kernel<T><<<static_cast<unsigned>(ceil_div(m * n, 256)), 256, 0, s>>>(X, ldx, m, n, Q, ldq);
     URV_LAUNCHED("init_q_kernel");
-    const int64_t nouter = ceil_div(n, NB2);
+    const int64_t nouter = ceil_div(n, nbo);
     for (int64_t blk = nouter - 1; blk >= 0; --blk) {
-      const int64_t j0 = blk * NB2;
-      const int jb = static_cast<int>(std::min<int64_t>(NB2, n - j0));
+      const int64_t j0 = blk * nbo;
+      const int jb = static_cast<int>(std::min<int64_t>(nbo, n - j0));
       const int64_t mp = m - j0, nq = n - j0;
       const T* Yb = w.Y + j0 + j0 * m;
-      const T* Tb = w.Tm + j0 * NB2;
+      const T* Tb = w.Tm + j0 * NBO;
       T* Qb = Q + j0 + j0 * ldq;
-      URV_TRY(gemm<T>(true, false, jb, nq, mp, T(1), Yb, m, Qb, ldq, T(0), w.W1, NB2, w.gemm_work,
+      URV_TRY(gemm<T>(true, false, jb, nq, mp, T(1), Yb, m, Qb, ldq, T(0), w.W1, NBO, w.gemm_work,
                       w.gemm_work_elems, s));
-      URV_TRY(gemm<T>(false, false, jb, nq, jb, T(1), Tb, NB2, w.W1, NB2, T(0), w.W2, NB2, nullptr, 0, s));
-      URV_TRY(gemm<T>(false, false, mp, nq, jb, T(-1), Yb, m, w.W2, NB2, T(1), Qb, ldq, nullptr, 0, s));
+      URV_TRY(gemm<T>(false, false, jb, nq, jb, T(1), Tb, NBO, w.W1, NBO, T(0), w.W2, NBO, nullptr, 0, s));
+      URV_TRY(gemm<T>(false, false, mp, nq, jb, T(-1), Yb, m, w.W2, NBO, T(1), Qb, ldq, nullptr, 0, s));
     }
   }
   return URV_OK;

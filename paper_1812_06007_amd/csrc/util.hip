@@ -150,25 +150,19 @@ int side_stream(SideStream* out) {
   std::lock_guard<std::mutex> g(init_mu);
   SideStream& e = table[dev];
   if (e.stream == nullptr) {
-    hipStream_t st = nullptr, st3 = nullptr, st4 = nullptr;
-    hipEvent_t a = nullptr, b = nullptr, c = nullptr, d = nullptr, f = nullptr;
-    URV_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    URV_HIP(hipStreamCreateWithFlags(&st3, hipStreamNonBlocking));
-    URV_HIP(hipStreamCreateWithFlags(&st4, hipStreamNonBlocking));
-    URV_HIP(hipEventCreateWithFlags(&a, hipEventDisableTiming));
-    URV_HIP(hipEventCreateWithFlags(&b, hipEventDisableTiming));
-    URV_HIP(hipEventCreateWithFlags(&c, hipEventDisableTiming));
-    URV_HIP(hipEventCreateWithFlags(&d, hipEventDisableTiming));
-    URV_HIP(hipEventCreateWithFlags(&f, hipEventDisableTiming));
-    e.ev_next = a;
-    e.ev_fact = b;
-    e.ev_tgt = c;
-    e.ev_near = d;
-    e.ev_bulk = f;
-    e.stream3 = st3;
-    e.stream4 = st4;
+    hipStream_t st[3];
+    for (auto& x : st) URV_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    hipEvent_t ev[5];
+    for (auto& x : ev) URV_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    e.ev_next = ev[0];
+    e.ev_fact = ev[1];
+    e.ev_tgt = ev[2];
+    e.ev_near = ev[3];
+    e.ev_bulk = ev[4];
+    e.stream3 = st[1];
+    e.stream4 = st[2];
     e.mu = &use_mu[dev];
-    e.stream = st;
+    e.stream = st[0];
   }
   *out = e;
   return URV_OK;
