@@ -130,8 +130,9 @@ struct QrWorkT {
   size_t gemm_work_b_elems = 0;
   // scratch of the reflectors applied to targets (third stream)
   int64_t target_rows = 0;  // largest target row count the workspace covers
-  T* W1f = nullptr;         // target_rows x 2 kPanelNB
-  T* W2f = nullptr;         // target_rows x 2 kPanelNB
+  T* W1f = nullptr;         // target_rows x 4 kPanelNB
+  T* W2f = nullptr;         // target_rows x 4 kPanelNB
+  T* Tp = nullptr;          // 4 kPanelNB x n: T of pairs of 128-column blocks, for the targets
   T* gemm_work_f = nullptr;
   size_t gemm_work_f_elems = 0;
 };
@@ -160,6 +161,7 @@ struct SideStream {
   hipEvent_t ev_tgt = nullptr;
   hipEvent_t ev_near = nullptr;
   hipEvent_t ev_bulk = nullptr;
+  hipEvent_t ev_pair = nullptr;
   std::mutex* mu = nullptr;
 };
 int side_stream(SideStream* out);

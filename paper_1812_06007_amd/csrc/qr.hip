@@ -534,6 +534,15 @@ __global__ __launch_bounds__(256) void reduce_tmul_kernel(int jb, int64_t N, int
   }
 }
 
+// dst (rows x cols, ld ldd) = src (ld lds).
+template <class T>
+__global__ void copy_block_kernel(const T* __restrict__ src, int64_t lds, T* __restrict__ dst, int64_t ldd,
+                                  int64_t rows, int64_t cols) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= rows * cols) return;
+  dst[idx % rows + (idx / rows) * ldd] = src[idx % rows + (idx / rows) * lds];
+}
+
 __global__ void fill_u32_kernel(unsigned* p, int64_t count, unsigned v) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx < count) p[idx] = v;
@@ -557,7 +566,7 @@ int outer_block() {
 }
 
 struct QrSizes {
-  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f, wn, gemm_work_n;
+  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f, wn, gemm_work_n, tp;
 };
 
 QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
@@ -590,7 +599,10 @@ QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
       gw = std::max(gw, gemm_partials_elems(jb, std::max<int64_t>(nc - nn - nn2, 0), mp));
       gw = std::max(gw, gemm_work_elems(jb, nc - nn, mp));
       gw = std::max(gw, gemm_work_elems(jb, n - j0, mp));
-      if (target_rows > 0) gwf = std::max(gwf, gemm_work_elems(target_rows, jb, mp));
+      if (target_rows > 0) {
+        gwf = std::max(gwf, gemm_work_elems(target_rows, jb, mp));
+        gwf = std::max(gwf, gemm_work_elems(NB2, NB2, mp));  // S of a block pair
+      }
     }
   }
   z.gemm_work = gw;
@@ -598,6 +610,7 @@ QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   z.gemm_work_b = gwb;
   z.wf = static_cast<size_t>(std::max<int64_t>(target_rows, 0)) * NBO;
   z.gemm_work_f = gwf;
+  z.tp = target_rows > 0 ? static_cast<size_t>(NBO) * n : 0;
   z.wn = static_cast<size_t>(NBO) * NBO;
   z.gemm_work_n = gwn;
   return z;
@@ -635,6 +648,7 @@ void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w, int64_t target
   w.W2f = a.take<T>(z.wf);
   w.gemm_work_f = a.take<T>(z.gemm_work_f);
   w.gemm_work_f_elems = z.gemm_work_f;
+  w.Tp = a.take<T>(z.tp);
   w.W1n = a.take<T>(z.wn);
   w.W2n = a.take<T>(z.wn);
   w.gemm_work_n = a.take<T>(z.gemm_work_n);
@@ -717,7 +731,10 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     const int ja = std::min(jbo, NB2), jbb = jbo - ja;
     const int64_t mp = m - j0;
     T* Tb = w.Tm + j0 * NBO;
-    URV_TRY(factor_sub(j0, j0, ja, Tb));
+    // Y is kept zero above the diagonal back to the start of the pair of
+    // 128-column blocks, so that the targets can take a pair at once
+    const int64_t jz = j0 - (j0 / NB2 % 2) * NB2;
+    URV_TRY(factor_sub(jz, j0, ja, Tb));
     if (jbb > 0) {
       const T* Ya = w.Y + j0 + j0 * m;
       T* CB = X + j0 + (j0 + ja) * ldx;
@@ -729,7 +746,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       URV_LAUNCHED("reduce_tmul_kernel");
       URV_TRY(gemm<T>(false, false, mp, jbb, ja, T(-1), Ya, m, w.W2b, NBO, T(1), CB, ldx, nullptr, 0, s2));
       T* TB = Tb + ja + static_cast<int64_t>(ja) * NBO;
-      URV_TRY(factor_sub(j0, j0 + ja, jbb, TB));
+      URV_TRY(factor_sub(jz, j0 + ja, jbb, TB));
       // Y_B is zero in the rows of A, so S_AB = Y_A^T Y_B over all mp rows
       URV_TRY(gemm<T>(true, false, ja, jbb, mp, T(1), Ya, m, Ya + static_cast<int64_t>(ja) * m, m, T(0),
                       w.W1b, NBO, w.gemm_work_b, w.gemm_work_b_elems, s2));
@@ -769,11 +786,43 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
 
   // Z <- Z (I - Y T Y^T) for the block at j0 and every target, on the third stream.
   const hipStream_t s3 = side.stream3;
-  auto apply_targets = [&](int64_t j0) -> int {
-    const int jb = static_cast<int>(std::min<int64_t>(nbo, n - j0));
+  // With 128-column blocks the targets take pairs of blocks (k = 256): for a
+  // pair (A, B) the joined T = [[T_A, -T_A (Y_A^T Y_B) T_B], [0, T_B]] is
+  // formed here, off the factorisation chain.
+  auto apply_targets = [&](int64_t jblk) -> int {
+    int64_t j0 = jblk;
+    int jb = static_cast<int>(std::min<int64_t>(nbo, n - j0));
+    const T* Tb = w.Tm + j0 * NBO;
+    if (nbo == NB2) {
+      const bool second = (jblk / NB2) % 2 == 1;
+      if (!second && jblk + NB2 < n) return URV_OK;  // wait for the pair's second block
+      if (second) {
+        j0 = jblk - NB2;
+        const int jbb = static_cast<int>(std::min<int64_t>(NB2, n - jblk));
+        jb = NB2 + jbb;
+        const int64_t mp = m - j0;
+        T* P = w.Tp + j0 * NBO;
+        const T* TA = w.Tm + j0 * NBO;
+        const T* TB = w.Tm + jblk * NBO;
+        const T* Ya = w.Y + j0 + j0 * m;
+        copy_block_kernel<T><<<static_cast<unsigned>(ceil_div(NB2 * NB2, 256)), 256, 0, s3>>>(TA, NBO, P, NBO, NB2,
+                                                                                             NB2);
+        URV_LAUNCHED("copy_block_kernel");
+        copy_block_kernel<T><<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(jbb) * jbb, 256)), 256, 0, s3>>>(
+            TB, NBO, P + NB2 + static_cast<int64_t>(NB2) * NBO, NBO, jbb, jbb);
+        URV_LAUNCHED("copy_block_kernel");
+        URV_TRY(gemm<T>(false, false, jbb, NB2, 0, T(0), P, NBO, P, NBO, T(0), P + NB2, NBO, nullptr, 0, s3));
+        URV_TRY(gemm<T>(true, false, NB2, jbb, mp, T(1), Ya, m, Ya + static_cast<int64_t>(NB2) * m, m, T(0), w.W1f,
+                        NB2, w.gemm_work_f, w.gemm_work_f_elems, s3));                           // S = Y_A^T Y_B
+        URV_TRY(gemm<T>(false, false, NB2, jbb, jbb, T(1), w.W1f, NB2, TB, NBO, T(0), w.W2f, NB2, nullptr, 0,
+                        s3));                                                                     // S T_B
+        URV_TRY(gemm<T>(false, false, NB2, jbb, NB2, T(-1), TA, NBO, w.W2f, NB2, T(0),
+                        P + static_cast<int64_t>(NB2) * NBO, NBO, nullptr, 0, s3));               // -T_A S T_B
+        Tb = P;
+      }
+    }
     const int64_t mp = m - j0;
     const T* Yb = w.Y + j0 + j0 * m;
-    const T* Tb = w.Tm + j0 * NBO;
     for (int i = 0; i < ntargets; ++i) {
       const QrTarget<T>& z = targets[i];
       T* Zb = z.Z + j0 * z.ldz;

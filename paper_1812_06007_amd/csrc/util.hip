@@ -152,13 +152,14 @@ int side_stream(SideStream* out) {
   if (e.stream == nullptr) {
     hipStream_t st[3];
     for (auto& x : st) URV_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-    hipEvent_t ev[5];
+    hipEvent_t ev[6];
     for (auto& x : ev) URV_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
     e.ev_next = ev[0];
     e.ev_fact = ev[1];
     e.ev_tgt = ev[2];
     e.ev_near = ev[3];
     e.ev_bulk = ev[4];
+    e.ev_pair = ev[5];
     e.stream3 = st[1];
     e.stream4 = st[2];
     e.mu = &use_mu[dev];
