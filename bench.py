@@ -125,9 +125,13 @@ def time_factor(A, q: int, variant: str, precision: str, steps: int, warmup: int
     return e0.elapsed_time(e1) / steps
 
 
-def compare_precisions(A, q: int, variant: str, ms64: float, met64: dict, steps: int, out64) -> dict:
+def compare_precisions(A, q: int, variant: str, ms64: float, met64: dict, steps: int, out64,
+                       half_too: bool = True) -> dict:
     """The mixed-precision forms against the FP64 run (time, reconstruction,
-    orthogonality, rank-k errors and the diagonal of R) on the same A and G."""
+    orthogonality, rank-k errors and the diagonal of R) on the same A and G,
+    for the variant timed and, with half_too, for HALF as well (one QR per
+    power step: the FULL mixed form runs six QRs, four of them FP32, against
+    five FP64 ones)."""
     import numpy as np
     import torch
 
@@ -139,19 +143,31 @@ def compare_precisions(A, q: int, variant: str, ms64: float, met64: dict, steps:
     d64 = torch.diagonal(out64[1]).abs().cpu().numpy()
     keep = ek64[:-1] > 1e-3 * na  # rank-k errors that rise above FP32-level noise
     res = {"fp64": {"ms": ms64, "recon": met64["recon"], "orthU": met64["orthU"], "orthV": met64["orthV"]}}
-    for prec in ("mixed_bf16", "mixed_fp16"):
+    runs = [(variant, prec, prec) for prec in ("mixed_bf16", "mixed_fp16")]
+    if half_too and variant != "half":
         out = (urv.empty_colmajor(m, n, device=A.device), urv.empty_colmajor(n, n, device=A.device),
                urv.empty_colmajor(n, n, device=A.device))
-        ms = time_factor(A, q, variant, prec, steps, 1, out)
+        ms = time_factor(A, q, "half", "fp64", steps, 1, out)
+        met = urv.metrics(A, *out)
+        res["fp64_half"] = {"ms": ms, "recon": met["recon"], "orthU": met["orthU"], "orthV": met["orthV"],
+                            "speedup_vs_fp64": ms64 / ms}
+        del out
+        runs += [("half", prec, prec + "_half") for prec in ("mixed_bf16", "mixed_fp16")]
+    for var, prec, key in runs:
+        out = (urv.empty_colmajor(m, n, device=A.device), urv.empty_colmajor(n, n, device=A.device),
+               urv.empty_colmajor(n, n, device=A.device))
+        ms = time_factor(A, q, var, prec, steps, 1, out)
         met = urv.metrics(A, *out)
         ek = met["ek"]
         ratio = ek[:-1][keep] / ek64[:-1][keep]
         d = torch.diagonal(out[1]).abs().cpu().numpy()
-        res[prec] = {"ms": ms, "speedup_vs_fp64": ms64 / ms, "recon": met["recon"], "orthU": met["orthU"],
+        res[key] = {"ms": ms, "speedup_vs_fp64": ms64 / ms, "recon": met["recon"], "orthU": met["orthU"],
                      "orthV": met["orthV"],
                      "ek_ratio_max": float(ratio.max()) if ratio.size else None,
                      "ek_ratio_at_k_n8": float(ek[n // 8] / ek64[n // 8]) if ek64[n // 8] > 0 else None,
                      "diagR_maxdiff_rel_normA": float(np.max(np.abs(d - d64)) / na)}
+        if var == "half" and "fp64_half" in res:
+            res[key]["speedup_vs_fp64_half"] = res["fp64_half"]["ms"] / ms
         del out
     return res
 

@@ -458,11 +458,10 @@ __device__ inline T sum_splits(const T* __restrict__ src, int splits, int64_t sl
 // Joins the T factors of two consecutive panels into the T of their union:
 // for H = (I - Y1 T1 Y1^T)(I - Y2 T2 Y2^T) = I - [Y1 Y2] T [Y1 Y2]^T,
 // T = [[T1, -T1 (Y1^T Y2) T2], [0, T2]].  T1 and T2 are already in place in
-// the (ld ldt) block at Tb; S12 = Y1^T Y2 arrives as `splits` partial sums
-// (jb1 x jb2 each, packed), added in order.  One workgroup.
+// the (ld ldt) block at Tb; S12 = Y1^T Y2 (jb1 x jb2, ld lds).  One workgroup.
 template <class T>
 __global__ __launch_bounds__(1024) void t_join_kernel(T* __restrict__ Tb, int ldt, int jb1, int jb2,
-                                                      const T* __restrict__ S12, int splits) {
+                                                      const T* __restrict__ S12, int lds) {
   __shared__ T t1[NB][NB + 1];
   __shared__ T t2[NB][NB + 1];
   __shared__ T u[NB][NB + 1];
@@ -471,9 +470,7 @@ __global__ __launch_bounds__(1024) void t_join_kernel(T* __restrict__ Tb, int ld
     const int i = e % NB, j = e / NB;
     t1[i][j] = (i < jb1 && j < jb1) ? Tb[i + static_cast<int64_t>(j) * ldt] : T(0);
     t2[i][j] = (i < jb2 && j < jb2) ? Tb[jb1 + i + static_cast<int64_t>(jb1 + j) * ldt] : T(0);
-    u[i][j] = (i < jb1 && j < jb2)
-                  ? sum_splits(S12 + static_cast<int64_t>(j) * jb1 + i, splits, static_cast<int64_t>(jb1) * jb2)
-                  : T(0);
+    u[i][j] = (i < jb1 && j < jb2) ? S12[i + static_cast<int64_t>(j) * lds] : T(0);
   }
   __syncthreads();
   // u <- S12 T2 (T2 upper triangular: only k <= j contributes)
@@ -555,6 +552,15 @@ int64_t panel_wgs(int64_t mp) { return ceil_div(mp, RPW); }
 // updated once per outer block, so their GEMMs have k = NBO.
 constexpr int NB2 = 2 * NB;
 constexpr int NBO = 4 * NB;  // widest outer block; T is stored with this leading dimension
+
+// Whether targets take pairs of 128-column blocks (URV_TARGET_PAIRS=0 turns it off, for tuning).
+bool target_pairs() {
+  static const bool on = [] {
+    const char* e = std::getenv("URV_TARGET_PAIRS");
+    return !(e && std::atoi(e) == 0);
+  }();
+  return on;
+}
 
 // Outer block width used by qr_pos: NB2 or NBO (URV_QR_BLOCK, for tuning).
 int outer_block() {
@@ -717,9 +723,9 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       URV_TRY(gemm<T>(false, false, mp, jb2, jb1, T(-1), Yb, m, w.W2b, NBO, T(1), C2, ldx, nullptr, 0, s2));
       // the second panel (Y2 zero above it), then the joined T from S12 = Y1^T Y2
       URV_TRY(panel(r0 + jb1, jb2, Tp + jb1 + static_cast<int64_t>(jb1) * NBO, static_cast<int>(r0 + jb1 - j0)));
-      URV_TRY(gemm_partials<T>(true, false, jb1, jb2, mp, Yb, m, Yb + static_cast<int64_t>(jb1) * m, m,
-                               w.gemm_work_b, w.gemm_work_b_elems, &splits, s2));
-      t_join_kernel<T><<<1, 1024, 0, s2>>>(Tp, NBO, jb1, jb2, w.gemm_work_b, splits);
+      URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, Yb + static_cast<int64_t>(jb1) * m, m, T(0), w.W1b,
+                      NBO, w.gemm_work_b, w.gemm_work_b_elems, s2));
+      t_join_kernel<T><<<1, 1024, 0, s2>>>(Tp, NBO, jb1, jb2, w.W1b, NBO);
       URV_LAUNCHED("t_join_kernel");
     }
     return URV_OK;
@@ -793,7 +799,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     int64_t j0 = jblk;
     int jb = static_cast<int>(std::min<int64_t>(nbo, n - j0));
     const T* Tb = w.Tm + j0 * NBO;
-    if (nbo == NB2) {
+    if (nbo == NB2 && target_pairs()) {
       const bool second = (jblk / NB2) % 2 == 1;
       if (!second && jblk + NB2 < n) return URV_OK;  // wait for the pair's second block
       if (second) {
