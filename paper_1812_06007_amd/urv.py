@@ -58,9 +58,10 @@ def lib() -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError("liburv.so is not built (%s); run python -m paper_1812_06007_amd.build" % LIB_PATH)
-    L = ctypes.CDLL(LIB_PATH)
+    path = os.environ.get("URV_LIBRARY") or LIB_PATH  # another build of the same ABI, for comparisons
+    if not os.path.exists(path):
+        raise RuntimeError("liburv.so is not built (%s); run python -m paper_1812_06007_amd.build" % path)
+    L = ctypes.CDLL(path)
     P, I32, I64, U32, U64, D, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                     ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
     L.urv_opts_init.argtypes = [ctypes.POINTER(UrvOpts)]
