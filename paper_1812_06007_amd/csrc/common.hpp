@@ -115,6 +115,8 @@ struct QrWorkT {
   T* W2 = nullptr;          // 2 kPanelNB x n
   uint64_t* xch = nullptr;  // panel exchange slots (tagged partial sums, pivot rows)
   size_t xch_words = 0;
+  uint64_t* jxch = nullptr; // exchange of the panel join: P x 4096 partial sums, then 4096 sums
+  size_t jxch_words = 0;
   unsigned* sync = nullptr; // panel error flag area
   T* gemm_work = nullptr;   // split-K partial sums of the bulk trailing updates
   size_t gemm_work_elems = 0;

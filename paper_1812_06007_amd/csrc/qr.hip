@@ -154,6 +154,21 @@ __device__ inline void t_column(T (*Tsh)[NB + 2], const T (*Ssh)[NB + 2], const 
   Tsh[i][jj] = (i < jj) ? -tj * sum : (i == jj ? tj : T(0));
 }
 
+// Second panel of a 128-column sub-block, joined with the first: the panel
+// also forms S12 = Y1^T Y2 (a device-wide reduction of 64 x 64 partial sums
+// in two tagged rounds) and workgroup 0 writes T12 = -T1 S12 T2 and the zero
+// lower-left block, so that the sub-block's T is complete when it returns.
+template <class T>
+struct PanelJoin {
+  const T* Y1 = nullptr;    // first panel's reflectors at this panel's first row (ld ldy1); null: no join
+  int64_t ldy1 = 0;
+  T* T1 = nullptr;          // first panel's T (ld ldt); this panel's T is at T1 + jb1 (1 + ldt)
+  int jb1 = 0;
+  uint64_t* ps = nullptr;   // P x 4096 tagged partial sums
+  uint64_t* sums = nullptr; // 4096 tagged sums
+};
+constexpr int kJoinEntries = NB * NB;
+
 // Householder panel.  Rows [0, mp) x columns [0, jb) at X (ld ldx); the
 // panel's first row is the diagonal row of its first column.  Writes back in
 // place (R above the diagonal, beta on it, v below), the explicit unit-lower
@@ -177,9 +192,11 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
                                                      int64_t ldy, T* __restrict__ tau,
                                                      T* __restrict__ Tout, int ldt,
                                                      uint64_t* __restrict__ xch, uint32_t tag0,
-                                                     unsigned* __restrict__ err, int zero_above) {
+                                                     unsigned* __restrict__ err, int zero_above,
+                                                     PanelJoin<T> join) {
   using V2 = typename Vec2<T>::type;
   __shared__ T stage[64][NB + 1];
+  __shared__ __attribute__((aligned(16))) T Ys[64][NB + 2];  // join: Y1 rows, then S12 and S12 T2
   __shared__ __attribute__((aligned(16))) T bc[PANEL_WAVES][RPT];  // pivot column, per wave
   __shared__ T red[PANEL_WAVES][NB];   // partial q of this workgroup, per wave
   __shared__ T red2[PANEL_WAVES][NB];  // gathered partial sums, per wave
@@ -385,12 +402,36 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
     for (int e = threadIdx.x; e < zero_above * jb; e += PANEL_THREADS)
       Y[(e % zero_above) - zero_above + static_cast<int64_t>(e / zero_above) * ldy] = T(0);
 
-  // ---- store: panel in place, and explicit Y (0 above, 1 on the diagonal)
+  // ---- store: panel in place, and explicit Y (0 above, 1 on the diagonal);
+  // with a join, the partial S12(i, c) = sum over this workgroup's rows of
+  // Y1(r, i) Y2(r, c), thread (wave g, lane c) holding rows i = 8g .. 8g+7
+  const bool fuse = join.Y1 != nullptr;
+  T sacc[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+  // Y1 rows of the next 64-row chunk, loaded one chunk ahead (element e = threadIdx.x + u * threads)
+  constexpr int YPT = 64 * NB / PANEL_THREADS;
+  T yv[YPT];
+  auto load_y1 = [&](int k) {
+#pragma unroll
+    for (int u = 0; u < YPT; ++u) {
+      const int e = threadIdx.x + u * PANEL_THREADS, r = e & 63, i = e >> 6;
+      const int64_t gi = row0 + k * 64 + r;
+      yv[u] = (gi < mp && i < join.jb1) ? join.Y1[gi + i * join.ldy1] : T(0);
+    }
+  };
+  if (fuse) load_y1(0);
   for (int k = 0; k < RPW / 64; ++k) {
     if (g / WAVES_PER_CHUNK == k) {
       const int r0 = (g % WAVES_PER_CHUNK) * RPT;
 #pragma unroll
       for (int r = 0; r < RPT; ++r) stage[r0 + r][c] = x[r];
+    }
+    if (fuse) {
+#pragma unroll
+      for (int u = 0; u < YPT; ++u) {
+        const int e = threadIdx.x + u * PANEL_THREADS;
+        Ys[e & 63][e >> 6] = yv[u];
+      }
+      if (k + 1 < RPW / 64) load_y1(k + 1);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * NB; e += PANEL_THREADS) {
@@ -402,7 +443,113 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
         Y[gi + col * ldy] = (gi > col) ? v : (gi == col ? T(1) : T(0));
       }
     }
+    if (fuse && c < jb) {
+      for (int r = 0; r < 64; ++r) {
+        const int64_t gi = row0 + k * 64 + r;
+        const T sv = stage[r][c];
+        const T y2 = (gi > c) ? sv : (gi == c ? T(1) : T(0));
+        const T* yr = &Ys[r][8 * g];
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          const V2 yy = *reinterpret_cast<const V2*>(yr + u);
+          sacc[u] += yy.x * y2;
+          sacc[u + 1] += yy.y * y2;
+        }
+      }
+    }
     __syncthreads();
+  }
+  if (!fuse) return;
+
+  // ---- join, round A: publish this workgroup's partial S12
+  const uint32_t tagS = tag0 + static_cast<uint32_t>(NB) + 1u;
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    tagged_store(join.ps + (static_cast<int64_t>(wg) * kJoinEntries + (8 * g + u) * NB + c) * 2, tagS,
+                 ok ? sacc[u] : static_cast<T>(__builtin_nan("")));
+  // round B: this workgroup sums its share of the entries over all workgroups.
+  // With few entries per workgroup, `parts` threads share an entry, each adding
+  // the partials of workgroups part, part + parts, ...; the parts are then added
+  // in order (a fixed order, so every run gives the same sums).
+  const int per = (kJoinEntries + P - 1) / P;
+  const int e_end = min(kJoinEntries, (wg + 1) * per);
+  const int parts = max(1, min(PANEL_THREADS / per, 8));
+  T* red_b = &red[0][0];  // PANEL_WAVES * NB = 512 values
+  for (int base = wg * per; base < e_end; base += PANEL_THREADS / parts) {
+    const int slot_e = threadIdx.x % (PANEL_THREADS / parts), part = threadIdx.x / (PANEL_THREADS / parts);
+    const int e = base + slot_e;
+    T total = T(0);
+    if (e < e_end && part < parts) {
+      for (int p0 = part; p0 < P && ok; p0 += 8 * parts) {
+        const uint64_t* ptrs[8];
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int pw = p0 + u * parts;
+          ptrs[u] = join.ps + (static_cast<int64_t>(pw < P ? pw : 0) * kJoinEntries + e) * 2;
+          cnt += (pw < P) ? 1 : 0;
+        }
+        T vals[8];
+        ok = tagged_load_all<T, 8>(ptrs, cnt, tagS, vals, err);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (u < cnt) total += vals[u];
+      }
+    }
+    __syncthreads();
+    if (part < parts) red_b[part * (PANEL_THREADS / parts) + slot_e] = total;
+    __syncthreads();
+    if (part == 0 && e < e_end) {
+      T sum = T(0);
+      for (int q = 0; q < parts; ++q) sum += red_b[q * (PANEL_THREADS / parts) + slot_e];
+      tagged_store(join.sums + static_cast<int64_t>(e) * 2, tagS, ok ? sum : static_cast<T>(__builtin_nan("")));
+    }
+  }
+  if (wg != 0) return;
+  // round C (workgroup 0): the sums, then T12 = -T1 (S12 T2) with T2 in Tsh
+  static_assert(kJoinEntries == 8 * PANEL_THREADS, "round C loads eight sums per thread");
+  if (ok) {
+    const uint64_t* ptrs[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ptrs[u] = join.sums + static_cast<int64_t>(threadIdx.x + u * PANEL_THREADS) * 2;
+    T v[8];
+    ok = tagged_load_all<T, 8>(ptrs, 8, tagS, v, err);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + u * PANEL_THREADS;
+      Ys[e / NB][e % NB] = v[u];  // S12(i, c), i = e / NB
+    }
+  }
+  for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+    const int i = e % NB, kk = e / NB;
+    Ssh[i][kk] = (i < join.jb1 && kk < join.jb1) ? join.T1[i + static_cast<int64_t>(kk) * ldt] : T(0);
+  }
+  ok = !__syncthreads_or(ok ? 0 : 1);
+  constexpr int PER = NB * NB / PANEL_THREADS;
+  T uacc[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int e = threadIdx.x + r * PANEL_THREADS, i = e % NB, j = e / NB;
+    T a = 0;
+    if (j < jb)
+      for (int kk = 0; kk <= j; ++kk) a += Ys[i][kk] * Tsh[kk][j];
+    uacc[r] = a;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int e = threadIdx.x + r * PANEL_THREADS;
+    Ys[e % NB][e / NB] = uacc[r];
+  }
+  __syncthreads();
+  const T nan = static_cast<T>(__builtin_nan(""));
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int e = threadIdx.x + r * PANEL_THREADS, i = e % NB, j = e / NB;
+    T a = 0;
+    for (int kk = i; kk < join.jb1; ++kk) a += Ssh[i][kk] * Ys[kk][j];
+    if (i < join.jb1 && j < jb) join.T1[i + static_cast<int64_t>(join.jb1 + j) * ldt] = ok ? -a : nan;
+    if (i < jb && j < join.jb1) join.T1[join.jb1 + i + static_cast<int64_t>(j) * ldt] = T(0);
   }
 }
 
@@ -553,6 +700,16 @@ int64_t panel_wgs(int64_t mp) { return ceil_div(mp, RPW); }
 constexpr int NB2 = 2 * NB;
 constexpr int NBO = 4 * NB;  // widest outer block; T is stored with this leading dimension
 
+// Whether the second panel of a sub-block forms S12 and the joined T itself
+// (URV_PANEL_JOIN=0 uses a GEMM and t_join_kernel instead, for tuning).
+bool panel_join() {
+  static const bool on = [] {
+    const char* e = std::getenv("URV_PANEL_JOIN");
+    return !(e && std::atoi(e) == 0);
+  }();
+  return on;
+}
+
 // Whether targets take pairs of 128-column blocks (URV_TARGET_PAIRS=0 turns it off, for tuning).
 bool target_pairs() {
   static const bool on = [] {
@@ -572,7 +729,7 @@ int outer_block() {
 }
 
 struct QrSizes {
-  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f, wn, gemm_work_n, tp;
+  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f, wn, gemm_work_n, tp, jxch;
 };
 
 QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
@@ -583,6 +740,7 @@ QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   z.tau = n;
   z.w = static_cast<size_t>(NBO) * n;
   z.xch = 2 * (static_cast<size_t>(panel_wgs(m)) + 1) * NB * 2;
+  z.jxch = (static_cast<size_t>(panel_wgs(m)) + 1) * kJoinEntries * 2;
   z.sync = nblocks + 2;
   size_t gw = 0, gwb = 0, gwf = 0, gwn = 0;
   for (const int64_t nbo : {static_cast<int64_t>(NB2), static_cast<int64_t>(NBO)}) {
@@ -642,6 +800,8 @@ void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w, int64_t target
   w.W2 = a.take<T>(z.w);
   w.xch = a.take<uint64_t>(z.xch);
   w.xch_words = z.xch;
+  w.jxch = a.take<uint64_t>(z.jxch);
+  w.jxch_words = z.jxch;
   w.sync = a.take<unsigned>(z.sync);
   w.gemm_work = a.take<T>(z.gemm_work);
   w.gemm_work_elems = z.gemm_work;
@@ -686,6 +846,9 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   fill_u64_kernel<<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(w.xch_words), 256)), 256, 0, s>>>(
       w.xch, static_cast<int64_t>(w.xch_words));
   URV_LAUNCHED("fill_u64_kernel");
+  fill_u64_kernel<<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(w.jxch_words), 256)), 256, 0, s>>>(
+      w.jxch, static_cast<int64_t>(w.jxch_words));
+  URV_LAUNCHED("fill_u64_kernel");
 
   // Look-ahead: 128-column blocks are factored on a second stream while the
   // other streams apply the previous blocks to the rest of the matrix.
@@ -694,11 +857,11 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   const int nbo = outer_block();
 
   uint32_t panels = 0;  // panel launches so far: exchange tags stay distinct
-  auto panel = [&](int64_t r0, int jbp, T* Tp, int zero_above) -> int {
+  auto panel = [&](int64_t r0, int jbp, T* Tp, int zero_above, const PanelJoin<T>& join) -> int {
     const int64_t mp = m - r0;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
     panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
-                                                 w.tau + r0, Tp, NBO, w.xch, panels * NB, err, zero_above);
+                                                 w.tau + r0, Tp, NBO, w.xch, panels * NB, err, zero_above, join);
     ++panels;
     URV_LAUNCHED("panel_kernel");
     return URV_OK;
@@ -709,7 +872,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     const int jb1 = std::min(jbs, NB), jb2 = jbs - jb1;
     const int64_t mp = m - r0;
     T* Yb = w.Y + r0 + r0 * m;
-    URV_TRY(panel(r0, jb1, Tp, static_cast<int>(r0 - j0)));
+    URV_TRY(panel(r0, jb1, Tp, static_cast<int>(r0 - j0), PanelJoin<T>{}));
     if (jb2 > 0) {
       // first panel's reflectors applied to the second panel's columns:
       // C2 -= Y1 (T1^T (Y1^T C2)), the reduction of Y1^T C2 fused with T1^T
@@ -721,12 +884,25 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
           jb1, jb2, splits, w.gemm_work_b, Tp, NBO, w.W2b, NBO);
       URV_LAUNCHED("reduce_tmul_kernel");
       URV_TRY(gemm<T>(false, false, mp, jb2, jb1, T(-1), Yb, m, w.W2b, NBO, T(1), C2, ldx, nullptr, 0, s2));
-      // the second panel (Y2 zero above it), then the joined T from S12 = Y1^T Y2
-      URV_TRY(panel(r0 + jb1, jb2, Tp + jb1 + static_cast<int64_t>(jb1) * NBO, static_cast<int>(r0 + jb1 - j0)));
-      URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, Yb + static_cast<int64_t>(jb1) * m, m, T(0), w.W1b,
-                      NBO, w.gemm_work_b, w.gemm_work_b_elems, s2));
-      t_join_kernel<T><<<1, 1024, 0, s2>>>(Tp, NBO, jb1, jb2, w.W1b, NBO);
-      URV_LAUNCHED("t_join_kernel");
+      // the second panel (Y2 zero above it), then the joined T from S12 = Y1^T Y2:
+      // formed by the panel itself, or by a GEMM and t_join_kernel
+      T* T2p = Tp + jb1 + static_cast<int64_t>(jb1) * NBO;
+      if (panel_join()) {
+        PanelJoin<T> join;
+        join.Y1 = Yb + jb1;  // rows from the second panel's first row, columns of the first
+        join.ldy1 = m;
+        join.T1 = Tp;
+        join.jb1 = jb1;
+        join.ps = w.jxch;
+        join.sums = w.jxch + w.jxch_words - 2 * kJoinEntries;
+        URV_TRY(panel(r0 + jb1, jb2, T2p, static_cast<int>(r0 + jb1 - j0), join));
+      } else {
+        URV_TRY(panel(r0 + jb1, jb2, T2p, static_cast<int>(r0 + jb1 - j0), PanelJoin<T>{}));
+        URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, Yb + static_cast<int64_t>(jb1) * m, m, T(0),
+                        w.W1b, NBO, w.gemm_work_b, w.gemm_work_b_elems, s2));
+        t_join_kernel<T><<<1, 1024, 0, s2>>>(Tp, NBO, jb1, jb2, w.W1b, NBO);
+        URV_LAUNCHED("t_join_kernel");
+      }
     }
     return URV_OK;
   };
