@@ -277,9 +277,11 @@ int factor_impl(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
   }
   FactorWork w;
   carve_factor(a, m, n, mixed, w);
-  int rc = a.overflow ? URV_EINVAL
-           : mixed    ? run_factor_mixed(A, m, n, q, seed, U, R, V, o, w, s)
-                      : run_factor(A, m, n, q, seed, U, R, V, o, w, s);
+  int rc = a.overflow ? URV_EINVAL : qr_clear_error_flag(w.qr, n, s);
+  if (rc == URV_OK && mixed) rc = qr_clear_error_flag(w.mx.qr, n, s);
+  if (rc == URV_OK)
+    rc = mixed ? run_factor_mixed(A, m, n, q, seed, U, R, V, o, w, s)
+               : run_factor(A, m, n, q, seed, U, R, V, o, w, s);
   if (rc == URV_OK && check_flag) {
     unsigned flag = 0;
     unsigned flag32 = 0;
@@ -340,7 +342,8 @@ int qr_entry(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, i
   a.size = need;
   QrWorkT<T> w;
   qr_work_carve(a, m, n, w);
-  const int rc = qr_pos<T>(X, m, n, ldx, Q, ldq, R, ldr, w, s);
+  int rc = qr_clear_error_flag(w, n, s);
+  if (rc == URV_OK) rc = qr_pos<T>(X, m, n, ldx, Q, ldq, R, ldr, w, s);
   hipFreeAsync(p, s);
   return rc;
 }

@@ -145,9 +145,12 @@ template <class T>
 size_t qr_work_bytes(int64_t m, int64_t n, int64_t target_rows = 0);
 template <class T>
 void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w, int64_t target_rows = 0);
-// Device flag set by a panel whose bounded device-wide wait expired.
+// Device flag set by a panel whose bounded device-wide wait expired.  qr_pos
+// does not clear it: a caller clears it once before a whole computation.
 template <class T>
 unsigned* qr_error_flag(const QrWorkT<T>& w, int64_t n);
+template <class T>
+int qr_clear_error_flag(const QrWorkT<T>& w, int64_t n, hipStream_t s);
 
 // Streams of the current device for the QR pipeline beside the caller's,
 // created on first use and kept for the life of the process (non-blocking,

@@ -35,6 +35,14 @@ constexpr int PANEL_THREADS = 64 * PANEL_WAVES;
 constexpr int kMaxPanelWgs = 240;   // all panel workgroups must be co-resident
 constexpr long kSpinLimit = 1L << 23;   // bounded wait: ~seconds, then give up
 
+// How the panel's waits end.  Normal runs: the spin limit above, tags as
+// published.  Failure tests: a short limit and an expected tag that is never
+// published, so every wait expires (and every kernel still returns).
+struct PanelWait {
+  long spin_limit = kSpinLimit;
+  uint32_t skew = 0;  // added to every expected tag
+};
+
 // Cross-workgroup exchange of the panel.  An FP64 value is published as two
 // 64-bit words (tag << 32 | high half) and (tag << 32 | low half), an FP32
 // value as one word (tag << 32 | bits), with agent-scope atomic stores, which
@@ -61,7 +69,7 @@ __device__ inline void tagged_store(uint64_t* p, uint32_t tag, float v) {
 // workgroup has raised *err.
 template <class T, int K>
 __device__ inline bool tagged_load_all(const uint64_t* const* ptr, int count, uint32_t tag,
-                                       T* out, unsigned* err) {
+                                       T* out, unsigned* err, long spin_limit) {
   constexpr bool kTwo = sizeof(T) == 8;
   long spins = 0;
   for (;;) {
@@ -92,7 +100,7 @@ __device__ inline bool tagged_load_all(const uint64_t* const* ptr, int count, ui
     }
     // the error flag is looked at every 64th poll only: each look is a round trip
     if ((++spins & 63) == 0 &&
-        (spins > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+        (spins > spin_limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
       __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
@@ -193,7 +201,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
                                                      T* __restrict__ Tout, int ldt,
                                                      uint64_t* __restrict__ xch, uint32_t tag0,
                                                      unsigned* __restrict__ err, int zero_above,
-                                                     PanelJoin<T> join) {
+                                                     PanelJoin<T> join, PanelWait pw) {
   using V2 = typename Vec2<T>::type;
   __shared__ T stage[64][NB + 1];
   __shared__ __attribute__((aligned(16))) T Ys[64][NB + 2];  // join: Y1 rows, then S12 and S12 T2
@@ -298,7 +306,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
         cnt += (w < P) ? 1 : 0;
       }
       T vals[6];
-      ok = tagged_load_all<T, 6>(ptrs, cnt, tag, vals, err);
+      ok = tagged_load_all<T, 6>(ptrs, cnt, tag + pw.skew, vals, err, pw.spin_limit);
       piv[0] = vals[0];
       piv[1] = vals[1];
 #pragma unroll
@@ -315,7 +323,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
         cnt += (w < P) ? 1 : 0;
       }
       T vals[4];
-      ok = tagged_load_all<T, 4>(ptrs, cnt, tag, vals, err);
+      ok = tagged_load_all<T, 4>(ptrs, cnt, tag + pw.skew, vals, err, pw.spin_limit);
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         if (u < cnt) sacc += vals[u];
@@ -490,7 +498,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
           cnt += (pw < P) ? 1 : 0;
         }
         T vals[8];
-        ok = tagged_load_all<T, 8>(ptrs, cnt, tagS, vals, err);
+        ok = tagged_load_all<T, 8>(ptrs, cnt, tagS + pw.skew, vals, err, pw.spin_limit);
 #pragma unroll
         for (int u = 0; u < 8; ++u)
           if (u < cnt) total += vals[u];
@@ -513,7 +521,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
 #pragma unroll
     for (int u = 0; u < 8; ++u) ptrs[u] = join.sums + static_cast<int64_t>(threadIdx.x + u * PANEL_THREADS) * 2;
     T v[8];
-    ok = tagged_load_all<T, 8>(ptrs, 8, tagS, v, err);
+    ok = tagged_load_all<T, 8>(ptrs, 8, tagS + pw.skew, v, err, pw.spin_limit);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = threadIdx.x + u * PANEL_THREADS;
@@ -703,29 +711,31 @@ constexpr int NBO = 4 * NB;  // widest outer block; T is stored with this leadin
 // Whether the second panel of a sub-block forms S12 and the joined T itself
 // (URV_PANEL_JOIN=0 uses a GEMM and t_join_kernel instead, for tuning).
 bool panel_join() {
-  static const bool on = [] {
-    const char* e = std::getenv("URV_PANEL_JOIN");
-    return !(e && std::atoi(e) == 0);
-  }();
-  return on;
+  const char* e = std::getenv("URV_PANEL_JOIN");
+  return !(e && std::atoi(e) == 0);
 }
 
 // Whether targets take pairs of 128-column blocks (URV_TARGET_PAIRS=0 turns it off, for tuning).
 bool target_pairs() {
-  static const bool on = [] {
-    const char* e = std::getenv("URV_TARGET_PAIRS");
-    return !(e && std::atoi(e) == 0);
-  }();
-  return on;
+  const char* e = std::getenv("URV_TARGET_PAIRS");
+  return !(e && std::atoi(e) == 0);
 }
 
 // Outer block width used by qr_pos: NB2 or NBO (URV_QR_BLOCK, for tuning).
 int outer_block() {
-  static const int nb = [] {
-    const char* e = std::getenv("URV_QR_BLOCK");
-    return (e && std::atoi(e) == NBO) ? NBO : NB2;
-  }();
-  return nb;
+  const char* e = std::getenv("URV_QR_BLOCK");
+  return (e && std::atoi(e) == NBO) ? NBO : NB2;
+}
+
+// URV_PANEL_EXPIRE_TEST=1 makes every panel wait expire (tests of the failure path).
+PanelWait panel_wait() {
+  PanelWait pw;
+  const char* e = std::getenv("URV_PANEL_EXPIRE_TEST");
+  if (e && std::atoi(e) == 1) {
+    pw.spin_limit = 256;
+    pw.skew = 1;
+  }
+  return pw;
 }
 
 struct QrSizes {
@@ -840,9 +850,9 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   URV_TRY(side_stream(&side));
   std::lock_guard<std::mutex> side_lock(*side.mu);
 
+  // the error flag is cleared by the caller of a whole computation, not here, so
+  // that an expired wait in one QR is still reported after the QRs that follow
   unsigned* err = w.sync + nblocks;
-  fill_u32_kernel<<<static_cast<unsigned>(ceil_div(nblocks + 2, 256)), 256, 0, s>>>(w.sync, nblocks + 2, 0u);
-  URV_LAUNCHED("fill_u32_kernel");
   fill_u64_kernel<<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(w.xch_words), 256)), 256, 0, s>>>(
       w.xch, static_cast<int64_t>(w.xch_words));
   URV_LAUNCHED("fill_u64_kernel");
@@ -855,13 +865,15 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   // The panels occupy a few dozen CUs; the trailing update fills the others.
   const hipStream_t s2 = side.stream;
   const int nbo = outer_block();
+  const PanelWait pwait = panel_wait();
 
   uint32_t panels = 0;  // panel launches so far: exchange tags stay distinct
   auto panel = [&](int64_t r0, int jbp, T* Tp, int zero_above, const PanelJoin<T>& join) -> int {
     const int64_t mp = m - r0;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
     panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
-                                                 w.tau + r0, Tp, NBO, w.xch, panels * NB, err, zero_above, join);
+                                                 w.tau + r0, Tp, NBO, w.xch, panels * NB, err, zero_above, join,
+                                                 pwait);
     ++panels;
     URV_LAUNCHED("panel_kernel");
     return URV_OK;
@@ -1096,12 +1108,20 @@ unsigned* qr_error_flag(const QrWorkT<T>& w, int64_t n) {
   return w.sync + ceil_div(n, NB);
 }
 
+template <class T>
+int qr_clear_error_flag(const QrWorkT<T>& w, int64_t n, hipStream_t s) {
+  fill_u32_kernel<<<1, 64, 0, s>>>(qr_error_flag(w, n), 1, 0u);
+  URV_LAUNCHED("fill_u32_kernel");
+  return URV_OK;
+}
+
 #define URV_QR_INSTANTIATE(T)                                                                 \
   template size_t qr_work_bytes<T>(int64_t, int64_t, int64_t);                                \
   template void qr_work_carve<T>(Arena&, int64_t, int64_t, QrWorkT<T>&, int64_t);            \
   template int qr_pos<T>(T*, int64_t, int64_t, int64_t, T*, int64_t, T*, int64_t,             \
                          const QrWorkT<T>&, hipStream_t, const QrTarget<T>*, int);            \
-  template unsigned* qr_error_flag<T>(const QrWorkT<T>&, int64_t);
+  template unsigned* qr_error_flag<T>(const QrWorkT<T>&, int64_t);                          \
+  template int qr_clear_error_flag<T>(const QrWorkT<T>&, int64_t, hipStream_t);
 URV_QR_INSTANTIATE(double)
 URV_QR_INSTANTIATE(float)
 #undef URV_QR_INSTANTIATE

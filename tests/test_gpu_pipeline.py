@@ -1,0 +1,99 @@
+"""The QR pipeline's alternative schedules and its failure path, through the C ABI.
+
+qr_pos runs the factorisation on several streams (block factorisations,
+near and bulk trailing updates, the products with A, A^T and I).  The
+schedule variants selectable for tuning -- 256-column outer blocks, targets
+per 128-column block instead of per pair, the second panel's T join done by a
+GEMM and a separate kernel -- must give the oracle's factorisation to the
+same 1e-11 tolerance as the default one.
+
+The failure path: with URV_PANEL_EXPIRE_TEST=1 every device-wide wait of the
+panel kernel expects a tag that is never published and gives up after a short
+bounded spin (every kernel still returns).  The blocking urv_factor must then
+report URV_EDEVICE, the outputs must be NaN, and the next call must succeed.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import urv_inputs as gen
+from gpu_helpers import announce, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+URV_EDEVICE = -3
+
+
+@pytest.fixture(scope="module")
+def urv():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1812_06007_amd import urv as u
+
+    u.lib()
+    return u
+
+
+def _parity(urv, orc, m, n, q, seed):
+    A = gen.spectral_matrix(m, n, gen.spectrum("geometric8", n), seed=seed)
+    G = gen.gaussian(n, n, seed + 1)
+    U, R, V = (to_np(t) for t in urv.factor(to_gpu(A), q, G=to_gpu(G)))
+    ref = orc.urv(A, q, G=G)
+    na = np.linalg.norm(A)
+    assert np.linalg.norm(R - ref[1]) <= TOL * na, np.linalg.norm(R - ref[1]) / na
+    ek = np.sqrt(np.cumsum((np.triu(R) ** 2).sum(axis=1)[::-1])[::-1])
+    ek_ref = np.sqrt(np.cumsum((np.triu(ref[1]) ** 2).sum(axis=1)[::-1])[::-1])
+    assert np.max(np.abs(ek - ek_ref)) <= TOL * na
+    assert np.linalg.norm(A - U @ R @ V.T) <= 1e-13 * na
+    assert np.linalg.norm(U.T @ U - np.eye(n)) <= 1e-12 * n
+    assert np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-12 * n
+
+
+@pytest.mark.parametrize("env", [
+    {"URV_QR_BLOCK": "256"},
+    {"URV_TARGET_PAIRS": "0"},
+    {"URV_PANEL_JOIN": "0"},
+    {"URV_QR_BLOCK": "256", "URV_PANEL_JOIN": "0", "URV_TARGET_PAIRS": "0"},
+], ids=["block256", "no_pairs", "no_join", "all_off"])
+@pytest.mark.parametrize("m,n", [(400, 400), (700, 520), (300, 197)])
+def test_schedule_variants_match_oracle(urv, orc, monkeypatch, env, m, n):
+    announce("schedule", env, m, n)
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    _parity(urv, orc, m, n, 2, seed=m * 7 + n)
+
+
+def _blocking_factor(urv, A, q, seed):
+    """urv_factor (FULL, FP64, blocking, packed) straight through the C ABI."""
+    import torch
+
+    m, n = A.shape
+    Ad = to_gpu(A)
+    assert Ad.stride(0) == 1
+    U = urv.empty_colmajor(m, n)
+    R = urv.empty_colmajor(n, n)
+    V = urv.empty_colmajor(n, n)
+    torch.cuda.synchronize()
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    rc = urv.lib().urv_factor(p(Ad), m, n, q, seed, p(U), p(R), p(V))
+    torch.cuda.synchronize()
+    return rc, to_np(U), to_np(R), to_np(V)
+
+
+def test_expired_panel_wait_is_reported_and_recovered(urv, monkeypatch):
+    announce("expired wait")
+    m, n = 600, 300
+    A = gen.spectral_matrix(m, n, gen.spectrum("geometric8", n), seed=77)
+    monkeypatch.setenv("URV_PANEL_EXPIRE_TEST", "1")
+    rc, U, R, V = _blocking_factor(urv, A, 1, 5)
+    assert rc == URV_EDEVICE
+    assert b"wait expired" in urv.lib().urv_last_error()
+    assert np.isnan(R).any() and np.isnan(U).any()
+    monkeypatch.delenv("URV_PANEL_EXPIRE_TEST")
+    rc, U, R, V = _blocking_factor(urv, A, 1, 5)
+    assert rc == 0
+    na = np.linalg.norm(A)
+    assert np.all(np.isfinite(R))
+    assert np.linalg.norm(A - U @ R @ V.T) <= 1e-13 * na
