@@ -121,6 +121,28 @@ struct Vec2<float> {
   static __device__ inline float2 make(float a, float b) { return make_float2(a, b); }
 };
 
+// One 16x16x4 matrix-core step: D = a b + C with operand a given by lane l as
+// element (i = l % 16, k = l / 16), operand b as (k = l / 16, j = l % 16), and
+// entry v of the result held by lane l being D(row(l / 16, v), l % 16).
+template <class T>
+struct PanelMma;
+template <>
+struct PanelMma<double> {
+  typedef double acc __attribute__((ext_vector_type(4)));
+  static __device__ inline acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct PanelMma<float> {
+  typedef float acc __attribute__((ext_vector_type(4)));
+  static __device__ inline acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int v) { return 4 * lk + v; }
+};
+
 // Makes one lane's LDS writes visible to the other lanes of its wave: the
 // lanes run in lockstep, so only the compiler must be kept from moving LDS
 // accesses across this point (and the LDS queue drained).
@@ -131,8 +153,8 @@ __device__ inline void wave_lds_sync() {
 }
 
 // sum over the waves of a workgroup, in a fixed order
-template <class T>
-__device__ inline T sum_waves(const T (*red)[NB], int c) {
+template <class T, int W>
+__device__ inline T sum_waves(const T (*red)[W], int c) {
   T a = 0, b = 0;
 #pragma unroll
   for (int w = 0; w < PANEL_WAVES; w += 2) {
@@ -190,10 +212,19 @@ constexpr int kJoinEntries = NB * NB;
 // for every column c (x_j before the step).  For c >= j these give the norm
 // of the pivot column and v^T x_c; for c < j, where x_c already holds the
 // reflector y_c, they give the Gram entries S(c,j) = y_c^T y_j =
-// x_c(j) + q_c / (alpha - beta), from which workgroup 0 builds T column by
-// column (T(j,j) = tau_j, T(0:j,j) = -tau_j T(0:j,0:j) S(0:j,j)).
+// x_c(j) + q_c / (alpha - beta), from which T is built column by column
+// (T(j,j) = tau_j, T(0:j,j) = -tau_j T(0:j,0:j) S(0:j,j)).
 // Partial sums of a round are added over workgroups in one fixed order, so
 // every workgroup derives bitwise-identical reflectors.
+//
+// Second part (jb2 > 0): the launch also factors the jb2 columns to the right
+// (columns NB.., diagonal rows NB..), on the same rows per workgroup.  While
+// the first part is stored, each workgroup forms its share of
+// W = Y1^T C2 (C2: the second part's columns); W is summed device-wide in
+// three tagged rounds, and each workgroup applies C2 -= Y1 (T1^T W) to its own
+// rows, which stay in registers for the second part.  That part's store forms
+// S12 = Y1^T Y2 and the joined T (as with `join`), so one launch factors a
+// 2 NB-column block: no second launch and no separate update between them.
 template <class T>
 __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X, int64_t ldx,
                                                      int64_t mp, int jb, T* __restrict__ Y,
@@ -201,10 +232,10 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
                                                      T* __restrict__ Tout, int ldt,
                                                      uint64_t* __restrict__ xch, uint32_t tag0,
                                                      unsigned* __restrict__ err, int zero_above,
-                                                     PanelJoin<T> join, PanelWait pw) {
+                                                     PanelJoin<T> join, PanelWait pw, int jb2) {
   using V2 = typename Vec2<T>::type;
   __shared__ T stage[64][NB + 1];
-  __shared__ __attribute__((aligned(16))) T Ys[64][NB + 2];  // join: Y1 rows, then S12 and S12 T2
+  __shared__ __attribute__((aligned(16))) T Ys[64][NB + 2];  // Y1 / C2 rows of a chunk; W or S12 sums
   __shared__ __attribute__((aligned(16))) T bc[PANEL_WAVES][RPT];  // pivot column, per wave
   __shared__ T red[PANEL_WAVES][NB];   // partial q of this workgroup, per wave
   __shared__ T red2[PANEL_WAVES][NB];  // gathered partial sums, per wave
@@ -224,6 +255,9 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
   auto slot = [&](int par, int w, int col) {
     return xch + ((static_cast<int64_t>(par) * (P + 1) + w) * NB + col) * 2;
   };
+  const bool two = jb2 > 0;
+  // every workgroup builds T when the second part needs T1 (W -> T1^T W)
+  const bool build_t = two || wg == 0;
 
   // ---- load through LDS, 64 rows at a time (coalesced along columns)
   constexpr int WAVES_PER_CHUNK = 64 / RPT;
@@ -242,322 +276,450 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
     }
     __syncthreads();
   }
-  if (wg == 0)
-    for (int e = threadIdx.x; e < NB * (NB + 2); e += PANEL_THREADS) (&Tsh[0][0])[e] = T(0);
-  __syncthreads();  // stage is reused below for the rows of R
-  // Column c keeps its reflector unscaled (u_c = (alpha_c - beta_c) y_c below the
-  // pivot) until the panel is done; my_rinv = 1 / (alpha_c - beta_c).
-  T my_rinv = T(0);
-  constexpr int TW = PANEL_WAVES - 1;  // wave of workgroup 0 that builds T
+
+  // a 64 x NB chunk of a column-major matrix, one chunk ahead in registers:
+  // thread t holds row t & 63 of columns (t >> 6) + 8u
+  constexpr int YPT = 64 * NB / PANEL_THREADS;
+  static_assert(PANEL_THREADS % 64 == 0 && YPT * (PANEL_THREADS / 64) == NB, "chunk layout");
+  const int ch_r = threadIdx.x & 63, ch_i = threadIdx.x >> 6;
+  T yv[YPT];
+  auto load_chunk = [&](const T* src, int64_t lds, int ncols, int k) {
+    const int64_t gi = row0 + k * 64 + ch_r;
+    const T* p = src + gi + ch_i * lds;
+    const int64_t step = static_cast<int64_t>(PANEL_THREADS / 64) * lds;
+#pragma unroll
+    for (int u = 0; u < YPT; ++u)
+      yv[u] = (gi < mp && ch_i + u * (PANEL_THREADS / 64) < ncols) ? p[u * step] : T(0);
+  };
+  auto chunk_to_lds = [&](T (*dst)[NB + 2]) {
+#pragma unroll
+    for (int u = 0; u < YPT; ++u) dst[ch_r][ch_i + u * (PANEL_THREADS / 64)] = yv[u];
+  };
 
   bool ok = true;
-  for (int j = 0; j < jb; ++j) {
-    const int par = j & 1;
-    const uint32_t tag = tag0 + static_cast<uint32_t>(j) + 1u;
-    // lo: local index of the pivot row in this wave (uniform); rows r > lo lie below it
-    const int lo = min(max(j - myrow0i, -1), RPT);  // 32-bit, wave-uniform
-    const bool owner = lo >= 0 && lo < RPT;
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+    if (part == 1 && !two) break;
+    const int p0 = part * NB;              // the part's first column and first pivot row
+    const int jbp = part ? jb2 : jb;
+    const uint32_t tagp = tag0 + static_cast<uint32_t>(part * NB);
+    T* Xp = X + static_cast<int64_t>(p0) * ldx;
+    T* Yp = Y + static_cast<int64_t>(p0) * ldy;
+    T* Tp = Tout + p0 + static_cast<int64_t>(p0) * ldt;
+    // S12 with an earlier panel: the first part of this launch, or the caller's
+    const bool fuse = part == 1 || join.Y1 != nullptr;
+    const T* jY1 = part == 1 ? Y : join.Y1;
+    const int64_t jld = part == 1 ? ldy : join.ldy1;
+    T* jT1 = part == 1 ? Tout : join.T1;
+    const int jjb1 = part == 1 ? NB : join.jb1;
 
-    // 1. lane j puts its column, zeroed on and above the pivot row, into LDS
-    if (c == j) {
-      if (lo < 0) {
-#pragma unroll
-        for (int r = 0; r < RPT; r += 2) *reinterpret_cast<V2*>(&bc[g][r]) = Vec2<T>::make(x[r], x[r + 1]);
-      } else {
-#pragma unroll
-        for (int r = 0; r < RPT; r += 2)
-          *reinterpret_cast<V2*>(&bc[g][r]) = Vec2<T>::make(r > lo ? x[r] : T(0), r + 1 > lo ? x[r + 1] : T(0));
-      }
-    }
-    wave_lds_sync();
-    // 2. q_c over this wave's rows below the pivot
-    T qa[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-    for (int r = 0; r < RPT; r += 2) {
-      const V2 xj = *reinterpret_cast<const V2*>(&bc[g][r]);
-      qa[r & 2] += xj.x * x[r];
-      qa[(r & 2) + 1] += xj.y * x[r + 1];
-    }
-    if (owner) {
-      T v = x[0];
-#pragma unroll
-      for (int r = 1; r < RPT; ++r) v = (r == lo) ? x[r] : v;
-      pivrow[c] = v;
-    }
-    red[g][c] = (qa[0] + qa[1]) + (qa[2] + qa[3]);
-    __syncthreads();
-    if (g == 0) {
-      tagged_store(slot(par, wg, c), tag, sum_waves(red, c));
-      if (j >= row0 && j < row0 + RPW) tagged_store(slot(par, P, c), tag, pivrow[c]);
-    }
-    // One wave of workgroup 0 finishes column j-1 of T while the exchange is in flight.
-    if (wg == 0 && g == TW && j > 0) t_column(Tsh, Ssh, tau_sh, j - 1, c);
-    // 3. gather, in one batch where possible: pivot row entries c and j, and this
-    //    wave's share (w = g, g + PANEL_WAVES, ...) of the partial sums
-    T piv[2];
-    T sacc = T(0);
-    {
-      const uint64_t* ptrs[6] = {slot(par, P, c), slot(par, P, j)};
-      int cnt = 2;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int w = g + PANEL_WAVES * u;
-        ptrs[2 + u] = slot(par, w < P ? w : 0, c);
-        cnt += (w < P) ? 1 : 0;
-      }
-      T vals[6];
-      ok = tagged_load_all<T, 6>(ptrs, cnt, tag + pw.skew, vals, err, pw.spin_limit);
-      piv[0] = vals[0];
-      piv[1] = vals[1];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (2 + u < cnt) sacc += vals[2 + u];
-    }
-    for (int w0 = g + 4 * PANEL_WAVES; w0 < P && ok; w0 += 4 * PANEL_WAVES) {
-      const uint64_t* ptrs[4];
-      int cnt = 0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int w = w0 + PANEL_WAVES * u;
-        ptrs[u] = slot(par, w < P ? w : 0, c);
-        cnt += (w < P) ? 1 : 0;
-      }
-      T vals[4];
-      ok = tagged_load_all<T, 4>(ptrs, cnt, tag + pw.skew, vals, err, pw.spin_limit);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (u < cnt) sacc += vals[u];
-    }
-    red2[g][c] = sacc;
-    // every wave failing to gather gives up together
-    if (__syncthreads_or(ok ? 0 : 1)) {
-      ok = false;
-      break;
-    }
-    const T xcj = piv[0];
-    const T alpha = piv[1];
-    const T qc = sum_waves(red2, c);
-    const T sigma2 = sum_waves(red2, j);
-    // 4. reflector of column j
-    T t = T(0), beta = alpha, rinv = T(0);
-    if (sigma2 != T(0)) {
-      const T norm = sqrt(alpha * alpha + sigma2);
-      beta = (alpha >= T(0)) ? -norm : norm;
-      rinv = T(1) / (alpha - beta);
-      t = (beta - alpha) / beta;
-    }
-    if (c == j) my_rinv = rinv;
-    if (g == 0) {
-      // S(c,j) = y_c^T y_j with y_c = my_rinv u_c
-      if (c < j) Ssh[j][c] = my_rinv * (xcj + qc * rinv);
-      if (c == 0) tau_sh[j] = t;
-      // row j of R is final after this step: R(j,c) for c >= j, kept for the end
-      if (wg == 0) stage[j][c] = (c == j) ? beta : xcj - t * (xcj + qc * rinv);
-    }
-    // its action on the columns right of j, below the pivot:
-    //   x_c -= tau (v^T x_c) v  with v = u_j / (alpha - beta),
-    // one FMA per element for every lane: the broadcast column is zero on and
-    // above the pivot row, and coef is zero for c <= j.
-    const bool upd = c > j && t != T(0);
-    const T coef = upd ? t * (xcj + qc * rinv) * rinv : T(0);
-#pragma unroll
-    for (int r = 0; r < RPT; r += 2) {
-      const V2 xj = *reinterpret_cast<const V2*>(&bc[g][r]);
-      x[r] = fma(-coef, xj.x, x[r]);
-      x[r + 1] = fma(-coef, xj.y, x[r + 1]);
-    }
-  }
-  __syncthreads();
+    if (build_t)
+      for (int e = threadIdx.x; e < NB * (NB + 2); e += PANEL_THREADS) (&Tsh[0][0])[e] = T(0);
+    __syncthreads();  // stage is reused below for the rows of R
+    // Column c keeps its reflector unscaled (u_c = (alpha_c - beta_c) y_c below the
+    // pivot) until the panel is done; my_rinv = 1 / (alpha_c - beta_c).
+    T my_rinv = T(0);
+    constexpr int TW = PANEL_WAVES - 1;  // the wave that builds T
 
-  if (ok) {
-    // scale each reflector below its pivot, and put the rows of R (kept in
-    // stage) back on and above the diagonal
-    const int loc = c - myrow0i;
-#pragma unroll
-    for (int r = 0; r < RPT; ++r)
-      if (c < jb && r > loc) x[r] *= my_rinv;
-    if (wg == 0 && myrow0i < jb) {
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int row = myrow0i + r;
-        if (row < jb && c >= row) x[r] = stage[row][c];
-      }
-    }
-  }
+    for (int j = 0; j < jbp && ok; ++j) {
+      const int par = j & 1;
+      const int pr = p0 + j;  // pivot row
+      const uint32_t tag = tagp + static_cast<uint32_t>(j) + 1u;
+      // lo: local index of the pivot row in this wave (uniform); rows r > lo lie below it
+      const int lo = min(max(pr - myrow0i, -1), RPT);  // 32-bit, wave-uniform
+      const bool owner = lo >= 0 && lo < RPT;
 
-  if (!ok) {
-    // A device-side wait gave up: poison the outputs so the failure is visible.
-    const T nan = static_cast<T>(__builtin_nan(""));
+      // 1. lane j puts its column, zeroed on and above the pivot row, into LDS
+      if (c == j) {
+        if (lo < 0) {
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) x[r] = nan;
-    if (g == 0) tau_sh[c] = nan;
-  }
-  __syncthreads();
-
-  // ---- last column of T, then T and tau out
-  if (wg == 0) {
-    if (ok && g == TW && jb > 0) t_column(Tsh, Ssh, tau_sh, jb - 1, c);
-    __syncthreads();
-    for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
-      const int i = e % NB, k = e / NB;
-      if (i < jb && k < jb) Tout[i + static_cast<int64_t>(k) * ldt] = ok ? Tsh[i][k] : static_cast<T>(__builtin_nan(""));
-    }
-    if (threadIdx.x < jb) tau[threadIdx.x] = tau_sh[threadIdx.x];
-  }
-
-  // ---- Y is zero in the zero_above rows above the panel (an earlier panel of the same block)
-  if (wg == 0)
-    for (int e = threadIdx.x; e < zero_above * jb; e += PANEL_THREADS)
-      Y[(e % zero_above) - zero_above + static_cast<int64_t>(e / zero_above) * ldy] = T(0);
-
-  // ---- store: panel in place, and explicit Y (0 above, 1 on the diagonal);
-  // with a join, the partial S12(i, c) = sum over this workgroup's rows of
-  // Y1(r, i) Y2(r, c), thread (wave g, lane c) holding rows i = 8g .. 8g+7
-  const bool fuse = join.Y1 != nullptr;
-  T sacc[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
-  // Y1 rows of the next 64-row chunk, loaded one chunk ahead (element e = threadIdx.x + u * threads)
-  constexpr int YPT = 64 * NB / PANEL_THREADS;
-  T yv[YPT];
-  auto load_y1 = [&](int k) {
+          for (int r = 0; r < RPT; r += 2) *reinterpret_cast<V2*>(&bc[g][r]) = Vec2<T>::make(x[r], x[r + 1]);
+        } else {
 #pragma unroll
-    for (int u = 0; u < YPT; ++u) {
-      const int e = threadIdx.x + u * PANEL_THREADS, r = e & 63, i = e >> 6;
-      const int64_t gi = row0 + k * 64 + r;
-      yv[u] = (gi < mp && i < join.jb1) ? join.Y1[gi + i * join.ldy1] : T(0);
-    }
-  };
-  if (fuse) load_y1(0);
-  for (int k = 0; k < RPW / 64; ++k) {
-    if (g / WAVES_PER_CHUNK == k) {
-      const int r0 = (g % WAVES_PER_CHUNK) * RPT;
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) stage[r0 + r][c] = x[r];
-    }
-    if (fuse) {
-#pragma unroll
-      for (int u = 0; u < YPT; ++u) {
-        const int e = threadIdx.x + u * PANEL_THREADS;
-        Ys[e & 63][e >> 6] = yv[u];
-      }
-      if (k + 1 < RPW / 64) load_y1(k + 1);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * NB; e += PANEL_THREADS) {
-      const int r = e & 63, col = e >> 6;
-      const int64_t gi = row0 + k * 64 + r;
-      if (gi < mp && col < jb) {
-        const T v = stage[r][col];
-        X[gi + col * ldx] = v;
-        Y[gi + col * ldy] = (gi > col) ? v : (gi == col ? T(1) : T(0));
-      }
-    }
-    if (fuse && c < jb) {
-      for (int r = 0; r < 64; ++r) {
-        const int64_t gi = row0 + k * 64 + r;
-        const T sv = stage[r][c];
-        const T y2 = (gi > c) ? sv : (gi == c ? T(1) : T(0));
-        const T* yr = &Ys[r][8 * g];
-#pragma unroll
-        for (int u = 0; u < 8; u += 2) {
-          const V2 yy = *reinterpret_cast<const V2*>(yr + u);
-          sacc[u] += yy.x * y2;
-          sacc[u + 1] += yy.y * y2;
+          for (int r = 0; r < RPT; r += 2)
+            *reinterpret_cast<V2*>(&bc[g][r]) =
+                Vec2<T>::make(r > lo ? x[r] : T(0), r + 1 > lo ? x[r + 1] : T(0));
         }
       }
-    }
-    __syncthreads();
-  }
-  if (!fuse) return;
-
-  // ---- join, round A: publish this workgroup's partial S12
-  const uint32_t tagS = tag0 + static_cast<uint32_t>(NB) + 1u;
+      wave_lds_sync();
+      // 2. q_c over this wave's rows below the pivot
+      T qa[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-  for (int u = 0; u < 8; ++u)
-    tagged_store(join.ps + (static_cast<int64_t>(wg) * kJoinEntries + (8 * g + u) * NB + c) * 2, tagS,
-                 ok ? sacc[u] : static_cast<T>(__builtin_nan("")));
-  // round B: this workgroup sums its share of the entries over all workgroups.
-  // With few entries per workgroup, `parts` threads share an entry, each adding
-  // the partials of workgroups part, part + parts, ...; the parts are then added
-  // in order (a fixed order, so every run gives the same sums).
-  const int per = (kJoinEntries + P - 1) / P;
-  const int e_end = min(kJoinEntries, (wg + 1) * per);
-  const int parts = max(1, min(PANEL_THREADS / per, 8));
-  T* red_b = &red[0][0];  // PANEL_WAVES * NB = 512 values
-  for (int base = wg * per; base < e_end; base += PANEL_THREADS / parts) {
-    const int slot_e = threadIdx.x % (PANEL_THREADS / parts), part = threadIdx.x / (PANEL_THREADS / parts);
-    const int e = base + slot_e;
-    T total = T(0);
-    if (e < e_end && part < parts) {
-      for (int p0 = part; p0 < P && ok; p0 += 8 * parts) {
-        const uint64_t* ptrs[8];
+      for (int r = 0; r < RPT; r += 2) {
+        const V2 xj = *reinterpret_cast<const V2*>(&bc[g][r]);
+        qa[r & 2] += xj.x * x[r];
+        qa[(r & 2) + 1] += xj.y * x[r + 1];
+      }
+      if (owner) {
+        T v = x[0];
+#pragma unroll
+        for (int r = 1; r < RPT; ++r) v = (r == lo) ? x[r] : v;
+        pivrow[c] = v;
+      }
+      red[g][c] = (qa[0] + qa[1]) + (qa[2] + qa[3]);
+      __syncthreads();
+      if (g == 0) {
+        tagged_store(slot(par, wg, c), tag, sum_waves(red, c));
+        if (pr >= row0 && pr < row0 + RPW) tagged_store(slot(par, P, c), tag, pivrow[c]);
+      }
+      // one wave finishes column j-1 of T while the exchange is in flight
+      if (build_t && g == TW && j > 0) t_column(Tsh, Ssh, tau_sh, j - 1, c);
+      // 3. gather, in one batch where possible: pivot row entries c and j, and this
+      //    wave's share (w = g, g + PANEL_WAVES, ...) of the partial sums
+      T piv[2];
+      T sacc = T(0);
+      {
+        const uint64_t* ptrs[6] = {slot(par, P, c), slot(par, P, j)};
+        int cnt = 2;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int w = g + PANEL_WAVES * u;
+          ptrs[2 + u] = slot(par, w < P ? w : 0, c);
+          cnt += (w < P) ? 1 : 0;
+        }
+        T vals[6];
+        ok = tagged_load_all<T, 6>(ptrs, cnt, tag + pw.skew, vals, err, pw.spin_limit);
+        piv[0] = vals[0];
+        piv[1] = vals[1];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (2 + u < cnt) sacc += vals[2 + u];
+      }
+      for (int w0 = g + 4 * PANEL_WAVES; w0 < P && ok; w0 += 4 * PANEL_WAVES) {
+        const uint64_t* ptrs[4];
         int cnt = 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int pw = p0 + u * parts;
-          ptrs[u] = join.ps + (static_cast<int64_t>(pw < P ? pw : 0) * kJoinEntries + e) * 2;
-          cnt += (pw < P) ? 1 : 0;
+        for (int u = 0; u < 4; ++u) {
+          const int w = w0 + PANEL_WAVES * u;
+          ptrs[u] = slot(par, w < P ? w : 0, c);
+          cnt += (w < P) ? 1 : 0;
         }
-        T vals[8];
-        ok = tagged_load_all<T, 8>(ptrs, cnt, tagS + pw.skew, vals, err, pw.spin_limit);
+        T vals[4];
+        ok = tagged_load_all<T, 4>(ptrs, cnt, tag + pw.skew, vals, err, pw.spin_limit);
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (u < cnt) total += vals[u];
+        for (int u = 0; u < 4; ++u)
+          if (u < cnt) sacc += vals[u];
+      }
+      red2[g][c] = sacc;
+      // every wave failing to gather gives up together
+      if (__syncthreads_or(ok ? 0 : 1)) {
+        ok = false;
+        break;
+      }
+      const T xcj = piv[0];
+      const T alpha = piv[1];
+      const T qc = sum_waves(red2, c);
+      const T sigma2 = sum_waves(red2, j);
+      // 4. reflector of column j
+      T t = T(0), beta = alpha, rinv = T(0);
+      if (sigma2 != T(0)) {
+        const T norm = sqrt(alpha * alpha + sigma2);
+        beta = (alpha >= T(0)) ? -norm : norm;
+        rinv = T(1) / (alpha - beta);
+        t = (beta - alpha) / beta;
+      }
+      if (c == j) my_rinv = rinv;
+      if (g == 0) {
+        // S(c,j) = y_c^T y_j with y_c = my_rinv u_c
+        if (c < j) Ssh[j][c] = my_rinv * (xcj + qc * rinv);
+        if (c == 0) tau_sh[j] = t;
+        // row j of R is final after this step: R(j,c) for c >= j, kept for the end
+        if (wg == 0) stage[j][c] = (c == j) ? beta : xcj - t * (xcj + qc * rinv);
+      }
+      // its action on the columns right of j, below the pivot:
+      //   x_c -= tau (v^T x_c) v  with v = u_j / (alpha - beta),
+      // one FMA per element for every lane: the broadcast column is zero on and
+      // above the pivot row, and coef is zero for c <= j.
+      const bool upd = c > j && t != T(0);
+      const T coef = upd ? t * (xcj + qc * rinv) * rinv : T(0);
+#pragma unroll
+      for (int r = 0; r < RPT; r += 2) {
+        const V2 xj = *reinterpret_cast<const V2*>(&bc[g][r]);
+        x[r] = fma(-coef, xj.x, x[r]);
+        x[r + 1] = fma(-coef, xj.y, x[r + 1]);
       }
     }
     __syncthreads();
-    if (part < parts) red_b[part * (PANEL_THREADS / parts) + slot_e] = total;
+
+    if (ok) {
+      // scale each reflector below its pivot, and put the rows of R (kept in
+      // stage) back on and above the diagonal
+      const int loc = p0 + c - myrow0i;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (c < jbp && r > loc) x[r] *= my_rinv;
+      if (wg == 0 && myrow0i < p0 + jbp && myrow0i + RPT > p0) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          const int row = myrow0i + r - p0;
+          if (row >= 0 && row < jbp && c >= row) x[r] = stage[row][c];
+        }
+      }
+    } else {
+      // A device-side wait gave up: poison the outputs so the failure is visible.
+      const T nan = static_cast<T>(__builtin_nan(""));
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) x[r] = nan;
+      if (g == 0) tau_sh[c] = nan;
+    }
     __syncthreads();
-    if (part == 0 && e < e_end) {
-      T sum = T(0);
-      for (int q = 0; q < parts; ++q) sum += red_b[q * (PANEL_THREADS / parts) + slot_e];
-      tagged_store(join.sums + static_cast<int64_t>(e) * 2, tagS, ok ? sum : static_cast<T>(__builtin_nan("")));
+
+    // ---- last column of T, then T and tau out
+    if (build_t) {
+      if (ok && g == TW && jbp > 0) t_column(Tsh, Ssh, tau_sh, jbp - 1, c);
+      __syncthreads();
     }
-  }
-  if (wg != 0) return;
-  // round C (workgroup 0): the sums, then T12 = -T1 (S12 T2) with T2 in Tsh
-  static_assert(kJoinEntries == 8 * PANEL_THREADS, "round C loads eight sums per thread");
-  if (ok) {
-    const uint64_t* ptrs[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) ptrs[u] = join.sums + static_cast<int64_t>(threadIdx.x + u * PANEL_THREADS) * 2;
-    T v[8];
-    ok = tagged_load_all<T, 8>(ptrs, 8, tagS + pw.skew, v, err, pw.spin_limit);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = threadIdx.x + u * PANEL_THREADS;
-      Ys[e / NB][e % NB] = v[u];  // S12(i, c), i = e / NB
+    if (wg == 0) {
+      for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+        const int i = e % NB, k = e / NB;
+        if (i < jbp && k < jbp)
+          Tp[i + static_cast<int64_t>(k) * ldt] = ok ? Tsh[i][k] : static_cast<T>(__builtin_nan(""));
+      }
+      if (threadIdx.x < jbp) tau[p0 + threadIdx.x] = tau_sh[threadIdx.x];
+      // Y is zero in the zero_above rows above the panel (an earlier panel of the same block)
+      for (int e = threadIdx.x; e < zero_above * jbp; e += PANEL_THREADS)
+        Yp[(e % zero_above) - zero_above + static_cast<int64_t>(e / zero_above) * ldy] = T(0);
     }
-  }
-  for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
-    const int i = e % NB, kk = e / NB;
-    Ssh[i][kk] = (i < join.jb1 && kk < join.jb1) ? join.T1[i + static_cast<int64_t>(kk) * ldt] : T(0);
-  }
-  ok = !__syncthreads_or(ok ? 0 : 1);
-  constexpr int PER = NB * NB / PANEL_THREADS;
-  T uacc[PER];
+
+    // ---- store: the part in place, and explicit Y (0 above, 1 on the diagonal).
+    // With S12 to form, the partial S12(i, c) = sum over this workgroup's rows of
+    // Y1(r, i) Y2(r, c); before a second part, the partial W(i, c) = sum of
+    // Y1(r, i) C2(r, c), and the rows of C2 are taken into registers.  Thread
+    // (wave g, lane c) holds entries i = 8g .. 8g+7.
+    const bool form_w = part == 0 && two;
+    // 64 x 64 products on the matrix cores: wave g owns rows ib .. ib+15 and the
+    // two 16-column blocks at cb0 and cb0 + 16 of the result
+    using Mma = PanelMma<T>;
+    const int l16 = c & 15, lk = c >> 4;
+    const int ib = (g >> 1) * 16, cb0 = (g & 1) * 32;
+    typename Mma::acc acc0 = {T(0), T(0), T(0), T(0)}, acc1 = {T(0), T(0), T(0), T(0)};
+    if (fuse) load_chunk(jY1, jld, jjb1, 0);
+    if (form_w) load_chunk(X + static_cast<int64_t>(NB) * ldx, ldx, jb2, 0);
+    for (int k = 0; k < RPW / 64; ++k) {
+      const bool mine = g / WAVES_PER_CHUNK == k;
+      const int r0 = (g % WAVES_PER_CHUNK) * RPT;
+      if (mine) {
 #pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const int e = threadIdx.x + r * PANEL_THREADS, i = e % NB, j = e / NB;
-    T a = 0;
-    if (j < jb)
-      for (int kk = 0; kk <= j; ++kk) a += Ys[i][kk] * Tsh[kk][j];
-    uacc[r] = a;
-  }
-  __syncthreads();
+        for (int r = 0; r < RPT; ++r) stage[r0 + r][c] = x[r];
+      }
+      if (fuse) {
+        chunk_to_lds(Ys);
+        if (k + 1 < RPW / 64) load_chunk(jY1, jld, jjb1, k + 1);
+      }
+      if (form_w) {
+        chunk_to_lds(Ys);
+        if (k + 1 < RPW / 64) load_chunk(X + static_cast<int64_t>(NB) * ldx, ldx, jb2, k + 1);
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < 64 * NB; e += PANEL_THREADS) {
+        const int r = e & 63, col = e >> 6;
+        const int64_t gi = row0 + k * 64 + r, dg = p0 + col;
+        if (gi < mp && col < jbp) {
+          const T v = stage[r][col];
+          Xp[gi + col * ldx] = v;
+          Yp[gi + col * ldy] = (gi > dg) ? v : (gi == dg ? T(1) : T(0));
+        }
+      }
+      if (fuse) {
+        // S12(i, c) += sum over the chunk of Y1(r, i) Y2(r, c); Y2 from the staged
+        // part (v below its diagonal, 1 on it, 0 above and in unused columns)
+#pragma unroll 4
+        for (int ks = 0; ks < 16; ++ks) {
+          const int r = 4 * ks + lk;
+          const int64_t gi = row0 + k * 64 + r;
+          const T a = Ys[r][ib + l16];
+          const int c0 = cb0 + l16, c1 = c0 + 16;
+          const T s0 = stage[r][c0], s1 = stage[r][c1];
+          const T b0 = c0 < jbp ? ((gi > p0 + c0) ? s0 : (gi == p0 + c0 ? T(1) : T(0))) : T(0);
+          const T b1 = c1 < jbp ? ((gi > p0 + c1) ? s1 : (gi == p0 + c1 ? T(1) : T(0))) : T(0);
+          acc0 = Mma::run(a, b0, acc0);
+          acc1 = Mma::run(a, b1, acc1);
+        }
+      }
+      if (form_w) {
+        // W(i, c) += sum over the chunk of Y1(r, i) C2(r, c); Y1 from the staged
+        // part (v below the diagonal, 1 on it, 0 above)
+#pragma unroll 4
+        for (int ks = 0; ks < 16; ++ks) {
+          const int r = 4 * ks + lk;
+          const int64_t gi = row0 + k * 64 + r;
+          const int i = ib + l16;
+          const T sv = stage[r][i];
+          const T a = (gi > i) ? sv : (gi == i ? T(1) : T(0));
+          acc0 = Mma::run(a, Ys[r][cb0 + l16], acc0);
+          acc1 = Mma::run(a, Ys[r][cb0 + 16 + l16], acc1);
+        }
+        if (mine) {
 #pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const int e = threadIdx.x + r * PANEL_THREADS;
-    Ys[e % NB][e / NB] = uacc[r];
-  }
-  __syncthreads();
-  const T nan = static_cast<T>(__builtin_nan(""));
+          for (int r = 0; r < RPT; ++r) x[r] = Ys[r0 + r][c];
+        }
+      }
+      __syncthreads();
+    }
+    if (!fuse && !form_w) return;
+
+    // ---- device-wide sum of the 64 x 64 partials (W, or S12)
+    // round A: publish this workgroup's partial sums
+    const uint32_t tagS = tagp + static_cast<uint32_t>(NB) + 1u;
 #pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const int e = threadIdx.x + r * PANEL_THREADS, i = e % NB, j = e / NB;
-    T a = 0;
-    for (int kk = i; kk < join.jb1; ++kk) a += Ssh[i][kk] * Ys[kk][j];
-    if (i < join.jb1 && j < jb) join.T1[i + static_cast<int64_t>(join.jb1 + j) * ldt] = ok ? -a : nan;
-    if (i < jb && j < join.jb1) join.T1[join.jb1 + i + static_cast<int64_t>(j) * ldt] = T(0);
+    for (int v = 0; v < 4; ++v) {
+      const int i = ib + Mma::row(lk, v);
+      uint64_t* pw0 = join.ps + (static_cast<int64_t>(wg) * kJoinEntries + i * NB + cb0 + l16) * 2;
+      tagged_store(pw0, tagS, ok ? acc0[v] : static_cast<T>(__builtin_nan("")));
+      tagged_store(pw0 + 32, tagS, ok ? acc1[v] : static_cast<T>(__builtin_nan("")));
+    }
+    // round B: this workgroup sums its share of the entries over all workgroups.
+    // With few entries per workgroup, `parts` threads share an entry, each adding
+    // the partials of workgroups part, part + parts, ...; the parts are then added
+    // in order (a fixed order, so every run gives the same sums).
+    {
+      const int per = (kJoinEntries + P - 1) / P;
+      const int e_end = min(kJoinEntries, (wg + 1) * per);
+      const int parts = max(1, min(PANEL_THREADS / per, 8));
+      T* red_b = &red[0][0];  // PANEL_WAVES * NB = 512 values
+      for (int base = wg * per; base < e_end; base += PANEL_THREADS / parts) {
+        const int slot_e = threadIdx.x % (PANEL_THREADS / parts), sub = threadIdx.x / (PANEL_THREADS / parts);
+        const int e = base + slot_e;
+        T total = T(0);
+        if (e < e_end && sub < parts) {
+          for (int p1 = sub; p1 < P && ok; p1 += 8 * parts) {
+            const uint64_t* ptrs[8];
+            int cnt = 0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int src = p1 + u * parts;
+              ptrs[u] = join.ps + (static_cast<int64_t>(src < P ? src : 0) * kJoinEntries + e) * 2;
+              cnt += (src < P) ? 1 : 0;
+            }
+            T vals[8];
+            ok = tagged_load_all<T, 8>(ptrs, cnt, tagS + pw.skew, vals, err, pw.spin_limit);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (u < cnt) total += vals[u];
+          }
+        }
+        __syncthreads();
+        if (sub < parts) red_b[sub * (PANEL_THREADS / parts) + slot_e] = total;
+        __syncthreads();
+        if (sub == 0 && e < e_end) {
+          T sum = T(0);
+          for (int q = 0; q < parts; ++q) sum += red_b[q * (PANEL_THREADS / parts) + slot_e];
+          tagged_store(join.sums + static_cast<int64_t>(e) * 2, tagS, ok ? sum : static_cast<T>(__builtin_nan("")));
+        }
+      }
+    }
+    // round C: the sums into Ys[i][c] (every workgroup for W, workgroup 0 for S12)
+    if (fuse && wg != 0) return;
+    static_assert(kJoinEntries == 8 * PANEL_THREADS, "round C loads eight sums per thread");
+    if (ok) {
+      const uint64_t* ptrs[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ptrs[u] = join.sums + static_cast<int64_t>(threadIdx.x + u * PANEL_THREADS) * 2;
+      T v[8];
+      ok = tagged_load_all<T, 8>(ptrs, 8, tagS + pw.skew, v, err, pw.spin_limit);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = threadIdx.x + u * PANEL_THREADS;
+        Ys[e / NB][e % NB] = v[u];
+      }
+    }
+
+    if (form_w) {
+      ok = !__syncthreads_or(ok ? 0 : 1);
+      // W' = T1^T W into Ssh (Ssh[i][c] = W'(i, c)): a(i, k) = T1(k, i)
+      typename Mma::acc w0 = {T(0), T(0), T(0), T(0)}, w1 = {T(0), T(0), T(0), T(0)};
+#pragma unroll 4
+      for (int ks = 0; ks < 16; ++ks) {
+        const int kk = 4 * ks + lk;
+        const T a = Tsh[kk][ib + l16];
+        w0 = Mma::run(a, Ys[kk][cb0 + l16], w0);
+        w1 = Mma::run(a, Ys[kk][cb0 + 16 + l16], w1);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = ib + Mma::row(lk, v);
+        Ssh[i][cb0 + l16] = w0[v];
+        Ssh[i][cb0 + 16 + l16] = w1[v];
+      }
+      __syncthreads();  // W read from Ys by every wave; W' complete in Ssh
+      // C2 -= Y1 W' on this workgroup's rows, 64 rows at a time: the owners put
+      // their rows of C2 into Ys, each wave updates a 16 x 32 block of the chunk
+      // on the matrix cores, the owners take the rows back
+      load_chunk(Y, ldy, NB, 0);
+      for (int k = 0; k < RPW / 64; ++k) {
+        const bool mine = g / WAVES_PER_CHUNK == k;
+        const int r0 = (g % WAVES_PER_CHUNK) * RPT;
+        if (mine) {
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) Ys[r0 + r][c] = x[r];
+        }
+#pragma unroll
+        for (int u = 0; u < YPT; ++u) stage[ch_r][ch_i + u * (PANEL_THREADS / 64)] = yv[u];
+        if (k + 1 < RPW / 64) load_chunk(Y, ldy, NB, k + 1);
+        __syncthreads();
+        typename Mma::acc u0, u1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = ib + Mma::row(lk, v);
+          u0[v] = Ys[r][cb0 + l16];
+          u1[v] = Ys[r][cb0 + 16 + l16];
+        }
+#pragma unroll 4
+        for (int ks = 0; ks < 16; ++ks) {
+          const int kk = 4 * ks + lk;
+          const T a = -stage[ib + l16][kk];  // a(r, k) = -Y1(r, k)
+          u0 = Mma::run(a, Ssh[kk][cb0 + l16], u0);
+          u1 = Mma::run(a, Ssh[kk][cb0 + 16 + l16], u1);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = ib + Mma::row(lk, v);
+          Ys[r][cb0 + l16] = u0[v];
+          Ys[r][cb0 + 16 + l16] = u1[v];
+        }
+        __syncthreads();
+        if (mine) {
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) x[r] = ok ? Ys[r0 + r][c] : static_cast<T>(__builtin_nan(""));
+        }
+        __syncthreads();
+      }
+      continue;
+    }
+
+    // ---- workgroup 0 joins T: T12 = -T1 (S12 T2) with T2 in Tsh
+    for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+      const int i = e % NB, kk = e / NB;
+      Ssh[i][kk] = (i < jjb1 && kk < jjb1) ? jT1[i + static_cast<int64_t>(kk) * ldt] : T(0);
+    }
+    ok = !__syncthreads_or(ok ? 0 : 1);
+    constexpr int PER = NB * NB / PANEL_THREADS;
+    T uacc[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = threadIdx.x + r * PANEL_THREADS, i = e % NB, j = e / NB;
+      T a = 0;
+      if (j < jbp)
+        for (int kk = 0; kk <= j; ++kk) a += Ys[i][kk] * Tsh[kk][j];
+      uacc[r] = a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = threadIdx.x + r * PANEL_THREADS;
+      Ys[e % NB][e / NB] = uacc[r];
+    }
+    __syncthreads();
+    const T nan = static_cast<T>(__builtin_nan(""));
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = threadIdx.x + r * PANEL_THREADS, i = e % NB, j = e / NB;
+      T a = 0;
+      for (int kk = i; kk < jjb1; ++kk) a += Ssh[i][kk] * Ys[kk][j];
+      if (i < jjb1 && j < jbp) jT1[i + static_cast<int64_t>(jjb1 + j) * ldt] = ok ? -a : nan;
+      if (i < jbp && j < jjb1) jT1[jjb1 + i + static_cast<int64_t>(j) * ldt] = T(0);
+    }
+    return;
   }
 }
 
@@ -715,6 +877,13 @@ bool panel_join() {
   return !(e && std::atoi(e) == 0);
 }
 
+// Whether the two panels of a 128-column sub-block are factored by one launch
+// (URV_PANEL_FUSED=0 launches them separately with an update in between, for tuning).
+bool panel_fused() {
+  const char* e = std::getenv("URV_PANEL_FUSED");
+  return !(e && std::atoi(e) == 0);
+}
+
 // Whether targets take pairs of 128-column blocks (URV_TARGET_PAIRS=0 turns it off, for tuning).
 bool target_pairs() {
   const char* e = std::getenv("URV_TARGET_PAIRS");
@@ -866,15 +1035,16 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   const hipStream_t s2 = side.stream;
   const int nbo = outer_block();
   const PanelWait pwait = panel_wait();
+  const bool fused = panel_fused();
 
   uint32_t panels = 0;  // panel launches so far: exchange tags stay distinct
-  auto panel = [&](int64_t r0, int jbp, T* Tp, int zero_above, const PanelJoin<T>& join) -> int {
+  auto panel = [&](int64_t r0, int jbp, T* Tp, int zero_above, const PanelJoin<T>& join, int jb2) -> int {
     const int64_t mp = m - r0;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
     panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
                                                  w.tau + r0, Tp, NBO, w.xch, panels * NB, err, zero_above, join,
-                                                 pwait);
-    ++panels;
+                                                 pwait, jb2);
+    panels += jb2 > 0 ? 2 : 1;
     URV_LAUNCHED("panel_kernel");
     return URV_OK;
   };
@@ -884,7 +1054,14 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     const int jb1 = std::min(jbs, NB), jb2 = jbs - jb1;
     const int64_t mp = m - r0;
     T* Yb = w.Y + r0 + r0 * m;
-    URV_TRY(panel(r0, jb1, Tp, static_cast<int>(r0 - j0), PanelJoin<T>{}));
+    if (jb2 > 0 && fused) {
+      // both panels in one launch; its exchange of W = Y1^T C2 and S12 uses the join buffers
+      PanelJoin<T> bufs;
+      bufs.ps = w.jxch;
+      bufs.sums = w.jxch + w.jxch_words - 2 * kJoinEntries;
+      return panel(r0, jb1, Tp, static_cast<int>(r0 - j0), bufs, jb2);
+    }
+    URV_TRY(panel(r0, jb1, Tp, static_cast<int>(r0 - j0), PanelJoin<T>{}, 0));
     if (jb2 > 0) {
       // first panel's reflectors applied to the second panel's columns:
       // C2 -= Y1 (T1^T (Y1^T C2)), the reduction of Y1^T C2 fused with T1^T
@@ -907,9 +1084,9 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
         join.jb1 = jb1;
         join.ps = w.jxch;
         join.sums = w.jxch + w.jxch_words - 2 * kJoinEntries;
-        URV_TRY(panel(r0 + jb1, jb2, T2p, static_cast<int>(r0 + jb1 - j0), join));
+        URV_TRY(panel(r0 + jb1, jb2, T2p, static_cast<int>(r0 + jb1 - j0), join, 0));
       } else {
-        URV_TRY(panel(r0 + jb1, jb2, T2p, static_cast<int>(r0 + jb1 - j0), PanelJoin<T>{}));
+        URV_TRY(panel(r0 + jb1, jb2, T2p, static_cast<int>(r0 + jb1 - j0), PanelJoin<T>{}, 0));
         URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, Yb + static_cast<int64_t>(jb1) * m, m, T(0),
                         w.W1b, NBO, w.gemm_work_b, w.gemm_work_b_elems, s2));
         t_join_kernel<T><<<1, 1024, 0, s2>>>(Tp, NBO, jb1, jb2, w.W1b, NBO);
