@@ -108,6 +108,39 @@ __device__ inline bool tagged_load_all(const uint64_t* const* ptr, int count, ui
   }
 }
 
+// A load that sees stores made by other kernels after this one started (an
+// agent-scope atomic load, as the exchange uses): for data that a kernel
+// waited for with a flag rather than by stream order.
+__device__ inline double load_coherent(const double* p) {
+  return __longlong_as_double(static_cast<long long>(
+      __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+}
+__device__ inline float load_coherent(const float* p) {
+  return __uint_as_float(
+      __hip_atomic_load(reinterpret_cast<const unsigned*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Waits until *flag >= value (one lane of the workgroup polls); false, with
+// *err raised, when the bounded wait expires or another workgroup gave up.
+__device__ inline bool wait_flag_geq(const unsigned* flag, unsigned value, unsigned* err, long spin_limit) {
+  long spins = 0;
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < value) {
+    if ((++spins & 63) == 0 &&
+        (spins > spin_limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+      __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+// Raises a flag for a kernel that is already running: launched after the work
+// the flag stands for, on the same stream.
+__global__ void signal_kernel(unsigned* flag, unsigned value) {
+  if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <class T>
 struct Vec2;
 template <>
@@ -232,7 +265,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
                                                      T* __restrict__ Tout, int ldt,
                                                      uint64_t* __restrict__ xch, uint32_t tag0,
                                                      unsigned* __restrict__ err, int zero_above,
-                                                     PanelJoin<T> join, PanelWait pw, int jb2) {
+                                                     PanelJoin<T> join, PanelWait pw, int jb2,
+                                                     const unsigned* __restrict__ wait_flag) {
   using V2 = typename Vec2<T>::type;
   __shared__ T stage[64][NB + 1];
   __shared__ __attribute__((aligned(16))) T Ys[64][NB + 2];  // Y1 / C2 rows of a chunk; W or S12 sums
@@ -259,6 +293,16 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
   // every workgroup builds T when the second part needs T1 (W -> T1^T W)
   const bool build_t = two || wg == 0;
 
+  // ---- launched ahead of the update of its columns: wait for that update's flag,
+  // then read X with loads that see it
+  bool ok = true;
+  const bool waited = wait_flag != nullptr;
+  if (waited) {
+    if (threadIdx.x == 0) ok = wait_flag_geq(wait_flag, 1u, err, pw.spin_limit);
+    ok = !__syncthreads_or(ok ? 0 : 1);
+  }
+  auto load_x = [&](const T* p) -> T { return waited ? load_coherent(p) : *p; };
+
   // ---- load through LDS, 64 rows at a time (coalesced along columns)
   constexpr int WAVES_PER_CHUNK = 64 / RPT;
   T x[RPT];
@@ -266,7 +310,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
     for (int e = threadIdx.x; e < 64 * NB; e += PANEL_THREADS) {
       const int r = e & 63, col = e >> 6;
       const int64_t gi = row0 + k * 64 + r;
-      stage[r][col] = (gi < mp && col < jb) ? X[gi + col * ldx] : T(0);
+      stage[r][col] = (gi < mp && col < jb) ? load_x(X + gi + col * ldx) : T(0);
     }
     __syncthreads();
     if (g / WAVES_PER_CHUNK == k) {
@@ -283,20 +327,27 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
   static_assert(PANEL_THREADS % 64 == 0 && YPT * (PANEL_THREADS / 64) == NB, "chunk layout");
   const int ch_r = threadIdx.x & 63, ch_i = threadIdx.x >> 6;
   T yv[YPT];
-  auto load_chunk = [&](const T* src, int64_t lds, int ncols, int k) {
+  auto load_chunk = [&](const T* src, int64_t lds, int ncols, int k, bool coherent) {
     const int64_t gi = row0 + k * 64 + ch_r;
     const T* p = src + gi + ch_i * lds;
     const int64_t step = static_cast<int64_t>(PANEL_THREADS / 64) * lds;
 #pragma unroll
     for (int u = 0; u < YPT; ++u)
-      yv[u] = (gi < mp && ch_i + u * (PANEL_THREADS / 64) < ncols) ? p[u * step] : T(0);
+      yv[u] = (gi < mp && ch_i + u * (PANEL_THREADS / 64) < ncols)
+                  ? (coherent ? load_coherent(p + u * step) : p[u * step])
+                  : T(0);
   };
   auto chunk_to_lds = [&](T (*dst)[NB + 2]) {
 #pragma unroll
     for (int u = 0; u < YPT; ++u) dst[ch_r][ch_i + u * (PANEL_THREADS / 64)] = yv[u];
   };
 
-  bool ok = true;
+  // the rows of the wave that holds the pivot row, transposed (the column loop
+  // does not use Ys otherwise)
+  constexpr int OWN_LD = RPT + 2;
+  static_assert(64 * OWN_LD <= 64 * (NB + 2), "transposed rows fit in Ys");
+  T* const own = &Ys[0][0];
+
 #pragma unroll
   for (int part = 0; part < 2; ++part) {
     if (part == 1 && !two) break;
@@ -329,32 +380,38 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
       const int lo = min(max(pr - myrow0i, -1), RPT);  // 32-bit, wave-uniform
       const bool owner = lo >= 0 && lo < RPT;
 
-      // 1. lane j puts its column, zeroed on and above the pivot row, into LDS
-      if (c == j) {
-        if (lo < 0) {
+      // 1. the pivot column of this wave's rows, zeroed on and above the pivot
+      //    row, into LDS.  Below the pivot, lane j copies it to bc[g].  The wave
+      //    holding the pivot row stores all its rows transposed (lane c at
+      //    own[c * OWN_LD ..]), takes the pivot row entry of every column from
+      //    there, and lane j zeroes its own copy down to the pivot.  A wave above
+      //    the pivot has nothing below it and skips the products.
+      const bool below = lo < RPT;  // wave-uniform: some of its rows lie below the pivot
+      const T* colp = &bc[g][0];
+      if (lo < 0) {
+        if (c == j) {
 #pragma unroll
           for (int r = 0; r < RPT; r += 2) *reinterpret_cast<V2*>(&bc[g][r]) = Vec2<T>::make(x[r], x[r + 1]);
-        } else {
-#pragma unroll
-          for (int r = 0; r < RPT; r += 2)
-            *reinterpret_cast<V2*>(&bc[g][r]) =
-                Vec2<T>::make(r > lo ? x[r] : T(0), r + 1 > lo ? x[r + 1] : T(0));
         }
+      } else if (owner) {
+        T* mine_t = own + c * OWN_LD;
+#pragma unroll
+        for (int r = 0; r < RPT; r += 2) *reinterpret_cast<V2*>(mine_t + r) = Vec2<T>::make(x[r], x[r + 1]);
+        pivrow[c] = mine_t[lo];
+        if (c == j)
+          for (int r = 0; r <= lo; ++r) mine_t[r] = T(0);
+        colp = own + j * OWN_LD;
       }
       wave_lds_sync();
       // 2. q_c over this wave's rows below the pivot
       T qa[4] = {T(0), T(0), T(0), T(0)};
+      if (below) {
 #pragma unroll
-      for (int r = 0; r < RPT; r += 2) {
-        const V2 xj = *reinterpret_cast<const V2*>(&bc[g][r]);
-        qa[r & 2] += xj.x * x[r];
-        qa[(r & 2) + 1] += xj.y * x[r + 1];
-      }
-      if (owner) {
-        T v = x[0];
-#pragma unroll
-        for (int r = 1; r < RPT; ++r) v = (r == lo) ? x[r] : v;
-        pivrow[c] = v;
+        for (int r = 0; r < RPT; r += 2) {
+          const V2 xj = *reinterpret_cast<const V2*>(colp + r);
+          qa[r & 2] += xj.x * x[r];
+          qa[(r & 2) + 1] += xj.y * x[r + 1];
+        }
       }
       red[g][c] = (qa[0] + qa[1]) + (qa[2] + qa[3]);
       __syncthreads();
@@ -432,11 +489,13 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
       // above the pivot row, and coef is zero for c <= j.
       const bool upd = c > j && t != T(0);
       const T coef = upd ? t * (xcj + qc * rinv) * rinv : T(0);
+      if (below) {
 #pragma unroll
-      for (int r = 0; r < RPT; r += 2) {
-        const V2 xj = *reinterpret_cast<const V2*>(&bc[g][r]);
-        x[r] = fma(-coef, xj.x, x[r]);
-        x[r + 1] = fma(-coef, xj.y, x[r + 1]);
+        for (int r = 0; r < RPT; r += 2) {
+          const V2 xj = *reinterpret_cast<const V2*>(colp + r);
+          x[r] = fma(-coef, xj.x, x[r]);
+          x[r + 1] = fma(-coef, xj.y, x[r + 1]);
+        }
       }
     }
     __syncthreads();
@@ -493,8 +552,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
     const int l16 = c & 15, lk = c >> 4;
     const int ib = (g >> 1) * 16, cb0 = (g & 1) * 32;
     typename Mma::acc acc0 = {T(0), T(0), T(0), T(0)}, acc1 = {T(0), T(0), T(0), T(0)};
-    if (fuse) load_chunk(jY1, jld, jjb1, 0);
-    if (form_w) load_chunk(X + static_cast<int64_t>(NB) * ldx, ldx, jb2, 0);
+    if (fuse) load_chunk(jY1, jld, jjb1, 0, false);
+    if (form_w) load_chunk(X + static_cast<int64_t>(NB) * ldx, ldx, jb2, 0, waited);
     for (int k = 0; k < RPW / 64; ++k) {
       const bool mine = g / WAVES_PER_CHUNK == k;
       const int r0 = (g % WAVES_PER_CHUNK) * RPT;
@@ -504,11 +563,11 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
       }
       if (fuse) {
         chunk_to_lds(Ys);
-        if (k + 1 < RPW / 64) load_chunk(jY1, jld, jjb1, k + 1);
+        if (k + 1 < RPW / 64) load_chunk(jY1, jld, jjb1, k + 1, false);
       }
       if (form_w) {
         chunk_to_lds(Ys);
-        if (k + 1 < RPW / 64) load_chunk(X + static_cast<int64_t>(NB) * ldx, ldx, jb2, k + 1);
+        if (k + 1 < RPW / 64) load_chunk(X + static_cast<int64_t>(NB) * ldx, ldx, jb2, k + 1, waited);
       }
       __syncthreads();
       for (int e = threadIdx.x; e < 64 * NB; e += PANEL_THREADS) {
@@ -645,7 +704,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
       // C2 -= Y1 W' on this workgroup's rows, 64 rows at a time: the owners put
       // their rows of C2 into Ys, each wave updates a 16 x 32 block of the chunk
       // on the matrix cores, the owners take the rows back
-      load_chunk(Y, ldy, NB, 0);
+      load_chunk(Y, ldy, NB, 0, false);
       for (int k = 0; k < RPW / 64; ++k) {
         const bool mine = g / WAVES_PER_CHUNK == k;
         const int r0 = (g % WAVES_PER_CHUNK) * RPT;
@@ -655,7 +714,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
         }
 #pragma unroll
         for (int u = 0; u < YPT; ++u) stage[ch_r][ch_i + u * (PANEL_THREADS / 64)] = yv[u];
-        if (k + 1 < RPW / 64) load_chunk(Y, ldy, NB, k + 1);
+        if (k + 1 < RPW / 64) load_chunk(Y, ldy, NB, k + 1, false);
         __syncthreads();
         typename Mma::acc u0, u1;
 #pragma unroll
@@ -884,6 +943,13 @@ bool panel_fused() {
   return !(e && std::atoi(e) == 0);
 }
 
+// Whether a block's factorisation is queued ahead of the update of its columns
+// and waits for it on the device (URV_PANEL_EARLY=0 orders them on one stream, for tuning).
+bool panel_early() {
+  const char* e = std::getenv("URV_PANEL_EARLY");
+  return !(e && std::atoi(e) == 0);
+}
+
 // Whether targets take pairs of 128-column blocks (URV_TARGET_PAIRS=0 turns it off, for tuning).
 bool target_pairs() {
   const char* e = std::getenv("URV_TARGET_PAIRS");
@@ -1028,6 +1094,10 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   fill_u64_kernel<<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(w.jxch_words), 256)), 256, 0, s>>>(
       w.jxch, static_cast<int64_t>(w.jxch_words));
   URV_LAUNCHED("fill_u64_kernel");
+  // per-block flags: "the columns of the block at column b * NB are up to date"
+  unsigned* ready = w.sync;
+  fill_u32_kernel<<<static_cast<unsigned>(ceil_div(nblocks, 256)), 256, 0, s>>>(ready, nblocks, 0u);
+  URV_LAUNCHED("fill_u32_kernel");
 
   // Look-ahead: 128-column blocks are factored on a second stream while the
   // other streams apply the previous blocks to the rest of the matrix.
@@ -1038,19 +1108,21 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   const bool fused = panel_fused();
 
   uint32_t panels = 0;  // panel launches so far: exchange tags stay distinct
-  auto panel = [&](int64_t r0, int jbp, T* Tp, int zero_above, const PanelJoin<T>& join, int jb2) -> int {
+  auto panel = [&](int64_t r0, int jbp, T* Tp, int zero_above, const PanelJoin<T>& join, int jb2,
+                   const unsigned* wf) -> int {
     const int64_t mp = m - r0;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
     panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
                                                  w.tau + r0, Tp, NBO, w.xch, panels * NB, err, zero_above, join,
-                                                 pwait, jb2);
+                                                 pwait, jb2, wf);
     panels += jb2 > 0 ? 2 : 1;
     URV_LAUNCHED("panel_kernel");
     return URV_OK;
   };
   // Householder vectors, tau and T (at Tp, ld NBO) of the sub-block of width
-  // jbs at row/column r0 of the outer block starting at j0, on the side stream.
-  auto factor_sub = [&](int64_t j0, int64_t r0, int jbs, T* Tp) -> int {
+  // jbs at row/column r0 of the outer block starting at j0, on the side stream;
+  // with wf, its first launch waits for that flag before reading its columns.
+  auto factor_sub = [&](int64_t j0, int64_t r0, int jbs, T* Tp, const unsigned* wf) -> int {
     const int jb1 = std::min(jbs, NB), jb2 = jbs - jb1;
     const int64_t mp = m - r0;
     T* Yb = w.Y + r0 + r0 * m;
@@ -1059,9 +1131,9 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       PanelJoin<T> bufs;
       bufs.ps = w.jxch;
       bufs.sums = w.jxch + w.jxch_words - 2 * kJoinEntries;
-      return panel(r0, jb1, Tp, static_cast<int>(r0 - j0), bufs, jb2);
+      return panel(r0, jb1, Tp, static_cast<int>(r0 - j0), bufs, jb2, wf);
     }
-    URV_TRY(panel(r0, jb1, Tp, static_cast<int>(r0 - j0), PanelJoin<T>{}, 0));
+    URV_TRY(panel(r0, jb1, Tp, static_cast<int>(r0 - j0), PanelJoin<T>{}, 0, wf));
     if (jb2 > 0) {
       // first panel's reflectors applied to the second panel's columns:
       // C2 -= Y1 (T1^T (Y1^T C2)), the reduction of Y1^T C2 fused with T1^T
@@ -1084,9 +1156,9 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
         join.jb1 = jb1;
         join.ps = w.jxch;
         join.sums = w.jxch + w.jxch_words - 2 * kJoinEntries;
-        URV_TRY(panel(r0 + jb1, jb2, T2p, static_cast<int>(r0 + jb1 - j0), join, 0));
+        URV_TRY(panel(r0 + jb1, jb2, T2p, static_cast<int>(r0 + jb1 - j0), join, 0, nullptr));
       } else {
-        URV_TRY(panel(r0 + jb1, jb2, T2p, static_cast<int>(r0 + jb1 - j0), PanelJoin<T>{}, 0));
+        URV_TRY(panel(r0 + jb1, jb2, T2p, static_cast<int>(r0 + jb1 - j0), PanelJoin<T>{}, 0, nullptr));
         URV_TRY(gemm<T>(true, false, jb1, jb2, mp, T(1), Yb, m, Yb + static_cast<int64_t>(jb1) * m, m, T(0),
                         w.W1b, NBO, w.gemm_work_b, w.gemm_work_b_elems, s2));
         t_join_kernel<T><<<1, 1024, 0, s2>>>(Tp, NBO, jb1, jb2, w.W1b, NBO);
@@ -1097,7 +1169,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   };
   // The outer block at column j0: sub-blocks A and B, B updated by A in
   // between, and T = [[T_A, -T_A (Y_A^T Y_B) T_B], [0, T_B]].
-  auto factor_block = [&](int64_t j0) -> int {
+  auto factor_block = [&](int64_t j0, const unsigned* wf) -> int {
     const int jbo = static_cast<int>(std::min<int64_t>(nbo, n - j0));
     const int ja = std::min(jbo, NB2), jbb = jbo - ja;
     const int64_t mp = m - j0;
@@ -1105,7 +1177,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     // Y is kept zero above the diagonal back to the start of the pair of
     // 128-column blocks, so that the targets can take a pair at once
     const int64_t jz = j0 - (j0 / NB2 % 2) * NB2;
-    URV_TRY(factor_sub(jz, j0, ja, Tb));
+    URV_TRY(factor_sub(jz, j0, ja, Tb, wf));
     if (jbb > 0) {
       const T* Ya = w.Y + j0 + j0 * m;
       T* CB = X + j0 + (j0 + ja) * ldx;
@@ -1117,7 +1189,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       URV_LAUNCHED("reduce_tmul_kernel");
       URV_TRY(gemm<T>(false, false, mp, jbb, ja, T(-1), Ya, m, w.W2b, NBO, T(1), CB, ldx, nullptr, 0, s2));
       T* TB = Tb + ja + static_cast<int64_t>(ja) * NBO;
-      URV_TRY(factor_sub(jz, j0 + ja, jbb, TB));
+      URV_TRY(factor_sub(jz, j0 + ja, jbb, TB, nullptr));
       // Y_B is zero in the rows of A, so S_AB = Y_A^T Y_B over all mp rows
       URV_TRY(gemm<T>(true, false, ja, jbb, mp, T(1), Ya, m, Ya + static_cast<int64_t>(ja) * m, m, T(0),
                       w.W1b, NBO, w.gemm_work_b, w.gemm_work_b_elems, s2));
@@ -1207,15 +1279,20 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     return URV_OK;
   };
 
-  // Streams: s2 factors block k, then updates block k+1's columns and factors
-  // it (the critical chain); s updates block k+2's columns once block k is
-  // factored; s4 updates the rest; s3 applies block k to the targets.  A
-  // stream waits only on events recorded at least one block earlier, except
-  // the chain itself.
+  // Streams: s2 factors the blocks, one after the other (the critical chain);
+  // s updates the next block's columns once block k is factored, raises that
+  // block's flag, and updates the block after next; s4 updates the rest; s3
+  // applies block k to the targets.  The factorisation of block k+1 is queued
+  // on s2 right behind block k's and waits for its flag on the device, so its
+  // workgroups take their CUs while the update runs.  The flag is always
+  // queued before the factorisation that waits for it, so the two can share a
+  // hardware queue.  With URV_PANEL_EARLY=0, s2 updates the next block's
+  // columns itself, between the factorisations.
+  const bool early = panel_early();
   URV_HIP(hipEventRecord(side.ev_next, s));      // the cleared flags and slots
   URV_HIP(hipStreamWaitEvent(s2, side.ev_next, 0));
   if (ntargets > 0) URV_HIP(hipStreamWaitEvent(s3, side.ev_next, 0));  // targets written before the call
-  URV_TRY(factor_block(0));
+  URV_TRY(factor_block(0, nullptr));
   URV_HIP(hipEventRecord(side.ev_fact, s2));
   bool near_pending = false, bulk_pending = false;
   for (int64_t j0 = 0; j0 < n; j0 += nbo) {
@@ -1227,10 +1304,19 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     const int64_t j1 = j0 + nbo;
     if (j1 >= n) break;
     const int64_t nn = std::min<int64_t>(nbo, n - j1);
-    // the chain: block j1's columns (the previous block's share came from s), then its factorisation
-    if (near_pending) URV_HIP(hipStreamWaitEvent(s2, side.ev_near, 0));
-    URV_TRY(apply_block(j0, j1, nn, kOnPanelStream));
-    URV_TRY(factor_block(j1));
+    if (early) {
+      // block j1's columns on s (after the previous block's share, also on s), its flag,
+      // then its factorisation on s2
+      URV_TRY(apply_block(j0, j1, nn, kOnCallerStream));
+      signal_kernel<<<1, 64, 0, s>>>(ready + j1 / NB, 1u);
+      URV_LAUNCHED("signal_kernel");
+      URV_TRY(factor_block(j1, ready + j1 / NB));
+    } else {
+      // the chain: block j1's columns (the previous block's share came from s), then its factorisation
+      if (near_pending) URV_HIP(hipStreamWaitEvent(s2, side.ev_near, 0));
+      URV_TRY(apply_block(j0, j1, nn, kOnPanelStream));
+      URV_TRY(factor_block(j1, nullptr));
+    }
     URV_HIP(hipEventRecord(side.ev_fact, s2));
     const int64_t j2 = j1 + nn;
     if (j2 >= n) continue;

@@ -5,7 +5,8 @@ near and bulk trailing updates, the products with A, A^T and I).  The
 schedule variants selectable for tuning -- 256-column outer blocks, targets
 per 128-column block instead of per pair, the two panels of a 128-column
 block in separate launches with GEMM updates between them, and with the T
-join done by a GEMM and a separate kernel -- must give the oracle's factorisation to the
+join done by a GEMM and a separate kernel, and each block's factorisation
+queued behind the update of its columns instead of ahead of it -- must give the oracle's factorisation to the
 same 1e-11 tolerance as the default one.
 
 The failure path: with URV_PANEL_EXPIRE_TEST=1 every device-wide wait of the
@@ -57,8 +58,10 @@ def _parity(urv, orc, m, n, q, seed):
     {"URV_TARGET_PAIRS": "0"},
     {"URV_PANEL_FUSED": "0"},
     {"URV_PANEL_FUSED": "0", "URV_PANEL_JOIN": "0"},
-    {"URV_QR_BLOCK": "256", "URV_PANEL_FUSED": "0", "URV_PANEL_JOIN": "0", "URV_TARGET_PAIRS": "0"},
-], ids=["block256", "no_pairs", "separate_panels", "no_join", "all_off"])
+    {"URV_PANEL_EARLY": "0"},
+    {"URV_QR_BLOCK": "256", "URV_PANEL_FUSED": "0", "URV_PANEL_JOIN": "0", "URV_TARGET_PAIRS": "0",
+     "URV_PANEL_EARLY": "0"},
+], ids=["block256", "no_pairs", "separate_panels", "no_join", "in_order", "all_off"])
 @pytest.mark.parametrize("m,n", [(400, 400), (700, 520), (300, 197)])
 def test_schedule_variants_match_oracle(urv, orc, monkeypatch, env, m, n):
     announce("schedule", env, m, n)
