@@ -78,7 +78,10 @@ def qr_adjoint(Q, R, dQ=None, dR=None) -> np.ndarray:
     n = R.shape[0]
     M = np.zeros((n, n))
     if dR is not None:
-        M += R @ np.asarray(dR, dtype=np.float64).T
+        # R's strictly lower entries are structural zeros, not functions of X,
+        # so only the upper triangle of Rb carries a derivative (the lower
+        # triangle of M reads only that part of Rb in any case)
+        M += R @ np.triu(np.asarray(dR, dtype=np.float64)).T
     B = np.zeros_like(Q)
     if dQ is not None:
         dQ = np.asarray(dQ, dtype=np.float64)

@@ -72,7 +72,7 @@ def test_qr_adjoint_finite_differences(m, n):
     r = _rng(m * 10 + n)
     X = r.standard_normal((m, n))
     Cq = r.standard_normal((m, n))
-    Cr = np.triu(r.standard_normal((n, n)))
+    Cr = r.standard_normal((n, n))
 
     def f(Z):
         Q, R = oracle.qr_pos(Z)
@@ -111,7 +111,8 @@ def _linear_fd_error(m, n, q, variant, seed):
     r = _rng(seed)
     A = r.standard_normal((m, n))
     G = r.standard_normal((n, n))
-    Cu, Cr, Cv = r.standard_normal((m, n)), np.triu(r.standard_normal((n, n))), r.standard_normal((n, n))
+    # Cr is full: R's strictly lower entries are constant zeros and must get no weight
+    Cu, Cr, Cv = r.standard_normal((m, n)), r.standard_normal((n, n)), r.standard_normal((n, n))
 
     def f(Z):
         U, R, V, _ = adjoint.forward(Z, G, q, variant)
