@@ -44,9 +44,11 @@ typedef enum {
   URV_REORTH_NONE = 2  /* (A^T A)^q G then a single Qpos; only for small q and mild spectra */
 } urv_variant;
 
-/* Arithmetic of the factorisation.  A, U, R, V are FP64 in every mode. */
+/* Arithmetic of the factorisation.  A, U, R, V are FP64 in every mode of
+ * urv_factor_ex; URV_FP32 is taken only by the derivative entry points below. */
 typedef enum {
   URV_FP64 = 0,       /* everything in FP64 */
+  URV_FP32 = 1,       /* everything in FP32 (derivative entry points only) */
   URV_MIXED_BF16 = 2, /* power-step products on BF16 MFMA with FP32 accumulation, QR of the
                          power iterates in FP32, V re-orthonormalised and the final
                          A V = U R in FP64 */
@@ -146,6 +148,93 @@ int urv_qr_pos_f32(float* X, int64_t m, int64_t n, int64_t ldx, float* Q, int64_
  */
 int urv_metrics(const double* A, int64_t m, int64_t n, const double* U, const double* R,
                 const double* V, double* out, double* ek, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Derivative of the factorisation with G held fixed (not in the paper).
+ *
+ * The forward chain is that of Section 3 (eqs. power and powerqr) from a
+ * given n x n starting matrix G: V_0 = G; for t = 1..q, X_t = A V_{t-1},
+ * (W_t, Rw_t) = Qpos(X_t), Y_t = A^T W_t, (V_t, Rv_t) = Qpos(Y_t) (HALF:
+ * Y_t = A^T X_t); then A V_q = U R and V = V_q.  q == 0 takes V = Qpos(G), a
+ * constant.  The reverse sweep applies the adjoint of each product and of each
+ * QR (for X = Q R with m >= n and diag(R) != 0: Xb = (Qb + Q S) R^{-T}, S
+ * the symmetric matrix from the lower triangle of R Rb^T - Qb^T Q, after
+ * Walter & Lehmann 2018 and Seeger et al. 2017) in the opposite order.
+ *
+ * All matrices are packed column-major device arrays (ld = rows) of the type
+ * opts->precision selects: double (URV_FP64) or float (URV_FP32).  The
+ * derivative exists where every QR of the chain has full column rank; where a
+ * diagonal entry of an R is zero the outputs are not finite.  Every call is
+ * asynchronous on opts->stream; a device-side wait of a QR that expired leaves
+ * NaN in the outputs.  Argument errors return URV_EINVAL before any launch;
+ * m beyond the QR panel's row limit returns URV_ENOTSUP.
+ * ---------------------------------------------------------------------- */
+
+/* What the tape between urv_factor_tape and urv_factor_backward keeps. */
+typedef enum {
+  URV_TAPE_ALL = 0,  /* every Q and R of the power steps: the reverse sweep recomputes nothing */
+  URV_TAPE_V = 1,    /* the V_t only: each power step is recomputed from its V_{t-1} */
+  URV_TAPE_NONE = 2  /* nothing: each V_{t-1} is recomputed from G as well (q(q+1)/2 steps) */
+} urv_tape_mode;
+
+typedef struct {
+  int32_t precision;   /* URV_FP64 or URV_FP32 */
+  int32_t variant;     /* URV_REORTH_FULL or URV_REORTH_HALF */
+  int32_t tape_mode;   /* urv_tape_mode; forward and backward must use the same value */
+  int32_t accumulate;  /* urv_factor_backward: nonzero adds to dA instead of overwriting it */
+  void* stream;        /* hipStream_t; NULL = default stream */
+  void* workspace;     /* optional device scratch of urv_grad_workspace_size bytes; NULL = the
+                          library allocates on the stream */
+  size_t workspace_bytes;
+} urv_grad_opts;
+
+/* Defaults: FP64, FULL, URV_TAPE_ALL, overwrite, default stream, library workspace. */
+void urv_grad_opts_init(urv_grad_opts* opts);
+
+/* Bytes of the tape for these arguments (0 for q == 0, URV_TAPE_NONE or bad arguments). */
+size_t urv_tape_bytes(int64_t m, int64_t n, int32_t q, const urv_grad_opts* opts);
+
+/* Bytes of scratch a derivative entry point needs (0 for n == 0 or bad arguments). */
+size_t urv_grad_workspace_size(int64_t m, int64_t n, int32_t q, const urv_grad_opts* opts);
+
+/*
+ * Forward pass: U (m x n), R (n x n, strictly lower part 0), V (n x n) of the
+ * chain above from A (m x n, m >= n, read only) and G (n x n, read only), and
+ * the tape (urv_tape_bytes, caller-owned, opaque) that urv_factor_backward
+ * reads.  The tape must stay unmodified, together with A, G, U, R and V,
+ * until the backward call has run.
+ */
+int urv_factor_tape(const void* A, int64_t m, int64_t n, int32_t q, const void* G, void* U, void* R,
+                    void* V, void* tape, const urv_grad_opts* opts);
+
+/*
+ * Reverse pass: dA (m x n) = dL/dA for a loss L(U, R, V) whose adjoints are
+ * dU (m x n), dR (n x n; only its upper triangle is read in effect) and dV
+ * (n x n); each may be NULL for zero.  A, G, U, R, V and the tape are those of
+ * the forward call.  With opts->accumulate the result is added to dA.
+ */
+int urv_factor_backward(const void* A, int64_t m, int64_t n, int32_t q, const void* G, const void* U,
+                        const void* R, const void* V, const void* tape, const void* dU, const void* dR,
+                        const void* dV, void* dA, const urv_grad_opts* opts);
+
+/*
+ * Adjoint of one QR X = Q R (Q m x n, R n x n upper, m >= n): dX = (dQ + Q S) R^{-T}
+ * with S from the lower triangle of R dR^T - dQ^T Q.  dQ or dR may be NULL
+ * (zero).  precision URV_FP64 or URV_FP32; asynchronous on stream.
+ */
+int urv_qr_adjoint(const void* Q, const void* R, int64_t m, int64_t n, const void* dQ, const void* dR,
+                   void* dX, int32_t precision, void* stream);
+
+/*
+ * The rank-k truncation loss L = ||A - A_k||_F^2 with A_k = U(:,1:k) R(1:k,:) V^T
+ * (its square root is the rank-k error of Section 5 when A = U R V^T), and
+ * its adjoints: dU, dR, dV (each may be NULL: not formed) and dA = 2 (A - A_k),
+ * the loss's own term in A (required).  loss (DEVICE, one double, may be
+ * NULL) receives L summed in FP64 in a fixed order.  0 <= k <= n.
+ */
+int urv_truncation_loss(const void* A, int64_t m, int64_t n, const void* U, const void* R, const void* V,
+                        int64_t k, double* loss, void* dU, void* dR, void* dV, void* dA,
+                        const urv_grad_opts* opts);
 
 /* Static text for a status code. */
 const char* urv_strerror(int code);

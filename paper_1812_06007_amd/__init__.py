@@ -8,12 +8,19 @@ from .urv import (  # noqa: F401
     dgemm,
     empty_colmajor,
     factor,
+    factor_backward,
+    factor_tape,
     gaussian,
+    grad_workspace_size,
     lib,
     metrics,
+    qr_adjoint,
     qr_pos,
+    tape_bytes,
+    truncation_loss,
     workspace_size,
 )
 
-__all__ = ["UrvError", "dgemm", "empty_colmajor", "factor", "gaussian", "lib", "metrics", "qr_pos",
+__all__ = ["UrvError", "dgemm", "empty_colmajor", "factor", "factor_backward", "factor_tape", "gaussian",
+           "grad_workspace_size", "lib", "metrics", "qr_adjoint", "qr_pos", "tape_bytes", "truncation_loss",
            "workspace_size"]

@@ -47,8 +47,24 @@ class UrvOpts(ctypes.Structure):
     ]
 
 
+class UrvGradOpts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
+        ("tape_mode", ctypes.c_int32),
+        ("accumulate", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+TAPE_MODES = {"all": 0, "v": 1, "none": 2}
+
 EXPORTS = ["urv_opts_init", "urv_factor_ex", "urv_factor", "urv_workspace_size", "urv_gaussian",
-           "urv_dgemm", "urv_qr_pos", "urv_qr_pos_f32", "urv_metrics", "urv_strerror", "urv_last_error"]
+           "urv_dgemm", "urv_qr_pos", "urv_qr_pos_f32", "urv_metrics", "urv_strerror", "urv_last_error",
+           "urv_grad_opts_init", "urv_tape_bytes", "urv_grad_workspace_size", "urv_factor_tape",
+           "urv_factor_backward", "urv_qr_adjoint", "urv_truncation_loss"]
 
 _lib = None
 
@@ -79,8 +95,20 @@ def lib() -> ctypes.CDLL:
     L.urv_strerror.restype = ctypes.c_char_p
     L.urv_last_error.argtypes = []
     L.urv_last_error.restype = ctypes.c_char_p
+    GO = ctypes.POINTER(UrvGradOpts)
+    L.urv_grad_opts_init.argtypes = [GO]
+    L.urv_grad_opts_init.restype = None
+    L.urv_tape_bytes.argtypes = [I64, I64, I32, GO]
+    L.urv_tape_bytes.restype = SZ
+    L.urv_grad_workspace_size.argtypes = [I64, I64, I32, GO]
+    L.urv_grad_workspace_size.restype = SZ
+    L.urv_factor_tape.argtypes = [P, I64, I64, I32, P, P, P, P, P, GO]
+    L.urv_factor_backward.argtypes = [P, I64, I64, I32, P, P, P, P, P, P, P, P, P, GO]
+    L.urv_qr_adjoint.argtypes = [P, P, I64, I64, P, P, P, I32, P]
+    L.urv_truncation_loss.argtypes = [P, I64, I64, P, P, P, I64, P, P, P, P, P, GO]
     for name in ("urv_factor_ex", "urv_factor", "urv_gaussian", "urv_dgemm", "urv_qr_pos", "urv_qr_pos_f32",
-                 "urv_metrics"):
+                 "urv_metrics", "urv_factor_tape", "urv_factor_backward", "urv_qr_adjoint",
+                 "urv_truncation_loss"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -258,3 +286,127 @@ def metrics(A, U, R, V) -> dict:
                              out.ctypes.data_as(ctypes.c_void_p), ek.ctypes.data_as(ctypes.c_void_p),
                              _stream_ptr()))
     return {"recon": out[0], "orthU": out[1], "orthV": out[2], "normA": out[3], "ek": ek}
+
+
+# ---------------------------------------------------------------- derivative (G held fixed)
+def _real_dtype(t):
+    torch = _torch()
+    if t.dtype not in (torch.float32, torch.float64):
+        raise TypeError("the derivative entry points take float32 or float64 tensors")
+    return t.dtype
+
+
+def _packed_as(t, dtype):
+    """Column-major, leading dimension == rows, of the given dtype (copy if needed)."""
+    c, ld = _colmajor(t, dtype)
+    if ld == max(c.shape[0], 1) or c.shape[1] <= 1:
+        return c
+    p = empty_colmajor(*c.shape, dtype=dtype, device=c.device)
+    p.copy_(c)
+    return p
+
+
+def _grad_opts(dtype, variant="full", tape_mode="all", accumulate=False, workspace=None) -> UrvGradOpts:
+    torch = _torch()
+    o = UrvGradOpts()
+    lib().urv_grad_opts_init(ctypes.byref(o))
+    o.precision = 1 if dtype == torch.float32 else 0
+    o.variant = VARIANTS[variant]
+    o.tape_mode = TAPE_MODES[tape_mode]
+    o.accumulate = int(bool(accumulate))
+    o.stream = _stream_ptr().value
+    if workspace is not None:
+        if workspace.dtype != torch.uint8 or not workspace.is_cuda:
+            raise ValueError("workspace must be a uint8 CUDA tensor")
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel()
+    return o
+
+
+def tape_bytes(m: int, n: int, q: int, dtype=None, variant: str = "full", tape_mode: str = "all") -> int:
+    torch = _torch()
+    o = _grad_opts(dtype or torch.float64, variant, tape_mode)
+    return int(lib().urv_tape_bytes(m, n, q, ctypes.byref(o)))
+
+
+def grad_workspace_size(m: int, n: int, q: int = 0, dtype=None) -> int:
+    torch = _torch()
+    o = _grad_opts(dtype or torch.float64)
+    return int(lib().urv_grad_workspace_size(m, n, q, ctypes.byref(o)))
+
+
+def factor_tape(A, G, q: int, variant: str = "full", tape_mode: str = "all", workspace=None):
+    """Forward pass of the differentiable factorisation from the fixed G.
+
+    Returns (U, R, V, tape): column-major tensors of A's dtype (float32 or
+    float64) and the uint8 tape that ``factor_backward`` reads."""
+    torch = _torch()
+    dt = _real_dtype(A)
+    A = _packed_as(A, dt)
+    m, n = A.shape
+    G = _packed_as(G, dt)
+    if tuple(G.shape) != (n, n):
+        raise ValueError("G must be n x n")
+    U = empty_colmajor(m, n, dtype=dt, device=A.device)
+    R = empty_colmajor(n, n, dtype=dt, device=A.device)
+    V = empty_colmajor(n, n, dtype=dt, device=A.device)
+    o = _grad_opts(dt, variant, tape_mode, workspace=workspace)
+    tape = torch.empty(max(int(lib().urv_tape_bytes(m, n, q, ctypes.byref(o))), 1), dtype=torch.uint8,
+                       device=A.device)
+    _check(lib().urv_factor_tape(_ptr(A), m, n, q, _ptr(G), _ptr(U), _ptr(R), _ptr(V), _ptr(tape),
+                                 ctypes.byref(o)))
+    return U, R, V, tape
+
+
+def factor_backward(A, G, U, R, V, tape, q: int, dU=None, dR=None, dV=None, variant: str = "full",
+                    tape_mode: str = "all", dA=None, accumulate: bool = False, workspace=None):
+    """dL/dA for the adjoints dU, dR, dV (None = zero) of a loss L(U, R, V)."""
+    dt = _real_dtype(A)
+    A = _packed_as(A, dt)
+    m, n = A.shape
+    G, U, R, V = (_packed_as(t, dt) for t in (G, U, R, V))
+    dU, dR, dV = (None if t is None else _packed_as(t, dt) for t in (dU, dR, dV))
+    if dA is None:
+        dA = empty_colmajor(m, n, dtype=dt, device=A.device)
+        accumulate = False
+    elif dA.dtype != dt or (dA.stride(0) != 1 and m > 1) or (n > 1 and dA.stride(1) != max(m, 1)):
+        raise ValueError("dA must be packed column-major of A's dtype")
+    o = _grad_opts(dt, variant, tape_mode, accumulate, workspace)
+    _check(lib().urv_factor_backward(_ptr(A), m, n, q, _ptr(G), _ptr(U), _ptr(R), _ptr(V), _ptr(tape),
+                                     _ptr(dU), _ptr(dR), _ptr(dV), _ptr(dA), ctypes.byref(o)))
+    return dA
+
+
+def qr_adjoint(Q, R, dQ=None, dR=None):
+    """Adjoint of X = Q R: (dQ + Q S) R^{-T} (see include/urv.h)."""
+    dt = _real_dtype(Q)
+    Q, R = _packed_as(Q, dt), _packed_as(R, dt)
+    dQ = None if dQ is None else _packed_as(dQ, dt)
+    dR = None if dR is None else _packed_as(dR, dt)
+    m, n = Q.shape
+    dX = empty_colmajor(m, n, dtype=dt, device=Q.device)
+    torch = _torch()
+    _check(lib().urv_qr_adjoint(_ptr(Q), _ptr(R), m, n, _ptr(dQ), _ptr(dR), _ptr(dX),
+                                1 if dt == torch.float32 else 0, _stream_ptr()))
+    return dX
+
+
+def truncation_loss(A, U, R, V, k: int, seeds: bool = True, workspace=None):
+    """L = ||A - U(:,:k) R(:k,:) V^T||_F^2 on the device.
+
+    Returns (L, dU, dR, dV, dA): L a 0-d float64 CUDA tensor; the adjoints
+    (None unless ``seeds``) and dA = 2 (A - A_k), in A's dtype."""
+    torch = _torch()
+    dt = _real_dtype(A)
+    A = _packed_as(A, dt)
+    m, n = A.shape
+    U, R, V = (_packed_as(t, dt) for t in (U, R, V))
+    L = torch.empty((), dtype=torch.float64, device=A.device)
+    dA = empty_colmajor(m, n, dtype=dt, device=A.device)
+    dU = empty_colmajor(m, n, dtype=dt, device=A.device) if seeds else None
+    dR = empty_colmajor(n, n, dtype=dt, device=A.device) if seeds else None
+    dV = empty_colmajor(n, n, dtype=dt, device=A.device) if seeds else None
+    o = _grad_opts(dt, workspace=workspace)
+    _check(lib().urv_truncation_loss(_ptr(A), m, n, _ptr(U), _ptr(R), _ptr(V), k, ctypes.c_void_p(L.data_ptr()),
+                                     _ptr(dU), _ptr(dR), _ptr(dV), _ptr(dA), ctypes.byref(o)))
+    return L, dU, dR, dV, dA

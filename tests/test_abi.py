@@ -125,3 +125,75 @@ def test_binding_refuses_cpu_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(ValueError):
         urv.factor(torch.zeros(4, 3, dtype=torch.float64), 1)
+
+
+# ---------------------------------------------------------------- derivative entry points
+def _gopts(**fields):
+    o = urv.UrvGradOpts()
+    urv.lib().urv_grad_opts_init(ctypes.byref(o))
+    for k, v in fields.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_grad_opts_struct_matches_header_layout():
+    # int32 x4, ptr, ptr, size_t
+    assert ctypes.sizeof(urv.UrvGradOpts) == 4 * 4 + 8 + 8 + 8
+    o = _gopts()
+    assert (o.precision, o.variant, o.tape_mode, o.accumulate, o.stream, o.workspace) == (0, 0, 0, 0, None, None)
+
+
+@pytest.mark.parametrize("m,n,q,fields", [
+    (3, 5, 1, {}),                        # m < n
+    (5, 3, -1, {}),                       # q < 0
+    (5, 3, 1, {"precision": 2}),          # mixed precision has no derivative
+    (5, 3, 1, {"variant": 2}),            # NONE has no derivative
+    (5, 3, 1, {"tape_mode": 3}),
+    (5, 3, 1, {"workspace_bytes": 64}),   # bytes without a buffer
+])
+def test_grad_entry_points_reject_bad_arguments(m, n, q, fields):
+    L = urv.lib()
+    o = _gopts(**fields)
+    P = FAKE
+    assert L.urv_factor_tape(P, m, n, q, P, P, P, P, P, ctypes.byref(o)) == urv.URV_EINVAL
+    assert L.urv_factor_backward(P, m, n, q, P, P, P, P, P, P, P, P, P, ctypes.byref(o)) == urv.URV_EINVAL
+    assert urv.lib().urv_last_error() != b""
+
+
+def test_grad_entry_points_validate():
+    L = urv.lib()
+    o = _gopts()
+    P = FAKE
+    # null pointers, empty calls, k outside [0, n], too many rows
+    assert L.urv_factor_tape(None, 5, 3, 1, P, P, P, P, P, ctypes.byref(o)) == urv.URV_EINVAL
+    assert L.urv_factor_tape(P, 5, 3, 1, P, P, P, P, None, ctypes.byref(o)) == urv.URV_EINVAL
+    assert L.urv_factor_tape(None, 5, 0, 1, None, None, None, None, None, ctypes.byref(o)) == urv.URV_OK
+    assert L.urv_factor_backward(P, 5, 3, 1, P, P, P, P, P, None, None, None, None, ctypes.byref(o)) == urv.URV_EINVAL
+    assert L.urv_factor_tape(P, 1 << 20, 8, 1, P, P, P, P, P, ctypes.byref(o)) == urv.URV_ENOTSUP
+    assert L.urv_truncation_loss(P, 5, 3, P, P, P, 4, None, None, None, None, P, ctypes.byref(o)) == urv.URV_EINVAL
+    assert L.urv_truncation_loss(P, 5, 3, P, P, P, -1, None, None, None, None, P, ctypes.byref(o)) == urv.URV_EINVAL
+    assert L.urv_truncation_loss(P, 5, 3, P, P, P, 2, None, None, None, None, None, ctypes.byref(o)) == urv.URV_EINVAL
+    assert L.urv_qr_adjoint(P, P, 3, 5, None, None, P, 0, None) == urv.URV_EINVAL
+    assert L.urv_qr_adjoint(P, P, 5, 3, None, None, P, 3, None) == urv.URV_EINVAL
+    assert L.urv_qr_adjoint(None, P, 5, 3, None, None, P, 0, None) == urv.URV_EINVAL
+    # with URV_TAPE_NONE no tape is needed
+    o_none = _gopts(tape_mode=2)
+    assert L.urv_tape_bytes(5, 3, 2, ctypes.byref(o_none)) == 0
+
+
+def test_tape_and_workspace_sizes():
+    L = urv.lib()
+    sizes = {}
+    for mode in (0, 1, 2):
+        sizes[mode] = L.urv_tape_bytes(1000, 500, 2, ctypes.byref(_gopts(tape_mode=mode)))
+    assert sizes[0] > sizes[1] > sizes[2] == 0
+    assert L.urv_tape_bytes(1000, 500, 0, ctypes.byref(_gopts())) == 0
+    f64 = L.urv_tape_bytes(1000, 500, 2, ctypes.byref(_gopts()))
+    f32 = L.urv_tape_bytes(1000, 500, 2, ctypes.byref(_gopts(precision=1)))
+    assert f32 < f64
+    half = L.urv_tape_bytes(1000, 500, 2, ctypes.byref(_gopts(variant=1)))
+    assert half < f64  # HALF keeps no Rw
+    w_small = L.urv_grad_workspace_size(100, 50, 2, ctypes.byref(_gopts()))
+    w_big = L.urv_grad_workspace_size(1000, 500, 2, ctypes.byref(_gopts()))
+    assert 0 < w_small < w_big
+    assert L.urv_grad_workspace_size(3, 5, 2, ctypes.byref(_gopts())) == 0

@@ -7,7 +7,8 @@ tests so that both see the same bytes.
 
 Every random draw comes from ``numpy.random.Generator(Philox(key=[seed,
 stream]))``; the stream ids are fixed: 0 = left Haar factor, 1 = right Haar
-factor, 2 = starting matrix G, 3 = additive noise, 4 = rank spike.
+factor, 2 = starting matrix G, 3 = additive noise, 4 and 5 = left and right
+factors of a rank spike.
 Haar factors are Q-factors of Gaussian matrices with the sign of the
 diagonal of R fixed positive, which makes them exactly Haar distributed
 (footnote to Section 2.2 of the paper).
@@ -24,6 +25,7 @@ import math
 import numpy as np
 
 STREAM_LEFT, STREAM_RIGHT, STREAM_G, STREAM_NOISE, STREAM_SPIKE = 0, 1, 2, 3, 4
+STREAM_SPIKE_RIGHT = 5
 
 
 def generator(seed: int, stream: int) -> np.random.Generator:
@@ -147,3 +149,14 @@ def sigma_sums(sigma: np.ndarray) -> dict:
     s = np.sort(np.asarray(sigma, dtype=np.float64))[::-1]
     tail = np.sqrt(np.concatenate([np.cumsum((s * s)[::-1])[::-1], [0.0]]))
     return {"fro": float(np.sqrt(np.sum(s * s))), "log10det": float(np.sum(np.log10(s))), "tail": tail}
+
+
+def spiked_gaussian(m: int, n: int, rank: int, scale: float, seed: int) -> np.ndarray:
+    """i.i.d. N(0, 1/n) noise (stream 3) plus scale * P Q^T with P (m x rank)
+    and Q (n x rank) Haar columns (streams 4 and 5): a rank-`rank` spike of
+    singular value `scale` over a Gaussian bulk of spectral radius about 2
+    (the differentiation workload)."""
+    E = generator(seed, STREAM_NOISE).standard_normal((m, n)) / math.sqrt(n)
+    P = haar_columns(m, rank, generator(seed, STREAM_SPIKE))
+    Q = haar_columns(n, rank, generator(seed, STREAM_SPIKE_RIGHT))
+    return np.asfortranarray(E + scale * (P @ Q.T))
