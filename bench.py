@@ -9,8 +9,10 @@ TFLOP/s at the executed operation count (standard LAPACK counts, explicit Q
 included), the reconstruction error, the MFMA roofline of the dominant
 kernel (the FP64 GEMM A V, timed with HIP events on the stream it runs on),
 the mixed-precision forms (BF16 / FP16 power steps) against plain FP64 on the
-same input and on the 16000 x 8000 noisy exp(-j/800) matrix, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+same input and on the 16000 x 8000 noisy exp(-j/800) matrix, the
+differentiation workload (forward, truncation loss and reverse sweep of a
+2048 x 2048 FP32 matrix with G fixed, against the FP64 oracle's gradient), and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -103,6 +105,96 @@ def cpu_baseline(q: int, variant: str, sample_n: int) -> dict:
             "seconds": dt}
 
 
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def grad_flops(m: int, n: int, q: int, k: int, variant: str = "full") -> dict:
+    """Operation counts of the differentiable FULL/HALF chain (standard counts,
+    explicit Q included): the forward pass, the truncation loss with its
+    adjoints, and the reverse sweep.  One QR adjoint of an m x n factor costs
+    Qb^T Q, Q S (2mn^2 each) and the solve with R^T (mn^2); with an R
+    adjoint R Rb^T adds 2n^3."""
+    m, n, k = float(m), float(n), float(k)
+    fwd = executed_flops(m, n, q, variant)
+    loss = 4 * m * n * n + 2 * k * n * n + 8 * m * n * k
+    bwd = 5 * m * n * n + 2 * n ** 3 + 4 * m * n * n          # final QR adjoint, Xb V^T, A^T Xb
+    per = 5 * n ** 3 + 8 * m * n * n + (5 * m * n * n if variant == "full" else 0.0)
+    bwd += q * per - 2 * m * n * n  # no A^T Xb where the sweep ends (V_0 = G, or q = 0)
+    return {"forward": fwd, "loss": loss, "backward": bwd, "total": fwd + loss + bwd}
+
+
+def bench_grad(steps: int, warmup: int, oracle_check: bool) -> dict:
+    """The differentiation workload: A 2048 x 2048 FP32 = N(0, 1/2048) + a
+    rank-256 spike of 10, G fixed, q = 2 FULL, loss ||A - A_k||_F^2 with
+    k = 256; forward (with tape), loss and reverse sweep timed together."""
+    import numpy as np
+    import torch
+
+    import urv_inputs as gen
+    from paper_1812_06007_amd import urv
+
+    m = n = 2048
+    q, k = 2, 256
+    A_np = gen.spiked_gaussian(m, n, k, 10.0, 1812).astype(np.float32)
+    G_np = gen.gaussian(n, n, 1812).astype(np.float32)
+    A = torch.from_numpy(np.ascontiguousarray(A_np.T)).cuda().t()
+    G = torch.from_numpy(np.ascontiguousarray(G_np.T)).cuda().t()
+    ws = torch.empty(urv.grad_workspace_size(m, n, q, torch.float32), dtype=torch.uint8, device=A.device)
+    state = {}
+
+    def fwd():
+        state["f"] = urv.factor_tape(A, G, q, workspace=ws)
+
+    def step():
+        U, R, V, tape = urv.factor_tape(A, G, q, workspace=ws)
+        L, dU, dR, dV, dA = urv.truncation_loss(A, U, R, V, k, workspace=ws)
+        urv.factor_backward(A, G, U, R, V, tape, q, dU, dR, dV, dA=dA, accumulate=True, workspace=ws)
+        state["out"] = (L, dA)
+
+    def timed(fn, reps):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_fwd = timed(fwd, steps)
+    ms = timed(step, steps)
+    L, dA = state["out"]
+    fl = grad_flops(m, n, q, k)
+    res = {"workload": "A 2048x2048 FP32 = N(0,1/2048) + rank-256 spike x10, G fixed (seed 1812), q=2 FULL, "
+                       "loss ||A - A_k||_F^2, k=256; forward with tape + loss + reverse sweep",
+           "dtype": "f32", "ms_forward": ms_fwd, "ms_forward_loss_backward": ms,
+           "flops_executed": fl["total"], "tflops": fl["total"] / (ms * 1e-3) / 1e12,
+           "frac_fp32_peak": fl["total"] / (ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+           "loss": float(L.item())}
+    if oracle_check:
+        from oracle import adjoint, oracle
+
+        oracle.build()
+        t0 = time.perf_counter()
+        L0, g0 = adjoint.loss_and_grad(A_np.astype(np.float64), G_np.astype(np.float64), q, k)
+        dt = time.perf_counter() - t0
+        g = dA.t().contiguous().t().cpu().double().numpy()
+        res["grad_rel_err_vs_fp64_oracle"] = float(np.linalg.norm(g - g0) / np.linalg.norm(g0))
+        res["loss_rel_err_vs_fp64_oracle"] = abs(res["loss"] - L0) / L0
+        cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)) or 1)
+        res["cpu_baseline"] = {"value": fl["total"] / dt / 1e12, "unit": "TFLOP/s", "cores": cores,
+                               "kind": "oracle", "seconds": dt,
+                               "sample": "FP64 oracle loss and gradient of the same 2048x2048 workload "
+                                         "(C loops for the forward, numpy FP64 for the adjoint)"}
+    del ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def time_factor(A, q: int, variant: str, precision: str, steps: int, warmup: int, out) -> float:
     """Mean milliseconds of urv.factor over `steps` runs (HIP events on the current stream)."""
     import torch
@@ -184,6 +276,10 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=3600, help="n of the oracle sample (0: skip)")
     ap.add_argument("--gemm-reps", type=int, default=5)
     ap.add_argument("--mixed-steps", type=int, default=3, help="timed steps per mixed comparison (0: skip)")
+    ap.add_argument("--grad-steps", type=int, default=5,
+                    help="timed steps of the differentiation workload (0: skip)")
+    ap.add_argument("--grad-only", action="store_true",
+                    help="run only the differentiation workload (for profiling) and exit")
     ap.add_argument("--gemm-only", action="store_true",
                     help="run only the A V GEMM launches (for counter collection) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -220,6 +316,11 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print("[bench] 3 copies of 1 GiB done", file=sys.stderr, flush=True)
+        return 0
+
+    if args.grad_only:
+        print("[bench] differentiation workload only", file=sys.stderr, flush=True)
+        print(json.dumps(bench_grad(max(args.grad_steps, 1), args.warmup, False)))
         return 0
 
     if args.gemm_only:
@@ -304,6 +405,11 @@ def main() -> int:
         del A3, out3
         torch.cuda.empty_cache()
 
+    grad = None
+    if args.grad_steps > 0:
+        print("[bench] differentiation workload (2048x2048 FP32, q=2, k=256)", file=sys.stderr, flush=True)
+        grad = bench_grad(args.grad_steps, args.warmup, args.cpu_sample > 0)
+
     cpu = None
     if args.cpu_sample > 0:
         print("[bench] oracle CPU baseline on a %dx%d sample" % (args.cpu_sample, args.cpu_sample),
@@ -339,6 +445,7 @@ def main() -> int:
                      "frac": gemm_tf / FP64_MFMA_PEAK_TFLOPS, "traffic": gemm_traffic(m, n),
                      "launch_ms": gemm_ms, "flop_per_launch": 2.0 * m * n * n},
         "mixed_vs_fp64": mixed,
+        "differentiation": grad,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
     }
     print(json.dumps(out))
