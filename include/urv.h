@@ -236,6 +236,54 @@ int urv_truncation_loss(const void* A, int64_t m, int64_t n, const void* U, cons
                         int64_t k, double* loss, void* dU, void* dR, void* dV, void* dA,
                         const urv_grad_opts* opts);
 
+/* ------------------------------------------------------------------------
+ * Batched factorisation: many independent FP32 matrices (1 <= n <= m <= 1024,
+ * sizes may all differ) factored by one persistent kernel launch.  Matrix i
+ * runs PowerURV (Section 3, eqs. power and powerqr, FULL re-orthonormalisation)
+ * with its own Gaussian G drawn as in urv_gaussian (FP32 rounding) under seed
+ * + i, stream id 2, and q power steps; diag(R) >= 0 as in urv_qr_pos.
+ * One workgroup factors one matrix at a time, taking matrices largest first
+ * from a device-side queue.  Matrices are packed column-major FP32 device
+ * arrays: A_i m_i x n_i (ld m_i, read only), U_i m_i x n_i, R_i n_i x n_i
+ * (zero below the diagonal), V_i n_i x n_i.
+ * ---------------------------------------------------------------------- */
+typedef struct urv_batch_plan urv_batch_plan; /* opaque */
+
+/* Plan for `count` matrices with HOST arrays m[count], n[count]: validates
+ * the sizes (URV_EINVAL; URV_ENOTSUP above 1024 rows), allocates the device
+ * scratch of every matrix and the queue (this call allocates; the run calls do
+ * not), and orders the queue by m n^2, largest first.  Blocking. */
+int urv_batch_create(int64_t count, const int64_t* m, const int64_t* n, int32_t q, uint64_t seed,
+                     urv_batch_plan** plan);
+
+/* Sets the matrices: HOST arrays of count DEVICE pointers.  Blocking (copies
+ * the descriptors to the device).  May be called again with other buffers of
+ * the same sizes; a captured graph stays valid. */
+int urv_batch_set_buffers(urv_batch_plan* plan, const float* const* A, float* const* U, float* const* R,
+                          float* const* V);
+
+/* Panel width nb (16 or 32) and number of persistent workgroups (1..65536)
+ * of the launch; urv_batch_autotune chooses them by timing. */
+int urv_batch_set_config(urv_batch_plan* plan, int32_t nb, int32_t grid);
+int urv_batch_get_config(const urv_batch_plan* plan, int32_t* nb, int32_t* grid);
+
+/* Times every (nb, grid) candidate on the plan's matrices (running the whole
+ * batch twice each on stream, blocking) and keeps the fastest; *best_ms
+ * (HOST, may be NULL) receives its time.  The outputs hold a valid result. */
+int urv_batch_autotune(urv_batch_plan* plan, void* stream, double* best_ms);
+
+/* One persistent launch on stream (asynchronous; no allocation, no host-side
+ * clearing).  Two runs of one plan must not overlap. */
+int urv_batch_run(urv_batch_plan* plan, void* stream);
+
+/* urv_batch_run through a graph: the launch is captured into a graph on the
+ * first call (and after a configuration change), then the graph is launched
+ * on stream. */
+int urv_batch_run_graph(urv_batch_plan* plan, void* stream);
+
+/* Frees the plan's device memory and graph (after the stream work that uses it). */
+void urv_batch_destroy(urv_batch_plan* plan);
+
 /* Static text for a status code. */
 const char* urv_strerror(int code);
 

@@ -4,7 +4,9 @@ The factorisation A = U R V^T runs in the HIP kernels of ``liburv.so``
 behind the C ABI of ``include/urv.h``; this package is its Python binding.
 """
 from .urv import (  # noqa: F401
+    BatchPlan,
     UrvError,
+    batch_outputs,
     dgemm,
     empty_colmajor,
     factor,
@@ -21,6 +23,6 @@ from .urv import (  # noqa: F401
     workspace_size,
 )
 
-__all__ = ["UrvError", "dgemm", "empty_colmajor", "factor", "factor_backward", "factor_tape", "gaussian",
+__all__ = ["BatchPlan", "UrvError", "batch_outputs", "dgemm", "empty_colmajor", "factor", "factor_backward", "factor_tape", "gaussian",
            "grad_workspace_size", "lib", "metrics", "qr_adjoint", "qr_pos", "tape_bytes", "truncation_loss",
            "workspace_size"]

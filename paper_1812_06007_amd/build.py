@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liburv.so")
 ARCH = os.environ.get("URV_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["adjoint.hip", "api.hip", "gemm.hip", "mixed.hip", "qr.hip", "rng.hip", "util.hip"]
+SOURCES = ["adjoint.hip", "api.hip", "batched.hip", "gemm.hip", "mixed.hip", "qr.hip", "rng.hip", "util.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

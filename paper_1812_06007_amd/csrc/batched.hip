@@ -1,0 +1,728 @@
+// Batched PowerURV: many independent FP32 matrices (up to 1024 rows) factored
+// in one persistent launch.
+//
+// Each matrix runs the method of Section 3 (eqs. power and powerqr, FULL
+// re-orthonormalisation): G from Philox stream 2 under key (seed + i, 0),
+// rounded to FP32; q times X = A V, W = Qpos(X), Y = A^T W, V = Qpos(Y); then
+// A V = U R.  Qpos is the unpivoted Householder QR of Section 2.2 with the
+// reflectors accumulated in compact WY form (I - V T V^T) and diag(R) made
+// non-negative (the footnote on Haar matrices).
+//
+// Design for gfx950: one workgroup (4 waves) owns one matrix at a time and
+// takes the next matrix from a device-side counter; matrices are queued
+// largest first, so the long ones start early and the short ones fill the
+// tail.  Within a workgroup:
+//  * GEMMs (A V, A^T W and the block-reflector updates) on FP32 MFMA
+//    (v_mfma_f32_16x16x4f32), 64 x 64 tiles staged through LDS;
+//  * the panel of NB columns lives in registers (4 rows per lane, rows up to
+//    1024); each column takes two workgroup reductions in a fixed order: the
+//    norm below the pivot, then the reflector's products with the remaining
+//    columns together with its Gram entries against the earlier reflectors,
+//    from which T is built without another pass;
+//  * Q is accumulated backward from [I; 0], then the sign fix.
+// The last workgroup to leave resets the counters, so one launch needs no
+// host-side clearing and can be replayed from a captured graph.
+#include "common.hpp"
+#include "philox.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+struct urv_batch_plan;
+
+namespace urv {
+namespace {
+
+constexpr int BT = 256;                  // threads per workgroup: 4 waves
+constexpr int RPT = 4;                   // panel rows per lane
+constexpr int kBatchMaxRows = BT * RPT;  // 1024
+constexpr int kNBMax = 32;               // widest panel
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+struct BatchItem {
+  int m = 0, n = 0;
+  uint64_t seed = 0;
+  const float* A = nullptr;  // m x n, ld m (read only)
+  float* U = nullptr;        // m x n
+  float* R = nullptr;        // n x n
+  float* V = nullptr;        // n x n
+  // scratch, packed column-major
+  float* X = nullptr;        // m x n: A V, factored in place
+  float* Q = nullptr;        // m x n: W = Qpos(X)
+  float* Y = nullptr;        // n x n: A^T W, factored in place
+  float* Vc = nullptr;       // n x n: the current V
+  float* Vr = nullptr;       // m x n: explicit unit-lower reflectors of the current QR
+  float* T = nullptr;        // kNBMax x n: T of each panel
+  float* Wb = nullptr;       // kNBMax x n
+  float* W2b = nullptr;      // kNBMax x n
+};
+
+struct Lds {
+  float As[16][64 + 1];
+  float Bs[16][64 + 1];
+  float red[kNBMax * (BT + BT / 32)];  // value v of lane t at v (BT + 8) + t + t / 32
+  float part[kNBMax][9];
+  float res[kNBMax];
+  float gram[kNBMax][kNBMax + 1];      // gram[b][c] = v_b^T v_c, b < c
+  float tau[kNBMax];
+  float trow[kNBMax][kNBMax + 1];      // rows of T, one per lane
+  float alpha;
+  int idx;
+};
+
+// Sums vals[0..CNT) over the workgroup into s.res (every lane may read it on
+// return).  Lane (v, p) = (t / 8, t % 8) adds lanes 32p .. 32p + 31 of value
+// v, then lane v adds the 8 parts: a fixed order, bitwise reproducible.
+template <int CNT>
+__device__ __forceinline__ void block_sum(const float (&vals)[CNT], Lds& s) {
+  static_assert(CNT >= 1 && CNT <= kNBMax, "reduction width");
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int v = 0; v < CNT; ++v) s.red[v * (BT + 8) + t + (t >> 5)] = vals[v];
+  __syncthreads();
+  {
+    const int v = t >> 3, p = t & 7;
+    if (v < CNT) {
+      const float* r = &s.red[v * (BT + 8) + p * 33];
+      float a = 0.f;
+#pragma unroll 8
+      for (int i = 0; i < 32; ++i) a += r[i];
+      s.part[v][p] = a;
+    }
+  }
+  __syncthreads();
+  if (t < CNT) {
+    float a = 0.f;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) a += s.part[t][p];
+    s.res[t] = a;
+  }
+  __syncthreads();
+}
+
+// C (M x N) = alpha op(A) B + beta C for the whole workgroup; op(A) = A (TA
+// false, A M x K) or A^T (A K x M).  64 x 64 tiles of C, K in steps of 16
+// through LDS; each wave owns a 32 x 32 quarter as 2 x 2 MFMA blocks.  beta ==
+// 0 never reads C.  C must not overlap A or B.  Ends with a barrier, so the
+// workgroup may read C right after.
+template <bool TA>
+__device__ __forceinline__ void wg_gemm(int M, int N, int K, float alpha, const float* __restrict__ A, int lda,
+                        const float* __restrict__ B, int ldb, float beta, float* __restrict__ C, int ldc,
+                        Lds& s) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow = lane & 15, lk = lane >> 4;
+  const int tiles_m = (M + 63) / 64, tiles_n = (N + 63) / 64;
+  for (int tile = 0; tile < tiles_m * tiles_n; ++tile) {
+    const int m0 = (tile % tiles_m) * 64, n0 = (tile / tiles_m) * 64;
+    f4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int qa = t + BT * r;
+        int i, k;
+        if (!TA) {
+          i = qa & 63;
+          k = qa >> 6;
+        } else {
+          k = qa & 15;
+          i = qa >> 4;
+        }
+        const int gi = m0 + i, gk = k0 + k;
+        float v = 0.f;
+        if (gi < M && gk < K)
+          v = TA ? A[gk + static_cast<int64_t>(gi) * lda] : A[gi + static_cast<int64_t>(gk) * lda];
+        s.As[k][i] = v;
+        const int kb = qa & 15, j = qa >> 4;
+        const int gj = n0 + j, gkb = k0 + kb;
+        s.Bs[kb][j] = (gj < N && gkb < K) ? B[gkb + static_cast<int64_t>(gj) * ldb] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        float fa[2], fb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) fa[a] = s.As[kk * 4 + lk][wm * 32 + a * 16 + lrow];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) fb[b] = s.Bs[kk * 4 + lk][wn * 32 + b * 16 + lrow];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[b], fa[a], acc[a][b], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+    // lane holds C(m0 + 32 wm + 16 a + lrow, n0 + 32 wn + 16 b + 4 lk + r)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int gm = m0 + wm * 32 + a * 16 + lrow;
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gn = n0 + wn * 32 + b * 16 + 4 * lk + r;
+          if (gm < M && gn < N) {
+            float* c = C + gm + static_cast<int64_t>(gn) * ldc;
+            *c = (beta == 0.f) ? alpha * acc[a][b][r] : alpha * acc[a][b][r] + beta * *c;
+          }
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// Wout (jb x ncols, ld kNBMax) = op(T) Win for the jb x jb upper triangular T
+// (ld kNBMax): op(T) = T^T when TRANS, else T.  Ends with a barrier.
+template <bool TRANS>
+__device__ __forceinline__ void small_tmul(const float* __restrict__ T, int jb, const float* __restrict__ Win,
+                           float* __restrict__ Wout, int ncols) {
+  for (int e = threadIdx.x; e < jb * ncols; e += BT) {
+    const int i = e % jb, col = e / jb;
+    const float* w = Win + static_cast<int64_t>(col) * kNBMax;
+    float acc = 0.f;
+    if (TRANS) {
+      for (int l = 0; l <= i; ++l) acc += T[l + i * kNBMax] * w[l];
+    } else {
+      for (int l = i; l < jb; ++l) acc += T[i + l * kNBMax] * w[l];
+    }
+    Wout[i + static_cast<int64_t>(col) * kNBMax] = acc;
+  }
+  __syncthreads();
+}
+
+// One column c of the panel factorisation (c a compile-time constant, so the
+// panel stays in registers).  The pivot row c is lane c's first row (c < NB
+// <= BT).  Reflector of x (pivot alpha, sigma^2 below it): beta = -sgn(alpha)
+// ||x||, tau = (beta - alpha) / beta, v = x / (alpha - beta) (LAPACK's
+// convention, sgn(0) = +1); tau = 0 when nothing lies below the pivot.
+template <int NB, int C>
+__device__ __forceinline__ void panel_column(float (&x)[RPT][NB], Lds& s) {
+  const int t = threadIdx.x;
+  float sg[1] = {0.f};
+#pragma unroll
+  for (int sl = 0; sl < RPT; ++sl)
+    if (t + sl * BT > C) sg[0] += x[sl][C] * x[sl][C];
+  if (t == C) s.alpha = x[0][C];
+  block_sum<1>(sg, s);
+  const float sigma2 = s.res[0], alpha = s.alpha;
+  float tau_c = 0.f, beta = alpha, scale = 0.f;
+  if (sigma2 != 0.f) {
+    const float nrm = sqrtf(alpha * alpha + sigma2);
+    beta = (alpha >= 0.f) ? -nrm : nrm;
+    tau_c = (beta - alpha) / beta;
+    scale = 1.f / (alpha - beta);
+  }
+#pragma unroll
+  for (int sl = 0; sl < RPT; ++sl) {
+    const int r = t + sl * BT;
+    if (r > C) x[sl][C] *= scale;
+    else if (r == C) x[sl][C] = beta;
+  }
+  // products of v_c with the later columns (index i >= C: column i + 1) and
+  // with the earlier reflectors (index i < C: v_i^T v_c)
+  constexpr int CNT = NB - 1;
+  float vals[CNT];
+#pragma unroll
+  for (int i = 0; i < CNT; ++i) vals[i] = 0.f;
+#pragma unroll
+  for (int sl = 0; sl < RPT; ++sl) {
+    const int r = t + sl * BT;
+    const float vc = (r > C) ? x[sl][C] : ((r == C) ? 1.f : 0.f);
+#pragma unroll
+    for (int i = 0; i < CNT; ++i) {
+      if (i < C) {
+        const float va = (r > i) ? x[sl][i] : ((r == i) ? 1.f : 0.f);
+        vals[i] += va * vc;
+      } else {
+        vals[i] += vc * x[sl][i + 1];
+      }
+    }
+  }
+  block_sum<CNT>(vals, s);
+#pragma unroll
+  for (int d = C + 1; d < NB; ++d) {
+    const float w = tau_c * s.res[d - 1];
+#pragma unroll
+    for (int sl = 0; sl < RPT; ++sl) {
+      const int r = t + sl * BT;
+      const float vc = (r > C) ? x[sl][C] : ((r == C) ? 1.f : 0.f);
+      x[sl][d] -= w * vc;
+    }
+  }
+  if (t < C) s.gram[t][C] = s.res[t];
+  if (t == 0) s.tau[C] = tau_c;
+}
+
+// The columns C..NB-1 that exist (C < jb), one instantiation per column.
+template <int NB, int C>
+struct PanelColumns {
+  static __device__ __forceinline__ void run(float (&x)[RPT][NB], int jb, Lds& s) {
+    if (C < jb) {
+      panel_column<NB, C>(x, s);
+      PanelColumns<NB, C + 1>::run(x, jb, s);
+    }
+  }
+};
+template <int NB>
+struct PanelColumns<NB, NB> {
+  static __device__ __forceinline__ void run(float (&)[RPT][NB], int, Lds&) {}
+};
+
+// Householder factorisation of the panel P (mp x jb, jb <= NB, top-left on the
+// diagonal) in registers: on return P holds R on and above the diagonal and
+// the reflectors below it, Vp the explicit unit-lower reflectors and Tp
+// (ld kNBMax) the upper triangular T with H_1 ... H_jb = I - V T V^T.
+template <int NB>
+__device__ __forceinline__ void panel_factor(float* __restrict__ P, int ldp, int mp, int jb,
+                                             float* __restrict__ Vp, int ldv, float* __restrict__ Tp, Lds& s) {
+  const int t = threadIdx.x;
+  float x[RPT][NB];
+#pragma unroll
+  for (int sl = 0; sl < RPT; ++sl) {
+    const int r = t + sl * BT;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) x[sl][c] = (r < mp && c < jb) ? P[r + static_cast<int64_t>(c) * ldp] : 0.f;
+  }
+  PanelColumns<NB, 0>::run(x, jb, s);
+#pragma unroll
+  for (int sl = 0; sl < RPT; ++sl) {
+    const int r = t + sl * BT;
+    if (r < mp) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < jb) {
+          P[r + static_cast<int64_t>(c) * ldp] = x[sl][c];
+          Vp[r + static_cast<int64_t>(c) * ldv] = (r > c) ? x[sl][c] : ((r == c) ? 1.f : 0.f);
+        }
+    }
+  }
+  __syncthreads();
+  // row a = t of T from the Gram entries, built in the lane's own LDS row:
+  // T(a,a) = tau_a and, for c > a, T(a,c) = -tau_c sum_{a <= b < c} T(a,b) v_b^T v_c
+  if (t < jb) {
+    for (int c = 0; c < jb; ++c) {
+      float v = 0.f;
+      if (c == t) {
+        v = s.tau[c];
+      } else if (c > t) {
+        float acc = 0.f;
+        for (int b = t; b < c; ++b) acc += s.trow[t][b] * s.gram[b][c];
+        v = -s.tau[c] * acc;
+      }
+      s.trow[t][c] = v;
+      Tp[t + c * kNBMax] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// Qpos of X (rows x cols, ld ldx, rows <= 1024, overwritten): Q (rows x cols,
+// ld ldq) explicit with diag(R) >= 0, R (cols x cols, ld ldr, zero below the
+// diagonal) when R is not null.
+template <int NB>
+__device__ __forceinline__ void qr_wg(float* X, int rows, int cols, int ldx, float* Q, int ldq, float* R, int ldr,
+                      const BatchItem& it, Lds& s) {
+  const int ldv = rows;
+  for (int j0 = 0; j0 < cols; j0 += NB) {
+    const int jb = min(NB, cols - j0), mp = rows - j0;
+    float* P = X + j0 + static_cast<int64_t>(j0) * ldx;
+    float* Vp = it.Vr + j0 + static_cast<int64_t>(j0) * ldv;
+    float* Tp = it.T + static_cast<int64_t>(j0) * kNBMax;
+    panel_factor<NB>(P, ldx, mp, jb, Vp, ldv, Tp, s);
+    const int nrest = cols - j0 - jb;
+    if (nrest > 0) {
+      // C -= V (T^T (V^T C))
+      float* C = X + j0 + static_cast<int64_t>(j0 + jb) * ldx;
+      wg_gemm<true>(jb, nrest, mp, 1.f, Vp, ldv, C, ldx, 0.f, it.Wb, kNBMax, s);
+      small_tmul<true>(Tp, jb, it.Wb, it.W2b, nrest);
+      wg_gemm<false>(mp, nrest, jb, -1.f, Vp, ldv, it.W2b, kNBMax, 1.f, C, ldx, s);
+    }
+  }
+  // Q = H_1 ... H_k [I; 0], accumulated from the last block back
+  for (int e = threadIdx.x; e < rows * cols; e += BT) {
+    const int i = e % rows, j = e / rows;
+    Q[i + static_cast<int64_t>(j) * ldq] = (i == j) ? 1.f : 0.f;
+  }
+  __syncthreads();
+  for (int j0 = ((cols - 1) / NB) * NB; j0 >= 0; j0 -= NB) {
+    const int jb = min(NB, cols - j0), mp = rows - j0, nq = cols - j0;
+    const float* Vp = it.Vr + j0 + static_cast<int64_t>(j0) * ldv;
+    const float* Tp = it.T + static_cast<int64_t>(j0) * kNBMax;
+    float* Qs = Q + j0 + static_cast<int64_t>(j0) * ldq;
+    wg_gemm<true>(jb, nq, mp, 1.f, Vp, ldv, Qs, ldq, 0.f, it.Wb, kNBMax, s);
+    small_tmul<false>(Tp, jb, it.Wb, it.W2b, nq);
+    wg_gemm<false>(mp, nq, jb, -1.f, Vp, ldv, it.W2b, kNBMax, 1.f, Qs, ldq, s);
+  }
+  // sign fix: Q(:,j) *= sgn(R(j,j)), R(j,:) = sgn(R(j,j)) R(j,:), sgn(0) = +1
+  for (int e = threadIdx.x; e < rows * cols; e += BT) {
+    const int i = e % rows, j = e / rows;
+    if (X[j + static_cast<int64_t>(j) * ldx] < 0.f) Q[i + static_cast<int64_t>(j) * ldq] *= -1.f;
+  }
+  if (R) {
+    for (int e = threadIdx.x; e < cols * cols; e += BT) {
+      const int i = e % cols, j = e / cols;
+      float v = 0.f;
+      if (i <= j) {
+        v = X[i + static_cast<int64_t>(j) * ldx];
+        if (X[i + static_cast<int64_t>(i) * ldx] < 0.f) v = -v;
+      }
+      R[i + static_cast<int64_t>(j) * ldr] = v;
+    }
+  }
+  __syncthreads();
+}
+
+template <int NB>
+__device__ __forceinline__ void factor_one(const BatchItem& it, int q, Lds& s) {
+  const int m = it.m, n = it.n;
+  // G: FP32 rounding of the FP64 Gaussian of stream 2 under key (seed, 0)
+  const int64_t total = static_cast<int64_t>(n) * n;
+  for (int64_t blk = threadIdx.x; 4 * blk < total; blk += BT) {
+    double z[4];
+    gaussian_block(static_cast<uint64_t>(blk), 2u, it.seed, z);
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+      if (4 * blk + l < total) it.Vc[4 * blk + l] = static_cast<float>(z[l]);
+  }
+  __syncthreads();
+  // 2q + 1 QRs (2 for q = 0), each after its product, in one loop so that the
+  // QR's code appears once: X-jobs factor A V (the last one into U, R),
+  // Y-jobs factor A^T W (or G itself when q = 0) into the next V.
+  const float* Vin = it.Vc;
+  const int nqr = (q == 0) ? 2 : 2 * q + 1;
+  for (int job = 0; job < nqr; ++job) {
+    const bool last = job == nqr - 1;
+    const bool on_x = last || (q > 0 && job % 2 == 0);
+    float *Xp, *Qp, *Rp = nullptr;
+    int rows;
+    if (on_x) {
+      wg_gemm<false>(m, n, n, 1.f, it.A, m, Vin, n, 0.f, it.X, m, s);    // X = A V
+      Xp = it.X;
+      rows = m;
+      Qp = last ? it.U : it.Q;                                          // W = Qpos(X), or U
+      if (last) Rp = it.R;
+    } else {
+      if (q == 0) {                                                     // DDH-URV (Section 2.2): Qpos(G)
+        for (int64_t e = threadIdx.x; e < total; e += BT) it.Y[e] = it.Vc[e];
+        __syncthreads();
+      } else {
+        wg_gemm<true>(n, n, m, 1.f, it.A, m, it.Q, m, 0.f, it.Y, n, s);  // Y = A^T W
+      }
+      Xp = it.Y;
+      rows = n;
+      Qp = (job == nqr - 2) ? it.V : it.Vc;                             // V = Qpos(Y)
+    }
+    qr_wg<NB>(Xp, rows, n, rows, Qp, rows, Rp, n, it, s);
+    if (!on_x) Vin = Qp;
+  }
+}
+
+// counters[0]: next queue position; counters[1]: workgroups that have left.
+template <int NB>
+__global__ __launch_bounds__(BT) void batched_urv_kernel(const BatchItem* __restrict__ items,
+                                                         const int* __restrict__ order, int count, int q,
+                                                         unsigned* __restrict__ counters) {
+  __shared__ Lds s;
+  for (;;) {
+    if (threadIdx.x == 0) s.idx = static_cast<int>(atomicAdd(&counters[0], 1u));
+    __syncthreads();
+    const int idx = s.idx;
+    __syncthreads();
+    if (idx >= count) break;
+    const BatchItem it = items[order[idx]];
+    factor_one<NB>(it, q, s);
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
+      atomicExch(&counters[0], 0u);
+      atomicExch(&counters[1], 0u);
+    }
+  }
+}
+
+size_t item_scratch_floats(int64_t m, int64_t n) {
+  auto a = [](int64_t e) { return static_cast<int64_t>(align_up(static_cast<size_t>(e), 64)); };
+  return static_cast<size_t>(3 * a(m * n) + 2 * a(n * n) + 3 * a(kNBMax * n));
+}
+
+int launch_batched(int nb, int grid, const BatchItem* items, const int* order, int count, int q,
+                   unsigned* counters, hipStream_t s) {
+  if (nb == 16)
+    batched_urv_kernel<16><<<grid, BT, 0, s>>>(items, order, count, q, counters);
+  else
+    batched_urv_kernel<32><<<grid, BT, 0, s>>>(items, order, count, q, counters);
+  URV_LAUNCHED("batched_urv_kernel");
+  return URV_OK;
+}
+
+}  // namespace
+}  // namespace urv
+
+struct urv_batch_plan {
+  int64_t count = 0;
+  int32_t q = 0;
+  uint64_t seed = 0;
+  int device = 0;
+  std::vector<urv::BatchItem> items;
+  std::vector<int> order;
+  char* scratch = nullptr;
+  urv::BatchItem* d_items = nullptr;
+  int* d_order = nullptr;
+  unsigned* d_counters = nullptr;
+  bool buffers = false;
+  int nb = 32;
+  int grid = 512;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+using urv::clear_last_error;
+using urv::set_last_error;
+
+void drop_graph(urv_batch_plan* p) {
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+}
+
+int check_plan(const urv_batch_plan* p, const char* who) {
+  if (!p) {
+    set_last_error(std::string(who) + ": null plan");
+    return URV_EINVAL;
+  }
+  if (!p->buffers) {
+    set_last_error(std::string(who) + ": urv_batch_set_buffers has not been called");
+    return URV_EINVAL;
+  }
+  return URV_OK;
+}
+
+const int kCandNB[] = {16, 32};
+const int kCandGrid[] = {256, 512, 1024};
+}  // namespace
+
+extern "C" {
+
+int urv_batch_create(int64_t count, const int64_t* m, const int64_t* n, int32_t q, uint64_t seed,
+                     urv_batch_plan** plan) {
+  clear_last_error();
+  if (!plan) {
+    set_last_error("urv_batch_create: null plan pointer");
+    return URV_EINVAL;
+  }
+  *plan = nullptr;
+  if (count < 1 || count > (int64_t{1} << 24) || !m || !n || q < 0) {
+    set_last_error("urv_batch_create: need count >= 1, size arrays and q >= 0");
+    return URV_EINVAL;
+  }
+  for (int64_t i = 0; i < count; ++i) {
+    if (n[i] < 1 || m[i] < n[i]) {
+      set_last_error("urv_batch_create: every matrix needs 1 <= n <= m");
+      return URV_EINVAL;
+    }
+    if (m[i] > urv::kBatchMaxRows) {
+      set_last_error("urv_batch_create: the batched kernel takes at most 1024 rows per matrix");
+      return URV_ENOTSUP;
+    }
+  }
+  auto* p = new urv_batch_plan();
+  p->count = count;
+  p->q = q;
+  p->seed = seed;
+  p->items.resize(static_cast<size_t>(count));
+  size_t floats = 0;
+  std::vector<size_t> off(static_cast<size_t>(count));
+  for (int64_t i = 0; i < count; ++i) {
+    off[static_cast<size_t>(i)] = floats;
+    floats += urv::item_scratch_floats(m[i], n[i]);
+  }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->scratch), std::max<size_t>(floats, 1) * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_items), sizeof(urv::BatchItem) * count);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_order), sizeof(int) * count);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_counters), 2 * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemset(p->d_counters, 0, 2 * sizeof(unsigned));
+  if (e != hipSuccess) {
+    const int rc = urv::hip_status(e, "urv_batch_create");
+    hipFree(p->scratch);
+    hipFree(p->d_items);
+    hipFree(p->d_order);
+    hipFree(p->d_counters);
+    delete p;
+    return rc;
+  }
+  for (int64_t i = 0; i < count; ++i) {
+    urv::BatchItem& it = p->items[static_cast<size_t>(i)];
+    it.m = static_cast<int>(m[i]);
+    it.n = static_cast<int>(n[i]);
+    it.seed = seed + static_cast<uint64_t>(i);
+    float* base = reinterpret_cast<float*>(p->scratch) + off[static_cast<size_t>(i)];
+    auto take = [&](int64_t elems) {
+      float* r = base;
+      base += urv::align_up(static_cast<size_t>(elems), 64);
+      return r;
+    };
+    it.X = take(m[i] * n[i]);
+    it.Q = take(m[i] * n[i]);
+    it.Vr = take(m[i] * n[i]);
+    it.Y = take(n[i] * n[i]);
+    it.Vc = take(n[i] * n[i]);
+    it.T = take(urv::kNBMax * n[i]);
+    it.Wb = take(urv::kNBMax * n[i]);
+    it.W2b = take(urv::kNBMax * n[i]);
+  }
+  // largest first (LPT): cost ~ m n^2, ties by index
+  p->order.resize(static_cast<size_t>(count));
+  std::iota(p->order.begin(), p->order.end(), 0);
+  std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) {
+    return static_cast<double>(m[a]) * n[a] * n[a] > static_cast<double>(m[b]) * n[b] * n[b];
+  });
+  e = hipMemcpy(p->d_order, p->order.data(), sizeof(int) * count, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    const int rc = urv::hip_status(e, "urv_batch_create");
+    hipFree(p->scratch);
+    hipFree(p->d_items);
+    hipFree(p->d_order);
+    hipFree(p->d_counters);
+    delete p;
+    return rc;
+  }
+  *plan = p;
+  return URV_OK;
+}
+
+int urv_batch_set_buffers(urv_batch_plan* p, const float* const* A, float* const* U, float* const* R,
+                          float* const* V) {
+  clear_last_error();
+  if (!p || !A || !U || !R || !V) {
+    set_last_error("urv_batch_set_buffers: null argument");
+    return URV_EINVAL;
+  }
+  for (int64_t i = 0; i < p->count; ++i) {
+    if (!A[i] || !U[i] || !R[i] || !V[i]) {
+      set_last_error("urv_batch_set_buffers: null matrix pointer");
+      return URV_EINVAL;
+    }
+    urv::BatchItem& it = p->items[static_cast<size_t>(i)];
+    it.A = A[i];
+    it.U = U[i];
+    it.R = R[i];
+    it.V = V[i];
+  }
+  URV_HIP(hipMemcpy(p->d_items, p->items.data(), sizeof(urv::BatchItem) * p->count, hipMemcpyHostToDevice));
+  p->buffers = true;
+  return URV_OK;
+}
+
+int urv_batch_set_config(urv_batch_plan* p, int32_t nb, int32_t grid) {
+  clear_last_error();
+  if (!p || (nb != 16 && nb != 32) || grid < 1 || grid > 65536) {
+    set_last_error("urv_batch_set_config: need a plan, nb 16 or 32 and 1 <= grid <= 65536");
+    return URV_EINVAL;
+  }
+  if (p->nb != nb || p->grid != grid) drop_graph(p);
+  p->nb = nb;
+  p->grid = grid;
+  return URV_OK;
+}
+
+int urv_batch_get_config(const urv_batch_plan* p, int32_t* nb, int32_t* grid) {
+  clear_last_error();
+  if (!p || !nb || !grid) {
+    set_last_error("urv_batch_get_config: null argument");
+    return URV_EINVAL;
+  }
+  *nb = p->nb;
+  *grid = p->grid;
+  return URV_OK;
+}
+
+int urv_batch_run(urv_batch_plan* p, void* stream) {
+  clear_last_error();
+  URV_TRY(check_plan(p, "urv_batch_run"));
+  return urv::launch_batched(p->nb, p->grid, p->d_items, p->d_order, static_cast<int>(p->count), p->q,
+                             p->d_counters, static_cast<hipStream_t>(stream));
+}
+
+int urv_batch_run_graph(urv_batch_plan* p, void* stream) {
+  clear_last_error();
+  URV_TRY(check_plan(p, "urv_batch_run_graph"));
+  if (!p->exec) {
+    if (!p->cap) URV_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+    URV_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = urv::launch_batched(p->nb, p->grid, p->d_items, p->d_order, static_cast<int>(p->count), p->q,
+                                       p->d_counters, p->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap, &g);
+    if (rc != URV_OK) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    URV_HIP(e);
+    p->graph = g;
+    URV_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+  }
+  URV_HIP(hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream)));
+  return URV_OK;
+}
+
+int urv_batch_autotune(urv_batch_plan* p, void* stream, double* best_ms) {
+  clear_last_error();
+  URV_TRY(check_plan(p, "urv_batch_autotune"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  URV_HIP(hipEventCreate(&e0));
+  URV_HIP(hipEventCreate(&e1));
+  float best = -1.f;
+  int best_nb = p->nb, best_grid = p->grid;
+  int rc = URV_OK;
+  for (int nb : kCandNB) {
+    for (int grid : kCandGrid) {
+      // one untimed run, then one timed run of the whole batch
+      rc = urv::launch_batched(nb, grid, p->d_items, p->d_order, static_cast<int>(p->count), p->q, p->d_counters, s);
+      if (rc == URV_OK && hipEventRecord(e0, s) != hipSuccess) rc = URV_EDEVICE;
+      if (rc == URV_OK)
+        rc = urv::launch_batched(nb, grid, p->d_items, p->d_order, static_cast<int>(p->count), p->q, p->d_counters, s);
+      if (rc == URV_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        rc = urv::hip_status(hipGetLastError(), "urv_batch_autotune");
+      if (rc != URV_OK) break;
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (best < 0.f || ms < best) {
+        best = ms;
+        best_nb = nb;
+        best_grid = grid;
+      }
+    }
+    if (rc != URV_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  URV_TRY(rc);
+  if (best_ms) *best_ms = best;
+  return urv_batch_set_config(p, best_nb, best_grid);
+}
+
+void urv_batch_destroy(urv_batch_plan* p) {
+  if (!p) return;
+  drop_graph(p);
+  if (p->cap) hipStreamDestroy(p->cap);
+  hipFree(p->scratch);
+  hipFree(p->d_items);
+  hipFree(p->d_order);
+  hipFree(p->d_counters);
+  delete p;
+}
+
+}  // extern "C"

@@ -64,7 +64,9 @@ TAPE_MODES = {"all": 0, "v": 1, "none": 2}
 EXPORTS = ["urv_opts_init", "urv_factor_ex", "urv_factor", "urv_workspace_size", "urv_gaussian",
            "urv_dgemm", "urv_qr_pos", "urv_qr_pos_f32", "urv_metrics", "urv_strerror", "urv_last_error",
            "urv_grad_opts_init", "urv_tape_bytes", "urv_grad_workspace_size", "urv_factor_tape",
-           "urv_factor_backward", "urv_qr_adjoint", "urv_truncation_loss"]
+           "urv_factor_backward", "urv_qr_adjoint", "urv_truncation_loss",
+           "urv_batch_create", "urv_batch_set_buffers", "urv_batch_set_config", "urv_batch_get_config",
+           "urv_batch_autotune", "urv_batch_run", "urv_batch_run_graph", "urv_batch_destroy"]
 
 _lib = None
 
@@ -106,9 +108,21 @@ def lib() -> ctypes.CDLL:
     L.urv_factor_backward.argtypes = [P, I64, I64, I32, P, P, P, P, P, P, P, P, P, GO]
     L.urv_qr_adjoint.argtypes = [P, P, I64, I64, P, P, P, I32, P]
     L.urv_truncation_loss.argtypes = [P, I64, I64, P, P, P, I64, P, P, P, P, P, GO]
+    PI64 = ctypes.POINTER(ctypes.c_int64)
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    L.urv_batch_create.argtypes = [I64, PI64, PI64, I32, U64, ctypes.POINTER(ctypes.c_void_p)]
+    L.urv_batch_set_buffers.argtypes = [P, PP, PP, PP, PP]
+    L.urv_batch_set_config.argtypes = [P, I32, I32]
+    L.urv_batch_get_config.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    L.urv_batch_autotune.argtypes = [P, P, ctypes.POINTER(D)]
+    L.urv_batch_run.argtypes = [P, P]
+    L.urv_batch_run_graph.argtypes = [P, P]
+    L.urv_batch_destroy.argtypes = [P]
+    L.urv_batch_destroy.restype = None
     for name in ("urv_factor_ex", "urv_factor", "urv_gaussian", "urv_dgemm", "urv_qr_pos", "urv_qr_pos_f32",
                  "urv_metrics", "urv_factor_tape", "urv_factor_backward", "urv_qr_adjoint",
-                 "urv_truncation_loss"):
+                 "urv_truncation_loss", "urv_batch_create", "urv_batch_set_buffers", "urv_batch_set_config",
+                 "urv_batch_get_config", "urv_batch_autotune", "urv_batch_run", "urv_batch_run_graph"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -410,3 +424,76 @@ def truncation_loss(A, U, R, V, k: int, seeds: bool = True, workspace=None):
     _check(lib().urv_truncation_loss(_ptr(A), m, n, _ptr(U), _ptr(R), _ptr(V), k, ctypes.c_void_p(L.data_ptr()),
                                      _ptr(dU), _ptr(dR), _ptr(dV), _ptr(dA), ctypes.byref(o)))
     return L, dU, dR, dV, dA
+
+
+# ---------------------------------------------------------------- batched factorisation
+class BatchPlan:
+    """Many FP32 matrices (1 <= n_i <= m_i <= 1024) factored by one persistent
+    launch (include/urv.h, urv_batch_*).  Matrix i uses G from seed + i."""
+
+    def __init__(self, ms, ns, q: int = 1, seed: int = 0):
+        count = len(ms)
+        if len(ns) != count:
+            raise ValueError("ms and ns differ in length")
+        self.ms, self.ns, self.q, self.seed = [int(x) for x in ms], [int(x) for x in ns], int(q), int(seed)
+        marr = (ctypes.c_int64 * count)(*self.ms)
+        narr = (ctypes.c_int64 * count)(*self.ns)
+        self._plan = ctypes.c_void_p()
+        _check(lib().urv_batch_create(count, marr, narr, self.q, self.seed & (2**64 - 1), ctypes.byref(self._plan)))
+        self._keep = None
+
+    def set_buffers(self, A, U, R, V) -> None:
+        """Lists of packed column-major float32 CUDA tensors (A read only)."""
+        torch = _torch()
+        count = len(self.ms)
+        for name, lst, shapes in (("A", A, [(m, n) for m, n in zip(self.ms, self.ns)]),
+                                  ("U", U, [(m, n) for m, n in zip(self.ms, self.ns)]),
+                                  ("R", R, [(n, n) for n in self.ns]), ("V", V, [(n, n) for n in self.ns])):
+            if len(lst) != count:
+                raise ValueError("%s: expected %d tensors" % (name, count))
+            for t, shp in zip(lst, shapes):
+                if (not t.is_cuda or t.dtype != torch.float32 or tuple(t.shape) != shp
+                        or (shp[1] > 1 and t.stride(1) != shp[0]) or (shp[0] > 1 and t.stride(0) != 1)):
+                    raise ValueError("%s: need packed column-major float32 CUDA tensors of the plan's sizes" % name)
+        arrs = [(ctypes.c_void_p * count)(*[t.data_ptr() for t in lst]) for lst in (A, U, R, V)]
+        _check(lib().urv_batch_set_buffers(self._plan, *arrs))
+        self._keep = (list(A), list(U), list(R), list(V))
+
+    def set_config(self, nb: int, grid: int) -> None:
+        _check(lib().urv_batch_set_config(self._plan, nb, grid))
+
+    def config(self):
+        nb, grid = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().urv_batch_get_config(self._plan, ctypes.byref(nb), ctypes.byref(grid)))
+        return nb.value, grid.value
+
+    def autotune(self) -> float:
+        ms = ctypes.c_double()
+        _check(lib().urv_batch_autotune(self._plan, _stream_ptr(), ctypes.byref(ms)))
+        return ms.value
+
+    def run(self, graph: bool = False) -> None:
+        fn = lib().urv_batch_run_graph if graph else lib().urv_batch_run
+        _check(fn(self._plan, _stream_ptr()))
+
+    def close(self) -> None:
+        if self._plan:
+            _torch().cuda.synchronize()
+            lib().urv_batch_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._plan:
+                lib().urv_batch_destroy(self._plan)
+        except Exception:  # pragma: no cover - interpreter shutdown
+            pass
+
+
+def batch_outputs(ms, ns, device=None):
+    """Packed column-major float32 (U, R, V) lists for the given sizes."""
+    torch = _torch()
+    U = [empty_colmajor(m, n, dtype=torch.float32, device=device) for m, n in zip(ms, ns)]
+    R = [empty_colmajor(n, n, dtype=torch.float32, device=device) for n in ns]
+    V = [empty_colmajor(n, n, dtype=torch.float32, device=device) for n in ns]
+    return U, R, V

@@ -197,3 +197,32 @@ def test_tape_and_workspace_sizes():
     w_big = L.urv_grad_workspace_size(1000, 500, 2, ctypes.byref(_gopts()))
     assert 0 < w_small < w_big
     assert L.urv_grad_workspace_size(3, 5, 2, ctypes.byref(_gopts())) == 0
+
+
+# ---------------------------------------------------------------- batched entry points
+def test_batch_create_validates_before_any_device_work():
+    L = urv.lib()
+    plan = ctypes.c_void_p()
+
+    def create(ms, ns, q=1):
+        arr_m = (ctypes.c_int64 * len(ms))(*ms)
+        arr_n = (ctypes.c_int64 * len(ns))(*ns)
+        return L.urv_batch_create(len(ms), arr_m, arr_n, q, 0, ctypes.byref(plan))
+
+    assert create([10, 20], [5, 30]) == urv.URV_EINVAL      # n > m
+    assert create([10, 20], [0, 3]) == urv.URV_EINVAL       # n = 0
+    assert create([10], [5], q=-1) == urv.URV_EINVAL
+    assert create([2000], [5]) == urv.URV_ENOTSUP           # more than 1024 rows
+    assert L.urv_batch_create(0, None, None, 1, 0, ctypes.byref(plan)) == urv.URV_EINVAL
+    assert L.urv_batch_create(1, None, None, 1, 0, None) == urv.URV_EINVAL
+    assert plan.value is None
+
+
+def test_batch_calls_reject_a_null_plan():
+    L = urv.lib()
+    assert L.urv_batch_run(None, None) == urv.URV_EINVAL
+    assert L.urv_batch_run_graph(None, None) == urv.URV_EINVAL
+    assert L.urv_batch_autotune(None, None, None) == urv.URV_EINVAL
+    assert L.urv_batch_set_config(None, 16, 256) == urv.URV_EINVAL
+    assert L.urv_batch_set_buffers(None, None, None, None, None) == urv.URV_EINVAL
+    L.urv_batch_destroy(None)
