@@ -11,8 +11,10 @@ kernel (the FP64 GEMM A V, timed with HIP events on the stream it runs on),
 the mixed-precision forms (BF16 / FP16 power steps) against plain FP64 on the
 same input and on the 16000 x 8000 noisy exp(-j/800) matrix, the
 differentiation workload (forward, truncation loss and reverse sweep of a
-2048 x 2048 FP32 matrix with G fixed, against the FP64 oracle's gradient), and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+2048 x 2048 FP32 matrix with G fixed, against the FP64 oracle's gradient), the
+batched workload (512 FP32 matrices of mixed sizes in one persistent launch,
+replayed from a graph), and the FP64 CPU oracle timed on a bounded sample of
+the same workload.
 """
 from __future__ import annotations
 
@@ -195,6 +197,87 @@ def bench_grad(steps: int, warmup: int, oracle_check: bool) -> dict:
     return res
 
 
+def batched_workload(device):
+    """512 FP32 matrices, m ~ U[64, 1024], n ~ U[32, m], sigma_j = 10^(-6 (j-1)/(n-1)),
+    drawn on the GPU (Haar factors from QRs of seeded Gaussians)."""
+    import urv_inputs as gen
+
+    rng = gen.generator(1812, 6)
+    ms = [int(x) for x in rng.integers(64, 1025, size=512)]
+    ns = [int(rng.integers(32, m + 1)) for m in ms]
+    A = [gen.spectral_matrix(m, n, gen.spectrum("geometric6", n), 1812 + i, device=device).float().t().contiguous().t()
+         for i, (m, n) in enumerate(zip(ms, ns))]
+    return ms, ns, A
+
+
+def bench_batched(steps: int, warmup: int, oracle_sample: int) -> dict:
+    """The batched workload: one persistent launch per step, replayed from a graph."""
+    import numpy as np
+    import torch
+
+    from paper_1812_06007_amd import urv
+
+    q = 1
+    ms, ns, A = batched_workload("cuda")
+    U, R, V = urv.batch_outputs(ms, ns)
+    plan = urv.BatchPlan(ms, ns, q=q, seed=1812)
+    plan.set_buffers(A, U, R, V)
+    tuned_ms = plan.autotune()
+    nb, grid = plan.config()
+    for _ in range(warmup):
+        plan.run(graph=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.run(graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    fl = sum(executed_flops(m, n, q, "full") for m, n in zip(ms, ns))
+    # the largest matrix alone, on one workgroup: the floor of a one-workgroup-per-matrix schedule
+    big = int(np.argmax([m * n * n for m, n in zip(ms, ns)]))
+    one = urv.BatchPlan([ms[big]], [ns[big]], q=q, seed=1812 + big)
+    u1, r1, v1 = urv.batch_outputs([ms[big]], [ns[big]])
+    one.set_buffers([A[big]], u1, r1, v1)
+    one.set_config(nb, 1)
+    one.run()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    one.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    big_ms = e0.elapsed_time(e1)
+    res = {"workload": "512 FP32 matrices, m ~ U[64,1024], n ~ U[32,m], sigma_j = 10^(-6(j-1)/(n-1)), "
+                       "G from seed 1812+i, q=1 FULL; one persistent launch per step, replayed from a graph",
+           "dtype": "f32", "ms_per_batch": ms_step, "flops_executed": fl,
+           "tflops": fl / (ms_step * 1e-3) / 1e12,
+           "frac_fp32_peak": fl / (ms_step * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+           "autotuned": {"nb": nb, "workgroups": grid, "ms": tuned_ms},
+           "largest_matrix_alone": {"m": ms[big], "n": ns[big], "ms": big_ms}}
+    one.close()
+    plan.close()
+    if oracle_sample > 0:
+        from oracle import oracle
+
+        oracle.build()
+        idx = list(range(0, 512, max(1, 512 // oracle_sample)))[:oracle_sample]
+        t0 = time.perf_counter()
+        for i in idx:
+            A_np = A[i].t().contiguous().t().cpu().double().numpy()
+            oracle.urv(A_np, q, seed=1812 + i)
+        dt = time.perf_counter() - t0
+        fl_s = sum(executed_flops(ms[i], ns[i], q, "full") for i in idx)
+        cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)) or 1)
+        res["cpu_baseline"] = {"value": fl_s / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+                               "seconds": dt,
+                               "sample": "FP64 oracle on %d of the 512 matrices (every %dth): %.3e flop"
+                                         % (len(idx), 512 // oracle_sample, fl_s)}
+    return res
+
+
 def time_factor(A, q: int, variant: str, precision: str, steps: int, warmup: int, out) -> float:
     """Mean milliseconds of urv.factor over `steps` runs (HIP events on the current stream)."""
     import torch
@@ -280,6 +363,10 @@ def main() -> int:
                     help="timed steps of the differentiation workload (0: skip)")
     ap.add_argument("--grad-only", action="store_true",
                     help="run only the differentiation workload (for profiling) and exit")
+    ap.add_argument("--batched-steps", type=int, default=5,
+                    help="timed launches of the batched workload (0: skip)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched workload (for profiling) and exit")
     ap.add_argument("--gemm-only", action="store_true",
                     help="run only the A V GEMM launches (for counter collection) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -316,6 +403,11 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print("[bench] 3 copies of 1 GiB done", file=sys.stderr, flush=True)
+        return 0
+
+    if args.batched_only:
+        print("[bench] batched workload only", file=sys.stderr, flush=True)
+        print(json.dumps(bench_batched(max(args.batched_steps, 1), args.warmup, 0)))
         return 0
 
     if args.grad_only:
@@ -410,6 +502,11 @@ def main() -> int:
         print("[bench] differentiation workload (2048x2048 FP32, q=2, k=256)", file=sys.stderr, flush=True)
         grad = bench_grad(args.grad_steps, args.warmup, args.cpu_sample > 0)
 
+    batched = None
+    if args.batched_steps > 0:
+        print("[bench] batched workload (512 FP32 matrices up to 1024 x 1024, q=1)", file=sys.stderr, flush=True)
+        batched = bench_batched(args.batched_steps, args.warmup, 16 if args.cpu_sample > 0 else 0)
+
     cpu = None
     if args.cpu_sample > 0:
         print("[bench] oracle CPU baseline on a %dx%d sample" % (args.cpu_sample, args.cpu_sample),
@@ -446,6 +543,7 @@ def main() -> int:
                      "launch_ms": gemm_ms, "flop_per_launch": 2.0 * m * n * n},
         "mixed_vs_fp64": mixed,
         "differentiation": grad,
+        "batched": batched,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
     }
     print(json.dumps(out))

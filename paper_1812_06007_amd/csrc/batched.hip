@@ -13,7 +13,8 @@
 // largest first, so the long ones start early and the short ones fill the
 // tail.  Within a workgroup:
 //  * GEMMs (A V, A^T W and the block-reflector updates) on FP32 MFMA
-//    (v_mfma_f32_16x16x4f32), 64 x 64 tiles staged through LDS;
+//    (v_mfma_f32_16x16x4f32), 64 x 64 tiles (32 x 64 for the products with
+//    32 rows) staged through double-buffered LDS, 4 waves;
 //  * the panel of NB columns lives in registers (4 rows per lane, rows up to
 //    1024); each column takes two workgroup reductions in a fixed order: the
 //    norm below the pivot, then the reflector's products with the remaining
@@ -60,11 +61,19 @@ struct BatchItem {
   float* W2b = nullptr;      // kNBMax x n
 };
 
+constexpr int GBK = 32;  // k step of the workgroup GEMM
+constexpr int RED_LD = BT + BT / 32;  // reduction staging: value v of lane t at v RED_LD + t + t / 32
+constexpr int PARTS = BT / 32;
+
 struct Lds {
-  float As[16][64 + 1];
-  float Bs[16][64 + 1];
-  float red[kNBMax * (BT + BT / 32)];  // value v of lane t at v (BT + 8) + t + t / 32
-  float part[kNBMax][9];
+  union {
+    struct {
+      float As[2][GBK][64 + 1];  // double-buffered tiles of the GEMM
+      float Bs[2][GBK][64 + 1];
+    } g;
+    float red[kNBMax * RED_LD];
+  } u;
+  float part[kNBMax][PARTS + 1];
   float res[kNBMax];
   float gram[kNBMax][kNBMax + 1];      // gram[b][c] = v_b^T v_c, b < c
   float tau[kNBMax];
@@ -74,19 +83,20 @@ struct Lds {
 };
 
 // Sums vals[0..CNT) over the workgroup into s.res (every lane may read it on
-// return).  Lane (v, p) = (t / 8, t % 8) adds lanes 32p .. 32p + 31 of value
-// v, then lane v adds the 8 parts: a fixed order, bitwise reproducible.
+// return).  Lane (v, p) = (t / PARTS, t % PARTS) adds lanes 32p .. 32p + 31 of
+// value v, then lane v adds the PARTS parts: a fixed order, bitwise
+// reproducible.
 template <int CNT>
 __device__ __forceinline__ void block_sum(const float (&vals)[CNT], Lds& s) {
-  static_assert(CNT >= 1 && CNT <= kNBMax, "reduction width");
+  static_assert(CNT >= 1 && CNT <= kNBMax && kNBMax * PARTS == BT, "reduction width");
   const int t = threadIdx.x;
 #pragma unroll
-  for (int v = 0; v < CNT; ++v) s.red[v * (BT + 8) + t + (t >> 5)] = vals[v];
+  for (int v = 0; v < CNT; ++v) s.u.red[v * RED_LD + t + (t >> 5)] = vals[v];
   __syncthreads();
   {
-    const int v = t >> 3, p = t & 7;
+    const int v = t / PARTS, p = t % PARTS;
     if (v < CNT) {
-      const float* r = &s.red[v * (BT + 8) + p * 33];
+      const float* r = &s.u.red[v * RED_LD + p * 33];
       float a = 0.f;
 #pragma unroll 8
       for (int i = 0; i < 32; ++i) a += r[i];
@@ -97,74 +107,113 @@ __device__ __forceinline__ void block_sum(const float (&vals)[CNT], Lds& s) {
   if (t < CNT) {
     float a = 0.f;
 #pragma unroll
-    for (int p = 0; p < 8; ++p) a += s.part[t][p];
+    for (int p = 0; p < PARTS; ++p) a += s.part[t][p];
     s.res[t] = a;
   }
   __syncthreads();
 }
 
 // C (M x N) = alpha op(A) B + beta C for the whole workgroup; op(A) = A (TA
-// false, A M x K) or A^T (A K x M).  64 x 64 tiles of C, K in steps of 16
-// through LDS; each wave owns a 32 x 32 quarter as 2 x 2 MFMA blocks.  beta ==
-// 0 never reads C.  C must not overlap A or B.  Ends with a barrier, so the
+// false, A M x K) or A^T (A K x M).  BM x 64 tiles of C (BM = 64, or 32 for
+// the short products with M <= 32), K in steps of GBK through double-buffered
+// LDS with the next step's global loads in flight during the current step's
+// MFMAs; the 4 waves are 2 x 2, each owning (BM / 2) x 32 of the tile.  beta
+// == 0 never reads C.  C must not overlap A or B.  Ends with a barrier, so the
 // workgroup may read C right after.
-template <bool TA>
-__device__ __forceinline__ void wg_gemm(int M, int N, int K, float alpha, const float* __restrict__ A, int lda,
-                        const float* __restrict__ B, int ldb, float beta, float* __restrict__ C, int ldc,
-                        Lds& s) {
+template <bool TA, int BM>
+__device__ __forceinline__ void wg_gemm_t(int M, int N, int K, float alpha, const float* __restrict__ A, int lda,
+                                          const float* __restrict__ B, int ldb, float beta, float* __restrict__ C,
+                                          int ldc, Lds& s) {
+  constexpr int FM = BM / 32;                  // 16-row MFMA blocks per wave
+  constexpr int FN = 2;                        // 16-column MFMA blocks per wave
+  constexpr int LA = BM * GBK / BT, LB = 64 * GBK / BT;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int lrow = lane & 15, lk = lane >> 4;
-  const int tiles_m = (M + 63) / 64, tiles_n = (N + 63) / 64;
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + 63) / 64;
+  float ra[LA], rb[LB];
+  auto load = [&](int m0, int n0, int k0) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int qa = t + BT * r;
+      int i, k;
+      if (!TA) {
+        i = qa % BM;
+        k = qa / BM;
+      } else {
+        k = qa % GBK;
+        i = qa / GBK;
+      }
+      const int gi = m0 + i, gk = k0 + k;
+      float v = 0.f;
+      if (gi < M && gk < K)
+        v = TA ? A[gk + static_cast<int64_t>(gi) * lda] : A[gi + static_cast<int64_t>(gk) * lda];
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int qb = t + BT * r;
+      const int k = qb % GBK, j = qb / GBK;
+      const int gj = n0 + j, gk = k0 + k;
+      rb[r] = (gj < N && gk < K) ? B[gk + static_cast<int64_t>(gj) * ldb] : 0.f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int qa = t + BT * r;
+      int i, k;
+      if (!TA) {
+        i = qa % BM;
+        k = qa / BM;
+      } else {
+        k = qa % GBK;
+        i = qa / GBK;
+      }
+      s.u.g.As[buf][k][i] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int qb = t + BT * r;
+      s.u.g.Bs[buf][qb % GBK][qb / GBK] = rb[r];
+    }
+  };
   for (int tile = 0; tile < tiles_m * tiles_n; ++tile) {
-    const int m0 = (tile % tiles_m) * 64, n0 = (tile / tiles_m) * 64;
-    f4 acc[2][2];
+    const int m0 = (tile % tiles_m) * BM, n0 = (tile / tiles_m) * 64;
+    f4 acc[FM][FN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
+      for (int b = 0; b < FN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    const int nk = (K + GBK - 1) / GBK;
+    load(m0, n0, 0);
+    store(0);
+    __syncthreads();
+    for (int ks = 0; ks < nk; ++ks) {
+      const int cur = ks & 1;
+      if (ks + 1 < nk) load(m0, n0, (ks + 1) * GBK);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int qa = t + BT * r;
-        int i, k;
-        if (!TA) {
-          i = qa & 63;
-          k = qa >> 6;
-        } else {
-          k = qa & 15;
-          i = qa >> 4;
-        }
-        const int gi = m0 + i, gk = k0 + k;
-        float v = 0.f;
-        if (gi < M && gk < K)
-          v = TA ? A[gk + static_cast<int64_t>(gi) * lda] : A[gi + static_cast<int64_t>(gk) * lda];
-        s.As[k][i] = v;
-        const int kb = qa & 15, j = qa >> 4;
-        const int gj = n0 + j, gkb = k0 + kb;
-        s.Bs[kb][j] = (gj < N && gkb < K) ? B[gkb + static_cast<int64_t>(gj) * ldb] : 0.f;
+      for (int kk = 0; kk < GBK / 4; ++kk) {
+        float fa[FM], fb[FN];
+#pragma unroll
+        for (int a = 0; a < FM; ++a) fa[a] = s.u.g.As[cur][kk * 4 + lk][wm * (BM / 2) + a * 16 + lrow];
+#pragma unroll
+        for (int b = 0; b < FN; ++b) fb[b] = s.u.g.Bs[cur][kk * 4 + lk][wn * 32 + b * 16 + lrow];
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[b], fa[a], acc[a][b], 0, 0, 0);
       }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        float fa[2], fb[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) fa[a] = s.As[kk * 4 + lk][wm * 32 + a * 16 + lrow];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) fb[b] = s.Bs[kk * 4 + lk][wn * 32 + b * 16 + lrow];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[b], fa[a], acc[a][b], 0, 0, 0);
-      }
+      if (ks + 1 < nk) store(cur ^ 1);
       __syncthreads();
     }
-    // lane holds C(m0 + 32 wm + 16 a + lrow, n0 + 32 wn + 16 b + 4 lk + r)
+    // lane holds C(m0 + (BM/2) wm + 16 a + lrow, n0 + 32 wn + 16 b + 4 lk + r)
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int gm = m0 + wm * 32 + a * 16 + lrow;
+    for (int a = 0; a < FM; ++a) {
+      const int gm = m0 + wm * (BM / 2) + a * 16 + lrow;
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < FN; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int gn = n0 + wn * 32 + b * 16 + 4 * lk + r;
@@ -176,6 +225,16 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, float alpha, const 
     }
   }
   __syncthreads();
+}
+
+template <bool TA>
+__device__ __forceinline__ void wg_gemm(int M, int N, int K, float alpha, const float* __restrict__ A, int lda,
+                                        const float* __restrict__ B, int ldb, float beta, float* __restrict__ C,
+                                        int ldc, Lds& s) {
+  if (M <= 32)
+    wg_gemm_t<TA, 32>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+  else
+    wg_gemm_t<TA, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
 }
 
 // Wout (jb x ncols, ld kNBMax) = op(T) Win for the jb x jb upper triangular T
