@@ -223,7 +223,7 @@ def bench_batched(steps: int, warmup: int, oracle_sample: int) -> dict:
     plan = urv.BatchPlan(ms, ns, q=q, seed=1812)
     plan.set_buffers(A, U, R, V)
     tuned_ms = plan.autotune()
-    nb, grid = plan.config()
+    nb, grid, team = plan.config()
     for _ in range(warmup):
         plan.run(graph=True)
     torch.cuda.synchronize()
@@ -242,7 +242,7 @@ def bench_batched(steps: int, warmup: int, oracle_sample: int) -> dict:
     one = urv.BatchPlan([ms[big]], [ns[big]], q=q, seed=1812 + big)
     u1, r1, v1 = urv.batch_outputs([ms[big]], [ns[big]])
     one.set_buffers([A[big]], u1, r1, v1)
-    one.set_config(nb, 1)
+    one.set_config(nb, 1, 1)
     one.run()
     torch.cuda.synchronize()
     e0.record(stream)
@@ -255,7 +255,7 @@ def bench_batched(steps: int, warmup: int, oracle_sample: int) -> dict:
            "dtype": "f32", "ms_per_batch": ms_step, "flops_executed": fl,
            "tflops": fl / (ms_step * 1e-3) / 1e12,
            "frac_fp32_peak": fl / (ms_step * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS,
-           "autotuned": {"nb": nb, "workgroups": grid, "ms": tuned_ms},
+           "autotuned": {"nb": nb, "workgroups": grid, "team_max": team, "ms": tuned_ms},
            "largest_matrix_alone": {"m": ms[big], "n": ns[big], "ms": big_ms}}
     one.close()
     plan.close()

@@ -262,14 +262,23 @@ int urv_batch_create(int64_t count, const int64_t* m, const int64_t* n, int32_t 
 int urv_batch_set_buffers(urv_batch_plan* plan, const float* const* A, float* const* U, float* const* R,
                           float* const* V);
 
-/* Panel width nb (16 or 32) and number of persistent workgroups (1..65536)
- * of the launch; urv_batch_autotune chooses them by timing. */
-int urv_batch_set_config(urv_batch_plan* plan, int32_t nb, int32_t grid);
-int urv_batch_get_config(const urv_batch_plan* plan, int32_t* nb, int32_t* grid);
+/* Panel width nb (16 or 32), number of persistent workgroups (1..65536) and
+ * largest team (1..64).  With team_max > 1 a matrix whose cost m n^2 exceeds
+ * the average load of one workgroup is factored by a team of up to team_max
+ * workgroups (GEMM tiles and element ranges split over the members, the panels
+ * on one member, device-wide barriers between the phases); teams need every
+ * workgroup resident at once, so grid must not exceed the device's capacity
+ * for the kernel (URV_EINVAL otherwise).  Results do not depend on grid or
+ * team_max, bit for bit.  Not while a run of the plan is in flight.
+ * urv_batch_create selects nb 32, the device's capacity and team_max 1;
+ * urv_batch_autotune chooses by timing. */
+int urv_batch_set_config(urv_batch_plan* plan, int32_t nb, int32_t grid, int32_t team_max);
+int urv_batch_get_config(const urv_batch_plan* plan, int32_t* nb, int32_t* grid, int32_t* team_max);
 
-/* Times every (nb, grid) candidate on the plan's matrices (running the whole
- * batch twice each on stream, blocking) and keeps the fastest; *best_ms
- * (HOST, may be NULL) receives its time.  The outputs hold a valid result. */
+/* Times every (nb, team_max) candidate, with the grid at the device's
+ * capacity, on the plan's matrices (running the whole batch twice each on
+ * stream, blocking) and keeps the fastest; *best_ms (HOST, may be NULL)
+ * receives its time.  The outputs hold a valid result. */
 int urv_batch_autotune(urv_batch_plan* plan, void* stream, double* best_ms);
 
 /* One persistent launch on stream (asynchronous; no allocation, no host-side
@@ -280,6 +289,10 @@ int urv_batch_run(urv_batch_plan* plan, void* stream);
  * first call (and after a configuration change), then the graph is launched
  * on stream. */
 int urv_batch_run_graph(urv_batch_plan* plan, void* stream);
+
+/* Blocking: URV_EDEVICE if a team barrier's bounded wait expired in a run so
+ * far (its outputs are then invalid), else URV_OK. */
+int urv_batch_status(urv_batch_plan* plan, void* stream);
 
 /* Frees the plan's device memory and graph (after the stream work that uses it). */
 void urv_batch_destroy(urv_batch_plan* plan);

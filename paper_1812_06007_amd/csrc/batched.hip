@@ -113,17 +113,56 @@ __device__ __forceinline__ void block_sum(const float (&vals)[CNT], Lds& s) {
   __syncthreads();
 }
 
+// A team of `size` workgroups factoring one matrix together; `member` is this
+// workgroup's rank.  Work of a phase is split over the members (GEMM tiles,
+// element ranges); the panel is factored by member 0; team_sync separates the
+// phases.  A team of one is a plain workgroup.
+struct Team {
+  int member = 0, size = 1;
+  unsigned* bar = nullptr;  // arrivals at the task's barriers (agent-scope counter)
+  unsigned* err = nullptr;  // raised when a bounded wait expires
+  unsigned phase = 0;       // barriers passed so far
+};
+
+constexpr long kTeamSpinLimit = 1l << 24;  // polls before a barrier wait gives up
+
+// Barrier of the whole team.  Lane 0 publishes its workgroup's writes with an
+// agent-scope fence, counts itself in, waits (bounded) until every member has
+// arrived, and fences again before the workgroup reads the others' results.
+__device__ __forceinline__ void team_sync(Team& tm) {
+  __syncthreads();
+  if (tm.size == 1) return;
+  ++tm.phase;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(tm.bar, 1u);
+    const unsigned target = tm.phase * static_cast<unsigned>(tm.size);
+    long spins = 0;
+    while (__hip_atomic_load(tm.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if ((++spins & 255) == 0 &&
+          (spins > kTeamSpinLimit || __hip_atomic_load(tm.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+        __hip_atomic_store(tm.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
 // C (M x N) = alpha op(A) B + beta C for the whole workgroup; op(A) = A (TA
 // false, A M x K) or A^T (A K x M).  BM x 64 tiles of C (BM = 64, or 32 for
 // the short products with M <= 32), K in steps of GBK through double-buffered
 // LDS with the next step's global loads in flight during the current step's
-// MFMAs; the 4 waves are 2 x 2, each owning (BM / 2) x 32 of the tile.  beta
-// == 0 never reads C.  C must not overlap A or B.  Ends with a barrier, so the
-// workgroup may read C right after.
+// MFMAs; the 4 waves are 2 x 2, each owning (BM / 2) x 32 of the tile.  The
+// members of a team take every size-th tile.  beta == 0 never reads C.  C must
+// not overlap A or B.  Ends with a team barrier, so the team may read C right
+// after.
 template <bool TA, int BM>
 __device__ __forceinline__ void wg_gemm_t(int M, int N, int K, float alpha, const float* __restrict__ A, int lda,
                                           const float* __restrict__ B, int ldb, float beta, float* __restrict__ C,
-                                          int ldc, Lds& s) {
+                                          int ldc, Lds& s, Team& tm) {
   constexpr int FM = BM / 32;                  // 16-row MFMA blocks per wave
   constexpr int FN = 2;                        // 16-column MFMA blocks per wave
   constexpr int LA = BM * GBK / BT, LB = 64 * GBK / BT;
@@ -178,7 +217,7 @@ __device__ __forceinline__ void wg_gemm_t(int M, int N, int K, float alpha, cons
       s.u.g.Bs[buf][qb % GBK][qb / GBK] = rb[r];
     }
   };
-  for (int tile = 0; tile < tiles_m * tiles_n; ++tile) {
+  for (int tile = tm.member; tile < tiles_m * tiles_n; tile += tm.size) {
     const int m0 = (tile % tiles_m) * BM, n0 = (tile / tiles_m) * 64;
     f4 acc[FM][FN];
 #pragma unroll
@@ -224,25 +263,25 @@ __device__ __forceinline__ void wg_gemm_t(int M, int N, int K, float alpha, cons
         }
     }
   }
-  __syncthreads();
+  team_sync(tm);
 }
 
 template <bool TA>
 __device__ __forceinline__ void wg_gemm(int M, int N, int K, float alpha, const float* __restrict__ A, int lda,
                                         const float* __restrict__ B, int ldb, float beta, float* __restrict__ C,
-                                        int ldc, Lds& s) {
+                                        int ldc, Lds& s, Team& tm) {
   if (M <= 32)
-    wg_gemm_t<TA, 32>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    wg_gemm_t<TA, 32>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
   else
-    wg_gemm_t<TA, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    wg_gemm_t<TA, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
 }
 
 // Wout (jb x ncols, ld kNBMax) = op(T) Win for the jb x jb upper triangular T
-// (ld kNBMax): op(T) = T^T when TRANS, else T.  Ends with a barrier.
+// (ld kNBMax): op(T) = T^T when TRANS, else T.  Ends with a team barrier.
 template <bool TRANS>
 __device__ __forceinline__ void small_tmul(const float* __restrict__ T, int jb, const float* __restrict__ Win,
-                           float* __restrict__ Wout, int ncols) {
-  for (int e = threadIdx.x; e < jb * ncols; e += BT) {
+                                           float* __restrict__ Wout, int ncols, Team& tm) {
+  for (int e = tm.member * BT + threadIdx.x; e < jb * ncols; e += tm.size * BT) {
     const int i = e % jb, col = e / jb;
     const float* w = Win + static_cast<int64_t>(col) * kNBMax;
     float acc = 0.f;
@@ -253,7 +292,7 @@ __device__ __forceinline__ void small_tmul(const float* __restrict__ T, int jb, 
     }
     Wout[i + static_cast<int64_t>(col) * kNBMax] = acc;
   }
-  __syncthreads();
+  team_sync(tm);
 }
 
 // One column c of the panel factorisation (c a compile-time constant, so the
@@ -387,45 +426,47 @@ __device__ __forceinline__ void panel_factor(float* __restrict__ P, int ldp, int
 // diagonal) when R is not null.
 template <int NB>
 __device__ __forceinline__ void qr_wg(float* X, int rows, int cols, int ldx, float* Q, int ldq, float* R, int ldr,
-                      const BatchItem& it, Lds& s) {
+                                      const BatchItem& it, Lds& s, Team& tm) {
+  const int e0 = tm.member * BT + static_cast<int>(threadIdx.x), es = tm.size * BT;
   const int ldv = rows;
   for (int j0 = 0; j0 < cols; j0 += NB) {
     const int jb = min(NB, cols - j0), mp = rows - j0;
     float* P = X + j0 + static_cast<int64_t>(j0) * ldx;
     float* Vp = it.Vr + j0 + static_cast<int64_t>(j0) * ldv;
     float* Tp = it.T + static_cast<int64_t>(j0) * kNBMax;
-    panel_factor<NB>(P, ldx, mp, jb, Vp, ldv, Tp, s);
+    if (tm.member == 0) panel_factor<NB>(P, ldx, mp, jb, Vp, ldv, Tp, s);
+    team_sync(tm);
     const int nrest = cols - j0 - jb;
     if (nrest > 0) {
       // C -= V (T^T (V^T C))
       float* C = X + j0 + static_cast<int64_t>(j0 + jb) * ldx;
-      wg_gemm<true>(jb, nrest, mp, 1.f, Vp, ldv, C, ldx, 0.f, it.Wb, kNBMax, s);
-      small_tmul<true>(Tp, jb, it.Wb, it.W2b, nrest);
-      wg_gemm<false>(mp, nrest, jb, -1.f, Vp, ldv, it.W2b, kNBMax, 1.f, C, ldx, s);
+      wg_gemm<true>(jb, nrest, mp, 1.f, Vp, ldv, C, ldx, 0.f, it.Wb, kNBMax, s, tm);
+      small_tmul<true>(Tp, jb, it.Wb, it.W2b, nrest, tm);
+      wg_gemm<false>(mp, nrest, jb, -1.f, Vp, ldv, it.W2b, kNBMax, 1.f, C, ldx, s, tm);
     }
   }
   // Q = H_1 ... H_k [I; 0], accumulated from the last block back
-  for (int e = threadIdx.x; e < rows * cols; e += BT) {
+  for (int e = e0; e < rows * cols; e += es) {
     const int i = e % rows, j = e / rows;
     Q[i + static_cast<int64_t>(j) * ldq] = (i == j) ? 1.f : 0.f;
   }
-  __syncthreads();
+  team_sync(tm);
   for (int j0 = ((cols - 1) / NB) * NB; j0 >= 0; j0 -= NB) {
     const int jb = min(NB, cols - j0), mp = rows - j0, nq = cols - j0;
     const float* Vp = it.Vr + j0 + static_cast<int64_t>(j0) * ldv;
     const float* Tp = it.T + static_cast<int64_t>(j0) * kNBMax;
     float* Qs = Q + j0 + static_cast<int64_t>(j0) * ldq;
-    wg_gemm<true>(jb, nq, mp, 1.f, Vp, ldv, Qs, ldq, 0.f, it.Wb, kNBMax, s);
-    small_tmul<false>(Tp, jb, it.Wb, it.W2b, nq);
-    wg_gemm<false>(mp, nq, jb, -1.f, Vp, ldv, it.W2b, kNBMax, 1.f, Qs, ldq, s);
+    wg_gemm<true>(jb, nq, mp, 1.f, Vp, ldv, Qs, ldq, 0.f, it.Wb, kNBMax, s, tm);
+    small_tmul<false>(Tp, jb, it.Wb, it.W2b, nq, tm);
+    wg_gemm<false>(mp, nq, jb, -1.f, Vp, ldv, it.W2b, kNBMax, 1.f, Qs, ldq, s, tm);
   }
   // sign fix: Q(:,j) *= sgn(R(j,j)), R(j,:) = sgn(R(j,j)) R(j,:), sgn(0) = +1
-  for (int e = threadIdx.x; e < rows * cols; e += BT) {
+  for (int e = e0; e < rows * cols; e += es) {
     const int i = e % rows, j = e / rows;
     if (X[j + static_cast<int64_t>(j) * ldx] < 0.f) Q[i + static_cast<int64_t>(j) * ldq] *= -1.f;
   }
   if (R) {
-    for (int e = threadIdx.x; e < cols * cols; e += BT) {
+    for (int e = e0; e < cols * cols; e += es) {
       const int i = e % cols, j = e / cols;
       float v = 0.f;
       if (i <= j) {
@@ -435,22 +476,23 @@ __device__ __forceinline__ void qr_wg(float* X, int rows, int cols, int ldx, flo
       R[i + static_cast<int64_t>(j) * ldr] = v;
     }
   }
-  __syncthreads();
+  team_sync(tm);
 }
 
 template <int NB>
-__device__ __forceinline__ void factor_one(const BatchItem& it, int q, Lds& s) {
+__device__ __forceinline__ void factor_one(const BatchItem& it, int q, Lds& s, Team& tm) {
   const int m = it.m, n = it.n;
+  const int64_t e0 = tm.member * BT + static_cast<int64_t>(threadIdx.x), es = tm.size * BT;
   // G: FP32 rounding of the FP64 Gaussian of stream 2 under key (seed, 0)
   const int64_t total = static_cast<int64_t>(n) * n;
-  for (int64_t blk = threadIdx.x; 4 * blk < total; blk += BT) {
+  for (int64_t blk = e0; 4 * blk < total; blk += es) {
     double z[4];
     gaussian_block(static_cast<uint64_t>(blk), 2u, it.seed, z);
 #pragma unroll
     for (int l = 0; l < 4; ++l)
       if (4 * blk + l < total) it.Vc[4 * blk + l] = static_cast<float>(z[l]);
   }
-  __syncthreads();
+  team_sync(tm);
   // 2q + 1 QRs (2 for q = 0), each after its product, in one loop so that the
   // QR's code appears once: X-jobs factor A V (the last one into U, R),
   // Y-jobs factor A^T W (or G itself when q = 0) into the next V.
@@ -462,45 +504,68 @@ __device__ __forceinline__ void factor_one(const BatchItem& it, int q, Lds& s) {
     float *Xp, *Qp, *Rp = nullptr;
     int rows;
     if (on_x) {
-      wg_gemm<false>(m, n, n, 1.f, it.A, m, Vin, n, 0.f, it.X, m, s);    // X = A V
+      wg_gemm<false>(m, n, n, 1.f, it.A, m, Vin, n, 0.f, it.X, m, s, tm);  // X = A V
       Xp = it.X;
       rows = m;
       Qp = last ? it.U : it.Q;                                          // W = Qpos(X), or U
       if (last) Rp = it.R;
     } else {
       if (q == 0) {                                                     // DDH-URV (Section 2.2): Qpos(G)
-        for (int64_t e = threadIdx.x; e < total; e += BT) it.Y[e] = it.Vc[e];
-        __syncthreads();
+        for (int64_t e = e0; e < total; e += es) it.Y[e] = it.Vc[e];
+        team_sync(tm);
       } else {
-        wg_gemm<true>(n, n, m, 1.f, it.A, m, it.Q, m, 0.f, it.Y, n, s);  // Y = A^T W
+        wg_gemm<true>(n, n, m, 1.f, it.A, m, it.Q, m, 0.f, it.Y, n, s, tm);  // Y = A^T W
       }
       Xp = it.Y;
       rows = n;
       Qp = (job == nqr - 2) ? it.V : it.Vc;                             // V = Qpos(Y)
     }
-    qr_wg<NB>(Xp, rows, n, rows, Qp, rows, Rp, n, it, s);
+    qr_wg<NB>(Xp, rows, n, rows, Qp, rows, Rp, n, it, s, tm);
     if (!on_x) Vin = Qp;
   }
 }
 
-// counters[0]: next queue position; counters[1]: workgroups that have left.
+// The queue is a list of tickets in largest-first order: matrix order[k] has
+// team_size[k] consecutive tickets, one per member.  A workgroup draws the next
+// ticket, joins that matrix's team, and draws again when it is done.  Tickets
+// are drawn in order by co-resident workgroups, so every team's members are
+// all running or finishing an earlier (complete) team: a team barrier never
+// waits on a workgroup that cannot arrive.
+// counters[0]: next ticket; counters[1]: workgroups that have left;
+// counters[2]: error flag (a bounded team wait expired).  bars[k]: arrivals
+// at the barriers of queue entry k.  The last workgroup to leave clears the
+// counters and the barriers for the next launch.
+struct Ticket {
+  int entry;   // queue position k
+  int member;  // rank in the team
+};
+
 template <int NB>
 __global__ __launch_bounds__(BT) void batched_urv_kernel(const BatchItem* __restrict__ items,
-                                                         const int* __restrict__ order, int count, int q,
-                                                         unsigned* __restrict__ counters) {
+                                                         const int* __restrict__ order, const int* __restrict__ team_size,
+                                                         const Ticket* __restrict__ tickets, int ntickets, int count,
+                                                         int q, unsigned* __restrict__ counters,
+                                                         unsigned* __restrict__ bars) {
   __shared__ Lds s;
   for (;;) {
     if (threadIdx.x == 0) s.idx = static_cast<int>(atomicAdd(&counters[0], 1u));
     __syncthreads();
-    const int idx = s.idx;
+    const int tk = s.idx;
     __syncthreads();
-    if (idx >= count) break;
-    const BatchItem it = items[order[idx]];
-    factor_one<NB>(it, q, s);
+    if (tk >= ntickets) break;
+    const Ticket ticket = tickets[tk];
+    Team tm;
+    tm.member = ticket.member;
+    tm.size = team_size[ticket.entry];
+    tm.bar = bars + ticket.entry;
+    tm.err = counters + 2;
+    const BatchItem it = items[order[ticket.entry]];
+    factor_one<NB>(it, q, s, tm);
   }
   if (threadIdx.x == 0) {
     __threadfence();
     if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
+      for (int k = 0; k < count; ++k) atomicExch(&bars[k], 0u);
       atomicExch(&counters[0], 0u);
       atomicExch(&counters[1], 0u);
     }
@@ -512,14 +577,40 @@ size_t item_scratch_floats(int64_t m, int64_t n) {
   return static_cast<size_t>(3 * a(m * n) + 2 * a(n * n) + 3 * a(kNBMax * n));
 }
 
-int launch_batched(int nb, int grid, const BatchItem* items, const int* order, int count, int q,
-                   unsigned* counters, hipStream_t s) {
+struct DeviceQueue {
+  const BatchItem* items;
+  const int* order;
+  const int* team_size;
+  const Ticket* tickets;
+  int ntickets;
+  int count;
+  unsigned* counters;
+  unsigned* bars;
+};
+
+int launch_batched(int nb, int grid, const DeviceQueue& dq, int q, hipStream_t s) {
   if (nb == 16)
-    batched_urv_kernel<16><<<grid, BT, 0, s>>>(items, order, count, q, counters);
+    batched_urv_kernel<16><<<grid, BT, 0, s>>>(dq.items, dq.order, dq.team_size, dq.tickets, dq.ntickets, dq.count,
+                                                q, dq.counters, dq.bars);
   else
-    batched_urv_kernel<32><<<grid, BT, 0, s>>>(items, order, count, q, counters);
+    batched_urv_kernel<32><<<grid, BT, 0, s>>>(dq.items, dq.order, dq.team_size, dq.tickets, dq.ntickets, dq.count,
+                                                q, dq.counters, dq.bars);
   URV_LAUNCHED("batched_urv_kernel");
   return URV_OK;
+}
+
+// Workgroups of the kernel for this panel width that fit on the device at once.
+int resident_capacity(int nb, int device) {
+  int per_cu = 0, cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e == hipSuccess)
+    e = (nb == 16) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_urv_kernel<16>, BT, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_urv_kernel<32>, BT, 0);
+  if (e != hipSuccess) {
+    hipGetLastError();
+    return 0;
+  }
+  return per_cu * cus;
 }
 
 }  // namespace
@@ -531,14 +622,21 @@ struct urv_batch_plan {
   uint64_t seed = 0;
   int device = 0;
   std::vector<urv::BatchItem> items;
-  std::vector<int> order;
+  std::vector<int> order;      // queue position -> matrix, largest first
+  std::vector<double> cost;    // per queue position
   char* scratch = nullptr;
   urv::BatchItem* d_items = nullptr;
   int* d_order = nullptr;
-  unsigned* d_counters = nullptr;
+  int* d_team = nullptr;            // team size per queue position
+  urv::Ticket* d_tickets = nullptr; // capacity count * kMaxTeam
+  int ntickets = 0;
+  unsigned* d_counters = nullptr;   // next ticket, workgroups out, error flag
+  unsigned* d_bars = nullptr;       // per queue position
   bool buffers = false;
   int nb = 32;
-  int grid = 512;
+  int grid = 256;
+  int team_max = 1;
+  int capacity[2] = {0, 0};         // co-resident workgroups for nb = 16, 32
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -547,6 +645,8 @@ struct urv_batch_plan {
 namespace {
 using urv::clear_last_error;
 using urv::set_last_error;
+
+constexpr int kMaxTeam = 64;
 
 void drop_graph(urv_batch_plan* p) {
   if (p->exec) hipGraphExecDestroy(p->exec);
@@ -567,8 +667,55 @@ int check_plan(const urv_batch_plan* p, const char* who) {
   return URV_OK;
 }
 
+int capacity_of(const urv_batch_plan* p, int nb) { return p->capacity[nb == 16 ? 0 : 1]; }
+
+// Team sizes for a configuration: a matrix whose cost exceeds the average
+// load of one workgroup (total cost / grid) gets ceil(cost / load) members,
+// at most team_max and grid; then the tickets, in queue order.
+int build_queue(urv_batch_plan* p, int nb, int grid, int team_max) {
+  double total = 0.0;
+  for (double c : p->cost) total += c;
+  const double load = total / grid;
+  std::vector<int> team(static_cast<size_t>(p->count));
+  std::vector<urv::Ticket> tickets;
+  const int cap = std::max(1, std::min({team_max, grid, kMaxTeam}));
+  for (int64_t k = 0; k < p->count; ++k) {
+    int sz = 1;
+    if (cap > 1 && load > 0.0) sz = static_cast<int>(std::min<double>(cap, std::max(1.0, std::ceil(p->cost[k] / load))));
+    team[static_cast<size_t>(k)] = sz;
+    for (int r = 0; r < sz; ++r) tickets.push_back(urv::Ticket{static_cast<int>(k), r});
+  }
+  if (cap > 1 && grid > capacity_of(p, nb)) {
+    set_last_error("urv_batch: teams of workgroups need every workgroup resident at once (grid <= " +
+                   std::to_string(capacity_of(p, nb)) + " here)");
+    return URV_EINVAL;
+  }
+  URV_HIP(hipMemcpy(p->d_team, team.data(), sizeof(int) * team.size(), hipMemcpyHostToDevice));
+  URV_HIP(hipMemcpy(p->d_tickets, tickets.data(), sizeof(urv::Ticket) * tickets.size(), hipMemcpyHostToDevice));
+  p->ntickets = static_cast<int>(tickets.size());
+  return URV_OK;
+}
+
+urv::DeviceQueue queue_of(const urv_batch_plan* p) {
+  return urv::DeviceQueue{p->d_items, p->d_order, p->d_team, p->d_tickets, p->ntickets,
+                          static_cast<int>(p->count), p->d_counters, p->d_bars};
+}
+
+void free_plan(urv_batch_plan* p) {
+  drop_graph(p);
+  if (p->cap) hipStreamDestroy(p->cap);
+  hipFree(p->scratch);
+  hipFree(p->d_items);
+  hipFree(p->d_order);
+  hipFree(p->d_team);
+  hipFree(p->d_tickets);
+  hipFree(p->d_counters);
+  hipFree(p->d_bars);
+  delete p;
+}
+
 const int kCandNB[] = {16, 32};
-const int kCandGrid[] = {256, 512, 1024};
+const int kCandTeam[] = {1, 4, 16};
 }  // namespace
 
 extern "C" {
@@ -610,15 +757,19 @@ int urv_batch_create(int64_t count, const int64_t* m, const int64_t* n, int32_t 
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->scratch), std::max<size_t>(floats, 1) * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_items), sizeof(urv::BatchItem) * count);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_order), sizeof(int) * count);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_counters), 2 * sizeof(unsigned));
-  if (e == hipSuccess) e = hipMemset(p->d_counters, 0, 2 * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_team), sizeof(int) * count);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_tickets), sizeof(urv::Ticket) * count * kMaxTeam);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_counters), 3 * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_bars), sizeof(unsigned) * count);
+  if (e == hipSuccess) e = hipMemset(p->d_counters, 0, 3 * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemset(p->d_bars, 0, sizeof(unsigned) * count);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    p->capacity[k] = urv::resident_capacity(k == 0 ? 16 : 32, p->device);
+    if (p->capacity[k] < 1) e = hipErrorInvalidDeviceFunction;
+  }
   if (e != hipSuccess) {
     const int rc = urv::hip_status(e, "urv_batch_create");
-    hipFree(p->scratch);
-    hipFree(p->d_items);
-    hipFree(p->d_order);
-    hipFree(p->d_counters);
-    delete p;
+    free_plan(p);
     return rc;
   }
   for (int64_t i = 0; i < count; ++i) {
@@ -647,14 +798,18 @@ int urv_batch_create(int64_t count, const int64_t* m, const int64_t* n, int32_t 
   std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) {
     return static_cast<double>(m[a]) * n[a] * n[a] > static_cast<double>(m[b]) * n[b] * n[b];
   });
+  p->cost.resize(static_cast<size_t>(count));
+  for (int64_t k = 0; k < count; ++k) {
+    const int i = p->order[static_cast<size_t>(k)];
+    p->cost[static_cast<size_t>(k)] = static_cast<double>(m[i]) * n[i] * n[i];
+  }
+  p->grid = p->capacity[1];
+  int rc = URV_OK;
   e = hipMemcpy(p->d_order, p->order.data(), sizeof(int) * count, hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    const int rc = urv::hip_status(e, "urv_batch_create");
-    hipFree(p->scratch);
-    hipFree(p->d_items);
-    hipFree(p->d_order);
-    hipFree(p->d_counters);
-    delete p;
+  if (e != hipSuccess) rc = urv::hip_status(e, "urv_batch_create");
+  if (rc == URV_OK) rc = build_queue(p, p->nb, p->grid, p->team_max);
+  if (rc != URV_OK) {
+    free_plan(p);
     return rc;
   }
   *plan = p;
@@ -684,34 +839,36 @@ int urv_batch_set_buffers(urv_batch_plan* p, const float* const* A, float* const
   return URV_OK;
 }
 
-int urv_batch_set_config(urv_batch_plan* p, int32_t nb, int32_t grid) {
+int urv_batch_set_config(urv_batch_plan* p, int32_t nb, int32_t grid, int32_t team_max) {
   clear_last_error();
-  if (!p || (nb != 16 && nb != 32) || grid < 1 || grid > 65536) {
-    set_last_error("urv_batch_set_config: need a plan, nb 16 or 32 and 1 <= grid <= 65536");
+  if (!p || (nb != 16 && nb != 32) || grid < 1 || grid > 65536 || team_max < 1 || team_max > kMaxTeam) {
+    set_last_error("urv_batch_set_config: need a plan, nb 16 or 32, 1 <= grid <= 65536, 1 <= team_max <= 64");
     return URV_EINVAL;
   }
-  if (p->nb != nb || p->grid != grid) drop_graph(p);
+  URV_TRY(build_queue(p, nb, grid, team_max));
+  if (p->nb != nb || p->grid != grid || p->team_max != team_max) drop_graph(p);
   p->nb = nb;
   p->grid = grid;
+  p->team_max = team_max;
   return URV_OK;
 }
 
-int urv_batch_get_config(const urv_batch_plan* p, int32_t* nb, int32_t* grid) {
+int urv_batch_get_config(const urv_batch_plan* p, int32_t* nb, int32_t* grid, int32_t* team_max) {
   clear_last_error();
-  if (!p || !nb || !grid) {
+  if (!p || !nb || !grid || !team_max) {
     set_last_error("urv_batch_get_config: null argument");
     return URV_EINVAL;
   }
   *nb = p->nb;
   *grid = p->grid;
+  *team_max = p->team_max;
   return URV_OK;
 }
 
 int urv_batch_run(urv_batch_plan* p, void* stream) {
   clear_last_error();
   URV_TRY(check_plan(p, "urv_batch_run"));
-  return urv::launch_batched(p->nb, p->grid, p->d_items, p->d_order, static_cast<int>(p->count), p->q,
-                             p->d_counters, static_cast<hipStream_t>(stream));
+  return urv::launch_batched(p->nb, p->grid, queue_of(p), p->q, static_cast<hipStream_t>(stream));
 }
 
 int urv_batch_run_graph(urv_batch_plan* p, void* stream) {
@@ -720,8 +877,7 @@ int urv_batch_run_graph(urv_batch_plan* p, void* stream) {
   if (!p->exec) {
     if (!p->cap) URV_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
     URV_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-    const int rc = urv::launch_batched(p->nb, p->grid, p->d_items, p->d_order, static_cast<int>(p->count), p->q,
-                                       p->d_counters, p->cap);
+    const int rc = urv::launch_batched(p->nb, p->grid, queue_of(p), p->q, p->cap);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(p->cap, &g);
     if (rc != URV_OK) {
@@ -736,6 +892,23 @@ int urv_batch_run_graph(urv_batch_plan* p, void* stream) {
   return URV_OK;
 }
 
+int urv_batch_status(urv_batch_plan* p, void* stream) {
+  clear_last_error();
+  if (!p) {
+    set_last_error("urv_batch_status: null plan");
+    return URV_EINVAL;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned flag = 0;
+  URV_HIP(hipMemcpyAsync(&flag, p->d_counters + 2, sizeof(flag), hipMemcpyDeviceToHost, s));
+  URV_HIP(hipStreamSynchronize(s));
+  if (flag != 0) {
+    set_last_error("urv_batch: a team barrier's bounded wait expired (another kernel held CUs?)");
+    return URV_EDEVICE;
+  }
+  return URV_OK;
+}
+
 int urv_batch_autotune(urv_batch_plan* p, void* stream, double* best_ms) {
   clear_last_error();
   URV_TRY(check_plan(p, "urv_batch_autotune"));
@@ -744,15 +917,17 @@ int urv_batch_autotune(urv_batch_plan* p, void* stream, double* best_ms) {
   URV_HIP(hipEventCreate(&e0));
   URV_HIP(hipEventCreate(&e1));
   float best = -1.f;
-  int best_nb = p->nb, best_grid = p->grid;
+  int best_nb = p->nb, best_team = p->team_max;
   int rc = URV_OK;
   for (int nb : kCandNB) {
-    for (int grid : kCandGrid) {
+    for (int team : kCandTeam) {
+      // every workgroup resident: the grid is the device's capacity for this kernel
+      rc = build_queue(p, nb, capacity_of(p, nb), team);
+      const urv::DeviceQueue dq = queue_of(p);
       // one untimed run, then one timed run of the whole batch
-      rc = urv::launch_batched(nb, grid, p->d_items, p->d_order, static_cast<int>(p->count), p->q, p->d_counters, s);
+      if (rc == URV_OK) rc = urv::launch_batched(nb, capacity_of(p, nb), dq, p->q, s);
       if (rc == URV_OK && hipEventRecord(e0, s) != hipSuccess) rc = URV_EDEVICE;
-      if (rc == URV_OK)
-        rc = urv::launch_batched(nb, grid, p->d_items, p->d_order, static_cast<int>(p->count), p->q, p->d_counters, s);
+      if (rc == URV_OK) rc = urv::launch_batched(nb, capacity_of(p, nb), dq, p->q, s);
       if (rc == URV_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
         rc = urv::hip_status(hipGetLastError(), "urv_batch_autotune");
       if (rc != URV_OK) break;
@@ -761,27 +936,25 @@ int urv_batch_autotune(urv_batch_plan* p, void* stream, double* best_ms) {
       if (best < 0.f || ms < best) {
         best = ms;
         best_nb = nb;
-        best_grid = grid;
+        best_team = team;
       }
     }
     if (rc != URV_OK) break;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  URV_TRY(rc);
+  if (rc != URV_OK) {
+    build_queue(p, p->nb, p->grid, p->team_max);
+    return rc;
+  }
   if (best_ms) *best_ms = best;
-  return urv_batch_set_config(p, best_nb, best_grid);
+  p->nb = -1;  // force the queue and the graph to follow the choice
+  return urv_batch_set_config(p, best_nb, capacity_of(p, best_nb), best_team);
 }
 
 void urv_batch_destroy(urv_batch_plan* p) {
   if (!p) return;
-  drop_graph(p);
-  if (p->cap) hipStreamDestroy(p->cap);
-  hipFree(p->scratch);
-  hipFree(p->d_items);
-  hipFree(p->d_order);
-  hipFree(p->d_counters);
-  delete p;
+  free_plan(p);
 }
 
 }  // extern "C"

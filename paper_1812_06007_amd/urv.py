@@ -66,7 +66,8 @@ EXPORTS = ["urv_opts_init", "urv_factor_ex", "urv_factor", "urv_workspace_size",
            "urv_grad_opts_init", "urv_tape_bytes", "urv_grad_workspace_size", "urv_factor_tape",
            "urv_factor_backward", "urv_qr_adjoint", "urv_truncation_loss",
            "urv_batch_create", "urv_batch_set_buffers", "urv_batch_set_config", "urv_batch_get_config",
-           "urv_batch_autotune", "urv_batch_run", "urv_batch_run_graph", "urv_batch_destroy"]
+           "urv_batch_autotune", "urv_batch_run", "urv_batch_run_graph", "urv_batch_status",
+           "urv_batch_destroy"]
 
 _lib = None
 
@@ -112,8 +113,9 @@ def lib() -> ctypes.CDLL:
     PP = ctypes.POINTER(ctypes.c_void_p)
     L.urv_batch_create.argtypes = [I64, PI64, PI64, I32, U64, ctypes.POINTER(ctypes.c_void_p)]
     L.urv_batch_set_buffers.argtypes = [P, PP, PP, PP, PP]
-    L.urv_batch_set_config.argtypes = [P, I32, I32]
-    L.urv_batch_get_config.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    L.urv_batch_set_config.argtypes = [P, I32, I32, I32]
+    L.urv_batch_get_config.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    L.urv_batch_status.argtypes = [P, P]
     L.urv_batch_autotune.argtypes = [P, P, ctypes.POINTER(D)]
     L.urv_batch_run.argtypes = [P, P]
     L.urv_batch_run_graph.argtypes = [P, P]
@@ -122,7 +124,8 @@ def lib() -> ctypes.CDLL:
     for name in ("urv_factor_ex", "urv_factor", "urv_gaussian", "urv_dgemm", "urv_qr_pos", "urv_qr_pos_f32",
                  "urv_metrics", "urv_factor_tape", "urv_factor_backward", "urv_qr_adjoint",
                  "urv_truncation_loss", "urv_batch_create", "urv_batch_set_buffers", "urv_batch_set_config",
-                 "urv_batch_get_config", "urv_batch_autotune", "urv_batch_run", "urv_batch_run_graph"):
+                 "urv_batch_get_config", "urv_batch_autotune", "urv_batch_run", "urv_batch_run_graph",
+                 "urv_batch_status"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -459,13 +462,18 @@ class BatchPlan:
         _check(lib().urv_batch_set_buffers(self._plan, *arrs))
         self._keep = (list(A), list(U), list(R), list(V))
 
-    def set_config(self, nb: int, grid: int) -> None:
-        _check(lib().urv_batch_set_config(self._plan, nb, grid))
+    def set_config(self, nb: int, grid: int, team_max: int = 1) -> None:
+        _check(lib().urv_batch_set_config(self._plan, nb, grid, team_max))
 
     def config(self):
-        nb, grid = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().urv_batch_get_config(self._plan, ctypes.byref(nb), ctypes.byref(grid)))
-        return nb.value, grid.value
+        """(nb, grid, team_max) of the next launch."""
+        nb, grid, team = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().urv_batch_get_config(self._plan, ctypes.byref(nb), ctypes.byref(grid), ctypes.byref(team)))
+        return nb.value, grid.value, team.value
+
+    def status(self) -> None:
+        """Raise if a team barrier's bounded wait expired in a run so far (blocking)."""
+        _check(lib().urv_batch_status(self._plan, _stream_ptr()))
 
     def autotune(self) -> float:
         ms = ctypes.c_double()

@@ -223,6 +223,7 @@ def test_batch_calls_reject_a_null_plan():
     assert L.urv_batch_run(None, None) == urv.URV_EINVAL
     assert L.urv_batch_run_graph(None, None) == urv.URV_EINVAL
     assert L.urv_batch_autotune(None, None, None) == urv.URV_EINVAL
-    assert L.urv_batch_set_config(None, 16, 256) == urv.URV_EINVAL
+    assert L.urv_batch_set_config(None, 16, 256, 1) == urv.URV_EINVAL
+    assert L.urv_batch_status(None, None) == urv.URV_EINVAL
     assert L.urv_batch_set_buffers(None, None, None, None, None) == urv.URV_EINVAL
     L.urv_batch_destroy(None)

@@ -75,7 +75,7 @@ def _oracle(orc, sizes, q):
     return _ORACLE[key]
 
 
-def _run(urv, sizes, q, nb=None, grid=None, graph=False):
+def _run(urv, sizes, q, nb=None, grid=None, graph=False, team=1):
     import torch
 
     ms, ns = [s[0] for s in sizes], [s[1] for s in sizes]
@@ -84,9 +84,10 @@ def _run(urv, sizes, q, nb=None, grid=None, graph=False):
     U, R, V = urv.batch_outputs(ms, ns)
     plan.set_buffers(A, U, R, V)
     if nb is not None:
-        plan.set_config(nb, grid)
+        plan.set_config(nb, grid if grid else plan.config()[1], team)
     plan.run(graph=graph)
     torch.cuda.synchronize()
+    plan.status()
     return plan, A, U, R, V
 
 
@@ -116,14 +117,36 @@ def test_batched_matches_oracle(urv, orc, nb, q):
 
 
 def test_schedule_does_not_change_the_bits(urv):
+    """Workgroup counts and teams (GEMM tiles and element ranges split over
+    several workgroups with device-wide barriers) give the same bits."""
     announce("batched schedules")
     outs = []
-    for grid in (1, 7, 256, 1024):
-        plan, A, U, R, V = _run(urv, SMALL, 1, nb=32, grid=grid)
+    for grid, team in ((1, 1), (7, 1), (256, 1), (1024, 1), (None, 4), (None, 16), (None, 64)):
+        plan, A, U, R, V = _run(urv, SMALL, 1, nb=32, grid=grid, team=team)
         outs.append([to_np(t) for t in U + R + V])
         plan.close()
     for other in outs[1:]:
         assert all(np.array_equal(a, b) for a, b in zip(outs[0], other))
+
+
+def test_teams_match_oracle(urv, orc):
+    announce("batched teams parity")
+    ref = _oracle(orc, SMALL, 2)
+    plan, A, U, R, V = _run(urv, SMALL, 2, nb=16, team=16)
+    for i, A_np in enumerate(_matrices(SMALL, SEED)):
+        _check_against_oracle(A_np, ref[i], U[i], R[i], V[i])
+    plan.close()
+
+
+def test_team_grid_beyond_capacity_is_refused(urv):
+    announce("batched team capacity check")
+    ms, ns = [s[0] for s in SMALL], [s[1] for s in SMALL]
+    plan = urv.BatchPlan(ms, ns, q=1, seed=SEED)
+    cap = plan.config()[1]
+    with pytest.raises(urv.UrvError):
+        plan.set_config(32, cap + 1, 4)
+    plan.set_config(32, cap + 1, 1)  # a single-workgroup schedule needs no residency
+    plan.close()
 
 
 def test_graph_replays_reproduce_the_eager_launch(urv):
@@ -131,7 +154,7 @@ def test_graph_replays_reproduce_the_eager_launch(urv):
 
     announce("batched graph")
     ms, ns = [s[0] for s in SMALL], [s[1] for s in SMALL]
-    plan, A, U, R, V = _run(urv, SMALL, 1, nb=16, grid=256)
+    plan, A, U, R, V = _run(urv, SMALL, 1, nb=16, team=4)
     eager = [to_np(t) for t in U + R + V]
     scratch = torch.ones(1 << 20, device="cuda")
     for rep in range(3):
@@ -140,6 +163,7 @@ def test_graph_replays_reproduce_the_eager_launch(urv):
         plan.run(graph=True)
         scratch.mul_(1.0001)  # the program's own work between replays
         torch.cuda.synchronize()
+        plan.status()
         assert all(np.array_equal(a, to_np(b)) for a, b in zip(eager, U + R + V)), rep
     # new output buffers: the captured launch reads the descriptors, so it writes there
     U2, R2, V2 = urv.batch_outputs(ms, ns)
@@ -158,8 +182,8 @@ def test_autotune_keeps_a_valid_result(urv, orc):
     plan, A, U, R, V = _run(urv, SMALL, 1)
     ms = plan.autotune()
     assert ms > 0
-    nb, grid = plan.config()
-    assert nb in (16, 32) and grid in (256, 512, 1024)
+    nb, grid, team = plan.config()
+    assert nb in (16, 32) and team in (1, 4, 16) and grid >= 1
     plan.run(graph=True)
     torch.cuda.synchronize()
     for i, A_np in enumerate(_matrices(SMALL, SEED)):
@@ -188,6 +212,7 @@ def test_full_batch_workload(urv, orc):
     plan.autotune()
     plan.run(graph=True)
     torch.cuda.synchronize()
+    plan.status()
     worst = {"orthU": 0.0, "orthV": 0.0, "recon": 0.0}  # each as a fraction of its bound
     for i in range(count):
         Ad, Ud, Rd, Vd = (t.double() for t in (A[i], U[i], R[i], V[i]))
