@@ -12,9 +12,11 @@
 // takes the next matrix from a device-side counter; matrices are queued
 // largest first, so the long ones start early and the short ones fill the
 // tail.  Within a workgroup:
-//  * GEMMs (A V, A^T W and the block-reflector updates) on FP32 MFMA
-//    (v_mfma_f32_16x16x4f32), 64 x 64 tiles (32 x 64 for the products with
-//    32 rows) staged through double-buffered LDS, 4 waves;
+//  * GEMMs (A V, A^T W and the block-reflector updates, T applied as a
+//    product too) on FP32 MFMA (v_mfma_f32_16x16x4f32), 64 x 64 tiles (32 x 64
+//    for the products with 32 rows) staged through double-buffered LDS, 4
+//    waves; the short-K updates run one flat loop over tiles that loads the
+//    next tile while the current one computes;
 //  * the panel of NB columns lives in registers (4 rows per lane, rows up to
 //    1024); each column takes two workgroup reductions in a fixed order: the
 //    norm below the pivot, then the reflector's products with the remaining
@@ -160,7 +162,7 @@ __device__ __forceinline__ void team_sync(Team& tm) {
 // not overlap A or B.  Ends with a team barrier, so the team may read C right
 // after.
 template <bool TA, int BM>
-__device__ __forceinline__ void wg_gemm_t(int M, int N, int K, float alpha, const float* __restrict__ A, int lda,
+__device__ __noinline__ void wg_gemm_t(int M, int N, int K, float alpha, const float* __restrict__ A, int lda,
                                           const float* __restrict__ B, int ldb, float beta, float* __restrict__ C,
                                           int ldc, Lds& s, Team& tm) {
   constexpr int FM = BM / 32;                  // 16-row MFMA blocks per wave
@@ -266,33 +268,164 @@ __device__ __forceinline__ void wg_gemm_t(int M, int N, int K, float alpha, cons
   team_sync(tm);
 }
 
+template <bool TA, int BM>
+__device__ __noinline__ void wg_gemm_short(int M, int N, int K, float alpha, const float* __restrict__ A, int lda,
+                                          const float* __restrict__ B, int ldb, float beta, float* __restrict__ C,
+                                          int ldc, Lds& s, Team& tm) {
+  constexpr int FM = BM / 32;                  // 16-row MFMA blocks per wave
+  constexpr int FN = 2;                        // 16-column MFMA blocks per wave
+  constexpr int LA = BM * GBK / BT, LB = 64 * GBK / BT;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow = lane & 15, lk = lane >> 4;
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + 63) / 64;
+  float ra[LA], rb[LB];
+  auto load = [&](int m0, int n0, int k0) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int qa = t + BT * r;
+      int i, k;
+      if (!TA) {
+        i = qa % BM;
+        k = qa / BM;
+      } else {
+        k = qa % GBK;
+        i = qa / GBK;
+      }
+      const int gi = m0 + i, gk = k0 + k;
+      float v = 0.f;
+      if (gi < M && gk < K)
+        v = TA ? A[gk + static_cast<int64_t>(gi) * lda] : A[gi + static_cast<int64_t>(gk) * lda];
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int qb = t + BT * r;
+      const int k = qb % GBK, j = qb / GBK;
+      const int gj = n0 + j, gk = k0 + k;
+      rb[r] = (gj < N && gk < K) ? B[gk + static_cast<int64_t>(gj) * ldb] : 0.f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int qa = t + BT * r;
+      int i, k;
+      if (!TA) {
+        i = qa % BM;
+        k = qa / BM;
+      } else {
+        k = qa % GBK;
+        i = qa / GBK;
+      }
+      s.u.g.As[buf][k][i] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int qb = t + BT * r;
+      s.u.g.Bs[buf][qb % GBK][qb / GBK] = rb[r];
+    }
+  };
+  // K <= GBK: one k step per tile.  Tiles are taken in pairs, so the C values
+  // of the next tile (for beta != 0) are loaded into the other register set
+  // while the current tile computes and stores; A and B of the next tile are
+  // in flight meanwhile too.
+  const int ntiles = tiles_m * tiles_n;
+  const int my_tiles = (tm.member < ntiles) ? (ntiles - tm.member + tm.size - 1) / tm.size : 0;
+  const bool with_c = beta != 0.f;
+  auto origin = [&](int lt, int& m0, int& n0) {
+    const int tile = tm.member + lt * tm.size;
+    m0 = (tile % tiles_m) * BM;
+    n0 = (tile / tiles_m) * 64;
+  };
+  auto load_c = [&](int m0, int n0, float (&dst)[FM][FN][4]) {
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      const int gm = m0 + wm * (BM / 2) + a * 16 + lrow;
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gn = n0 + wn * 32 + b * 16 + 4 * lk + r;
+          dst[a][b][r] = (gm < M && gn < N) ? C[gm + static_cast<int64_t>(gn) * ldc] : 0.f;
+        }
+    }
+  };
+  float c0[FM][FN][4], c1[FM][FN][4];
+  auto step = [&](int lt, int cur, float (&cv)[FM][FN][4], float (&cn)[FM][FN][4]) {
+    const bool has_next = lt + 1 < my_tiles;
+    if (has_next) {
+      int m1, n1;
+      origin(lt + 1, m1, n1);
+      load(m1, n1, 0);
+      if (with_c) load_c(m1, n1, cn);
+    }
+    f4 acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < GBK / 4; ++kk) {
+      float fa[FM], fb[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) fa[a] = s.u.g.As[cur][kk * 4 + lk][wm * (BM / 2) + a * 16 + lrow];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) fb[b] = s.u.g.Bs[cur][kk * 4 + lk][wn * 32 + b * 16 + lrow];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[b], fa[a], acc[a][b], 0, 0, 0);
+    }
+    // lane holds C(m0 + (BM/2) wm + 16 a + lrow, n0 + 32 wn + 16 b + 4 lk + r)
+    int m0, n0;
+    origin(lt, m0, n0);
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+      const int gm = m0 + wm * (BM / 2) + a * 16 + lrow;
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gn = n0 + wn * 32 + b * 16 + 4 * lk + r;
+          if (gm < M && gn < N)
+            C[gm + static_cast<int64_t>(gn) * ldc] =
+                with_c ? alpha * acc[a][b][r] + beta * cv[a][b][r] : alpha * acc[a][b][r];
+        }
+    }
+    if (has_next) store(cur ^ 1);
+    __syncthreads();
+  };
+  if (my_tiles > 0) {
+    int m0, n0;
+    origin(0, m0, n0);
+    load(m0, n0, 0);
+    store(0);
+    if (with_c) load_c(m0, n0, c0);
+    __syncthreads();
+  }
+  for (int lt = 0; lt < my_tiles; lt += 2) {
+    step(lt, 0, c0, c1);
+    if (lt + 1 < my_tiles) step(lt + 1, 1, c1, c0);
+  }
+  team_sync(tm);
+}
+
 template <bool TA>
 __device__ __forceinline__ void wg_gemm(int M, int N, int K, float alpha, const float* __restrict__ A, int lda,
                                         const float* __restrict__ B, int ldb, float beta, float* __restrict__ C,
                                         int ldc, Lds& s, Team& tm) {
-  if (M <= 32)
+  if (K <= GBK) {  // rank-GBK updates: latency hidden across tiles
+    if (M <= 32)
+      wg_gemm_short<TA, 32>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
+    else
+      wg_gemm_short<TA, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
+  } else if (M <= 32) {
     wg_gemm_t<TA, 32>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
-  else
+  } else {
     wg_gemm_t<TA, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
-}
-
-// Wout (jb x ncols, ld kNBMax) = op(T) Win for the jb x jb upper triangular T
-// (ld kNBMax): op(T) = T^T when TRANS, else T.  Ends with a team barrier.
-template <bool TRANS>
-__device__ __forceinline__ void small_tmul(const float* __restrict__ T, int jb, const float* __restrict__ Win,
-                                           float* __restrict__ Wout, int ncols, Team& tm) {
-  for (int e = tm.member * BT + threadIdx.x; e < jb * ncols; e += tm.size * BT) {
-    const int i = e % jb, col = e / jb;
-    const float* w = Win + static_cast<int64_t>(col) * kNBMax;
-    float acc = 0.f;
-    if (TRANS) {
-      for (int l = 0; l <= i; ++l) acc += T[l + i * kNBMax] * w[l];
-    } else {
-      for (int l = i; l < jb; ++l) acc += T[i + l * kNBMax] * w[l];
-    }
-    Wout[i + static_cast<int64_t>(col) * kNBMax] = acc;
   }
-  team_sync(tm);
 }
 
 // One column c of the panel factorisation (c a compile-time constant, so the
@@ -441,7 +574,7 @@ __device__ __forceinline__ void qr_wg(float* X, int rows, int cols, int ldx, flo
       // C -= V (T^T (V^T C))
       float* C = X + j0 + static_cast<int64_t>(j0 + jb) * ldx;
       wg_gemm<true>(jb, nrest, mp, 1.f, Vp, ldv, C, ldx, 0.f, it.Wb, kNBMax, s, tm);
-      small_tmul<true>(Tp, jb, it.Wb, it.W2b, nrest, tm);
+      wg_gemm<true>(jb, nrest, jb, 1.f, Tp, kNBMax, it.Wb, kNBMax, 0.f, it.W2b, kNBMax, s, tm);  // T^T W
       wg_gemm<false>(mp, nrest, jb, -1.f, Vp, ldv, it.W2b, kNBMax, 1.f, C, ldx, s, tm);
     }
   }
@@ -457,7 +590,7 @@ __device__ __forceinline__ void qr_wg(float* X, int rows, int cols, int ldx, flo
     const float* Tp = it.T + static_cast<int64_t>(j0) * kNBMax;
     float* Qs = Q + j0 + static_cast<int64_t>(j0) * ldq;
     wg_gemm<true>(jb, nq, mp, 1.f, Vp, ldv, Qs, ldq, 0.f, it.Wb, kNBMax, s, tm);
-    small_tmul<false>(Tp, jb, it.Wb, it.W2b, nq, tm);
+    wg_gemm<false>(jb, nq, jb, 1.f, Tp, kNBMax, it.Wb, kNBMax, 0.f, it.W2b, kNBMax, s, tm);   // T W
     wg_gemm<false>(mp, nq, jb, -1.f, Vp, ldv, it.W2b, kNBMax, 1.f, Qs, ldq, s, tm);
   }
   // sign fix: Q(:,j) *= sgn(R(j,j)), R(j,:) = sgn(R(j,j)) R(j,:), sgn(0) = +1
@@ -715,7 +848,7 @@ void free_plan(urv_batch_plan* p) {
 }
 
 const int kCandNB[] = {16, 32};
-const int kCandTeam[] = {1, 4, 16};
+const int kCandTeam[] = {1, 2, 4, 8, 16};
 }  // namespace
 
 extern "C" {
