@@ -140,16 +140,19 @@ def qr_pos(X):
 
 
 def urv(A, q: int, seed: int = 0, G=None, variant: str | int = "full", orth_g: bool = False):
-    """PowerURV A = U R V^T (eqs. power / powerqr).  Returns (U, R, V)."""
+    """PowerURV A = U R V^T (eqs. power / powerqr).  Returns (U, R, V): with
+    p = min(m, n), U m x p, R p x p upper, V n x p (m < n: the ULV of A^T,
+    transposed, Section 1)."""
     A = _f64(A)
     m, n = A.shape
+    p = min(m, n)
     v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     Gf = None if G is None else _f64(G)
-    U = np.zeros((m, n), order="F")
-    R = np.zeros((n, n), order="F")
-    V = np.zeros((n, n), order="F")
-    rc = lib().orc_urv(_ptr(A), m, n, max(m, 1), q, seed, _ptr(Gf), max(n, 1), v, int(orth_g),
-                       _ptr(U), max(m, 1), _ptr(R), max(n, 1), _ptr(V), max(n, 1))
+    U = np.zeros((m, p), order="F")
+    R = np.zeros((p, p), order="F")
+    V = np.zeros((n, p), order="F")
+    rc = lib().orc_urv(_ptr(A), m, n, max(m, 1), q, seed, _ptr(Gf), max(p, 1), v, int(orth_g),
+                       _ptr(U), max(m, 1), _ptr(R), max(p, 1), _ptr(V), max(n, 1))
     if rc != 0:
         raise ValueError("orc_urv failed")
     return U, R, V
@@ -159,9 +162,10 @@ def metrics(A, U, R, V):
     """dict(recon, orthU, orthV, normA, ek) for A = U R V^T."""
     A, U, R, V = _f64(A), _f64(U), _f64(R), _f64(V)
     m, n = A.shape
+    p = min(m, n)
     out = np.zeros(4)
-    ek = np.zeros(n + 1)
-    rc = lib().orc_metrics(_ptr(A), m, n, m, _ptr(U), m, _ptr(R), n, _ptr(V), n, _ptr(out), _ptr(ek))
+    ek = np.zeros(p + 1)
+    rc = lib().orc_metrics(_ptr(A), m, n, m, _ptr(U), m, _ptr(R), max(p, 1), _ptr(V), n, _ptr(out), _ptr(ek))
     if rc != 0:
         raise ValueError("orc_metrics failed")
     return {"recon": out[0], "orthU": out[1], "orthV": out[2], "normA": out[3], "ek": ek}

@@ -225,20 +225,12 @@ static int orthonormalize_square(double* V, int64_t n, double* scratch) {
   return orc_qr_pos(scratch, n, n, n, V, n, NULL, 0);
 }
 
-int orc_urv(const double* A, int64_t m, int64_t n, int64_t lda, int32_t q,
-            uint64_t seed, const double* G, int64_t ldg, int32_t variant,
-            int32_t orth_g, double* U, int64_t ldu, double* R, int64_t ldr,
-            double* V, int64_t ldv) {
-  if (n < 0 || m < n || q < 0 || variant < 0 || variant > 2) return -1;
-  if (n == 0) return 0;
-  if (lda < m || ldu < m || ldr < n || ldv < n || (G && ldg < n)) return -1;
-
-  double* Vw = alloc_mat(n, n);   /* current V, packed n x n */
-  double* X = alloc_mat(m, n);    /* A V, packed m x n */
-  double* W = alloc_mat(m, n);    /* Qpos(A V), packed */
-  double* S = alloc_mat(m, n);    /* scratch for QR */
-  if (!Vw || !X || !W || !S) { free(Vw); free(X); free(W); free(S); return -1; }
-
+/* The power steps of eq. (power) for a tall A (m x n, m >= n): Vw (n x n,
+ * packed) = V after q steps from G (or the Gaussian of seed, stream 2).
+ * X and W (m x n) and S (m x n) are scratch. */
+static void power_steps(const double* A, int64_t m, int64_t n, int64_t lda, int32_t q,
+                        uint64_t seed, const double* G, int64_t ldg, int32_t variant,
+                        int32_t orth_g, double* Vw, double* X, double* W, double* S) {
   /* Starting matrix: the Gaussian G of eq. (power). */
   if (G) copy_mat(G, ldg, Vw, n, n, n);
   else orc_gaussian(Vw, n, n, n, seed, 2u);
@@ -259,17 +251,62 @@ int orc_urv(const double* A, int64_t m, int64_t n, int64_t lda, int32_t q,
     }
   }
   if (variant == ORC_NONE && q > 0) orthonormalize_square(Vw, n, S); /* (A^T A)^q G = V Z */
+}
 
-  /* eq. (powerqr): A V = U R. */
-  orc_gemm(0, 0, m, n, n, 1.0, A, lda, Vw, n, 0.0, X, m);
-  double* Up = alloc_mat(m, n);
-  double* Rp = alloc_mat(n, n);
-  if (!Up || !Rp) { free(Vw); free(X); free(W); free(S); free(Up); free(Rp); return -1; }
-  orc_qr_pos(X, m, n, m, Up, m, Rp, n);
-  copy_mat(Up, m, U, ldu, m, n);
-  copy_mat(Rp, n, R, ldr, n, n);
-  copy_mat(Vw, n, V, ldv, n, n);
-  free(Up); free(Rp);
+int orc_urv(const double* A, int64_t m, int64_t n, int64_t lda, int32_t q,
+            uint64_t seed, const double* G, int64_t ldg, int32_t variant,
+            int32_t orth_g, double* U, int64_t ldu, double* R, int64_t ldr,
+            double* V, int64_t ldv) {
+  if (m < 0 || n < 0 || q < 0 || variant < 0 || variant > 2) return -1;
+  const int64_t p = m < n ? m : n;
+  if (p == 0) return 0;
+  if (lda < m || ldu < m || ldr < p || ldv < n || (G && ldg < p)) return -1;
+
+  /* m < n (Section 1): a ULV of B = A^T, transposed.  The rows and columns of
+   * the tall problem are (mt, nt) = (n, m). */
+  const int wide = m < n;
+  const int64_t mt = wide ? n : m, nt = p;
+  double* B = NULL;
+  if (wide) {
+    B = alloc_mat(n, m);
+    if (!B) return -1;
+    for (int64_t j = 0; j < m; ++j)
+      for (int64_t i = 0; i < n; ++i) B[i + j * n] = A[j + i * lda];
+  }
+  const double* At = wide ? B : A;
+  const int64_t ldat = wide ? n : lda;
+
+  double* Vw = alloc_mat(nt, nt);  /* current V, packed nt x nt */
+  double* X = alloc_mat(mt, nt);   /* A V, packed mt x nt */
+  double* W = alloc_mat(mt, nt);   /* Qpos(A V), packed */
+  double* S = alloc_mat(mt, nt);   /* scratch for QR */
+  double* Up = alloc_mat(mt, nt);
+  double* Rp = alloc_mat(nt, nt);
+  if (!Vw || !X || !W || !S || !Up || !Rp) {
+    free(B); free(Vw); free(X); free(W); free(S); free(Up); free(Rp);
+    return -1;
+  }
+  power_steps(At, mt, nt, ldat, q, seed, G, ldg, variant, orth_g, Vw, X, W, S);
+  orc_gemm(0, 0, mt, nt, nt, 1.0, At, ldat, Vw, nt, 0.0, X, mt);    /* X = A V */
+  if (!wide) {
+    /* eq. (powerqr): A V = U R. */
+    orc_qr_pos(X, mt, nt, mt, Up, mt, Rp, nt);
+    copy_mat(Up, mt, U, ldu, m, n);
+    copy_mat(Rp, nt, R, ldr, n, n);
+    copy_mat(Vw, nt, V, ldv, n, n);
+  } else {
+    /* B V = X, and X J = Q R' with J the reversal of the p columns, so
+     * B = (Q J)(J R' J) V^T with J R' J lower triangular (a ULV of B) and
+     * A = B^T = V (J R' J)^T (Q J)^T: U = V (m x m), R = J R'^T J (upper,
+     * R(i,j) = R'(p-1-j, p-1-i)), V = Q J (n x m). */
+    for (int64_t j = 0; j < p; ++j) memcpy(S + j * mt, X + (p - 1 - j) * mt, (size_t)mt * sizeof(double));
+    orc_qr_pos(S, mt, p, mt, Up, mt, Rp, p);
+    copy_mat(Vw, p, U, ldu, m, m);
+    for (int64_t j = 0; j < p; ++j)
+      for (int64_t i = 0; i < p; ++i) R[i + j * ldr] = Rp[(p - 1 - j) + (p - 1 - i) * p];
+    for (int64_t j = 0; j < p; ++j) memcpy(V + j * ldv, Up + (p - 1 - j) * mt, (size_t)mt * sizeof(double));
+  }
+  free(B); free(Up); free(Rp);
   free(Vw); free(X); free(W); free(S);
   return 0;
 }
@@ -285,35 +322,36 @@ static double frob(const double* X, int64_t rows, int64_t cols, int64_t ld) {
 int orc_metrics(const double* A, int64_t m, int64_t n, int64_t lda,
                 const double* U, int64_t ldu, const double* R, int64_t ldr,
                 const double* V, int64_t ldv, double out[4], double* ek) {
-  if (n <= 0 || m < n) return -1;
-  double* UR = alloc_mat(m, n);
+  const int64_t p = m < n ? m : n;  /* U m x p, R p x p, V n x p */
+  if (p <= 0) return -1;
+  double* UR = alloc_mat(m, p);
   double* E = alloc_mat(m, n);
-  double* Gm = alloc_mat(n, n);
+  double* Gm = alloc_mat(p, p);
   if (!UR || !E || !Gm) { free(UR); free(E); free(Gm); return -1; }
 
   /* recon: A - (U R) V^T */
-  orc_gemm(0, 0, m, n, n, 1.0, U, ldu, R, ldr, 0.0, UR, m);
+  orc_gemm(0, 0, m, p, p, 1.0, U, ldu, R, ldr, 0.0, UR, m);
   copy_mat(A, lda, E, m, m, n);
-  orc_gemm(0, 1, m, n, n, -1.0, UR, m, V, ldv, 1.0, E, m);
+  orc_gemm(0, 1, m, n, p, -1.0, UR, m, V, ldv, 1.0, E, m);
   double normA = frob(A, m, n, lda);
   out[0] = frob(E, m, n, m) / normA;
   out[3] = normA;
 
-  orc_gemm(1, 0, n, n, m, 1.0, U, ldu, U, ldu, 0.0, Gm, n);
-  for (int64_t i = 0; i < n; ++i) Gm[i + i * n] -= 1.0;
-  out[1] = frob(Gm, n, n, n);
-  orc_gemm(1, 0, n, n, n, 1.0, V, ldv, V, ldv, 0.0, Gm, n);
-  for (int64_t i = 0; i < n; ++i) Gm[i + i * n] -= 1.0;
-  out[2] = frob(Gm, n, n, n);
+  orc_gemm(1, 0, p, p, m, 1.0, U, ldu, U, ldu, 0.0, Gm, p);
+  for (int64_t i = 0; i < p; ++i) Gm[i + i * p] -= 1.0;
+  out[1] = frob(Gm, p, p, p);
+  orc_gemm(1, 0, p, p, n, 1.0, V, ldv, V, ldv, 0.0, Gm, p);
+  for (int64_t i = 0; i < p; ++i) Gm[i + i * p] -= 1.0;
+  out[2] = frob(Gm, p, p, p);
 
   if (ek) {
     /* ek[k]^2 = sum over rows i >= k of sum_{j >= i} R(i,j)^2 (the trailing
      * block R22 of eq. blocks, which is upper triangular). */
     double acc = 0.0;
-    ek[n] = 0.0;
-    for (int64_t k = n - 1; k >= 0; --k) {
+    ek[p] = 0.0;
+    for (int64_t k = p - 1; k >= 0; --k) {
       double row = 0.0;
-      for (int64_t j = k; j < n; ++j) row += R[k + j * ldr] * R[k + j * ldr];
+      for (int64_t j = k; j < p; ++j) row += R[k + j * ldr] * R[k + j * ldr];
       acc += row;
       ek[k] = sqrt(acc);
     }

@@ -54,21 +54,25 @@ int orc_qr_pos(double* X, int64_t m, int64_t n, int64_t ldx,
                double* Q, int64_t ldq, double* R, int64_t ldr);
 
 /* PowerURV (Section 3, eqs. power and powerqr): A = U R V^T.
- * A m x n (m >= n) is read only.  G: n x n starting matrix, or NULL to draw it
- * with orc_gaussian(seed, stream 2).  q >= 0 power steps; variant ORC_FULL
- * re-orthonormalises after every product with A or A^T, ORC_HALF once per
- * A^T A step, ORC_NONE only at the end.  q == 0 or orth_g != 0 starts from
- * V = Qpos(G) (q == 0 is DDH-URV, Section 2.2).  Outputs U (m x n), R (n x n
- * upper, strictly lower part 0), V (n x n).  Returns 0 or -1. */
+ * A m x n is read only; p = min(m, n).  G: p x p starting matrix, or NULL to
+ * draw it with orc_gaussian(seed, stream 2).  q >= 0 power steps; variant
+ * ORC_FULL re-orthonormalises after every product with A or A^T, ORC_HALF once
+ * per A^T A step, ORC_NONE only at the end.  q == 0 or orth_g != 0 starts from
+ * V = Qpos(G) (q == 0 is DDH-URV, Section 2.2).  Outputs U (m x p), R (p x p
+ * upper, strictly lower part 0), V (n x p).  m < n (Section 1): the tall
+ * method runs on B = A^T (n x m) up to X = B V; X with its columns reversed
+ * (J) is factored, X J = Q R', and A = V (J R' J)^T (Q J)^T is returned:
+ * U = V, R = J R'^T J, V = Q J.  Returns 0 or -1. */
 int orc_urv(const double* A, int64_t m, int64_t n, int64_t lda, int32_t q,
             uint64_t seed, const double* G, int64_t ldg, int32_t variant,
             int32_t orth_g, double* U, int64_t ldu, double* R, int64_t ldr,
             double* V, int64_t ldv);
 
-/* Checks of a factorisation (rank-k errors of Section 5, eq. blocks):
+/* Checks of a factorisation (rank-k errors of Section 5, eq. blocks), with
+ * p = min(m, n), U m x p, R p x p, V n x p:
  * out[0] = ||A - U R V^T||_F / ||A||_F, out[1] = ||U^T U - I||_F,
- * out[2] = ||V^T V - I||_F, out[3] = ||A||_F; ek (length n+1, may be NULL):
- * ek[k] = ||R(k:n-1, k:n-1)||_F over the upper triangle (0-based). */
+ * out[2] = ||V^T V - I||_F, out[3] = ||A||_F; ek (length p+1, may be NULL):
+ * ek[k] = ||R(k:p-1, k:p-1)||_F over the upper triangle (0-based). */
 int orc_metrics(const double* A, int64_t m, int64_t n, int64_t lda,
                 const double* U, int64_t ldu, const double* R, int64_t ldr,
                 const double* V, int64_t ldv, double out[4], double* ek);

@@ -35,10 +35,14 @@ MUTANTS = [
     ("FULL skips re-orthonormalisation of A V",
      "orc_gemm(1, 0, n, n, m, 1.0, A, lda, W, m, 0.0, Vw, n);        /* Y = A^T W */",
      "orc_gemm(1, 0, n, n, m, 1.0, A, lda, X, m, 0.0, Vw, n);        /* Y = A^T W */"),
-    ("final product uses A^T", "  orc_gemm(0, 0, m, n, n, 1.0, A, lda, Vw, n, 0.0, X, m);\n  double* Up",
-     "  orc_gemm(1, 0, m, n, n, 1.0, A, lda, Vw, n, 0.0, X, m);\n  double* Up"),
+    ("final product uses A^T", "orc_gemm(0, 0, mt, nt, nt, 1.0, At, ldat, Vw, nt, 0.0, X, mt);    /* X = A V */",
+     "orc_gemm(1, 0, mt, nt, nt, 1.0, At, ldat, Vw, nt, 0.0, X, mt);    /* X = A V */"),
+    ("wide: columns of A V not reversed", "memcpy(S + j * mt, X + (p - 1 - j) * mt,", "memcpy(S + j * mt, X + j * mt,"),
+    ("wide: R not transposed", "R[i + j * ldr] = Rp[(p - 1 - j) + (p - 1 - i) * p];",
+     "R[i + j * ldr] = Rp[(p - 1 - i) + (p - 1 - j) * p];"),
+    ("wide: V not reversed", "memcpy(V + j * ldv, Up + (p - 1 - j) * mt,", "memcpy(V + j * ldv, Up + j * mt,"),
     ("q = 0 start not orthonormalised", "if (q == 0 || orth_g) orthonormalize_square", "if (orth_g) orthonormalize_square"),
-    ("rank-k error drops the diagonal", "for (int64_t j = k; j < n; ++j) row +=", "for (int64_t j = k + 1; j < n; ++j) row +="),
+    ("rank-k error drops the diagonal", "for (int64_t j = k; j < p; ++j) row +=", "for (int64_t j = k + 1; j < p; ++j) row +="),
     ("jacobi rotation sign", "ap[i] = c * x - s * y;", "ap[i] = c * x + s * y;"),
 ]
 

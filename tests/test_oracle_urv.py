@@ -174,8 +174,6 @@ def test_invariants(orc, m, n, variant, q):
 
 def test_empty_and_bad_arguments(orc):
     with pytest.raises(ValueError):
-        orc.urv(np.zeros((3, 5)), 1)  # m < n
-    with pytest.raises(ValueError):
         orc.urv(np.zeros((5, 3)), -1)
 
 
@@ -240,3 +238,59 @@ def test_half_rounding_spread_exceeds_full(orc):
         spread[v] = np.linalg.norm(R1 - R2) / np.linalg.norm(A)
     assert spread["full"] < 1e-13
     assert spread["half"] > 10 * spread["full"]
+
+
+# --------------------------------------------------------------- m < n (Section 1: a ULV of A^T, transposed)
+WIDE = [(20, 35, 0), (20, 35, 2), (34, 35, 1), (1, 10, 1), (12, 40, 2)]
+
+
+@pytest.mark.parametrize("m,n,q", WIDE)
+@pytest.mark.parametrize("variant", ["full", "half"])
+def test_wide_invariants_and_closed_forms(orc, m, n, q, variant):
+    rng = np.random.default_rng(m * 100 + n + q)
+    sigma = 10.0 ** (-3.0 * np.arange(m) / max(m - 1, 1))
+    Q1, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((n, m)))
+    A = (Q1 * sigma) @ Q2.T
+    U, R, V = orc.urv(A, q, seed=7, variant=variant)
+    assert U.shape == (m, m) and R.shape == (m, m) and V.shape == (n, m)
+    met = orc.metrics(A, U, R, V)
+    assert met["recon"] < 1e-13 and met["orthU"] < 1e-13 and met["orthV"] < 1e-13
+    assert np.array_equal(R, np.triu(R)) and np.all(np.diag(R) >= 0)
+    assert met["ek"][0] == pytest.approx(np.linalg.norm(A), rel=1e-13)        # ||R||_F = ||A||_F
+    assert np.sum(np.log(np.abs(np.diag(R)))) == pytest.approx(np.sum(np.log(sigma)), abs=1e-9 * m)
+
+
+@pytest.mark.parametrize("m,n", [(24, 40), (30, 31)])
+def test_wide_equals_the_tall_problem_of_the_transpose(orc, m, n):
+    """U of the wide factorisation is V of the tall factorisation of B = A^T
+    (the same power steps), and its rank-k errors are ||B V(:, k:)||_F: the
+    leading block of R' over the reversed columns is the QR of B V(:, k:)."""
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((m, n)) * (0.7 ** np.arange(n))
+    U, R, V = orc.urv(A, 2, seed=11)
+    Ut, Rt, Vt = orc.urv(A.T.copy(), 2, seed=11)
+    assert np.array_equal(U, Vt)
+    ek = orc.metrics(A, U, R, V)["ek"]
+    BV = A.T @ Vt
+    ref = np.array([np.linalg.norm(BV[:, k:]) for k in range(m + 1)])
+    assert np.max(np.abs(ek - ref)) <= 1e-13 * np.linalg.norm(A)
+
+
+def test_wide_reveals_rank(orc):
+    """Decay 10^-8 over 40 values, q = 2: the rank-k errors stay within 2x of
+    the optimum (Eckart-Young); they are ||B V(:, k:)||_F, which the tall
+    problem's ||R22||_F does not exceed, so the bound is looser than there.
+    Without the column reversal the ratio would be orders of magnitude."""
+    m, n = 40, 64
+    rng = np.random.default_rng(5)
+    sigma = 10.0 ** (-8.0 * np.arange(m) / (m - 1))
+    Q1, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((n, m)))
+    A = (Q1 * sigma) @ Q2.T
+    U, R, V = orc.urv(A, 2, seed=3)
+    ek = orc.metrics(A, U, R, V)["ek"]
+    opt = np.sqrt(np.concatenate([np.cumsum((sigma ** 2)[::-1])[::-1], [0.0]]))
+    keep = opt[1:m] > 1e-12
+    ratio = ek[1:m][keep] / opt[1:m][keep]
+    assert np.all(ratio >= 1 - 1e-9) and np.max(ratio) < 2.0
