@@ -60,9 +60,9 @@ typedef struct {
   int32_t precision;  /* urv_precision */
   int32_t orth_g;     /* nonzero: start the power iteration from Qpos(G) instead of G */
   int32_t reserved;   /* must be 0 */
-  int64_t lda, ldu, ldr, ldv; /* leading dimensions; 0 selects the packed value (m, m, n, n) */
-  const double* G;    /* optional n x n starting matrix (device); NULL draws it from seed */
-  int64_t ldg;        /* leading dimension of G; 0 = n */
+  int64_t lda, ldu, ldr, ldv; /* leading dimensions; 0 selects the packed value (m, m, p, n), p = min(m, n) */
+  const double* G;    /* optional p x p starting matrix (device); NULL draws it from seed */
+  int64_t ldg;        /* leading dimension of G; 0 = p */
   void* stream;       /* hipStream_t; NULL = default stream */
   void* workspace;    /* optional device workspace; NULL = the library allocates on the stream */
   size_t workspace_bytes;
@@ -73,17 +73,21 @@ typedef struct {
 void urv_opts_init(urv_opts* opts);
 
 /*
- * PowerURV (Section 3, eqs. power and powerqr).  A is m x n with m >= n
- * (read only).  A Gaussian n x n G (eq. power) is drawn from seed (see
+ * PowerURV (Section 3, eqs. power and powerqr).  A is m x n (read only);
+ * p = min(m, n).  A Gaussian p x p G (eq. power) is drawn from seed (see
  * urv_gaussian, stream id 2) unless opts->G is given.  Then q >= 0 power
  * steps are taken on V (V starts as G, or Qpos(G) when q == 0 -- the DDH-URV
  * case of Section 2.2 -- or when orth_g is set), and the final step factors
  * A V = U R.  Qpos is an unpivoted blocked Householder QR whose R has a
  * non-negative diagonal.
- * Outputs: U m x n with orthonormal columns, R n x n upper triangular (its
- * strictly lower part is written as 0), V n x n orthogonal; A = U R V^T.
- * n == 0 is a no-op returning URV_OK.  m < n, q < 0, ld < rows, unknown
- * enums, null pointers with n > 0 or a too-small workspace give URV_EINVAL.
+ * Outputs: U m x p with orthonormal columns, R p x p upper triangular (its
+ * strictly lower part is written as 0), V n x p with orthonormal columns;
+ * A = U R V^T.  m < n (Section 1: a ULV of A^T, transposed): the method runs
+ * on B = A^T up to X = B V_B; X with its columns reversed (J) is factored,
+ * X J = Q R', and U = V_B (m x m), R = J R'^T J, V = Q J (n x m).
+ * min(m, n) == 0 is a no-op returning URV_OK.  q < 0, ld < rows (ldr < p,
+ * ldv < n, ldg < p), unknown enums, null pointers or a too-small workspace
+ * give URV_EINVAL; max(m, n) beyond the panel kernel's rows, URV_ENOTSUP.
  * Asynchronous on opts->stream.
  */
 int urv_factor_ex(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
@@ -95,7 +99,7 @@ int urv_factor(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
                double* U, double* R, double* V);
 
 /* Bytes of device workspace urv_factor_ex needs for these arguments (opts may
- * be NULL for the defaults).  0 when n == 0. */
+ * be NULL for the defaults).  0 when min(m, n) == 0. */
 size_t urv_workspace_size(int64_t m, int64_t n, int32_t q, const urv_opts* opts);
 
 /*
@@ -140,9 +144,10 @@ int urv_qr_pos_f32(float* X, int64_t m, int64_t n, int64_t ldx, float* Q, int64_
 
 /*
  * Checks of a factorisation, in FP64 on the device (rank-k errors of
- * Section 5 and the partition of eq. blocks).  Blocking.  out (HOST, 4
+ * Section 5 and the partition of eq. blocks), with p = min(m, n), U m x p,
+ * R p x p, V n x p.  Blocking.  out (HOST, 4
  * doubles): ||A - U R V^T||_F / ||A||_F, ||U^T U - I||_F, ||V^T V - I||_F,
- * ||A||_F.  ek (HOST, n+1 doubles, may be NULL): ek[k] = ||R(k:n-1,k:n-1)||_F
+ * ||A||_F.  ek (HOST, p+1 doubles, may be NULL): ek[k] = ||R(k:p-1,k:p-1)||_F
  * over the upper triangle, the Frobenius error of the rank-k truncation
  * U(:,1:k) R(1:k,:) V^T when A = U R V^T.  Packed leading dimensions.
  */

@@ -79,12 +79,50 @@ size_t factor_bytes(int64_t m, int64_t n, bool mixed) {
   return a.used;
 }
 
+// m < n: the tall problem of B = A^T (n x m) and the buffers of the transposed
+// ULV (Section 1).
+struct WideWork {
+  double* B = nullptr;   // n x m: A^T
+  double* Ut = nullptr;  // n x m: U of B's factorisation
+  double* T = nullptr;   // n x m
+  double* Rt = nullptr;  // m x m: R of B's factorisation
+  double* RJ = nullptr;  // m x m: Rt with its columns reversed
+  double* Q2 = nullptr;  // m x m
+  double* R2 = nullptr;  // m x m
+  double* gw = nullptr;
+  size_t gw_elems = 0;
+};
+
+void carve_wide(Arena& a, int64_t m, int64_t n, WideWork& x) {
+  const size_t nm = static_cast<size_t>(n) * m, mm = static_cast<size_t>(m) * m;
+  x.B = a.take<double>(nm);
+  x.Ut = a.take<double>(nm);
+  x.T = a.take<double>(nm);
+  x.Rt = a.take<double>(mm);
+  x.RJ = a.take<double>(mm);
+  x.Q2 = a.take<double>(mm);
+  x.R2 = a.take<double>(mm);
+  x.gw_elems = dgemm_work_elems(n, m, m);
+  x.gw = a.take<double>(x.gw_elems);
+}
+
+// Workspace of urv_factor_ex for any shape.
+size_t work_bytes(int64_t m, int64_t n, bool mixed) {
+  if (m >= n) return factor_bytes(m, n, mixed);
+  Arena a;
+  FactorWork w;
+  carve_factor(a, n, m, mixed, w);
+  WideWork x;
+  carve_wide(a, m, n, x);
+  return a.used;
+}
+
 constexpr int64_t kMaxRows = 240 * 256;  // rows the panel kernel's co-resident grid covers
 
 int validate_factor(const double* A, int64_t m, int64_t n, int32_t q, const double* U,
                     const double* R, const double* V, const urv_opts& o) {
-  if (n < 0 || m < n || q < 0) {
-    set_last_error("urv_factor: need 0 <= n <= m and q >= 0");
+  if (n < 0 || m < 0 || q < 0) {
+    set_last_error("urv_factor: need m, n >= 0 and q >= 0");
     return URV_EINVAL;
   }
   if (o.variant < URV_REORTH_FULL || o.variant > URV_REORTH_NONE) {
@@ -99,14 +137,15 @@ int validate_factor(const double* A, int64_t m, int64_t n, int32_t q, const doub
     set_last_error("urv_factor: reserved field must be 0");
     return URV_EINVAL;
   }
-  if (n == 0) return URV_OK;
+  const int64_t p = std::min(m, n);
+  if (p == 0) return URV_OK;
   if (!A || !U || !R || !V) {
     set_last_error("urv_factor: null matrix pointer");
     return URV_EINVAL;
   }
   const int64_t lda = o.lda ? o.lda : m, ldu = o.ldu ? o.ldu : m;
-  const int64_t ldr = o.ldr ? o.ldr : n, ldv = o.ldv ? o.ldv : n, ldg = o.ldg ? o.ldg : n;
-  if (lda < m || ldu < m || ldr < n || ldv < n || ldg < n || o.lda < 0 || o.ldu < 0 ||
+  const int64_t ldr = o.ldr ? o.ldr : p, ldv = o.ldv ? o.ldv : n, ldg = o.ldg ? o.ldg : p;
+  if (lda < m || ldu < m || ldr < p || ldv < n || ldg < p || o.lda < 0 || o.ldu < 0 ||
       o.ldr < 0 || o.ldv < 0 || o.ldg < 0) {
     set_last_error("urv_factor: leading dimension smaller than the row count");
     return URV_EINVAL;
@@ -115,11 +154,11 @@ int validate_factor(const double* A, int64_t m, int64_t n, int32_t q, const doub
     set_last_error("urv_factor: workspace_bytes given without a workspace");
     return URV_EINVAL;
   }
-  if (o.workspace != nullptr && o.workspace_bytes < factor_bytes(m, n, o.precision != URV_FP64)) {
+  if (o.workspace != nullptr && o.workspace_bytes < work_bytes(m, n, o.precision != URV_FP64 && q > 0)) {
     set_last_error("urv_factor: workspace too small (see urv_workspace_size)");
     return URV_EINVAL;
   }
-  if (m > kMaxRows) {
+  if (std::max(m, n) > kMaxRows) {
     set_last_error("urv_factor: more rows than the panel kernel supports");
     return URV_ENOTSUP;
   }
@@ -248,16 +287,42 @@ int run_factor_mixed(const double* A, int64_t m, int64_t n, int32_t q, uint64_t 
   return final_qr(m, n, U, ldu, R, ldr, w, s);
 }
 
+// m < n (Section 1): the ULV of B = A^T, transposed.  B = Ut Rt V_B^T is the
+// tall factorisation; X = B V_B = Ut Rt, and X J (J the column reversal) =
+// Ut (Rt J) = (Ut Q2) R2 with Rt J = Q2 R2.  So B = (Ut Q2 J)(J R2 J) V_B^T,
+// J R2 J lower triangular, and A = V_B (J R2^T J) (Ut Q2 J)^T: U = V_B,
+// R = J R2^T J, V = Ut Q2 J.
+int run_wide(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, double* U, double* R, double* V,
+             const urv_opts& o, const FactorWork& w, const WideWork& x, bool mixed, hipStream_t s) {
+  const int64_t lda = o.lda ? o.lda : m, ldu = o.ldu ? o.ldu : m;
+  const int64_t ldr = o.ldr ? o.ldr : m, ldv = o.ldv ? o.ldv : n;
+  URV_TRY(transpose_matrix(A, lda, m, n, x.B, n, s));                       // B = A^T
+  urv_opts ob = o;
+  ob.lda = n;
+  ob.ldu = n;
+  ob.ldr = m;
+  ob.ldv = ldu;
+  URV_TRY(mixed ? run_factor_mixed(x.B, n, m, q, seed, x.Ut, x.Rt, U, ob, w, s)
+                : run_factor(x.B, n, m, q, seed, x.Ut, x.Rt, U, ob, w, s));  // U = V_B
+  URV_TRY(reverse_cols(x.Rt, m, m, m, x.RJ, m, s));
+  URV_TRY(qr_pos<double>(x.RJ, m, m, m, x.Q2, m, x.R2, m, w.qr, s));     // Rt J = Q2 R2
+  URV_TRY(dgemm(false, false, n, m, m, 1.0, x.Ut, n, x.Q2, m, 0.0, x.T, n, x.gw, x.gw_elems, s));
+  URV_TRY(reverse_cols(x.T, n, n, m, V, ldv, s));                           // V = Ut Q2 J
+  return transpose_reverse(x.R2, m, m, R, ldr, s);                           // R = J R2^T J
+}
+
 // Runs the factorisation; when check_flag, waits for the stream and reports a
 // panel wait that expired on the device.
 int factor_impl(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, double* U,
                 double* R, double* V, const urv_opts& o, bool check_flag) {
   clear_last_error();
   URV_TRY(validate_factor(A, m, n, q, U, R, V, o));
-  if (n == 0) return URV_OK;
+  if (std::min(m, n) == 0) return URV_OK;
   hipStream_t s = static_cast<hipStream_t>(o.stream);
   const bool mixed = o.precision != URV_FP64 && q > 0;
-  const size_t need = factor_bytes(m, n, mixed);
+  const bool wide = m < n;
+  const int64_t mt = wide ? n : m, nt = wide ? m : n;  // the tall problem
+  const size_t need = work_bytes(m, n, mixed);
   Arena a;
   bool owned = false;
   if (o.workspace) {
@@ -276,18 +341,24 @@ int factor_impl(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
     owned = true;
   }
   FactorWork w;
-  carve_factor(a, m, n, mixed, w);
-  int rc = a.overflow ? URV_EINVAL : qr_clear_error_flag(w.qr, n, s);
-  if (rc == URV_OK && mixed) rc = qr_clear_error_flag(w.mx.qr, n, s);
-  if (rc == URV_OK)
-    rc = mixed ? run_factor_mixed(A, m, n, q, seed, U, R, V, o, w, s)
-               : run_factor(A, m, n, q, seed, U, R, V, o, w, s);
+  carve_factor(a, mt, nt, mixed, w);
+  WideWork x;
+  if (wide) carve_wide(a, m, n, x);
+  int rc = a.overflow ? URV_EINVAL : qr_clear_error_flag(w.qr, nt, s);
+  if (rc == URV_OK && mixed) rc = qr_clear_error_flag(w.mx.qr, nt, s);
+  if (rc == URV_OK) {
+    if (wide)
+      rc = run_wide(A, m, n, q, seed, U, R, V, o, w, x, mixed, s);
+    else
+      rc = mixed ? run_factor_mixed(A, m, n, q, seed, U, R, V, o, w, s)
+                 : run_factor(A, m, n, q, seed, U, R, V, o, w, s);
+  }
   if (rc == URV_OK && check_flag) {
     unsigned flag = 0;
     unsigned flag32 = 0;
-    if (hipMemcpyAsync(&flag, qr_error_flag(w.qr, n), sizeof(flag), hipMemcpyDeviceToHost, s) !=
+    if (hipMemcpyAsync(&flag, qr_error_flag(w.qr, nt), sizeof(flag), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
-        (mixed && hipMemcpyAsync(&flag32, qr_error_flag(w.mx.qr, n), sizeof(flag32),
+        (mixed && hipMemcpyAsync(&flag32, qr_error_flag(w.mx.qr, nt), sizeof(flag32),
                                  hipMemcpyDeviceToHost, s) != hipSuccess) ||
         hipStreamSynchronize(s) != hipSuccess) {
       rc = hip_status(hipGetLastError(), "urv_factor: synchronize");
@@ -377,9 +448,9 @@ int urv_factor(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, 
 }
 
 size_t urv_workspace_size(int64_t m, int64_t n, int32_t q, const urv_opts* opts) {
-  if (n <= 0 || m < n) return 0;
+  if (m <= 0 || n <= 0 || q < 0) return 0;
   const bool mixed = opts && opts->precision != URV_FP64 && q > 0;
-  return factor_bytes(m, n, mixed);
+  return work_bytes(m, n, mixed);
 }
 
 int urv_gaussian(void* G, int64_t rows, int64_t cols, int64_t ld, uint64_t seed,
@@ -440,8 +511,8 @@ int urv_qr_pos_f32(float* X, int64_t m, int64_t n, int64_t ldx, float* Q, int64_
 int urv_metrics(const double* A, int64_t m, int64_t n, const double* U, const double* R,
                 const double* V, double* out, double* ek, void* stream) {
   clear_last_error();
-  if (n <= 0 || m < n || !A || !U || !R || !V || !out) {
-    set_last_error("urv_metrics: need 0 < n <= m and non-null pointers");
+  if (n <= 0 || m <= 0 || !A || !U || !R || !V || !out) {
+    set_last_error("urv_metrics: need m, n > 0 and non-null pointers");
     return URV_EINVAL;
   }
   return metrics(A, m, n, U, R, V, out, ek, static_cast<hipStream_t>(stream));

@@ -181,6 +181,12 @@ struct QrTarget {
   int64_t ldz = 0;
 };
 
+// dst(:, j) = src(:, cols - 1 - j).
+int reverse_cols(const double* src, int64_t lds, int64_t rows, int64_t cols, double* dst, int64_t ldd,
+                 hipStream_t s);
+// dst(i, j) = src(p - 1 - j, p - 1 - i) for p x p (J src^T J, J the reversal).
+int transpose_reverse(const double* src, int64_t lds, int64_t p, double* dst, int64_t ldd, hipStream_t s);
+
 // dst (cols x rows, ldd) = src^T for src rows x cols.
 int transpose_matrix(const double* src, int64_t lds, int64_t rows, int64_t cols, double* dst, int64_t ldd,
                      hipStream_t s);

@@ -208,6 +208,40 @@ int copy_matrix(const double* src, int64_t lds, double* dst, int64_t ldd, int64_
   return URV_OK;
 }
 
+// dst(:, j) = src(:, cols - 1 - j): the columns in reverse order.
+__global__ void reverse_cols_kernel(const double* __restrict__ src, int64_t lds, int64_t rows, int64_t cols,
+                                    double* __restrict__ dst, int64_t ldd) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx % rows, j = idx / rows;
+  dst[i + j * ldd] = src[i + (cols - 1 - j) * lds];
+}
+
+// dst(i, j) = src(p - 1 - j, p - 1 - i) for p x p: J src^T J with J the reversal.
+__global__ void transpose_reverse_kernel(const double* __restrict__ src, int64_t lds, int64_t p,
+                                         double* __restrict__ dst, int64_t ldd) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= p * p) return;
+  const int64_t i = idx % p, j = idx / p;
+  dst[i + j * ldd] = src[(p - 1 - j) + (p - 1 - i) * lds];
+}
+
+int reverse_cols(const double* src, int64_t lds, int64_t rows, int64_t cols, double* dst, int64_t ldd,
+                 hipStream_t s) {
+  if (rows == 0 || cols == 0) return URV_OK;
+  reverse_cols_kernel<<<static_cast<unsigned>(ceil_div(rows * cols, 256)), 256, 0, s>>>(src, lds, rows, cols, dst,
+                                                                                         ldd);
+  URV_LAUNCHED("reverse_cols_kernel");
+  return URV_OK;
+}
+
+int transpose_reverse(const double* src, int64_t lds, int64_t p, double* dst, int64_t ldd, hipStream_t s) {
+  if (p == 0) return URV_OK;
+  transpose_reverse_kernel<<<static_cast<unsigned>(ceil_div(p * p, 256)), 256, 0, s>>>(src, lds, p, dst, ldd);
+  URV_LAUNCHED("transpose_reverse_kernel");
+  return URV_OK;
+}
+
 int copy_matrix_f32(const float* src, int64_t lds, float* dst, int64_t ldd, int64_t rows, int64_t cols,
                     hipStream_t s) {
   if (rows == 0 || cols == 0) return URV_OK;
@@ -219,38 +253,40 @@ int copy_matrix_f32(const float* src, int64_t lds, float* dst, int64_t ldd, int6
 
 int metrics(const double* A, int64_t m, int64_t n, const double* U, const double* R,
             const double* V, double* out_host, double* ek_host, hipStream_t s) {
-  // Workspace: UR (m x n), E (m x n), Gram (n x n), partials, scalars, rowsq, ek.
-  const size_t mn = static_cast<size_t>(m) * n, nn = static_cast<size_t>(n) * n;
-  const size_t gw = std::max({dgemm_work_elems(m, n, n), dgemm_work_elems(n, n, m),
-                              dgemm_work_elems(n, n, n)});
-  const size_t total = 2 * mn + nn + kRedBlocks + 8 + 2 * (n + 1) + gw;
+  // U m x p, R p x p, V n x p with p = min(m, n).
+  // Workspace: UR (m x p), E (m x n), Gram (p x p), partials, scalars, rowsq, ek.
+  const int64_t p = std::min(m, n);
+  const size_t mp = static_cast<size_t>(m) * p, mn = static_cast<size_t>(m) * n, pp = static_cast<size_t>(p) * p;
+  const size_t gw = std::max({dgemm_work_elems(m, p, p), dgemm_work_elems(m, n, p), dgemm_work_elems(p, p, m),
+                              dgemm_work_elems(p, p, n)});
+  const size_t total = mp + mn + pp + kRedBlocks + 8 + 2 * (p + 1) + gw;
   double* buf = nullptr;
   URV_HIP(hipMallocAsync(reinterpret_cast<void**>(&buf), total * sizeof(double), s));
   double* UR = buf;
-  double* E = UR + mn;
+  double* E = UR + mp;
   double* Gm = E + mn;
-  double* part = Gm + nn;
+  double* part = Gm + pp;
   double* scal = part + kRedBlocks;
   double* rowsq = scal + 8;
-  double* ek = rowsq + (n + 1);
-  double* gwork = ek + (n + 1);
+  double* ek = rowsq + (p + 1);
+  double* gwork = ek + (p + 1);
   int rc = URV_OK;
   do {
-    if ((rc = dgemm(false, false, m, n, n, 1.0, U, m, R, n, 0.0, UR, m, gwork, gw, s))) break;
+    if ((rc = dgemm(false, false, m, p, p, 1.0, U, m, R, p, 0.0, UR, m, gwork, gw, s))) break;
     if ((rc = copy_matrix(A, m, E, m, m, n, s))) break;
-    if ((rc = dgemm(false, true, m, n, n, -1.0, UR, m, V, n, 1.0, E, m, gwork, gw, s))) break;
+    if ((rc = dgemm(false, true, m, n, p, -1.0, UR, m, V, n, 1.0, E, m, gwork, gw, s))) break;
     if ((rc = sumsq(E, m, m, n, 0.0, part, scal + 0, s))) break;
     if ((rc = sumsq(A, m, m, n, 0.0, part, scal + 1, s))) break;
-    if ((rc = dgemm(true, false, n, n, m, 1.0, U, m, U, m, 0.0, Gm, n, gwork, gw, s))) break;
-    if ((rc = sumsq(Gm, n, n, n, 1.0, part, scal + 2, s))) break;
-    if ((rc = dgemm(true, false, n, n, n, 1.0, V, n, V, n, 0.0, Gm, n, gwork, gw, s))) break;
-    if ((rc = sumsq(Gm, n, n, n, 1.0, part, scal + 3, s))) break;
-    upper_row_sumsq_kernel<<<static_cast<unsigned>(ceil_div(n, 256)), 256, 0, s>>>(R, n, n, rowsq);
-    suffix_sqrt_kernel<<<1, 1, 0, s>>>(rowsq, n, ek);
+    if ((rc = dgemm(true, false, p, p, m, 1.0, U, m, U, m, 0.0, Gm, p, gwork, gw, s))) break;
+    if ((rc = sumsq(Gm, p, p, p, 1.0, part, scal + 2, s))) break;
+    if ((rc = dgemm(true, false, p, p, n, 1.0, V, n, V, n, 0.0, Gm, p, gwork, gw, s))) break;
+    if ((rc = sumsq(Gm, p, p, p, 1.0, part, scal + 3, s))) break;
+    upper_row_sumsq_kernel<<<static_cast<unsigned>(ceil_div(p, 256)), 256, 0, s>>>(R, p, p, rowsq);
+    suffix_sqrt_kernel<<<1, 1, 0, s>>>(rowsq, p, ek);
     finalize_metrics_kernel<<<1, 1, 0, s>>>(scal, scal + 4);
     if (hipGetLastError() != hipSuccess) { rc = URV_EDEVICE; break; }
     if (hipMemcpyAsync(out_host, scal + 4, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) { rc = URV_EDEVICE; break; }
-    if (ek_host && hipMemcpyAsync(ek_host, ek, (n + 1) * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) { rc = URV_EDEVICE; break; }
+    if (ek_host && hipMemcpyAsync(ek_host, ek, (p + 1) * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) { rc = URV_EDEVICE; break; }
     if (hipStreamSynchronize(s) != hipSuccess) { rc = URV_EDEVICE; break; }
   } while (false);
   hipFreeAsync(buf, s);

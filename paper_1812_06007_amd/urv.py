@@ -202,7 +202,8 @@ def workspace_size(m: int, n: int, q: int = 0, variant: str = "full", precision:
 
 def factor(A, q: int, seed: int = 0, variant: str = "full", precision: str = "fp64", G=None,
            orth_g: bool = False, workspace=None, out=None):
-    """PowerURV A = U R V^T (Section 3).  Returns (U, R, V) as column-major FP64 tensors.
+    """PowerURV A = U R V^T (Section 3).  Returns (U, R, V) as column-major FP64 tensors:
+    U m x p, R p x p, V n x p with p = min(m, n) (m < n: a ULV of A^T, transposed).
 
     Asynchronous on the current stream.  ``workspace`` may be a uint8 CUDA
     tensor of at least ``workspace_size(...)`` bytes; ``out`` may be a
@@ -211,10 +212,11 @@ def factor(A, q: int, seed: int = 0, variant: str = "full", precision: str = "fp
     torch = _torch()
     A, lda = _colmajor(A)
     m, n = A.shape
+    p = min(m, n)
     if out is None:
-        U = empty_colmajor(m, n, device=A.device)
-        R = empty_colmajor(n, n, device=A.device)
-        V = empty_colmajor(n, n, device=A.device)
+        U = empty_colmajor(m, p, device=A.device)
+        R = empty_colmajor(p, p, device=A.device)
+        V = empty_colmajor(n, p, device=A.device)
     else:
         U, R, V = out
     o = UrvOpts()
@@ -223,14 +225,14 @@ def factor(A, q: int, seed: int = 0, variant: str = "full", precision: str = "fp
     o.precision = PRECISIONS[precision]
     o.orth_g = int(bool(orth_g))
     o.lda = lda
-    o.ldu = max(U.stride(1), m) if n > 1 else max(m, 1)
-    o.ldr = max(R.stride(1), n) if n > 1 else max(n, 1)
-    o.ldv = max(V.stride(1), n) if n > 1 else max(n, 1)
+    o.ldu = max(U.stride(1), m) if p > 1 else max(m, 1)
+    o.ldr = max(R.stride(1), p) if p > 1 else max(p, 1)
+    o.ldv = max(V.stride(1), n) if p > 1 else max(n, 1)
     Gk = None
     if G is not None:
         Gk, ldg = _colmajor(G)
-        if tuple(Gk.shape) != (n, n):
-            raise ValueError("G must be n x n")
+        if tuple(Gk.shape) != (p, p):
+            raise ValueError("G must be min(m, n) x min(m, n)")
         o.G = Gk.data_ptr()
         o.ldg = ldg
     o.stream = _stream_ptr().value
@@ -298,7 +300,7 @@ def metrics(A, U, R, V) -> dict:
     A, U, R, V = (_packed(t) for t in (A, U, R, V))
     m, n = A.shape
     out = np.zeros(4)
-    ek = np.zeros(n + 1)
+    ek = np.zeros(min(m, n) + 1)
     _check(lib().urv_metrics(_ptr(A), m, n, _ptr(U), _ptr(R), _ptr(V),
                              out.ctypes.data_as(ctypes.c_void_p), ek.ctypes.data_as(ctypes.c_void_p),
                              _stream_ptr()))

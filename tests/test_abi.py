@@ -63,8 +63,9 @@ def _factor(m, n, q, ptrs=True, **fields):
 
 
 @pytest.mark.parametrize("m,n,q,fields", [
-    (3, 5, 1, {}),                      # m < n
     (5, -1, 1, {}),                     # n < 0
+    (3, 5, 1, {"ldv": 3}),              # m < n: V is n x m, ldv >= n
+    (3, 5, 1, {"ldr": 2}),              # m < n: R is m x m
     (5, 3, -1, {}),                     # q < 0
     (5, 3, 1, {"variant": 3}),          # unknown variant
     (5, 3, 1, {"precision": 1}),        # unknown precision
@@ -101,7 +102,7 @@ def test_workspace_size_monotone():
     big = urv.workspace_size(1000, 500)
     assert 0 < small < big
     assert urv.workspace_size(10, 0) == 0
-    assert urv.workspace_size(3, 5) == 0
+    assert urv.workspace_size(3, 5) > 0          # m < n: the transposed problem
     # the FP64 workspace of the 8000 x 8000 case stays far below 288 GB of HBM
     assert urv.workspace_size(8000, 8000, 2) < 4 * 2**30
 
