@@ -472,7 +472,7 @@ int with_work(int64_t m, int64_t n, const urv_grad_opts& o, const char* who, F b
     void* p = nullptr;
     const hipError_t e = hipMallocAsync(&p, need, s);
     if (e != hipSuccess) {
-      hipGetLastError();
+      (void)hipGetLastError();  // clear the sticky error; the failure is reported below
       set_last_error(std::string(who) + ": workspace allocation failed: " + hipGetErrorString(e));
       return URV_ENOMEM;
     }
@@ -484,7 +484,10 @@ int with_work(int64_t m, int64_t n, const urv_grad_opts& o, const char* who, F b
   carve_grad(a, m, n, w);
   int rc = a.overflow ? URV_EINVAL : qr_clear_error_flag(w.qr, n, s);
   if (rc == URV_OK) rc = body(w, s);
-  if (owned) hipFreeAsync(a.base, s);
+  if (owned) {
+    const hipError_t e = hipFreeAsync(a.base, s);
+    if (e != hipSuccess && rc == URV_OK) rc = hip_status(e, who);
+  }
   return rc;
 }
 

@@ -332,7 +332,7 @@ int factor_impl(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
     void* p = nullptr;
     const hipError_t e = hipMallocAsync(&p, need, s);
     if (e != hipSuccess) {
-      hipGetLastError();
+      (void)hipGetLastError();  // clear the sticky error; the failure is reported below
       set_last_error(std::string("urv_factor: workspace allocation failed: ") + hipGetErrorString(e));
       return URV_ENOMEM;
     }
@@ -368,7 +368,10 @@ int factor_impl(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
       rc = URV_EDEVICE;
     }
   }
-  if (owned) hipFreeAsync(a.base, s);
+  if (owned) {
+    const hipError_t e = hipFreeAsync(a.base, s);
+    if (e != hipSuccess && rc == URV_OK) rc = hip_status(e, "urv_factor");
+  }
   return rc;
 }
 
@@ -415,7 +418,8 @@ int qr_entry(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, i
   qr_work_carve(a, m, n, w);
   int rc = qr_clear_error_flag(w, n, s);
   if (rc == URV_OK) rc = qr_pos<T>(X, m, n, ldx, Q, ldq, R, ldr, w, s);
-  hipFreeAsync(p, s);
+  const hipError_t e = hipFreeAsync(p, s);
+  if (e != hipSuccess && rc == URV_OK) rc = hip_status(e, "urv_qr_pos");
   return rc;
 }
 }  // namespace
@@ -492,9 +496,11 @@ int urv_dgemm(int32_t transA, int32_t transB, int64_t M, int64_t N, int64_t K, d
   const size_t we = dgemm_work_elems(M, N, K);
   double* work = nullptr;
   if (we) URV_HIP(hipMallocAsync(reinterpret_cast<void**>(&work), we * sizeof(double), s));
-  const int rc = dgemm(transA != 0, transB != 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                       work, we, s);
-  if (work) hipFreeAsync(work, s);
+  int rc = dgemm(transA != 0, transB != 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work, we, s);
+  if (work) {
+    const hipError_t e = hipFreeAsync(work, s);
+    if (e != hipSuccess && rc == URV_OK) rc = hip_status(e, "urv_dgemm");
+  }
   return rc;
 }
 

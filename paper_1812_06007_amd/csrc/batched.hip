@@ -740,7 +740,7 @@ int resident_capacity(int nb, int device) {
     e = (nb == 16) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_urv_kernel<16>, BT, 0)
                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_urv_kernel<32>, BT, 0);
   if (e != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();  // clear the sticky error: no capacity means no team schedules
     return 0;
   }
   return per_cu * cus;
@@ -782,8 +782,8 @@ using urv::set_last_error;
 constexpr int kMaxTeam = 64;
 
 void drop_graph(urv_batch_plan* p) {
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);  // teardown: nothing to do on failure
+  if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
   p->graph = nullptr;
 }
@@ -836,14 +836,15 @@ urv::DeviceQueue queue_of(const urv_batch_plan* p) {
 
 void free_plan(urv_batch_plan* p) {
   drop_graph(p);
-  if (p->cap) hipStreamDestroy(p->cap);
-  hipFree(p->scratch);
-  hipFree(p->d_items);
-  hipFree(p->d_order);
-  hipFree(p->d_team);
-  hipFree(p->d_tickets);
-  hipFree(p->d_counters);
-  hipFree(p->d_bars);
+  // teardown: failures here cannot be reported to anyone, and are ignored
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  (void)hipFree(p->scratch);
+  (void)hipFree(p->d_items);
+  (void)hipFree(p->d_order);
+  (void)hipFree(p->d_team);
+  (void)hipFree(p->d_tickets);
+  (void)hipFree(p->d_counters);
+  (void)hipFree(p->d_bars);
   delete p;
 }
 
@@ -1014,7 +1015,7 @@ int urv_batch_run_graph(urv_batch_plan* p, void* stream) {
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(p->cap, &g);
     if (rc != URV_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return rc;
     }
     URV_HIP(e);
@@ -1065,7 +1066,10 @@ int urv_batch_autotune(urv_batch_plan* p, void* stream, double* best_ms) {
         rc = urv::hip_status(hipGetLastError(), "urv_batch_autotune");
       if (rc != URV_OK) break;
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = urv::hip_status(hipGetLastError(), "urv_batch_autotune");
+        break;
+      }
       if (best < 0.f || ms < best) {
         best = ms;
         best_nb = nb;
@@ -1074,8 +1078,8 @@ int urv_batch_autotune(urv_batch_plan* p, void* stream, double* best_ms) {
     }
     if (rc != URV_OK) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc != URV_OK) {
     build_queue(p, p->nb, p->grid, p->team_max);
     return rc;

@@ -956,6 +956,18 @@ bool target_pairs() {
   return !(e && std::atoi(e) == 0);
 }
 
+// How many blocks the targets trail the factorisation by (URV_TARGET_LAG
+// overrides it, for tuning).  The targets only have to be done when the QR
+// returns, while the trailing updates of the first blocks gate the chain: held
+// back, the target products leave the CUs to those updates while the trailing
+// matrix is large and run beside the later, lighter blocks.  Measured on
+// MI355X at n = 8000, q = 2: 343 ms with no lag, 335-334 ms with 10-14
+// blocks, 338 ms with 20 (the held-back products then outlast the chain).
+int target_lag() {
+  const char* e = std::getenv("URV_TARGET_LAG");
+  return e ? std::max(0, std::atoi(e)) : 12;
+}
+
 // Outer block width used by qr_pos: NB2 or NBO (URV_QR_BLOCK, for tuning).
 int outer_block() {
   const char* e = std::getenv("URV_QR_BLOCK");
@@ -1289,6 +1301,8 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   // hardware queue.  With URV_PANEL_EARLY=0, s2 updates the next block's
   // columns itself, between the factorisations.
   const bool early = panel_early();
+  const int64_t lag = target_lag();
+  int64_t tgt_next = 0;  // first block whose targets are not yet queued
   URV_HIP(hipEventRecord(side.ev_next, s));      // the cleared flags and slots
   URV_HIP(hipStreamWaitEvent(s2, side.ev_next, 0));
   if (ntargets > 0) URV_HIP(hipStreamWaitEvent(s3, side.ev_next, 0));  // targets written before the call
@@ -1297,11 +1311,13 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   bool near_pending = false, bulk_pending = false;
   for (int64_t j0 = 0; j0 < n; j0 += nbo) {
     URV_HIP(hipStreamWaitEvent(s, side.ev_fact, 0));  // block j0 is factored
-    if (ntargets > 0) {
-      URV_HIP(hipStreamWaitEvent(s3, side.ev_fact, 0));
-      URV_TRY(apply_targets(j0));
-    }
     const int64_t j1 = j0 + nbo;
+    if (ntargets > 0) {
+      // blocks up to j0 - lag now; at the last block, all that are left
+      const int64_t upto = j1 >= n ? j0 : j0 - lag * nbo;
+      if (tgt_next <= upto) URV_HIP(hipStreamWaitEvent(s3, side.ev_fact, 0));
+      for (; tgt_next <= upto; tgt_next += nbo) URV_TRY(apply_targets(tgt_next));
+    }
     if (j1 >= n) break;
     const int64_t nn = std::min<int64_t>(nbo, n - j1);
     if (early) {

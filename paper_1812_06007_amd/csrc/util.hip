@@ -289,7 +289,7 @@ int metrics(const double* A, int64_t m, int64_t n, const double* U, const double
     if (ek_host && hipMemcpyAsync(ek_host, ek, (p + 1) * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) { rc = URV_EDEVICE; break; }
     if (hipStreamSynchronize(s) != hipSuccess) { rc = URV_EDEVICE; break; }
   } while (false);
-  hipFreeAsync(buf, s);
+  if (hipFreeAsync(buf, s) != hipSuccess && rc == URV_OK) rc = URV_EDEVICE;
   if (rc == URV_EDEVICE) set_last_error("metrics: HIP error");
   return rc;
 }
