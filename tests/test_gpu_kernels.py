@@ -94,6 +94,40 @@ def test_dgemm_leading_dimensions_and_beta_zero(urv, orc):
     assert torch.isnan(Cbig[70:, :]).all()  # rows beyond M untouched
 
 
+@pytest.mark.parametrize("ta", [False, True])
+@pytest.mark.parametrize("tb", [False, True])
+@pytest.mark.parametrize("layout", ["odd_ld", "offset_by_one", "aligned"])
+def test_dgemm_operand_alignment(urv, ta, tb, layout):
+    """Full 128 x 128 tiles load pairs of elements with one 16-byte load only
+    when both operands are 16-byte aligned with even leading dimensions; odd
+    leading dimensions and operands starting one element in take the
+    element-by-element loads.  Small integers: every product is exact."""
+    import torch
+
+    announce("dgemm alignment", ta, tb, layout)
+    rng = np.random.default_rng(11)
+    M, N, K = 300, 260, 200
+    A = rng.integers(-4, 5, size=(K, M) if ta else (M, K)).astype(np.float64)
+    B = rng.integers(-4, 5, size=(N, K) if tb else (K, N)).astype(np.float64)
+
+    def place(X):
+        r, c = X.shape
+        if layout == "aligned":
+            return to_gpu(X)
+        extra = 1 if layout == "odd_ld" else 2
+        big = torch.zeros((c + 1, r + extra), dtype=torch.float64, device="cuda").t()  # ld r + extra
+        off = 0 if layout == "odd_ld" else 1
+        big[off:off + r, :c] = to_gpu(X)
+        view = big[off:off + r, :c]
+        assert view.stride(1) == r + extra
+        assert (view.data_ptr() % 16 != 0) == (layout == "offset_by_one")
+        return view
+
+    C = urv.dgemm(place(A), place(B), ta, tb)
+    ref = (A.T if ta else A) @ (B.T if tb else B)
+    np.testing.assert_array_equal(to_np(C), ref)
+
+
 def test_dgemm_is_deterministic(urv):
     announce("dgemm determinism")
     rng = np.random.default_rng(5)

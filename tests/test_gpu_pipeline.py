@@ -59,15 +59,33 @@ def _parity(urv, orc, m, n, q, seed):
     {"URV_PANEL_FUSED": "0"},
     {"URV_PANEL_FUSED": "0", "URV_PANEL_JOIN": "0"},
     {"URV_PANEL_EARLY": "0"},
+    {"URV_TARGET_LAG": "0"},
+    {"URV_TARGET_LAG": "1000"},
     {"URV_QR_BLOCK": "256", "URV_PANEL_FUSED": "0", "URV_PANEL_JOIN": "0", "URV_TARGET_PAIRS": "0",
-     "URV_PANEL_EARLY": "0"},
-], ids=["block256", "no_pairs", "separate_panels", "no_join", "in_order", "all_off"])
+     "URV_PANEL_EARLY": "0", "URV_TARGET_LAG": "1"},
+], ids=["block256", "no_pairs", "separate_panels", "no_join", "in_order", "targets_at_once", "targets_at_end",
+        "all_off"])
 @pytest.mark.parametrize("m,n", [(400, 400), (700, 520), (300, 197)])
 def test_schedule_variants_match_oracle(urv, orc, monkeypatch, env, m, n):
     announce("schedule", env, m, n)
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     _parity(urv, orc, m, n, 2, seed=m * 7 + n)
+
+
+def test_target_lag_does_not_change_the_bits(urv, monkeypatch):
+    """When the target products run (with their block, a few blocks later, or
+    all after the last block) changes only the schedule: same operations in
+    the same order, so the same bits."""
+    announce("target lag bits")
+    m, n = 900, 700
+    A = to_gpu(gen.spectral_matrix(m, n, gen.spectrum("geometric8", n), seed=31))
+    outs = []
+    for lag in ("0", "3", "12", "1000"):
+        monkeypatch.setenv("URV_TARGET_LAG", lag)
+        outs.append([to_np(t) for t in urv.factor(A, 2, seed=32)])
+    for other in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(outs[0], other))
 
 
 def _blocking_factor(urv, A, q, seed):
