@@ -369,6 +369,9 @@ def main() -> int:
                     help="run only the batched workload (for profiling) and exit")
     ap.add_argument("--gemm-only", action="store_true",
                     help="run only the A V GEMM launches (for counter collection) and exit")
+    ap.add_argument("--factor-only", action="store_true",
+                    help="run only two factorisations of a Gaussian A of the bench's shape (for counter "
+                         "collection: no input construction through torch) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only plain 1 GiB device copies (counter calibration) and exit")
     ap.add_argument("--gemm-source-hash", action="store_true",
@@ -413,6 +416,18 @@ def main() -> int:
     if args.grad_only:
         print("[bench] differentiation workload only", file=sys.stderr, flush=True)
         print(json.dumps(bench_grad(max(args.grad_steps, 1), args.warmup, False)))
+        return 0
+
+    if args.factor_only:
+        # the factorisation itself, on an input that needs no QR of torch's to build
+        A = urv.gaussian(m, n, seed=1812, stream_id=5)
+        U, R, V = urv.empty_colmajor(m, n, device=dev), urv.empty_colmajor(n, n, device=dev), \
+            urv.empty_colmajor(n, n, device=dev)
+        ws = torch.empty(urv.workspace_size(m, n, q, args.variant), dtype=torch.uint8, device=dev)
+        for _ in range(2):
+            urv.factor(A, q, seed=1812, variant=args.variant, workspace=ws, out=(U, R, V))
+        torch.cuda.synchronize()
+        print("[bench] 2 factorisations (%s, %dx%d, q=%d) done" % (args.variant, m, n, q), file=sys.stderr, flush=True)
         return 0
 
     if args.gemm_only:
