@@ -278,6 +278,34 @@ def bench_batched(steps: int, warmup: int, oracle_sample: int) -> dict:
     return res
 
 
+def bench_wide(q: int, variant: str, steps: int, warmup: int) -> dict:
+    """m < n (a ULV of A^T, transposed): A 4000 x 8000 against the tall
+    factorisation of the same A^T (8000 x 4000), same spectrum (1/j^2), FP64."""
+    import torch
+
+    import urv_inputs as gen
+    from paper_1812_06007_amd import urv
+
+    m, n = 4000, 8000
+    dev = torch.device("cuda:0")
+    B = gen.spectral_matrix(n, m, gen.spectrum("poly2", m), seed=1812, device=dev)  # tall, n x m
+    A = B.contiguous().t()  # its transpose: m x n, column-major (row-major copy of B, transposed view)
+    out_w = (urv.empty_colmajor(m, m, device=dev), urv.empty_colmajor(m, m, device=dev),
+             urv.empty_colmajor(n, m, device=dev))
+    out_t = (urv.empty_colmajor(n, m, device=dev), urv.empty_colmajor(m, m, device=dev),
+             urv.empty_colmajor(m, m, device=dev))
+    ms_w = time_factor(A, q, variant, "fp64", steps, warmup, out_w)
+    ms_t = time_factor(B, q, variant, "fp64", steps, warmup, out_t)
+    met = urv.metrics(A, *out_w)
+    # the tall problem of A^T, plus the m x m QR of its R with reversed columns and the n x m x m product
+    fl = executed_flops(n, m, q, variant) + 8.0 / 3.0 * m ** 3 + 2.0 * n * m * m
+    return {"workload": "A 4000x8000 = (Q1 diag(1/j^2) Q2^T)^T, FP64 %s q=%d, against the tall 8000x4000 A^T"
+                        % (variant.upper(), q),
+            "ms": ms_w, "ms_tall_transpose": ms_t, "flops_executed": fl,
+            "tflops": fl / (ms_w * 1e-3) / 1e12, "recon": met["recon"], "orthU": met["orthU"],
+            "orthV": met["orthV"]}
+
+
 def time_factor(A, q: int, variant: str, precision: str, steps: int, warmup: int, out) -> float:
     """Mean milliseconds of urv.factor over `steps` runs (HIP events on the current stream)."""
     import torch
@@ -359,6 +387,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=3600, help="n of the oracle sample (0: skip)")
     ap.add_argument("--gemm-reps", type=int, default=5)
     ap.add_argument("--mixed-steps", type=int, default=3, help="timed steps per mixed comparison (0: skip)")
+    ap.add_argument("--wide-steps", type=int, default=3,
+                    help="timed steps of the m < n workload, 4000x8000 (0: skip)")
     ap.add_argument("--grad-steps", type=int, default=5,
                     help="timed steps of the differentiation workload (0: skip)")
     ap.add_argument("--grad-only", action="store_true",
@@ -512,6 +542,12 @@ def main() -> int:
         del A3, out3
         torch.cuda.empty_cache()
 
+    wide = None
+    if args.wide_steps > 0:
+        print("[bench] m < n: 4000x8000 against its tall transpose", file=sys.stderr, flush=True)
+        wide = bench_wide(q, args.variant, args.wide_steps, 1)
+        torch.cuda.empty_cache()
+
     grad = None
     if args.grad_steps > 0:
         print("[bench] differentiation workload (2048x2048 FP32, q=2, k=256)", file=sys.stderr, flush=True)
@@ -557,6 +593,7 @@ def main() -> int:
                      "frac": gemm_tf / FP64_MFMA_PEAK_TFLOPS, "traffic": gemm_traffic(m, n),
                      "launch_ms": gemm_ms, "flop_per_launch": 2.0 * m * n * n},
         "mixed_vs_fp64": mixed,
+        "m_lt_n": wide,
         "differentiation": grad,
         "batched": batched,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
