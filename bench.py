@@ -412,8 +412,8 @@ def main() -> int:
         return 0
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); the multi-GPU layout is described "
-              "in DESIGN.md and not implemented", file=sys.stderr)
+        print("bench.py: only one GPU is supported (--gpus 1); a layout over several GPUs is designed "
+              "but not implemented", file=sys.stderr)
         return 2
 
     import numpy as np
