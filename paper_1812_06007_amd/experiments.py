@@ -15,6 +15,9 @@ prescribed spectrum gives in closed form: sqrt(sum_{j>k} sigma_j^2).  The
 singular values of R11 and R22 against sigma_k and sigma_{k+1} (the
 rank-revealing bounds of Section 1, shown in the figure of Section 3) are
 reported too; those small SVDs are analysis on the host, not part of the path.
+
+The section relating PowerURV to the RSVD is reproduced by `rsvd_comparison`:
+Matrix 2, l = 60, q = 0 and 1, both methods from the same G.
 """
 from __future__ import annotations
 
@@ -62,6 +65,78 @@ def run(q_values=(0, 1, 2), m: int = 200, n: int = 160, seed: int = 1812, device
     return out
 
 
+def rsvd_comparison(q_values=(0, 1), l: int = 60, m: int = 200, n: int = 160, seed: int = 1812,
+                    device="cuda") -> dict:
+    """PowerURV against the RSVD on Matrix 2 with l = 60 (the section relating
+    the two; its figures for q = 0 and q = 1).
+
+    The RSVD starts from the first l columns of the same G: Y = A (A^T A)^q G(:, 1:l)
+    by the library's GEMMs, Q = Qpos(Y) by its QR, Q^T A = W S Vr^T (an l x n SVD,
+    analysis on the host, as the paper's deterministic SVD step), U_rsvd = Q W.
+    Reported for k = 1..l: ||A - U_k U_k^T A||_F and ||A - A V_k V_k^T||_F for both
+    methods (U_k, V_k the first k columns).  The section's Lemma makes the two
+    U-errors equal at k = l (the leading l columns of U and U_rsvd span the same
+    space); below l the RSVD, which applies A once more, is closer to the optimum."""
+    import torch
+
+    import urv_inputs as gen
+
+    from . import urv
+
+    sigma = gen.spectrum("matrix2", n)
+    A_np = gen.spectral_matrix(m, n, sigma, seed)
+    A = torch.from_numpy(np.ascontiguousarray(A_np.T)).to(device).t()
+    G = urv.gaussian(n, n, seed=seed, device=device)
+    normA = float(np.linalg.norm(A_np))
+    opt = np.sqrt(np.concatenate([np.cumsum((sigma ** 2)[::-1])[::-1], [0.0]]))
+    out = {}
+    for q in q_values:
+        U, R, V = urv.factor(A, q, G=G)
+        Z = G[:, :l].contiguous().t().contiguous().t()
+        for _ in range(q):
+            Z = urv.dgemm(A, urv.dgemm(A, Z), transA=True)  # A^T (A Z)
+        Q, _ = urv.qr_pos(urv.dgemm(A, Z), want_r=False)
+        B = urv.dgemm(Q, A, transA=True)                    # Q^T A, l x n
+        Wr, _, Vrt = np.linalg.svd(B.cpu().numpy())
+        Ur = Q.cpu().numpy() @ Wr[:, :l]
+        Vr = Vrt[:l].T
+        Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+
+        def left(Bk, k):
+            return float(np.linalg.norm(A_np - Bk[:, :k] @ (Bk[:, :k].T @ A_np)))
+
+        def right(Bk, k):
+            return float(np.linalg.norm(A_np - (A_np @ Bk[:, :k]) @ Bk[:, :k].T))
+
+        ks = range(1, l + 1)
+        eu = np.array([left(Uh, k) for k in ks])
+        er = np.array([left(Ur, k) for k in ks])
+        fu = np.array([right(Vh, k) for k in ks])
+        fr = np.array([right(Vr, k) for k in ks])
+        out["q%d" % q] = {
+            "q": q, "l": l, "normA": normA, "opt": opt[1:l + 1].tolist(),
+            "powerurv_left": eu.tolist(), "rsvd_left": er.tolist(),
+            "powerurv_right": fu.tolist(), "rsvd_right": fr.tolist(),
+            "lemma_gap_at_l": abs(eu[-1] - er[-1]) / normA,
+            "projector_gap_at_l": float(np.linalg.norm(Uh[:, :l] @ (Uh[:, :l].T @ A_np) - Ur @ (Ur.T @ A_np))) / normA,
+            "left_ratio_median_k_lt_l": float(np.median(er[:-1] / eu[:-1])),
+            "right_ratio_median_k_lt_l": float(np.median(fr[:-1] / fu[:-1])),
+        }
+    return out
+
+
+def rsvd_table(res: dict) -> str:
+    lines = ["| q | k = l: PowerURV / RSVD / optimum (left errors, /||A||) | projectors at l | median RSVD/PowerURV, k < l: left, right |",
+             "|---|---|---|---|"]
+    for key in sorted(res):
+        r = res[key]
+        na = r["normA"]
+        lines.append("| %d | %.6f / %.6f / %.6f | %.1e | %.3f, %.3f |" % (
+            r["q"], r["powerurv_left"][-1] / na, r["rsvd_left"][-1] / na, r["opt"][-1] / na,
+            r["projector_gap_at_l"], r["left_ratio_median_k_lt_l"], r["right_ratio_median_k_lt_l"]))
+    return "\n".join(lines)
+
+
 def table(res: dict) -> str:
     lines = ["| matrix | variant | q | max_k e_k / e_k^opt | median | sigma_min(R11)/sigma_k at k = 10, 20, 40, 80 |",
              "|---|---|---|---|---|---|"]
@@ -80,7 +155,8 @@ def main() -> int:
     ap.add_argument("--json", action="store_true", help="print the full results as JSON")
     args = ap.parse_args()
     res = run(tuple(args.q), seed=args.seed)
-    print(json.dumps(res) if args.json else table(res))
+    rs = rsvd_comparison(seed=args.seed)
+    print(json.dumps({"section5": res, "rsvd": rs}) if args.json else table(res) + "\n\n" + rsvd_table(rs))
     return 0
 
 

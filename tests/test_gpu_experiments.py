@@ -57,3 +57,63 @@ def test_curves_equal_the_oracle(results, orc):
             ek = orc.metrics(A, U, R, V)["ek"]
             gpu = np.array(results["%s/full/q%d" % (name, q)]["ek"])
             assert np.max(np.abs(gpu - ek)) <= 1e-11 * np.linalg.norm(A), (name, q)
+
+
+# ------------------------------------------- PowerURV and the RSVD (Matrix 2, l = 60)
+@pytest.fixture(scope="module")
+def rsvd():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1812_06007_amd import experiments
+
+    announce("RSVD comparison, Matrix 2, l = 60, q = 0 and 1")
+    return experiments.rsvd_comparison()
+
+
+def test_rsvd_lemma_at_l(rsvd):
+    """The Lemma of the RSVD section: from the same G, the leading l columns of
+    U and U_rsvd span the same space, so the two projections of A agree."""
+    for key, r in rsvd.items():
+        print("[gpu-case]", key, "projector gap", r["projector_gap_at_l"], "error gap", r["lemma_gap_at_l"], flush=True)
+        assert r["projector_gap_at_l"] <= 1e-10, key
+        assert r["lemma_gap_at_l"] <= 1e-12, key
+
+
+def test_rsvd_curves_against_host_computations(rsvd, orc):
+    """Both error curves recomputed on the host in FP64 from the same A and G:
+    PowerURV through the oracle, the RSVD through numpy's QR and SVD.  Every
+    error is at least the optimal rank-k error (Eckart-Young)."""
+    m, n, l, seed = 200, 160, 60, 1812
+    sigma = gen.spectrum("matrix2", n)
+    A = gen.spectral_matrix(m, n, sigma, seed)
+    G = orc.gaussian(n, n, seed, stream_id=2)
+    na = np.linalg.norm(A)
+    for key, r in rsvd.items():
+        q = r["q"]
+        U, _, V = orc.urv(A, q, G=G)
+        Y = G[:, :l]
+        for _ in range(q):
+            Y = A.T @ (A @ Y)
+        Q, _ = np.linalg.qr(A @ Y)
+        W, _, _ = np.linalg.svd(Q.T @ A)
+        Ur = Q @ W
+        ks = range(1, l + 1)
+        eu = np.array([np.linalg.norm(A - U[:, :k] @ (U[:, :k].T @ A)) for k in ks])
+        er = np.array([np.linalg.norm(A - Ur[:, :k] @ (Ur[:, :k].T @ A)) for k in ks])
+        assert np.max(np.abs(eu - r["powerurv_left"])) <= 1e-10 * na, key
+        assert np.max(np.abs(er - r["rsvd_left"])) <= 1e-8 * na, key
+        opt = np.array(r["opt"])
+        for curve in ("powerurv_left", "rsvd_left", "powerurv_right", "rsvd_right"):
+            assert np.all(np.array(r[curve]) >= opt * (1 - 1e-12)), (key, curve)
+
+
+def test_rsvd_leading_columns_are_closer_to_optimal(rsvd):
+    """The section's observation: with one more application of A, the RSVD's
+    leading columns (left and right) give smaller errors than PowerURV's for
+    k < l; the curves meet at k = l."""
+    for key, r in rsvd.items():
+        print("[gpu-case]", key, "median RSVD/PowerURV left", r["left_ratio_median_k_lt_l"],
+              "right", r["right_ratio_median_k_lt_l"], flush=True)
+        assert r["left_ratio_median_k_lt_l"] < 1.0, key
+        assert r["right_ratio_median_k_lt_l"] < 1.0, key
