@@ -57,11 +57,18 @@ def run(q_values=(0, 1, 2), m: int = 200, n: int = 160, seed: int = 1812, device
                 ks = [k for k in (10, 20, 40, 80) if k < n and opt[k] > 1e-13 * normA]
                 r11 = {k: float(np.linalg.svd(Rh[:k, :k], compute_uv=False)[-1] / sigma[k - 1]) for k in ks}
                 r22 = {k: float(np.linalg.svd(Rh[k:, k:], compute_uv=False)[0] / sigma[k]) for k in ks}
+                # the figure of Section 3 over every k: sigma_min(R11) against sigma_k and
+                # sigma_max(R22) against sigma_{k+1}, where sigma_k is above the FP64 noise floor
+                kall = [k for k in range(1, n) if sigma[k - 1] > 1e-13 * sigma[0]]
+                p11 = np.array([np.linalg.svd(Rh[:k, :k], compute_uv=False)[-1] / sigma[k - 1] for k in kall])
+                p22 = np.array([np.linalg.svd(Rh[k:, k:], compute_uv=False)[0] / sigma[k] for k in kall])
                 out["%s/%s/q%d" % (name, variant, q)] = {
                     "matrix": name, "decay": MATRICES[name], "variant": variant, "q": q,
                     "recon": float(met["recon"]), "ek": ek.tolist(), "opt": opt.tolist(),
                     "ratio_max": float(ratio.max()), "ratio_median": float(np.median(ratio)),
-                    "sigma_min_R11_over_sigma_k": r11, "norm_R22_over_sigma_k1": r22}
+                    "sigma_min_R11_over_sigma_k": r11, "norm_R22_over_sigma_k1": r22,
+                    "profile_k": kall, "profile_R11": p11.tolist(), "profile_R22": p22.tolist(),
+                    "profile_R11_median": float(np.median(p11)), "profile_R22_median": float(np.median(p22))}
     return out
 
 
@@ -138,13 +145,15 @@ def rsvd_table(res: dict) -> str:
 
 
 def table(res: dict) -> str:
-    lines = ["| matrix | variant | q | max_k e_k / e_k^opt | median | sigma_min(R11)/sigma_k at k = 10, 20, 40, 80 |",
-             "|---|---|---|---|---|---|"]
+    lines = ["| matrix | variant | q | max_k e_k / e_k^opt | median | sigma_min(R11)/sigma_k at k = 10, 20, 40, 80 "
+             "| median over k: sigma_min(R11)/sigma_k, sigma_max(R22)/sigma_{k+1} |",
+             "|---|---|---|---|---|---|---|"]
     for key in sorted(res):
         r = res[key]
         r11 = ", ".join("%.3f" % v for v in r["sigma_min_R11_over_sigma_k"].values())
-        lines.append("| %s (%s) | %s | %d | %.3f | %.3f | %s |" % (
-            r["matrix"], r["decay"], r["variant"].upper(), r["q"], r["ratio_max"], r["ratio_median"], r11))
+        lines.append("| %s (%s) | %s | %d | %.3f | %.3f | %s | %.3f, %.3f |" % (
+            r["matrix"], r["decay"], r["variant"].upper(), r["q"], r["ratio_max"], r["ratio_median"], r11,
+            r["profile_R11_median"], r["profile_R22_median"]))
     return "\n".join(lines)
 
 

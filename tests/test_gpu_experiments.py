@@ -48,6 +48,21 @@ def test_exact_inequalities(results):
         assert r["recon"] <= 1e-13, key
 
 
+def test_rank_revealing_profiles(results):
+    """The figure of Section 3 over every k: sigma_min(R11) <= sigma_k and
+    sigma_max(R22) >= sigma_{k+1} always (interlacing); with power steps both
+    stay close to the singular values (median ratio within 2x), without them
+    Matrix 1's are off by about an order of magnitude."""
+    for key, r in results.items():
+        p11, p22 = np.array(r["profile_R11"]), np.array(r["profile_R22"])
+        assert np.all(p11 <= 1 + 1e-10) and np.all(p22 >= 1 - 1e-10), key
+        print("[gpu-case]", key, "median profiles", r["profile_R11_median"], r["profile_R22_median"], flush=True)
+        if r["q"] >= 1 and r["matrix"] in ("matrix1", "matrix2"):
+            assert r["profile_R11_median"] >= 0.5 and r["profile_R22_median"] <= 2.0, key
+    m1 = results["matrix1/full/q0"]
+    assert m1["profile_R11_median"] <= 0.3 and m1["profile_R22_median"] >= 3.0
+
+
 def test_curves_equal_the_oracle(results, orc):
     for name in ("matrix1", "matrix2", "matrix3"):
         sigma = gen.spectrum(name, 160)
