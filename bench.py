@@ -495,13 +495,18 @@ def main() -> int:
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps - 1)]
     e0.record(stream)
-    for _ in range(args.steps):
+    for i in range(args.steps):
         step()
+        if i + 1 < args.steps:
+            marks[i].record(stream)  # per-step boundaries, for the spread of the step times
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / args.steps
+    bounds = [e0] + marks + [e1]
+    step_ms = sorted(bounds[i].elapsed_time(bounds[i + 1]) for i in range(args.steps))
 
     met = urv.metrics(A, U, R, V)
     fl = executed_flops(m, n, q, args.variant)
@@ -588,6 +593,9 @@ def main() -> int:
         "orthU": met["orthU"],
         "orthV": met["orthV"],
         "wall_s_timed": wall,
+        "step_ms": {"median": step_ms[len(step_ms) // 2] if len(step_ms) % 2 else
+                    0.5 * (step_ms[len(step_ms) // 2 - 1] + step_ms[len(step_ms) // 2]),
+                    "min": step_ms[0], "max": step_ms[-1]},
         "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double,NN,128x128,4x4 waves> (X = A V)",
                      "achieved": gemm_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": gemm_tf / FP64_MFMA_PEAK_TFLOPS, "traffic": gemm_traffic(m, n),
