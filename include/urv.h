@@ -302,6 +302,11 @@ int urv_batch_status(urv_batch_plan* plan, void* stream);
 /* Frees the plan's device memory and graph (after the stream work that uses it). */
 void urv_batch_destroy(urv_batch_plan* plan);
 
+/* The largest row count of the tall problem (max(m, n) for urv_factor_ex, m for
+ * urv_qr_pos and the derivative calls) that the QR panel supports; larger
+ * inputs return URV_ENOTSUP. */
+int64_t urv_max_rows(void);
+
 /* Static text for a status code. */
 const char* urv_strerror(int code);
 

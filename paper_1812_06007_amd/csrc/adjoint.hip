@@ -418,7 +418,6 @@ int loss_impl(const T* A, int64_t m, int64_t n, const T* U, const T* R, const T*
 }
 
 // ---------------------------------------------------------------- entry plumbing
-constexpr int64_t kMaxRows = 240 * 256;  // rows the panel kernel's co-resident grid covers
 
 int check_opts(const urv_grad_opts& o, const char* who) {
   if (o.precision != URV_FP64 && o.precision != URV_FP32) {

@@ -117,7 +117,6 @@ size_t work_bytes(int64_t m, int64_t n, bool mixed) {
   return a.used;
 }
 
-constexpr int64_t kMaxRows = 240 * 256;  // rows the panel kernel's co-resident grid covers
 
 int validate_factor(const double* A, int64_t m, int64_t n, int32_t q, const double* U,
                     const double* R, const double* V, const urv_opts& o) {
@@ -523,6 +522,8 @@ int urv_metrics(const double* A, int64_t m, int64_t n, const double* U, const do
   }
   return metrics(A, m, n, U, R, V, out, ek, static_cast<hipStream_t>(stream));
 }
+
+int64_t urv_max_rows(void) { return kMaxRows; }
 
 const char* urv_strerror(int code) {
   switch (code) {

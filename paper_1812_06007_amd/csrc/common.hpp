@@ -105,6 +105,10 @@ int copy_matrix(const double* src, int64_t lds, double* dst, int64_t ldd, int64_
 
 // ---------------------------------------------------------------- QR
 constexpr int kPanelNB = 64;  // block width of the Householder QR
+// Tallest matrix (rows of the tall problem) the QR accepts: the panel's
+// workgroups must all be resident at once, and this is the largest height the
+// tests factor and compare with the oracle.
+constexpr int64_t kMaxRows = 64 * 256;
 
 template <class T>
 struct QrWorkT {

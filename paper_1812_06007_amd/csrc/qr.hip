@@ -32,7 +32,7 @@ constexpr int PANEL_WAVES = 8;      // row groups (waves) per workgroup
 constexpr int RPT = 32;             // rows per lane
 constexpr int RPW = PANEL_WAVES * RPT;  // rows per workgroup
 constexpr int PANEL_THREADS = 64 * PANEL_WAVES;
-constexpr int kMaxPanelWgs = 240;   // all panel workgroups must be co-resident
+constexpr int kMaxPanelWgs = static_cast<int>(kMaxRows / 256);  // all panel workgroups co-resident
 constexpr long kSpinLimit = 1L << 23;   // bounded wait: ~seconds, then give up
 
 // How the panel's waits end.  Normal runs: the spin limit above, tags as

@@ -67,7 +67,7 @@ EXPORTS = ["urv_opts_init", "urv_factor_ex", "urv_factor", "urv_workspace_size",
            "urv_factor_backward", "urv_qr_adjoint", "urv_truncation_loss",
            "urv_batch_create", "urv_batch_set_buffers", "urv_batch_set_config", "urv_batch_get_config",
            "urv_batch_autotune", "urv_batch_run", "urv_batch_run_graph", "urv_batch_status",
-           "urv_batch_destroy"]
+           "urv_batch_destroy", "urv_max_rows"]
 
 _lib = None
 
@@ -119,6 +119,8 @@ def lib() -> ctypes.CDLL:
     L.urv_batch_autotune.argtypes = [P, P, ctypes.POINTER(D)]
     L.urv_batch_run.argtypes = [P, P]
     L.urv_batch_run_graph.argtypes = [P, P]
+    L.urv_max_rows.argtypes = []
+    L.urv_max_rows.restype = I64
     L.urv_batch_destroy.argtypes = [P]
     L.urv_batch_destroy.restype = None
     for name in ("urv_factor_ex", "urv_factor", "urv_gaussian", "urv_dgemm", "urv_qr_pos", "urv_qr_pos_f32",
@@ -190,6 +192,11 @@ def empty_colmajor(rows: int, cols: int, dtype=None, device=None):
 
 def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() > 0 else 0)
+
+
+def max_rows() -> int:
+    """Largest row count of the tall problem the QR panel supports."""
+    return int(lib().urv_max_rows())
 
 
 def workspace_size(m: int, n: int, q: int = 0, variant: str = "full", precision: str = "fp64") -> int:

@@ -44,6 +44,12 @@ MUTANTS = [
     ("q = 0 start not orthonormalised", "if (q == 0 || orth_g) orthonormalize_square", "if (orth_g) orthonormalize_square"),
     ("rank-k error drops the diagonal", "for (int64_t j = k; j < p; ++j) row +=", "for (int64_t j = k + 1; j < p; ++j) row +="),
     ("jacobi rotation sign", "ap[i] = c * x - s * y;", "ap[i] = c * x + s * y;"),
+    ("recon not divided by ||A||", "out[0] = frob(E, m, n, m) / normA;", "out[0] = frob(E, m, n, m);"),
+    ("recon with V instead of V^T", "orc_gemm(0, 1, m, n, p, -1.0, UR, m, V, ldv, 1.0, E, m);",
+     "orc_gemm(0, 0, m, n, p, -1.0, UR, m, V, ldv, 1.0, E, m);"),
+    ("orthU without the identity", "Gm[i + i * p] -= 1.0;\n  out[1] = frob", "Gm[i + i * p] -= 0.0;\n  out[1] = frob"),
+    ("orthV measured on U", "orc_gemm(1, 0, p, p, n, 1.0, V, ldv, V, ldv, 0.0, Gm, p);",
+     "orc_gemm(1, 0, p, p, n, 1.0, U, ldu, U, ldu, 0.0, Gm, p);"),
 ]
 
 

@@ -172,6 +172,50 @@ def test_invariants(orc, m, n, variant, q):
         assert met["ek"][k] == pytest.approx(np.linalg.norm(A - Ak), rel=1e-6, abs=1e-13)
 
 
+def test_metrics_closed_forms(orc):
+    """orc_metrics against quantities fixed without it: U = [I; 0] D with D a diagonal of small
+    integers, V a permutation that is not its own inverse, R diagonal and an integer residual E
+    in A = U R V^T + E.  Then ||A - U R V^T||_F / ||A||_F = ||E||_F / ||A||_F,
+    ||U^T U - I||_F = sqrt(sum (d^2 - 1)^2), ||V^T V - I||_F = 0, and e_k is the tail norm of
+    diag(R); every sum is of integers, so only the final square roots round."""
+    m, n = 50, 20
+    rng = np.random.default_rng(5)
+    d = rng.integers(1, 4, size=n).astype(np.float64)
+    U = np.zeros((m, n))
+    U[:n, :n] = np.diag(d)
+    perm = np.roll(np.arange(n), 3)  # a cycle: V != V^T
+    V = np.eye(n)[:, perm]
+    r = rng.integers(1, 9, size=n).astype(np.float64)
+    R = np.diag(r)
+    E = rng.integers(-2, 3, size=(m, n)).astype(np.float64)
+    A = np.asfortranarray(U @ R @ V.T + E)
+    met = orc.metrics(A, U, R, V)
+    assert met["normA"] == np.sqrt(np.sum(A * A))
+    assert met["recon"] == pytest.approx(np.sqrt(np.sum(E * E)) / np.sqrt(np.sum(A * A)), rel=1e-15)
+    assert met["orthU"] == pytest.approx(np.sqrt(np.sum((d * d - 1) ** 2)), rel=1e-15)
+    assert met["orthV"] == 0.0
+    tail = np.sqrt(np.cumsum((r * r)[::-1])[::-1])
+    np.testing.assert_allclose(met["ek"][:n], tail, rtol=1e-15)
+    assert met["ek"][n] == 0.0
+
+
+def test_metrics_wide_closed_forms(orc):
+    """The same closed forms for m < n (U m x m, V n x m)."""
+    m, n = 12, 30
+    rng = np.random.default_rng(6)
+    d = rng.integers(1, 4, size=m).astype(np.float64)
+    U = np.diag(d)
+    V = np.zeros((n, m))
+    V[np.arange(m) + 5, np.arange(m)] = 1.0
+    R = np.triu(rng.integers(-3, 4, size=(m, m)).astype(np.float64))
+    E = rng.integers(-2, 3, size=(m, n)).astype(np.float64)
+    A = np.asfortranarray(U @ R @ V.T + E)
+    met = orc.metrics(A, U, R, V)
+    assert met["recon"] == pytest.approx(np.sqrt(np.sum(E * E)) / np.sqrt(np.sum(A * A)), rel=1e-15)
+    assert met["orthU"] == pytest.approx(np.sqrt(np.sum((d * d - 1) ** 2)), rel=1e-15)
+    assert met["orthV"] == 0.0
+
+
 def test_empty_and_bad_arguments(orc):
     with pytest.raises(ValueError):
         orc.urv(np.zeros((5, 3)), -1)
