@@ -121,6 +121,8 @@ struct QrWorkT {
   size_t xch_words = 0;
   uint64_t* jxch = nullptr; // exchange of the panel join: P x 4096 partial sums, then 4096 sums
   size_t jxch_words = 0;
+  uint64_t* txch = nullptr; // exchange of the tall-skinny panel: R factors, U^-1 and T
+  size_t txch_words = 0;
   unsigned* sync = nullptr; // panel error flag area
   T* gemm_work = nullptr;   // split-K partial sums of the bulk trailing updates
   size_t gemm_work_elems = 0;

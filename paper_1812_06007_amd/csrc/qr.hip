@@ -179,7 +179,7 @@ struct PanelMma<float> {
 // Makes one lane's LDS writes visible to the other lanes of its wave: the
 // lanes run in lockstep, so only the compiler must be kept from moving LDS
 // accesses across this point (and the LDS queue drained).
-__device__ inline void wave_lds_sync() {
+__device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -187,7 +187,7 @@ __device__ inline void wave_lds_sync() {
 
 // sum over the waves of a workgroup, in a fixed order
 template <class T, int W>
-__device__ inline T sum_waves(const T (*red)[W], int c) {
+__device__ __forceinline__ T sum_waves(const T (*red)[W], int c) {
   T a = 0, b = 0;
 #pragma unroll
   for (int w = 0; w < PANEL_WAVES; w += 2) {
@@ -231,6 +231,632 @@ struct PanelJoin {
   uint64_t* sums = nullptr; // 4096 tagged sums
 };
 constexpr int kJoinEntries = NB * NB;
+
+// ---------------------------------------------------------------------------
+// Tall-skinny QR of a panel with Householder reconstruction.
+//
+// The loop above needs one device-wide reduction per column.  The TSQR form
+// needs three exchanges per panel:
+//  1. Leaf.  Each workgroup factors its own rows alone (registers, lane =
+//     column, one workgroup barrier per column): R_w (64 x 64 upper), its
+//     reflectors (written to the Y rows it owns) and T_w (from the Gram
+//     entries).
+//  2. Tree.  The R factors of up to 8 workgroups are stacked and factored by
+//     every member of the group (each gets bitwise the same result); with more
+//     than 8 workgroups a second node combines the group factors likewise.  In
+//     a stack of upper-triangular factors the reflector of column j touches
+//     row j of the top factor and rows 0..j of the others, a pattern the steps
+//     keep, so the top block of the node's reflector matrix is I and the
+//     node's Q is [I; 0] - Yc Tc.
+//  3. Each workgroup forms its rows of the panel's Q (orthonormal columns),
+//     Q_w = Q_leaf M_w with M_w its 64 x 64 block of the tree's Q.
+//  4. Householder vectors are rebuilt from Q (Ballard, Demmel, Grigori,
+//     Jacquelin, Knight, Nguyen, "Reconstructing Householder vectors from
+//     tall-skinny QR", 2015): with S diagonal (+-1, chosen during the
+//     elimination so that every pivot has modulus >= 1), S - Q1 = L U (Q1 the
+//     panel's top 64 rows of Q, no pivoting) gives Y = [L; -Q2 U^-1],
+//     T = U S L^-T and R = S R_tree; then H_1 ... H_64 = I - Y T Y^T with
+//     H[:, 0:64] = Q S.  Workgroup 0 factors S - Q1 and sends U^-1 and T.
+// Every sum runs in a fixed order, so results are bitwise reproducible.
+constexpr int kTriEntries = NB * (NB + 1) / 2;  // packed upper triangle, column by column
+constexpr int kTsqrFan = 4;                     // factors per tree node (two waves each)
+static_assert(2 * kTsqrFan == PANEL_WAVES, "two waves per stacked factor");
+__host__ __device__ __forceinline__ int tri_index(int i, int c) { return c * (c + 1) / 2 + i; }  // i <= c
+
+// Exchange areas of the TSQR panel: values (one 8-byte word each) and the flags
+// that announce them.
+struct TsqrXch {
+  uint64_t* tri = nullptr;    // 2 kMaxPanelWgs x kTriEntries: the R of every unit of every tree level
+  uint64_t* recon = nullptr;  // 2 NB^2: U^-1 and T from workgroup 0
+  uint64_t* gram = nullptr;   // (P + 1) x kTriEntries: Gram partials, then the sums
+  uint64_t* flags = nullptr;  // one per unit (2 kMaxPanelWgs), one for recon, 2 kMaxPanelWgs for the Gram sums
+  int chol = 1;               // try CholeskyQR2 first
+};
+constexpr int kTsqrUnits = 2 * kMaxPanelWgs;  // P + P/4 + P/16 + ... < 2 P
+constexpr int kTsqrFlags = kTsqrUnits + 1 + 2 * kMaxPanelWgs;
+
+// Announced exchange: every thread writes its values with agent-scope stores
+// (write-through), waits for them to complete (s_waitcnt vmcnt(0)), and after a
+// workgroup barrier one thread raises the flag to the tag; a reader waits for
+// the tag, then reads the values with agent-scope loads.  One flag per block of
+// values, so the values travel as plain words (no tag in each).
+constexpr unsigned kWaitStores = 0x0F70;  // s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15)
+__device__ __forceinline__ void store_agent(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), static_cast<uint64_t>(__double_as_longlong(v)),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(float* p, float v) {
+  __hip_atomic_store(reinterpret_cast<unsigned*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void raise_flag(uint64_t* flag, uint32_t tag) {
+  __builtin_amdgcn_s_waitcnt(kWaitStores);
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, static_cast<uint64_t>(tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Bounded wait until *flag == tag (every calling lane polls the same word).
+__device__ __forceinline__ bool await_flag(const uint64_t* flag, uint32_t tag, unsigned* err, long spin_limit) {
+  long spins = 0;
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != static_cast<uint64_t>(tag)) {
+    if ((++spins & 63) == 0 &&
+        (spins > spin_limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+      __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // the value loads stay after the wait
+  return true;
+}
+
+// A 64 x 64 matrix on the matrix cores: wave g holds rows ib = 16 (g >> 1) ..
+// +16 and columns cb0 = 32 (g & 1) .. +32 as two 16 x 16 accumulators.
+template <class T>
+struct Frag {
+  typename PanelMma<T>::acc a0, a1;
+};
+
+struct FragPos {
+  int ib, cb0, l16, lk;
+};
+
+template <class T>
+__device__ __forceinline__ void frag_zero(Frag<T>& f) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    f.a0[v] = T(0);
+    f.a1[v] = T(0);
+  }
+}
+
+// f = diag * I - f
+template <class T>
+__device__ __forceinline__ void frag_negate_plus_identity(Frag<T>& f, const FragPos& p, bool identity) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = p.ib + PanelMma<T>::row(p.lk, v);
+    f.a0[v] = ((identity && i == p.cb0 + p.l16) ? T(1) : T(0)) - f.a0[v];
+    f.a1[v] = ((identity && i == p.cb0 + 16 + p.l16) ? T(1) : T(0)) - f.a1[v];
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void frag_identity(Frag<T>& f, const FragPos& p) {
+  frag_zero(f);
+  frag_negate_plus_identity(f, p, true);
+}
+
+template <class T>
+__device__ __forceinline__ void frag_to_lds(const Frag<T>& f, T (*M)[NB + 2], const FragPos& p) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = p.ib + PanelMma<T>::row(p.lk, v);
+    M[i][p.cb0 + p.l16] = f.a0[v];
+    M[i][p.cb0 + 16 + p.l16] = f.a1[v];
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void frag_from_lds(Frag<T>& f, const T (*M)[NB + 2], const FragPos& p) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = p.ib + PanelMma<T>::row(p.lk, v);
+    f.a0[v] = M[i][p.cb0 + p.l16];
+    f.a1[v] = M[i][p.cb0 + 16 + p.l16];
+  }
+}
+
+// f += op(A) op(B) for 64 x 64 A, B in LDS; op(A)(i, k) = A[i][k] (A[k][i] when
+// TA), op(B)(k, j) = B[k][j] (B[j][k] when TB).
+template <class T, bool TA, bool TB = false>
+__device__ __forceinline__ void frag_mma(Frag<T>& f, const T (*A)[NB + 2], const T (*B)[NB + 2], const FragPos& p) {
+#pragma unroll 4
+  for (int ks = 0; ks < NB / 4; ++ks) {
+    const int kk = 4 * ks + p.lk;
+    const T a = TA ? A[kk][p.ib + p.l16] : A[p.ib + p.l16][kk];
+    const T b0 = TB ? B[p.cb0 + p.l16][kk] : B[kk][p.cb0 + p.l16];
+    const T b1 = TB ? B[p.cb0 + 16 + p.l16][kk] : B[kk][p.cb0 + 16 + p.l16];
+    f.a0 = PanelMma<T>::run(a, b0, f.a0);
+    f.a1 = PanelMma<T>::run(a, b1, f.a1);
+  }
+}
+
+// f += sum over k in [k0, k1) of a(i, k) b(k, j), the operands given by
+// functors (an LDS read, with masking); k0, k1 multiples of 16.
+template <class T, class FA, class FB>
+__device__ __forceinline__ void frag_mma_f(Frag<T>& f, FA a, FB b, const FragPos& p, int k0, int k1) {
+  for (int k = k0; k < k1; k += 16) {  // k0, k1 multiples of 16: four steps with their loads in flight
+    T av[4], b0[4], b1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k + 4 * u + p.lk;
+      av[u] = a(p.ib + p.l16, kk);
+      b0[u] = b(kk, p.cb0 + p.l16);
+      b1[u] = b(kk, p.cb0 + 16 + p.l16);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      f.a0 = PanelMma<T>::run(av[u], b0[u], f.a0);
+      f.a1 = PanelMma<T>::run(av[u], b1[u], f.a1);
+    }
+  }
+}
+
+// fn(i, j, value) for the 8 entries of f this lane holds.
+template <class T, class F>
+__device__ __forceinline__ void frag_each(Frag<T>& f, const FragPos& p, F fn) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = p.ib + PanelMma<T>::row(p.lk, v);
+    fn(i, p.cb0 + p.l16, f.a0[v]);
+    fn(i, p.cb0 + 16 + p.l16, f.a1[v]);
+  }
+}
+
+// ---- 64 x 64 triangular algebra in one workgroup, in 16 x 16 blocks
+constexpr int BS = 16;
+
+// A double or float of lane `lane` to every lane (through scalar registers).
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffff), lane);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Wave 0: LU without pivoting of the 16 x 16 block of M at (b0, b0), in place
+// (multipliers below the diagonal, U on and above it).  With signs, the pivot
+// of step j is u = m_jj + s, s = sgn(m_jj) (sgn(0) = +1, so |u| >= 1); without,
+// u = m_jj.  u, 1/u and s go to ubuf, ubuf + NB and sgnb at b0 + j.  Lane c <
+// 16 holds column c; the column of step j reaches the other lanes through
+// scalar registers.
+template <class T>
+__device__ __forceinline__ void base16_lu(T (*M)[NB + 2], int b0, bool signs, T* ubuf, T* sgnb, int c) {
+  const bool act = c < BS;
+  T m[BS];
+#pragma unroll
+  for (int r = 0; r < BS; ++r) m[r] = act ? M[b0 + r][b0 + c] : T(0);
+#pragma unroll
+  for (int j = 0; j < BS; ++j) {
+    const T d = lane_value(m[j], j);
+    const T sj = signs ? (d >= T(0) ? T(1) : T(-1)) : T(0);
+    const T u = d + sj;
+    const T rinv = T(1) / u;
+    T col[BS];
+#pragma unroll
+    for (int r = j + 1; r < BS; ++r) col[r] = lane_value(m[r], j) * rinv;  // the multipliers
+    if (c > j) {
+#pragma unroll
+      for (int r = j + 1; r < BS; ++r) m[r] = fma(-col[r], m[j], m[r]);
+    } else if (c == j) {
+#pragma unroll
+      for (int r = j + 1; r < BS; ++r) m[r] = col[r];
+      m[j] = u;
+    }
+    if (c == 0) {
+      ubuf[b0 + j] = u;
+      ubuf[NB + b0 + j] = rinv;
+      sgnb[b0 + j] = sj;
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < BS; ++r) M[b0 + r][b0 + c] = m[r];
+  }
+}
+
+// Inverse of the 16 x 16 diagonal block of a triangular factor held in M
+// (upper: U on and above the diagonal, rdiag the reciprocals of its diagonal;
+// lower: unit L below it) into Z's same block, one column per lane c < 16 by
+// substitution.
+template <class T, bool kUpper>
+__device__ __forceinline__ void base16_inv(const T (*M)[NB + 2], int b0, const T* rdiag, T (*Z)[NB + 2], int c) {
+  if (c >= BS) return;
+  T z[BS];
+  if constexpr (kUpper) {
+#pragma unroll
+    for (int r = BS - 1; r >= 0; --r) {
+      T a = (r == c) ? T(1) : T(0);
+#pragma unroll
+      for (int k = r + 1; k < BS; ++k) a = fma(-M[b0 + r][b0 + k], z[k], a);
+      z[r] = a * rdiag[b0 + r];
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < BS; ++r) {
+      T a = (r == c) ? T(1) : T(0);
+#pragma unroll
+      for (int k = 0; k < r; ++k) a = fma(-M[b0 + r][b0 + k], z[k], a);
+      z[r] = a;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < BS; ++r) Z[b0 + r][b0 + c] = z[r];
+}
+
+// LU without pivoting of the 64 x 64 M in place, in 16-column blocks: the
+// diagonal block (base16_lu, wave 0), its inverses (waves 0 and 1, into the
+// diagonal blocks of Ui and Li, zero elsewhere), then U's block row
+// L_kk^-1 M_k*, L's block column M_*k U_kk^-1 and the Schur update on the matrix
+// cores.  ubuf receives the pivots and, at ubuf + NB, their reciprocals.
+template <class T>
+__device__ __forceinline__ void blocked_lu(T (*M)[NB + 2], bool signs, T* ubuf, T* sgnb,
+                                           T (*Ui)[NB + 2], T (*Li)[NB + 2], int g, int c, const FragPos& fp) {
+  for (int e = threadIdx.x; e < NB * (NB + 2); e += PANEL_THREADS) {
+    (&Ui[0][0])[e] = T(0);
+    (&Li[0][0])[e] = T(0);
+  }
+  for (int kb = 0; kb < NB / BS; ++kb) {
+    const int b0 = kb * BS, b1 = b0 + BS;
+    __syncthreads();
+    if (g == 0) base16_lu(M, b0, signs, ubuf, sgnb, c);
+    __syncthreads();
+    if (g == 0) base16_inv<T, true>(M, b0, ubuf + NB, Ui, c);
+    if (g == 1) base16_inv<T, false>(M, b0, ubuf + NB, Li, c);
+    __syncthreads();
+    if (b1 >= NB) break;
+    Frag<T> fu, fl;
+    frag_zero(fu);
+    frag_zero(fl);
+    frag_mma_f(fu, [&](int i, int k) { return Li[i][k]; }, [&](int k, int j) { return M[k][j]; }, fp, b0, b1);
+    frag_mma_f(fl, [&](int i, int k) { return M[i][k]; }, [&](int k, int j) { return Ui[k][j]; }, fp, b0, b1);
+    __syncthreads();
+    frag_each(fu, fp, [&](int i, int j, T v) {
+      if (i >= b0 && i < b1 && j >= b1) M[i][j] = v;
+    });
+    frag_each(fl, fp, [&](int i, int j, T v) {
+      if (j >= b0 && j < b1 && i >= b1) M[i][j] = v;
+    });
+    __syncthreads();
+    Frag<T> fs;
+    frag_zero(fs);
+    frag_mma_f(fs, [&](int i, int k) { return M[i][k]; }, [&](int k, int j) { return M[k][j]; }, fp, b0, b1);
+    __syncthreads();
+    frag_each(fs, fp, [&](int i, int j, T v) {
+      if (i >= b1 && j >= b1) M[i][j] -= v;
+    });
+  }
+  __syncthreads();
+}
+
+// Z triangular 64 x 64 with its 16 x 16 diagonal blocks in place and zero
+// elsewhere: fills the off-diagonal blocks, joining pairs of 16-, then 32-blocks
+// by Z_AB = -Z_A C_AB Z_B (upper) or Z_BA = -Z_B C_BA Z_A (lower), C(a, b) =
+// cf(a, b) the coupling.  This gives the inverse of a triangular matrix C from
+// the inverses of its diagonal blocks, and T of a compact WY form from the
+// Gram entries.  W is scratch.
+template <class T, bool kUpper, class CF>
+__device__ __forceinline__ void tri_join(T (*Z)[NB + 2], CF cf, T (*W)[NB + 2], const FragPos& fp) {
+  for (int half = BS; half < NB; half *= 2) {
+    // A = [2q half, (2q + 1) half), B = [(2q + 1) half, (2q + 2) half)
+    auto first = [&](int a) { return (a / half) % 2 == 0; };
+    Frag<T> f;
+    frag_zero(f);
+    if constexpr (kUpper)  // X = C_AB Z_B
+      frag_mma_f(f, [&](int i, int k) { return (first(i) && k / half == i / half + 1) ? cf(i, k) : T(0); },
+                 [&](int k, int j) { return Z[k][j]; }, fp, 0, NB);
+    else  // X = C_BA Z_A
+      frag_mma_f(f, [&](int i, int k) { return (!first(i) && k / half == i / half - 1) ? cf(i, k) : T(0); },
+                 [&](int k, int j) { return Z[k][j]; }, fp, 0, NB);
+    frag_to_lds(f, W, fp);
+    __syncthreads();
+    frag_zero(f);
+    frag_mma_f(f, [&](int i, int k) { return Z[i][k]; }, [&](int k, int j) { return W[k][j]; }, fp, 0, NB);
+    __syncthreads();
+    frag_each(f, fp, [&](int i, int j, T v) { Z[i][j] -= v; });
+    __syncthreads();
+  }
+}
+
+// v unchanged, through a step the compiler cannot see into: LDS addresses
+// derived from it are then formed in the phase that uses them instead of being
+// hoisted to the kernel's entry and held in registers across every phase.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// LDS of the TSQR steps.
+template <class T>
+struct TsqrLds {
+  T (*S1)[NB + 2];           // R of the leaf, then of a tree node
+  T (*S2)[NB + 2];           // work matrices
+  T (*S3)[NB + 2];           // Gram entries (S3[j][c] = y_c^T y_j, c < j), work matrix
+  T (*S4)[NB + 2];           // T of the leaf / node, then of the panel
+  T (*cb)[NB];               // pivot column of each wave's rows
+  T (*red0)[NB];             // partial sums of even steps, per wave
+  T (*red1)[NB];             // partial sums of odd steps
+  T (*piv)[NB];              // [2][NB]: pivot row by step parity
+  T* tau;                    // [NB]
+  T* aux;                    // [8][NB]: elimination buffers, pivots, signs
+};
+
+// One reflector: x_j = (alpha; x_below) with sigma2 = ||x_below||^2 gives
+// beta = -sgn(alpha) ||x_j|| (sgn(0) = +1), tau = (beta - alpha) / beta and
+// v = x_j / (alpha - beta) with v_1 = 1 (LAPACK's convention); H = I when
+// sigma2 = 0.
+template <class T>
+__device__ __forceinline__ void reflector(T alpha, T sigma2, T& t, T& beta, T& rinv) {
+  t = T(0);
+  beta = alpha;
+  rinv = T(0);
+  if (sigma2 != T(0)) {
+    const T norm = sqrt(alpha * alpha + sigma2);
+    beta = (alpha >= T(0)) ? -norm : norm;
+    rinv = T(1) / (alpha - beta);
+    t = (beta - alpha) / beta;
+  }
+}
+
+// T (upper triangular, 64 x 64, into Tm) of H_0 ... H_{jb-1} = I - Y T Y^T from
+// tau and the Gram entries G[j][c] = y_c^T y_j (c < j), Schreiber and Van Loan's
+// recurrence taken in blocks: the four 16 x 16 diagonal blocks column by column
+// (waves 0..3, lane l < 16 holding row l of its block in registers), then the
+// blocks joined, T_AB = -T_A (Y_A^T Y_B) T_B (tri_join).  Columns from jb on are
+// zero.  W is scratch.
+template <class T>
+__device__ __forceinline__ void tsqr_build_t(T (*Tm)[NB + 2], const T (*G)[NB + 2], const T* tau, int jb,
+                                             T (*W)[NB + 2], int g, int c, const FragPos& fp) {
+  for (int e = threadIdx.x; e < NB * (NB + 2); e += PANEL_THREADS) (&Tm[0][0])[e] = T(0);
+  __syncthreads();
+  if (g < NB / BS && c < BS) {
+    const int b0 = g * BS, il = c;
+    T tr[BS];
+#pragma unroll
+    for (int jj = 0; jj < BS; ++jj) {
+      const int col = b0 + jj;
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < jj; ++k) acc = fma(tr[k], G[col][b0 + k], acc);
+      const T tc = col < jb ? tau[col] : T(0);
+      tr[jj] = col >= jb ? T(0) : (il == jj ? tc : (il < jj ? -tc * acc : T(0)));
+    }
+#pragma unroll
+    for (int jj = 0; jj < BS; ++jj) Tm[b0 + il][b0 + jj] = tr[jj];
+  }
+  __syncthreads();
+  tri_join<T, true>(Tm, [&](int a, int b) { return b < jb ? G[b][a] : T(0); }, W, fp);
+}
+
+// Leaf: Householder QR of this workgroup's rows alone.  Column j's pivot is
+// block row lbase + j; rows above lbase are outside the leaf and untouched.
+// On return x holds the reflectors, scaled (y_c below the pivot of lane c's
+// column), L.S1 the leaf's R (S1[i][c], i <= c, zero elsewhere), L.S4 its T
+// and L.tau its tau.  Wave 0 builds T column by column, one step behind; its
+// own rows leave the leaf first.
+template <class T>
+__device__ __forceinline__ void tsqr_leaf(T (&x)[RPT], int jbp, int lbase, int myrow0i, int g, int c,
+                                 const TsqrLds<T>& L) {
+  using V2 = typename Vec2<T>::type;
+  c = opaque(c);
+  for (int e = threadIdx.x; e < NB * (NB + 2); e += PANEL_THREADS) {
+    (&L.S1[0][0])[e] = T(0);
+    (&L.S4[0][0])[e] = T(0);
+  }
+  __syncthreads();
+  T my_rinv = T(0);
+  constexpr int OWN_LD = RPT + 2;
+  T* const own = &L.S2[0][0];
+  for (int j = 0; j < jbp; ++j) {
+    const int par = j & 1;
+    T (*red)[NB] = par ? L.red1 : L.red0;
+    const int lo = min(max(lbase + j - myrow0i, -1), RPT);  // wave-uniform
+    const bool owner = lo >= 0 && lo < RPT;
+    const bool below = lo < RPT;
+    const T* colp = &L.cb[g][0];
+    if (lo < 0) {
+      if (c == j) {
+#pragma unroll
+        for (int r = 0; r < RPT; r += 2) *reinterpret_cast<V2*>(&L.cb[g][r]) = Vec2<T>::make(x[r], x[r + 1]);
+      }
+    } else if (owner) {
+      T* mine_t = own + c * OWN_LD;
+#pragma unroll
+      for (int r = 0; r < RPT; r += 2) *reinterpret_cast<V2*>(mine_t + r) = Vec2<T>::make(x[r], x[r + 1]);
+      L.piv[par][c] = mine_t[lo];
+      if (c == j)
+        for (int r = 0; r <= lo; ++r) mine_t[r] = T(0);
+      colp = own + j * OWN_LD;
+    }
+    wave_lds_sync();
+    T qa[4] = {T(0), T(0), T(0), T(0)};
+    if (below) {
+#pragma unroll
+      for (int r = 0; r < RPT; r += 2) {
+        const V2 xj = *reinterpret_cast<const V2*>(colp + r);
+        qa[r & 2] += xj.x * x[r];
+        qa[(r & 2) + 1] += xj.y * x[r + 1];
+      }
+    }
+    red[g][c] = (qa[0] + qa[1]) + (qa[2] + qa[3]);
+    __syncthreads();
+    const T xcj = L.piv[par][c];
+    const T alpha = L.piv[par][j];
+    const T qc = sum_waves(red, c);
+    const T sigma2 = sum_waves(red, j);
+    T t, beta, rinv;
+    reflector(alpha, sigma2, t, beta, rinv);
+    if (c == j) my_rinv = rinv;
+    const T w = xcj + qc * rinv;  // v^T x_c
+    if (g == 0) {
+      if (c < j) L.S3[j][c] = my_rinv * w;
+      if (c == 0) L.tau[j] = t;
+      L.S1[j][c] = (c == j) ? beta : (c > j ? xcj - t * w : T(0));
+    }
+    const T coef = (c > j && t != T(0)) ? t * w * rinv : T(0);
+    if (below) {
+#pragma unroll
+      for (int r = 0; r < RPT; r += 2) {
+        const V2 xj = *reinterpret_cast<const V2*>(colp + r);
+        x[r] = fma(-coef, xj.x, x[r]);
+        x[r + 1] = fma(-coef, xj.y, x[r + 1]);
+      }
+    }
+  }
+  __syncthreads();
+  const FragPos fp{(g >> 1) * 16, (g & 1) * 32, c & 15, c >> 4};
+  tsqr_build_t(L.S4, L.S3, L.tau, jbp, L.S2, g, c, fp);
+  const int loc = lbase + c - myrow0i;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r)
+    if (c < jbp && r > loc) x[r] *= my_rinv;
+  __syncthreads();
+}
+
+// A packed upper-triangular 64 x 64 factor (S1) published, then announced.
+template <class T>
+__device__ __forceinline__ void tsqr_publish_tri(const T (*S1)[NB + 2], uint64_t* dst, uint64_t* flag, uint32_t tag) {
+  T* d = reinterpret_cast<T*>(dst);
+  for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+    const int i = e & (NB - 1), c = e / NB;
+    if (i <= c) store_agent(d + tri_index(i, c), S1[i][c]);
+  }
+  raise_flag(flag, tag);
+}
+
+// One tree node: the QR of K (2..4) stacked upper-triangular factors taken from
+// `src` (packed) once their flags carry the tag.  The top factor goes to L.S2,
+// where row j is read at step j only (no step before touches it); factor t >=
+// 1 lives in the registers of waves 2t (rows 0..31) and 2t + 1 (rows 32..63),
+// lane c holding column c (rows 0..c).  On return tri holds this wave's half of
+// its factor's block of the scaled reflectors, L.S1 the node's R, L.S4 its T;
+// false if a wait expired.
+template <class T>
+__device__ __forceinline__ bool tsqr_node(T (&tri)[RPT], const uint64_t* src, const uint64_t* flags, int K, uint32_t tag,
+                                 int jbp, int g, int c, const TsqrLds<T>& L, unsigned* err, const PanelWait& pw) {
+  static_assert(2 * RPT == NB, "a factor spans two waves");
+  c = opaque(c);
+  for (int e = threadIdx.x; e < NB * (NB + 2); e += PANEL_THREADS) {
+    (&L.S1[0][0])[e] = T(0);
+    (&L.S4[0][0])[e] = T(0);
+  }
+  const int t = g >> 1, h0 = (g & 1) * RPT;  // this wave's factor and first row
+  bool ok = true;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) tri[r] = T(0);
+  if (t < K) {
+    // rows h0 .. h0 + 31 of column c (those on or above the diagonal), all in flight at once
+    ok = await_flag(flags + t, tag + pw.skew, err, pw.spin_limit);
+    // (each unit's area is kTriEntries 8-byte words, whatever T is)
+    const T* colp = reinterpret_cast<const T*>(src + static_cast<int64_t>(t) * kTriEntries) + tri_index(h0, c);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) tri[r] = (ok && h0 + r <= c) ? load_coherent(colp + r) : T(0);
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      L.S2[h0 + r][c] = tri[r];
+      tri[r] = T(0);
+    }
+  }
+  if (__syncthreads_or(ok ? 0 : 1)) return false;
+
+  T my_rinv = T(0);
+  const bool act = t >= 1 && t < K;  // wave-uniform
+  for (int j = 0; j < jbp; ++j) {
+    const int par = j & 1;
+    T (*red)[NB] = par ? L.red1 : L.red0;
+    if (act && h0 <= j) {
+      // rows h0 + 8 rb .. of column j that lie on or above its diagonal (the rest are zero)
+      if (c == j) {
+#pragma unroll
+        for (int rb = 0; rb < RPT; rb += 8)
+          if (h0 + rb <= j) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) L.cb[g][rb + u] = tri[rb + u];
+          }
+      }
+      wave_lds_sync();
+      T qa[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int rb = 0; rb < RPT; rb += 8)
+        if (h0 + rb <= j) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) qa[u & 3] += L.cb[g][rb + u] * tri[rb + u];
+        }
+      red[g][c] = (qa[0] + qa[1]) + (qa[2] + qa[3]);
+    } else {
+      red[g][c] = T(0);
+    }
+    __syncthreads();
+    const T xcj = L.S2[j][c];
+    const T alpha = L.S2[j][j];
+    const T qc = sum_waves(red, c);
+    const T sigma2 = sum_waves(red, j);
+    T tt, beta, rinv;
+    reflector(alpha, sigma2, tt, beta, rinv);
+    if (c == j) my_rinv = rinv;
+    const T w = xcj + qc * rinv;
+    if (g == 0) {
+      if (c < j) L.S3[j][c] = my_rinv * w;
+      if (c == 0) L.tau[j] = tt;
+      L.S1[j][c] = (c == j) ? beta : (c > j ? xcj - tt * w : T(0));
+    }
+    const T coef = (c > j && tt != T(0)) ? tt * w * rinv : T(0);
+    if (act && h0 <= j) {
+#pragma unroll
+      for (int rb = 0; rb < RPT; rb += 8)
+        if (h0 + rb <= j) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) tri[rb + u] = fma(-coef, L.cb[g][rb + u], tri[rb + u]);
+        }
+    }
+  }
+  __syncthreads();
+  const FragPos fp{(g >> 1) * 16, (g & 1) * 32, c & 15, c >> 4};
+  tsqr_build_t(L.S4, L.S3, L.tau, jbp, L.S2, g, c, fp);  // Rtop in S2 is no longer needed
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) tri[r] *= my_rinv;
+  __syncthreads();
+  return true;
+}
+
+// Block s of a node's Q, [I; 0] - Yc Tc (Tc in L.S4): I - Tc for s = 0, whose
+// reflector block is I; -Yc_s Tc otherwise, Yc_s held by waves 2s and 2s + 1.
+template <class T>
+__device__ __forceinline__ void tsqr_node_q(const T (&tri)[RPT], int s, int g, int c, const TsqrLds<T>& L, const FragPos& p,
+                                   Frag<T>& f) {
+  c = opaque(c);
+  if (s > 0 && (g >> 1) == s) {
+    const int h0 = (g & 1) * RPT;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) L.S2[h0 + r][c] = tri[r];
+  }
+  __syncthreads();
+  frag_zero(f);
+  if (s == 0) {
+    frag_from_lds(f, L.S4, p);
+    frag_negate_plus_identity(f, p, true);
+  } else {
+    frag_mma<T, false>(f, L.S2, L.S4, p);
+    frag_negate_plus_identity(f, p, false);
+  }
+  __syncthreads();
+}
+
 
 // Householder panel.  Rows [0, mp) x columns [0, jb) at X (ld ldx); the
 // panel's first row is the diagonal row of its first column.  Writes back in
@@ -782,6 +1408,615 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
   }
 }
 
+// ---------------------------------------------------------------------------
+// The panel kernel the QR uses: one launch per block of up to 128 columns, two
+// 64-column parts, each factored without a device-wide step per column
+// (CholeskyQR2, or the tall-skinny QR when that is refused, then the rebuilt
+// Householder vectors).  The panel never lives in registers: every step
+// streams this workgroup's rows through LDS 64 rows at a time, from X (the
+// input, kept for the fallback) and the Y rows (the working copy, which ends
+// as the explicit reflectors).
+
+// Sum of a 64 x 64 matrix over the P workgroups of the launch, every workgroup
+// getting bitwise the same sum (one fixed order): this workgroup's term is in M
+// (LDS) on entry, the sum on return.  With sym only entries i <= j travel (the
+// rest is mirrored).  Each workgroup sums a slice of the entries over all
+// terms, then every workgroup gathers the slices (two announced exchanges).
+// False if a wait expired.
+template <class T>
+__device__ __forceinline__ bool allreduce64(T (*M)[NB + 2], bool sym, int P, int wg, const TsqrXch& xt,
+                                            uint32_t tag, unsigned* err, const PanelWait& pw) {
+  if (P == 1) return true;
+  const int tid = opaque(static_cast<int>(threadIdx.x));
+  T* const part = reinterpret_cast<T*>(xt.gram);
+  T* const sum = reinterpret_cast<T*>(xt.gram + static_cast<int64_t>(P) * NB * NB);
+  uint64_t* const fa = xt.flags + kTsqrUnits + 1;
+  uint64_t* const fb = fa + kMaxPanelWgs;
+  for (int e = tid; e < NB * NB; e += PANEL_THREADS) {
+    const int i = e & (NB - 1), j = e / NB;
+    if (!sym || i <= j) store_agent(part + static_cast<int64_t>(wg) * NB * NB + e, M[i][j]);
+  }
+  raise_flag(fa + wg, tag);
+  bool ok = static_cast<int>(threadIdx.x) >= P || await_flag(fa + threadIdx.x, tag + pw.skew, err, pw.spin_limit);
+  if (__syncthreads_or(ok ? 0 : 1)) return false;
+  const int e0 = NB * NB * wg / P, e1 = NB * NB * (wg + 1) / P;
+  for (int e = e0 + tid; e < e1; e += PANEL_THREADS) {
+    if (sym && (e & (NB - 1)) > e / NB) continue;
+    T a = T(0);
+    for (int q = 0; q < P; ++q) a += load_coherent(part + static_cast<int64_t>(q) * NB * NB + e);
+    store_agent(sum + e, a);
+  }
+  raise_flag(fb + wg, tag);
+  ok = static_cast<int>(threadIdx.x) >= P || await_flag(fb + threadIdx.x, tag + pw.skew, err, pw.spin_limit);
+  if (__syncthreads_or(ok ? 0 : 1)) return false;
+  for (int e = tid; e < NB * NB; e += PANEL_THREADS) {
+    const int i = e & (NB - 1), j = e / NB;
+    M[i][j] = load_coherent(sum + ((sym && i > j) ? j + NB * i : e));
+  }
+  __syncthreads();
+  return true;
+}
+
+// Where this workgroup's rows of one part are and how to move them.
+template <class T>
+struct CqrRows {
+  int64_t row0, mp;  // first block row of the workgroup; rows of the block
+  int lbase;         // first row of the part this workgroup holds (p0 in workgroup 0)
+  int p0, jbp;       // the part's first pivot row and width
+  int kc;            // chunk of the workgroup's first 64 part rows (the pivot rows in workgroup 0)
+  __device__ __forceinline__ bool above(int k) const { return row0 + k * 64 + 64 <= lbase; }
+  // rows row0 + 64k .. of a column-major matrix (ld lds) into dst; 0 outside the part
+  // (lane indices through opaque(): the addresses are formed at each call, not
+  // hoisted out of the phases and held in registers or scratch)
+  __device__ __forceinline__ void in(T (*dst)[NB + 2], const T* src, int64_t lds, int k, bool coherent) const {
+    const int r = opaque(threadIdx.x & 63), i0 = opaque(threadIdx.x >> 6);
+    const int64_t gi = row0 + k * 64 + r;
+    const bool rowok = gi < mp && gi >= lbase;
+    constexpr int YPT = 64 * NB / PANEL_THREADS;
+    T v[YPT];
+#pragma unroll
+    for (int u = 0; u < YPT; ++u) {
+      const int col = i0 + u * (PANEL_THREADS / 64);
+      const T* p = src + gi + static_cast<int64_t>(col) * lds;
+      v[u] = (rowok && col < jbp) ? (coherent ? load_coherent(p) : *p) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < YPT; ++u) dst[r][i0 + u * (PANEL_THREADS / 64)] = v[u];
+  }
+  __device__ __forceinline__ void out(const T (*sr)[NB + 2], T* dst, int64_t ldd, int k) const {
+    const int r = opaque(threadIdx.x & 63), i0 = opaque(threadIdx.x >> 6);
+    const int64_t gi = row0 + k * 64 + r;
+    if (!(gi < mp && gi >= lbase)) return;
+    constexpr int YPT = 64 * NB / PANEL_THREADS;
+#pragma unroll
+    for (int u = 0; u < YPT; ++u) {
+      const int col = i0 + u * (PANEL_THREADS / 64);
+      if (col < jbp) dst[gi + static_cast<int64_t>(col) * ldd] = sr[r][col];
+    }
+  }
+};
+
+// Z <- Z B for this workgroup's rows of Z (ld ldz), B in LDS; S is the chunk buffer.
+template <class T>
+__device__ __forceinline__ void cqr_rows_times(const CqrRows<T>& rw, T* Z, int64_t ldz, const T (*B)[NB + 2],
+                                               T (*S)[NB + 2], const FragPos& fp) {
+  for (int k = 0; k < RPW / 64; ++k) {
+    if (rw.above(k)) continue;
+    rw.in(S, Z, ldz, k, false);
+    __syncthreads();
+    Frag<T> f;
+    frag_zero(f);
+    frag_mma<T, false>(f, S, B, fp);
+    __syncthreads();
+    frag_to_lds(f, S, fp);
+    __syncthreads();
+    rw.out(S, Z, ldz, k);
+    __syncthreads();
+  }
+}
+
+// One 64-column part.  On entry the part's columns are in Xp (rows of the
+// block, ld ldx; `coherent` when another kernel may have written them after
+// this one started).  On return Yp holds the explicit reflectors of this
+// workgroup's rows (1 on the diagonal, 0 above), Xp R on and above the
+// diagonal of the pivot rows and the reflectors below it, L.S4 the part's T
+// (workgroup 0, and every workgroup when all_t) and L.tau its tau.
+template <class T>
+__device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, int g, int c, T* __restrict__ Xp,
+                                         int64_t ldx, T* __restrict__ Yp, int64_t ldy, bool coherent,
+                                         const TsqrXch& xt, uint32_t tagp, unsigned* err, const PanelWait& pw,
+                                         bool all_t, bool use_chol, const TsqrLds<T>& L) {
+  const uint32_t tagR = tagp + 1, tagU = tagp + 2, tagG = tagp + 3;
+  FragPos fp{(g >> 1) * 16, (g & 1) * 32, c & 15, c >> 4};
+  auto phase = [&]() {
+    c = opaque(c);
+    fp.l16 = c & 15;
+    fp.lk = c >> 4;
+  };
+  const int jbp = rw.jbp, p0 = rw.p0, kc = rw.kc;
+  T* const ubuf = L.aux;          // pivots, then (at + NB) their reciprocals
+  T* const sgn = L.aux + 2 * NB;  // signs of the reconstruction
+  T* const dsq = L.aux + 3 * NB;  // square roots of the Cholesky pivots
+
+  // ---- working copy Xp -> Yp; is the part upper triangular already?
+  phase();
+  int below_nz = 0;
+  for (int k = 0; k < RPW / 64; ++k) {
+    if (rw.above(k)) continue;
+    const int r = opaque(threadIdx.x & 63), i0 = opaque(threadIdx.x >> 6);
+    const int64_t gi = rw.row0 + k * 64 + r;
+    if (gi < rw.mp && gi >= rw.lbase) {
+#pragma unroll
+      for (int u = 0; u < 64 * NB / PANEL_THREADS; ++u) {
+        const int col = i0 + u * (PANEL_THREADS / 64);
+        if (col < jbp) {
+          const T* p = Xp + gi + static_cast<int64_t>(col) * ldx;
+          const T v = coherent ? load_coherent(p) : *p;
+          Yp[gi + static_cast<int64_t>(col) * ldy] = v;
+          below_nz |= (gi > p0 + col && v != T(0)) ? 1 : 0;
+        }
+      }
+    }
+  }
+  // (also the barrier after the copy); every workgroup takes the answer of
+  // all of them, which travels with the first Gram sum
+  bool chol = use_chol && __syncthreads_or(below_nz);
+
+  // ---- CholeskyQR2
+  Frag<T> f;
+  for (int pass = 0; pass < 2 && use_chol; ++pass) {
+    phase();
+    frag_zero(f);
+    for (int k = 0; k < RPW / 64; ++k) {
+      if (rw.above(k)) continue;
+      rw.in(L.S1, Yp, ldy, k, false);
+      __syncthreads();
+      frag_mma<T, true>(f, L.S1, L.S1, fp);
+      __syncthreads();
+    }
+    frag_to_lds(f, L.S3, fp);
+    // the triangular test rides in entry (63, 0), below the diagonal (restored from (0, 63) below)
+    __syncthreads();
+    if (pass == 0 && threadIdx.x == 0) L.S3[NB - 1][0] = chol ? T(1) : T(0);
+    __syncthreads();
+    if (pass == 0 && P > 1) {
+      // entry (63, 0) is not among the symmetric ones: a full reduction for pass 0
+      if (!allreduce64(L.S3, false, P, wg, xt, tagG, err, pw)) return false;
+      chol = L.S3[NB - 1][0] != T(0);  // some workgroup saw a nonzero below the diagonal
+      for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+        const int i = e & (NB - 1), j = e / NB;
+        if (i > j) L.S3[i][j] = L.S3[j][i];
+      }
+      __syncthreads();
+    } else if (pass == 1 && P > 1) {
+      if (!allreduce64(L.S3, true, P, wg, xt, tagG + 1, err, pw)) return false;
+    } else if (pass == 0) {
+      chol = L.S3[NB - 1][0] != T(0);
+      for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+        const int i = e & (NB - 1), j = e / NB;
+        if (i > j) L.S3[i][j] = L.S3[j][i];
+      }
+      __syncthreads();
+    }
+    if (!chol) break;
+    // columns beyond the part: identity
+    for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+      const int i = e & (NB - 1), j = e / NB;
+      if (i >= jbp || j >= jbp) L.S3[i][j] = (i == j) ? T(1) : T(0);
+    }
+    __syncthreads();
+    if (pass == 1) {
+      // the first pass must have left the rows nearly orthonormal
+      int far = 0;
+      for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+        const T d = L.S3[e & (NB - 1)][e / NB] - ((e & (NB - 1)) == e / NB ? T(1) : T(0));
+        far |= !(d <= T(0.1) && d >= T(-0.1)) ? 1 : 0;  // also NaN
+      }
+      if (__syncthreads_or(far)) {
+        chol = false;
+        break;
+      }
+    }
+    phase();
+    blocked_lu(L.S3, false, ubuf, sgn, L.S2, L.S1, g, c, fp);  // G = L U, U = D R (S4 keeps R1)
+    int bad = 0;
+    if (threadIdx.x < NB) {
+      const T u = ubuf[threadIdx.x];
+      bad = !(u > T(0)) ? 1 : 0;
+      dsq[threadIdx.x] = sqrt(u);
+    }
+    if (__syncthreads_or(bad)) {
+      chol = false;
+      break;
+    }
+    phase();
+    // R^-1 = U^-1 diag(sqrt u) into S2 (U^-1 from its diagonal blocks; S1 scratch)
+    tri_join<T, true>(L.S2, [&](int a, int b) { return L.S3[a][b]; }, L.S1, fp);
+    for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) L.S2[e & (NB - 1)][e / NB] *= dsq[e / NB];
+    if (pass == 0) {
+      // R1 = diag(sqrt u)^-1 U, kept in S4
+      for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+        const int i = e & (NB - 1), j = e / NB;
+        L.S4[i][j] = i <= j ? L.S3[i][j] / dsq[i] : T(0);
+      }
+      __syncthreads();
+    } else {
+      // R = R2 R1 into S3 (S1 is the chunk buffer below)
+      __syncthreads();
+      frag_zero(f);
+      frag_mma_f(f, [&](int i, int k) { return k >= i ? L.S3[i][k] / dsq[i] : T(0); },
+                 [&](int k, int j) { return L.S4[k][j]; }, fp, 0, NB);
+      __syncthreads();
+      frag_to_lds(f, L.S3, fp);
+      __syncthreads();
+    }
+    phase();
+    cqr_rows_times(rw, Yp, ldy, L.S2, L.S1, fp);  // rows <- rows R^-1
+  }
+  if (chol) {
+    for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) L.S1[e & (NB - 1)][e / NB] = L.S3[e & (NB - 1)][e / NB];
+    __syncthreads();
+  } else {
+    // ---- tall-skinny QR: the leaf needs the rows in registers (every row, from X)
+    phase();
+    const int myrow0i = static_cast<int>(rw.row0) + g * RPT;
+    constexpr int WAVES_PER_CHUNK = 64 / RPT;
+    const int kw = g / WAVES_PER_CHUNK, r0w = (g % WAVES_PER_CHUNK) * RPT;
+    {
+      T x[RPT];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int64_t gi = myrow0i + r;
+        const T* p = Xp + gi + static_cast<int64_t>(c) * ldx;
+        x[r] = (gi < rw.mp && gi >= rw.lbase && c < jbp) ? (coherent ? load_coherent(p) : *p) : T(0);
+      }
+      tsqr_leaf(x, jbp, rw.lbase, myrow0i, g, c, L);
+      const int loc = rw.lbase + c - myrow0i;  // local row of lane c's pivot in this wave
+      if (P == 1) {
+        // one leaf: its reflectors are the panel's; Y explicit, R onto the pivot rows of X
+        for (int k = 0; k < RPW / 64; ++k) {
+          if (rw.above(k)) continue;
+          if (kw == k) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+              L.S2[r0w + r][c] = c < jbp ? (r > loc ? x[r] : (r == loc ? T(1) : T(0))) : T(0);
+              const int row = myrow0i + r - p0;
+              L.S3[r0w + r][c] = (row >= 0 && row < jbp && c >= row) ? L.S1[row][c] : x[r];
+            }
+          }
+          __syncthreads();
+          rw.out(L.S2, Yp, ldy, k);
+          rw.out(L.S3, Xp, ldx, k);
+          __syncthreads();
+        }
+        return true;
+      }
+      phase();
+      tsqr_publish_tri(L.S1, xt.tri + static_cast<int64_t>(wg) * kTriEntries, xt.flags + wg, tagR);
+      // the leaf's explicit Q, Qt = [I; 0] - Y_w (T_w Y_w0^T), into the Y rows
+      if (kw == kc) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) L.S2[r0w + r][c] = c < jbp ? (r > loc ? x[r] : (r == loc ? T(1) : T(0))) : T(0);
+      }
+      __syncthreads();
+      frag_zero(f);
+      frag_mma<T, false, true>(f, L.S4, L.S2, fp);  // T_w Y_w0^T
+      frag_to_lds(f, L.S3, fp);
+      for (int k = 0; k < RPW / 64; ++k) {
+        __syncthreads();
+        if (rw.above(k)) continue;
+        if (kw == k) {
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) L.S2[r0w + r][c] = c < jbp ? (r > loc ? x[r] : (r == loc ? T(1) : T(0))) : T(0);
+        }
+        __syncthreads();
+        frag_zero(f);
+        frag_mma<T, false>(f, L.S2, L.S3, fp);
+        frag_negate_plus_identity(f, fp, k == kc);
+        __syncthreads();
+        frag_to_lds(f, L.S2, fp);
+        __syncthreads();
+        rw.out(L.S2, Yp, ldy, k);
+      }
+      __syncthreads();
+    }
+    // tree
+    Frag<T> fM;
+    frag_identity(fM, fp);
+    {
+      T tri[RPT];
+      int units = P, off = 0, span = 1;  // units of the current level, their first slot, workgroups per unit
+      while (units > 1) {
+        phase();
+        const int unit = wg / span, grp = unit / kTsqrFan, s = unit % kTsqrFan;
+        const int K = min(kTsqrFan, units - grp * kTsqrFan);
+        if (span > 1 && wg % span == 0)  // the unit's first workgroup publishes its R (level 0 did above)
+          tsqr_publish_tri(L.S1, xt.tri + static_cast<int64_t>(off + unit) * kTriEntries, xt.flags + off + unit,
+                           tagR);
+        if (K >= 2) {
+          __syncthreads();
+          const int first = off + grp * kTsqrFan;
+          if (!tsqr_node(tri, xt.tri + static_cast<int64_t>(first) * kTriEntries, xt.flags + first, K, tagR, jbp, g,
+                         c, L, err, pw))
+            return false;
+          Frag<T> fb;
+          tsqr_node_q(tri, s, g, c, L, fp, fb);
+          frag_to_lds(fM, L.S3, fp);
+          frag_to_lds(fb, L.S2, fp);
+          __syncthreads();
+          frag_zero(fM);
+          frag_mma<T, false>(fM, L.S3, L.S2, fp);  // M <- M B
+          __syncthreads();
+        }
+        off += units;
+        units = (units + kTsqrFan - 1) / kTsqrFan;
+        span *= kTsqrFan;
+      }
+    }
+    // Q_w = Qt M into the Y rows; L.S1 holds the root's R
+    phase();
+    frag_to_lds(fM, L.S2, fp);
+    __syncthreads();
+    cqr_rows_times(rw, Yp, ldy, L.S2, L.S3, fp);
+  }
+  // Q in the Y rows, R in S1 (up to the signs S)
+
+  // ---- reconstruction: workgroup 0 factors S - Q1 = L U and sends U^-1 and T
+  phase();
+  const int tid = opaque(static_cast<int>(threadIdx.x));
+  T* const xu = reinterpret_cast<T*>(xt.recon);  // U^-1 (NB^2), then T (NB^2), entry i + NB c
+  uint64_t* const rflag = xt.flags + kTsqrUnits;
+  if (wg == 0) {
+    rw.in(L.S4, Yp, ldy, kc, false);
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += PANEL_THREADS) L.S4[e & (NB - 1)][e / NB] = -L.S4[e & (NB - 1)][e / NB];
+    __syncthreads();
+    // S - Q1 = L U (blocked, in place on -Q1; S = diag(sgn) chosen during the
+    // elimination), inverses of the diagonal blocks of U and L in S2, S3
+    blocked_lu(L.S4, true, ubuf, sgn, L.S2, L.S3, g, c, fp);
+    phase();
+    // the pivot rows: Y = L (unit lower), X = L below the diagonal and S R on and above it
+    for (int e = tid; e < NB * NB; e += PANEL_THREADS) {
+      const int i = e & (NB - 1), j = e / NB;
+      const int64_t gi = p0 + i;
+      if (gi < rw.mp && j < jbp) {
+        const T lij = L.S4[i][j];
+        Yp[gi + static_cast<int64_t>(j) * ldy] = i > j ? lij : (i == j ? T(1) : T(0));
+        Xp[gi + static_cast<int64_t>(j) * ldx] = i > j ? lij : sgn[i] * L.S1[i][j];
+      }
+    }
+    __syncthreads();
+    phase();
+    // U^-1 (S2) and L^-1 (S3) from the inverses of their diagonal blocks; S1 is scratch
+    tri_join<T, true>(L.S2, [&](int a, int b) { return L.S4[a][b]; }, L.S1, fp);
+    tri_join<T, false>(L.S3, [&](int a, int b) { return L.S4[a][b]; }, L.S1, fp);
+    phase();
+    // T = (U S) L^-T into S4 (through S1); U^-1 and T out
+    frag_zero(f);
+    frag_mma_f(f, [&](int i, int k) { return k >= i ? L.S4[i][k] * sgn[k] : T(0); },
+               [&](int k, int j) { return L.S3[j][k]; }, fp, 0, NB);
+    frag_to_lds(f, L.S1, fp);
+    for (int e = tid; e < NB * NB; e += PANEL_THREADS) store_agent(xu + e, L.S2[e & (NB - 1)][e / NB]);
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += PANEL_THREADS) {
+      const T v = L.S1[e & (NB - 1)][e / NB];
+      L.S4[e & (NB - 1)][e / NB] = v;
+      store_agent(xu + NB * NB + e, v);
+    }
+    raise_flag(rflag, tagU);
+  } else {
+    // U^-1 into S2, and T into S4 when every workgroup needs it
+    const bool ok = await_flag(rflag, tagU + pw.skew, err, pw.spin_limit);
+    const int nget = all_t ? 2 : 1;
+    for (int hh = 0; hh < nget && ok; ++hh) {
+      T (*dst)[NB + 2] = hh ? L.S4 : L.S2;
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = load_coherent(xu + hh * NB * NB + tid + u * PANEL_THREADS);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + u * PANEL_THREADS;
+        dst[e & (NB - 1)][e / NB] = v[u];
+      }
+    }
+    if (__syncthreads_or(ok ? 0 : 1)) return false;
+  }
+  if (threadIdx.x < NB && (wg == 0 || all_t)) L.tau[threadIdx.x] = L.S4[threadIdx.x][threadIdx.x];
+
+  // ---- Y2 = -Q_w U^-1 below the pivot rows, into the Y rows and X
+  phase();
+  for (int k = 0; k < RPW / 64; ++k) {
+    if (rw.above(k) || (wg == 0 && k == kc)) continue;  // workgroup-uniform
+    rw.in(L.S3, Yp, ldy, k, false);
+    __syncthreads();
+    frag_zero(f);
+    frag_mma<T, false>(f, L.S3, L.S2, fp);
+    frag_negate_plus_identity(f, fp, false);
+    __syncthreads();
+    frag_to_lds(f, L.S3, fp);
+    __syncthreads();
+    rw.out(L.S3, Yp, ldy, k);
+    rw.out(L.S3, Xp, ldx, k);
+    __syncthreads();
+  }
+  return true;
+}
+
+// The block of columns [0, jb + jb2) (jb2 > 0: a second part of jb2 columns,
+// with the first part's reflectors applied to it in between and the joined T)
+// of rows [0, mp) at X: Householder vectors (explicit, into Y), T (into Tout,
+// ld ldt, from workgroup 0), tau; R in place in X.  P = ceil(mp / 256)
+// co-resident workgroups.  With wait_flag, the launch waits (bounded) for that
+// flag before reading its columns, which another stream updates.
+template <class T>
+__global__ __launch_bounds__(PANEL_THREADS) void cqr_panel_kernel(T* __restrict__ X, int64_t ldx, int64_t mp, int jb,
+                                                                 T* __restrict__ Y, int64_t ldy, T* __restrict__ tau,
+                                                                 T* __restrict__ Tout, int ldt, uint32_t tag0,
+                                                                 unsigned* __restrict__ err, int zero_above,
+                                                                 PanelWait pw, int jb2,
+                                                                 const unsigned* __restrict__ wait_flag, TsqrXch xt) {
+  __shared__ __attribute__((aligned(16))) T S1[NB][NB + 2];
+  __shared__ __attribute__((aligned(16))) T S2[NB][NB + 2];
+  __shared__ __attribute__((aligned(16))) T S3[NB][NB + 2];
+  __shared__ __attribute__((aligned(16))) T S4[NB][NB + 2];
+  __shared__ __attribute__((aligned(16))) T cb[PANEL_WAVES][NB];
+  __shared__ T red0[PANEL_WAVES][NB];
+  __shared__ T red1[PANEL_WAVES][NB];
+  __shared__ T piv[2][NB];
+  __shared__ T aux[8 * NB];
+  __shared__ T tau_sh[NB];
+  const TsqrLds<T> L{S1, S2, S3, S4, cb, red0, red1, piv, tau_sh, aux};
+
+  const int P = gridDim.x, wg = blockIdx.x;
+  int c = threadIdx.x & 63;
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t row0 = static_cast<int64_t>(wg) * RPW;
+  const bool two = jb2 > 0;
+  FragPos fp{(g >> 1) * 16, (g & 1) * 32, c & 15, c >> 4};
+  auto phase = [&]() {
+    c = opaque(c);
+    fp.l16 = c & 15;
+    fp.lk = c >> 4;
+  };
+
+  bool ok = true;
+  const bool waited = wait_flag != nullptr;
+  if (waited) {
+    if (threadIdx.x == 0) ok = wait_flag_geq(wait_flag, 1u, err, pw.spin_limit);
+    ok = !__syncthreads_or(ok ? 0 : 1);
+  }
+  for (int part = 0; part < (two ? 2 : 1); ++part) {
+    phase();
+    const int p0 = part * NB;
+    const int jbp = part ? jb2 : jb;
+    const uint32_t tagp = tag0 + static_cast<uint32_t>(part * NB);
+    T* Xp = X + static_cast<int64_t>(p0) * ldx;
+    T* Yp = Y + static_cast<int64_t>(p0) * ldy;
+    T* Tp = Tout + p0 + static_cast<int64_t>(p0) * ldt;
+    CqrRows<T> rw;
+    rw.row0 = row0;
+    rw.mp = mp;
+    rw.lbase = wg == 0 ? p0 : static_cast<int>(row0);
+    rw.p0 = p0;
+    rw.jbp = jbp;
+    rw.kc = (rw.lbase - static_cast<int>(row0)) / 64;
+    // part 0 reads columns another kernel may have just written; part 1 reads this kernel's own
+    ok = ok && cqr_part(rw, P, wg, g, c, Xp, ldx, Yp, ldy, waited && part == 0, xt, tagp, err, pw, two,
+                        xt.chol != 0, L);
+    if (!ok) {
+      // A device-side wait gave up: poison T and tau so that the failure is visible.
+      if (threadIdx.x < NB) tau_sh[threadIdx.x] = static_cast<T>(__builtin_nan(""));
+      for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) S4[e & (NB - 1)][e / NB] = static_cast<T>(__builtin_nan(""));
+    }
+    __syncthreads();
+    if (wg == 0) {
+      for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+        const int i = e % NB, k = e / NB;
+        if (i < jbp && k < jbp) Tp[i + static_cast<int64_t>(k) * ldt] = S4[i][k];
+      }
+      if (threadIdx.x < jbp) tau[p0 + threadIdx.x] = tau_sh[threadIdx.x];
+      // Y is zero in the zero_above rows above the panel (an earlier panel of the same block)
+      for (int e = threadIdx.x; e < zero_above * jbp; e += PANEL_THREADS)
+        Yp[(e % zero_above) - zero_above + static_cast<int64_t>(e / zero_above) * ldy] = T(0);
+      // and in the rows of the first part above the second
+      if (part == 1)
+        for (int e = threadIdx.x; e < NB * jbp; e += PANEL_THREADS)
+          Yp[(e % NB) + static_cast<int64_t>(e / NB) * ldy] = T(0);
+    }
+    if (!two || !ok) break;
+    phase();
+    CqrRows<T> all = rw;  // every row of the block that this workgroup holds
+    all.lbase = static_cast<int>(row0);
+    all.jbp = NB;
+    all.kc = 0;
+    CqrRows<T> rw2 = all;
+    rw2.jbp = jb2;
+    T* X2 = X + static_cast<int64_t>(NB) * ldx;
+    T* Y2 = Y + static_cast<int64_t>(NB) * ldy;
+    if (part == 0) {
+      // ---- the second part's columns C2 <- (I - Y1 T1^T Y1^T) C2: W = Y1^T C2 summed over the workgroups
+      Frag<T> f;
+      frag_zero(f);
+      for (int k = 0; k < RPW / 64; ++k) {
+        all.in(S1, Y, ldy, k, false);
+        rw2.in(S2, X2, ldx, k, waited);
+        __syncthreads();
+        frag_mma<T, true>(f, S1, S2, fp);
+        __syncthreads();
+      }
+      frag_to_lds(f, S3, fp);
+      __syncthreads();
+      ok = allreduce64(S3, false, P, wg, xt, tagp + 5, err, pw);
+      if (!ok) break;
+      phase();
+      // W' = T1^T W (T1 in S4, every workgroup) into S2
+      frag_zero(f);
+      frag_mma<T, true>(f, S4, S3, fp);
+      __syncthreads();
+      frag_to_lds(f, S2, fp);
+      __syncthreads();
+      // C2 -= Y1 W', chunk by chunk, back into X
+      for (int k = 0; k < RPW / 64; ++k) {
+        all.in(S1, Y, ldy, k, false);
+        rw2.in(S3, X2, ldx, k, waited);
+        __syncthreads();
+        frag_from_lds(f, S3, fp);
+        Frag<T> g1;
+        frag_zero(g1);
+        frag_mma<T, false>(g1, S1, S2, fp);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          f.a0[v] -= g1.a0[v];
+          f.a1[v] -= g1.a1[v];
+        }
+        __syncthreads();
+        frag_to_lds(f, S3, fp);
+        __syncthreads();
+        rw2.out(S3, X2, ldx, k);
+        __syncthreads();
+      }
+    } else {
+      // ---- T of the whole block: T12 = -T1 (Y1^T Y2) T2, S12 = Y1^T Y2 summed over the
+      // workgroups (Y2 is zero above its part: rows from the part's first pivot row on)
+      Frag<T> f;
+      frag_zero(f);
+      for (int k = 0; k < RPW / 64; ++k) {
+        all.in(S1, Y, ldy, k, false);
+        rw.in(S2, Y2, ldy, k, false);
+        __syncthreads();
+        frag_mma<T, true>(f, S1, S2, fp);
+        __syncthreads();
+      }
+      frag_to_lds(f, S3, fp);
+      __syncthreads();
+      ok = allreduce64(S3, false, P, wg, xt, tagp + 6, err, pw);
+      if (!ok) break;
+      if (wg == 0) {
+        phase();
+        // S12 T2 (T2 in S4) into S2, T1 (from Tout) into S1, T12 = -T1 (S12 T2)
+        frag_zero(f);
+        frag_mma<T, false>(f, S3, S4, fp);
+        for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+          const int i = e & (NB - 1), k = e / NB;
+          S1[i][k] = (i < jb && k < jb) ? Tout[i + static_cast<int64_t>(k) * ldt] : T(0);
+        }
+        __syncthreads();
+        frag_to_lds(f, S2, fp);
+        __syncthreads();
+        frag_zero(f);
+        frag_mma<T, false>(f, S1, S2, fp);
+        frag_each(f, fp, [&](int i, int j, T v) {
+          if (i < jb && j < jb2) Tout[i + static_cast<int64_t>(NB + j) * ldt] = -v;
+        });
+        for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
+          const int i = e & (NB - 1), j = e / NB;
+          if (i < jb2 && j < jb) Tout[NB + i + static_cast<int64_t>(j) * ldt] = T(0);
+        }
+      }
+    }
+  }
+}
+
 // R(i,c) = d_i X(i,c) for i <= c, 0 below; d_i = sign(X(i,i)), sign(0) = +1.
 template <class T>
 __global__ void extract_r_kernel(const T* __restrict__ X, int64_t ldx, int64_t n,
@@ -950,6 +2185,21 @@ bool panel_early() {
   return !(e && std::atoi(e) == 0);
 }
 
+// Whether panels are factored by the tall-skinny QR with reconstructed
+// reflectors (URV_PANEL_TSQR=0 selects the loop with one device-wide reduction
+// per column, for comparison).
+bool panel_tsqr() {
+  const char* e = std::getenv("URV_PANEL_TSQR");
+  return !(e && std::atoi(e) == 0);
+}
+
+// Whether the panels try CholeskyQR2 before the tall-skinny QR
+// (URV_PANEL_CHOL=0 goes straight to the tall-skinny QR, for comparison).
+bool panel_chol() {
+  const char* e = std::getenv("URV_PANEL_CHOL");
+  return !(e && std::atoi(e) == 0);
+}
+
 // Whether targets take pairs of 128-column blocks (URV_TARGET_PAIRS=0 turns it off, for tuning).
 bool target_pairs() {
   const char* e = std::getenv("URV_TARGET_PAIRS");
@@ -986,8 +2236,13 @@ PanelWait panel_wait() {
 }
 
 struct QrSizes {
-  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f, wn, gemm_work_n, tp, jxch;
+  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f, wn, gemm_work_n, tp, jxch, txch;
 };
+
+// Words of the exchange of the streaming panel: the units' R, U^-1 and T, the 64 x 64 sums, the flags.
+size_t tsqr_tri_words(int64_t m) { return static_cast<size_t>(2) * panel_wgs(m) * kTriEntries; }
+size_t tsqr_recon_words() { return static_cast<size_t>(2) * NB * NB; }
+size_t tsqr_gram_words(int64_t m) { return (static_cast<size_t>(panel_wgs(m)) + 1) * NB * NB; }
 
 QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   QrSizes z;
@@ -998,6 +2253,7 @@ QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   z.w = static_cast<size_t>(NBO) * n;
   z.xch = 2 * (static_cast<size_t>(panel_wgs(m)) + 1) * NB * 2;
   z.jxch = (static_cast<size_t>(panel_wgs(m)) + 1) * kJoinEntries * 2;
+  z.txch = tsqr_tri_words(m) + tsqr_recon_words() + tsqr_gram_words(m) + kTsqrFlags;
   z.sync = nblocks + 2;
   size_t gw = 0, gwb = 0, gwf = 0, gwn = 0;
   for (const int64_t nbo : {static_cast<int64_t>(NB2), static_cast<int64_t>(NBO)}) {
@@ -1059,6 +2315,8 @@ void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w, int64_t target
   w.xch_words = z.xch;
   w.jxch = a.take<uint64_t>(z.jxch);
   w.jxch_words = z.jxch;
+  w.txch = a.take<uint64_t>(z.txch);
+  w.txch_words = z.txch;
   w.sync = a.take<unsigned>(z.sync);
   w.gemm_work = a.take<T>(z.gemm_work);
   w.gemm_work_elems = z.gemm_work;
@@ -1106,6 +2364,18 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   fill_u64_kernel<<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(w.jxch_words), 256)), 256, 0, s>>>(
       w.jxch, static_cast<int64_t>(w.jxch_words));
   URV_LAUNCHED("fill_u64_kernel");
+  const bool tsqr = panel_tsqr();
+  if (tsqr) {
+    fill_u64_kernel<<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(w.txch_words), 256)), 256, 0, s>>>(
+        w.txch, static_cast<int64_t>(w.txch_words));
+    URV_LAUNCHED("fill_u64_kernel");
+  }
+  TsqrXch txch;
+  txch.tri = w.txch;
+  txch.recon = txch.tri + tsqr_tri_words(m);
+  txch.gram = txch.recon + tsqr_recon_words();
+  txch.chol = panel_chol() ? 1 : 0;
+  txch.flags = txch.gram + tsqr_gram_words(m);
   // per-block flags: "the columns of the block at column b * NB are up to date"
   unsigned* ready = w.sync;
   fill_u32_kernel<<<static_cast<unsigned>(ceil_div(nblocks, 256)), 256, 0, s>>>(ready, nblocks, 0u);
@@ -1124,11 +2394,18 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
                    const unsigned* wf) -> int {
     const int64_t mp = m - r0;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
-    panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
-                                                 w.tau + r0, Tp, NBO, w.xch, panels * NB, err, zero_above, join,
-                                                 pwait, jb2, wf);
+    if (tsqr && join.Y1 == nullptr) {
+      cqr_panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
+                                                       w.tau + r0, Tp, NBO, panels * NB, err, zero_above, pwait,
+                                                       jb2, wf, txch);
+      URV_LAUNCHED("cqr_panel_kernel");
+    } else {
+      panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
+                                                   w.tau + r0, Tp, NBO, w.xch, panels * NB, err, zero_above, join,
+                                                   pwait, jb2, wf);
+      URV_LAUNCHED("panel_kernel");
+    }
     panels += jb2 > 0 ? 2 : 1;
-    URV_LAUNCHED("panel_kernel");
     return URV_OK;
   };
   // Householder vectors, tau and T (at Tp, ld NBO) of the sub-block of width
