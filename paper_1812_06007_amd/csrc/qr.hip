@@ -427,84 +427,126 @@ __device__ __forceinline__ float lane_value(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Wave 0: LU without pivoting of the 16 x 16 block of M at (b0, b0), in place
-// (multipliers below the diagonal, U on and above it).  With signs, the pivot
-// of step j is u = m_jj + s, s = sgn(m_jj) (sgn(0) = +1, so |u| >= 1); without,
-// u = m_jj.  u, 1/u and s go to ubuf, ubuf + NB and sgnb at b0 + j.  Lane c <
-// 16 holds column c; the column of step j reaches the other lanes through
-// scalar registers.
+// 1 / u: the hardware estimate refined by Newton's iteration r <- r + r (1 - u r)
+// (two steps in double precision, one in single), within an ulp or two of the
+// quotient.  u = 0 gives NaN (callers reject such pivots).
+__device__ __forceinline__ double recip(double u) {
+  double r = __builtin_amdgcn_rcp(u);
+  r = fma(r, fma(-u, r, 1.0), r);
+  r = fma(r, fma(-u, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ float recip(float u) {
+  float r = __builtin_amdgcn_rcpf(u);
+  r = fmaf(r, fmaf(-u, r, 1.0f), r);
+  return r;
+}
+
+// One wave: LU without pivoting of the 16 x 16 block of M at (b0, b0), in
+// place (multipliers below the diagonal, U on and above it).  With signs, the
+// pivot of step j is u = m_jj + s, s = sgn(m_jj) (sgn(0) = +1, so |u| >= 1);
+// without, u = m_jj.  u, 1/u and s go to ubuf, ubuf + NB and sgnb at b0 + j.
+// Lane r < 16 holds row r; the pivot row reaches the other lanes through
+// scalar registers, and every step is free of branches.
 template <class T>
 __device__ __forceinline__ void base16_lu(T (*M)[NB + 2], int b0, bool signs, T* ubuf, T* sgnb, int c) {
   const bool act = c < BS;
   T m[BS];
 #pragma unroll
-  for (int r = 0; r < BS; ++r) m[r] = act ? M[b0 + r][b0 + c] : T(0);
+  for (int k = 0; k < BS; ++k) m[k] = act ? M[b0 + c][b0 + k] : T(0);
+  T myrinv = T(0), mys = T(0);
 #pragma unroll
   for (int j = 0; j < BS; ++j) {
     const T d = lane_value(m[j], j);
     const T sj = signs ? (d >= T(0) ? T(1) : T(-1)) : T(0);
     const T u = d + sj;
-    const T rinv = T(1) / u;
-    T col[BS];
+    const T rinv = recip(u);
+    const T l = m[j] * rinv;  // this row's multiplier (rows below j)
+    const T coef = c > j ? l : T(0);
 #pragma unroll
-    for (int r = j + 1; r < BS; ++r) col[r] = lane_value(m[r], j) * rinv;  // the multipliers
-    if (c > j) {
-#pragma unroll
-      for (int r = j + 1; r < BS; ++r) m[r] = fma(-col[r], m[j], m[r]);
-    } else if (c == j) {
-#pragma unroll
-      for (int r = j + 1; r < BS; ++r) m[r] = col[r];
-      m[j] = u;
-    }
-    if (c == 0) {
-      ubuf[b0 + j] = u;
-      ubuf[NB + b0 + j] = rinv;
-      sgnb[b0 + j] = sj;
-    }
+    for (int k = j + 1; k < BS; ++k) m[k] = fma(-coef, lane_value(m[k], j), m[k]);
+    m[j] = c > j ? l : (c == j ? u : m[j]);
+    myrinv = c == j ? rinv : myrinv;
+    mys = c == j ? sj : mys;
   }
   if (act) {
 #pragma unroll
-    for (int r = 0; r < BS; ++r) M[b0 + r][b0 + c] = m[r];
+    for (int k = 0; k < BS; ++k) M[b0 + c][b0 + k] = m[k];
+    ubuf[b0 + c] = m[c];
+    ubuf[NB + b0 + c] = myrinv;
+    sgnb[b0 + c] = mys;
   }
 }
 
 // Inverse of the 16 x 16 diagonal block of a triangular factor held in M
 // (upper: U on and above the diagonal, rdiag the reciprocals of its diagonal;
-// lower: unit L below it) into Z's same block, one column per lane c < 16 by
-// substitution.
+// lower: unit L below it) into Z's same block, one column per lane c < 16, by
+// column-oriented substitution (the updates of one step are independent).
 template <class T, bool kUpper>
 __device__ __forceinline__ void base16_inv(const T (*M)[NB + 2], int b0, const T* rdiag, T (*Z)[NB + 2], int c) {
   if (c >= BS) return;
   T z[BS];
+#pragma unroll
+  for (int r = 0; r < BS; ++r) z[r] = r == c ? T(1) : T(0);
   if constexpr (kUpper) {
 #pragma unroll
     for (int r = BS - 1; r >= 0; --r) {
-      T a = (r == c) ? T(1) : T(0);
+      z[r] *= rdiag[b0 + r];
 #pragma unroll
-      for (int k = r + 1; k < BS; ++k) a = fma(-M[b0 + r][b0 + k], z[k], a);
-      z[r] = a * rdiag[b0 + r];
+      for (int i = 0; i < r; ++i) z[i] = fma(-M[b0 + i][b0 + r], z[r], z[i]);
     }
   } else {
 #pragma unroll
     for (int r = 0; r < BS; ++r) {
-      T a = (r == c) ? T(1) : T(0);
 #pragma unroll
-      for (int k = 0; k < r; ++k) a = fma(-M[b0 + r][b0 + k], z[k], a);
-      z[r] = a;
+      for (int i = r + 1; i < BS; ++i) z[i] = fma(-M[b0 + i][b0 + r], z[r], z[i]);
     }
   }
 #pragma unroll
   for (int r = 0; r < BS; ++r) Z[b0 + r][b0 + c] = z[r];
 }
 
+// One wave's 16 x 16 tile on the matrix cores: acc += sum over k in [k0, k0 + nk)
+// of a(i0 + i, k) b(k, j0 + j), nk a multiple of 16, the operands given by
+// functors (LDS reads); four k-steps have their loads in flight together.
+template <class T>
+using TileAcc = typename PanelMma<T>::acc;
+template <class T>
+__device__ __forceinline__ void tile_zero(TileAcc<T>& a) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) a[v] = T(0);
+}
+template <class T, class FA, class FB>
+__device__ __forceinline__ void tile_mm(TileAcc<T>& acc, FA a, FB b, int i0, int j0, int k0, int nk, int c) {
+  const int l16 = c & 15, lk = c >> 4;
+  for (int k = k0; k < k0 + nk; k += 16) {
+    T av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k + 4 * u + lk;
+      av[u] = a(i0 + l16, kk);
+      bv[u] = b(kk, j0 + l16);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = PanelMma<T>::run(av[u], bv[u], acc);
+  }
+}
+// fn(i, j, value) for the 4 entries of the tile at (i0, j0) this lane holds.
+template <class T, class F>
+__device__ __forceinline__ void tile_each(const TileAcc<T>& acc, int i0, int j0, int c, F fn) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) fn(i0 + PanelMma<T>::row(c >> 4, v), j0 + (c & 15), acc[v]);
+}
+
 // LU without pivoting of the 64 x 64 M in place, in 16-column blocks: the
 // diagonal block (base16_lu, wave 0), its inverses (waves 0 and 1, into the
-// diagonal blocks of Ui and Li, zero elsewhere), then U's block row
-// L_kk^-1 M_k*, L's block column M_*k U_kk^-1 and the Schur update on the matrix
-// cores.  ubuf receives the pivots and, at ubuf + NB, their reciprocals.
+// diagonal blocks of Ui and Li, zero elsewhere), then the tiles of U's block
+// row L_kk^-1 M_k* and of L's block column M_*k U_kk^-1, and the Schur update,
+// one 16 x 16 tile per wave.  ubuf receives the pivots and, at ubuf + NB,
+// their reciprocals.
 template <class T>
-__device__ __forceinline__ void blocked_lu(T (*M)[NB + 2], bool signs, T* ubuf, T* sgnb,
-                                           T (*Ui)[NB + 2], T (*Li)[NB + 2], int g, int c, const FragPos& fp) {
+__device__ __forceinline__ void blocked_lu(T (*M)[NB + 2], bool signs, T* ubuf, T* sgnb, T (*Ui)[NB + 2],
+                                           T (*Li)[NB + 2], int g, int c) {
   for (int e = threadIdx.x; e < NB * (NB + 2); e += PANEL_THREADS) {
     (&Ui[0][0])[e] = T(0);
     (&Li[0][0])[e] = T(0);
@@ -517,58 +559,92 @@ __device__ __forceinline__ void blocked_lu(T (*M)[NB + 2], bool signs, T* ubuf, 
     if (g == 0) base16_inv<T, true>(M, b0, ubuf + NB, Ui, c);
     if (g == 1) base16_inv<T, false>(M, b0, ubuf + NB, Li, c);
     __syncthreads();
-    if (b1 >= NB) break;
-    Frag<T> fu, fl;
-    frag_zero(fu);
-    frag_zero(fl);
-    frag_mma_f(fu, [&](int i, int k) { return Li[i][k]; }, [&](int k, int j) { return M[k][j]; }, fp, b0, b1);
-    frag_mma_f(fl, [&](int i, int k) { return M[i][k]; }, [&](int k, int j) { return Ui[k][j]; }, fp, b0, b1);
+    const int nt = (NB - b1) / BS;
+    if (nt == 0) break;
+    if (g < 2 * nt) {  // wave g < nt: U's tile (kb, kb + 1 + g); else L's tile (kb + 1 + g - nt, kb)
+      TileAcc<T> a;
+      tile_zero<T>(a);
+      if (g < nt) {
+        const int j0 = b1 + BS * g;
+        tile_mm<T>(a, [&](int i, int k) { return Li[i][k]; }, [&](int k, int j) { return M[k][j]; }, b0, j0, b0, BS, c);
+        tile_each<T>(a, b0, j0, c, [&](int i, int j, T v) { M[i][j] = v; });
+      } else {
+        const int i0 = b1 + BS * (g - nt);
+        tile_mm<T>(a, [&](int i, int k) { return M[i][k]; }, [&](int k, int j) { return Ui[k][j]; }, i0, b0, b0, BS, c);
+        tile_each<T>(a, i0, b0, c, [&](int i, int j, T v) { M[i][j] = v; });
+      }
+    }
     __syncthreads();
-    frag_each(fu, fp, [&](int i, int j, T v) {
-      if (i >= b0 && i < b1 && j >= b1) M[i][j] = v;
-    });
-    frag_each(fl, fp, [&](int i, int j, T v) {
-      if (j >= b0 && j < b1 && i >= b1) M[i][j] = v;
-    });
-    __syncthreads();
-    Frag<T> fs;
-    frag_zero(fs);
-    frag_mma_f(fs, [&](int i, int k) { return M[i][k]; }, [&](int k, int j) { return M[k][j]; }, fp, b0, b1);
-    __syncthreads();
-    frag_each(fs, fp, [&](int i, int j, T v) {
-      if (i >= b1 && j >= b1) M[i][j] -= v;
-    });
+    for (int t = g; t < nt * nt; t += PANEL_WAVES) {
+      const int i0 = b1 + BS * (t / nt), j0 = b1 + BS * (t % nt);
+      TileAcc<T> a;
+      tile_zero<T>(a);
+      tile_mm<T>(a, [&](int i, int k) { return M[i][k]; }, [&](int k, int j) { return M[k][j]; }, i0, j0, b0, BS, c);
+      tile_each<T>(a, i0, j0, c, [&](int i, int j, T v) { M[i][j] -= v; });
+    }
   }
   __syncthreads();
 }
 
 // Z triangular 64 x 64 with its 16 x 16 diagonal blocks in place and zero
-// elsewhere: fills the off-diagonal blocks, joining pairs of 16-, then 32-blocks
-// by Z_AB = -Z_A C_AB Z_B (upper) or Z_BA = -Z_B C_BA Z_A (lower), C(a, b) =
-// cf(a, b) the coupling.  This gives the inverse of a triangular matrix C from
-// the inverses of its diagonal blocks, and T of a compact WY form from the
-// Gram entries.  W is scratch.
+// elsewhere: the off-diagonal blocks are filled by joining pairs of 16-, then
+// 32-blocks, Z_AB = -Z_A C_AB Z_B (upper) or Z_BA = -Z_B C_BA Z_A (lower),
+// C(a, b) = cf(a, b) the coupling.  This gives the inverse of a triangular
+// matrix C from the inverses of its diagonal blocks, and T of a compact WY form
+// from the Gram entries.  One phase of one level: wave w < 4 takes every fourth
+// 16 x 16 tile; phase 0 forms X = C_AB Z_B (C_BA Z_A) into W, phase 1
+// Z_AB = -Z_A X (Z_BA = -Z_B X).  W is used in its strictly upper (upper) or
+// strictly lower (lower) part only, so an upper and a lower join may share it.
 template <class T, bool kUpper, class CF>
-__device__ __forceinline__ void tri_join(T (*Z)[NB + 2], CF cf, T (*W)[NB + 2], const FragPos& fp) {
-  for (int half = BS; half < NB; half *= 2) {
-    // A = [2q half, (2q + 1) half), B = [(2q + 1) half, (2q + 2) half)
-    auto first = [&](int a) { return (a / half) % 2 == 0; };
-    Frag<T> f;
-    frag_zero(f);
-    if constexpr (kUpper)  // X = C_AB Z_B
-      frag_mma_f(f, [&](int i, int k) { return (first(i) && k / half == i / half + 1) ? cf(i, k) : T(0); },
-                 [&](int k, int j) { return Z[k][j]; }, fp, 0, NB);
-    else  // X = C_BA Z_A
-      frag_mma_f(f, [&](int i, int k) { return (!first(i) && k / half == i / half - 1) ? cf(i, k) : T(0); },
-                 [&](int k, int j) { return Z[k][j]; }, fp, 0, NB);
-    frag_to_lds(f, W, fp);
-    __syncthreads();
-    frag_zero(f);
-    frag_mma_f(f, [&](int i, int k) { return Z[i][k]; }, [&](int k, int j) { return W[k][j]; }, fp, 0, NB);
-    __syncthreads();
-    frag_each(f, fp, [&](int i, int j, T v) { Z[i][j] -= v; });
-    __syncthreads();
+__device__ __forceinline__ void tri_join_phase(T (*Z)[NB + 2], CF cf, T (*W)[NB + 2], int half, int phase, int w,
+                                               int c) {
+  const int side = half / BS, per = side * side, tiles = (NB / (2 * half)) * per;
+  for (int t = w; t < tiles; t += 4) {
+    const int p0 = (t / per) * 2 * half, ti = BS * ((t % per) / side), tj = BS * ((t % per) % side);
+    TileAcc<T> a;
+    tile_zero<T>(a);
+    if (phase == 0) {
+      if constexpr (kUpper) {  // rows of A, columns of B; Z_B upper: k up to tj + 16
+        tile_mm<T>(a, cf, [&](int k, int j) { return Z[k][j]; }, p0 + ti, p0 + half + tj, p0 + half, tj + BS, c);
+        tile_each<T>(a, p0 + ti, p0 + half + tj, c, [&](int i, int j, T v) { W[i][j] = v; });
+      } else {  // rows of B, columns of A; Z_A lower: k from tj
+        tile_mm<T>(a, cf, [&](int k, int j) { return Z[k][j]; }, p0 + half + ti, p0 + tj, p0 + tj, half - tj, c);
+        tile_each<T>(a, p0 + half + ti, p0 + tj, c, [&](int i, int j, T v) { W[i][j] = v; });
+      }
+    } else {
+      if constexpr (kUpper) {  // Z_A upper: k from ti
+        tile_mm<T>(a, [&](int i, int k) { return Z[i][k]; }, [&](int k, int j) { return W[k][j]; }, p0 + ti,
+                   p0 + half + tj, p0 + ti, half - ti, c);
+        tile_each<T>(a, p0 + ti, p0 + half + tj, c, [&](int i, int j, T v) { Z[i][j] = -v; });
+      } else {  // Z_B lower: k up to ti + 16
+        tile_mm<T>(a, [&](int i, int k) { return Z[i][k]; }, [&](int k, int j) { return W[k][j]; }, p0 + half + ti,
+                   p0 + tj, p0 + half, ti + BS, c);
+        tile_each<T>(a, p0 + half + ti, p0 + tj, c, [&](int i, int j, T v) { Z[i][j] = -v; });
+      }
+    }
   }
+}
+// The join on waves 0..3 (every wave of the workgroup calls: barriers inside).
+template <class T, bool kUpper, class CF>
+__device__ __forceinline__ void tri_join(T (*Z)[NB + 2], CF cf, T (*W)[NB + 2], int g, int c) {
+  for (int half = BS; half < NB; half *= 2)
+    for (int phase = 0; phase < 2; ++phase) {
+      if (g < 4) tri_join_phase<T, kUpper>(Z, cf, W, half, phase, g, c);
+      __syncthreads();
+    }
+}
+// An upper join on waves 0..3 beside a lower one on waves 4..7, sharing W.
+template <class T, class CFU, class CFL>
+__device__ __forceinline__ void tri_join_both(T (*Zu)[NB + 2], CFU cfu, T (*Zl)[NB + 2], CFL cfl, T (*W)[NB + 2],
+                                              int g, int c) {
+  for (int half = BS; half < NB; half *= 2)
+    for (int phase = 0; phase < 2; ++phase) {
+      if (g < 4)
+        tri_join_phase<T, true>(Zu, cfu, W, half, phase, g, c);
+      else
+        tri_join_phase<T, false>(Zl, cfl, W, half, phase, g - 4, c);
+      __syncthreads();
+    }
 }
 
 // v unchanged, through a step the compiler cannot see into: LDS addresses
@@ -638,7 +714,7 @@ __device__ __forceinline__ void tsqr_build_t(T (*Tm)[NB + 2], const T (*G)[NB + 
     for (int jj = 0; jj < BS; ++jj) Tm[b0 + il][b0 + jj] = tr[jj];
   }
   __syncthreads();
-  tri_join<T, true>(Tm, [&](int a, int b) { return b < jb ? G[b][a] : T(0); }, W, fp);
+  tri_join<T, true>(Tm, [&](int a, int b) { return b < jb ? G[b][a] : T(0); }, W, g, c);
 }
 
 // Leaf: Householder QR of this workgroup's rows alone.  Column j's pivot is
@@ -1618,7 +1694,7 @@ __device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, in
       }
     }
     phase();
-    blocked_lu(L.S3, false, ubuf, sgn, L.S2, L.S1, g, c, fp);  // G = L U, U = D R (S4 keeps R1)
+    blocked_lu(L.S3, false, ubuf, sgn, L.S2, L.S1, g, c);  // G = L U, U = D R (S4 keeps R1)
     int bad = 0;
     if (threadIdx.x < NB) {
       const T u = ubuf[threadIdx.x];
@@ -1631,7 +1707,7 @@ __device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, in
     }
     phase();
     // R^-1 = U^-1 diag(sqrt u) into S2 (U^-1 from its diagonal blocks; S1 scratch)
-    tri_join<T, true>(L.S2, [&](int a, int b) { return L.S3[a][b]; }, L.S1, fp);
+    tri_join<T, true>(L.S2, [&](int a, int b) { return L.S3[a][b]; }, L.S1, g, c);
     for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) L.S2[e & (NB - 1)][e / NB] *= dsq[e / NB];
     if (pass == 0) {
       // R1 = diag(sqrt u)^-1 U, kept in S4
@@ -1773,7 +1849,7 @@ __device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, in
     __syncthreads();
     // S - Q1 = L U (blocked, in place on -Q1; S = diag(sgn) chosen during the
     // elimination), inverses of the diagonal blocks of U and L in S2, S3
-    blocked_lu(L.S4, true, ubuf, sgn, L.S2, L.S3, g, c, fp);
+    blocked_lu(L.S4, true, ubuf, sgn, L.S2, L.S3, g, c);
     phase();
     // the pivot rows: Y = L (unit lower), X = L below the diagonal and S R on and above it
     for (int e = tid; e < NB * NB; e += PANEL_THREADS) {
@@ -1788,8 +1864,8 @@ __device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, in
     __syncthreads();
     phase();
     // U^-1 (S2) and L^-1 (S3) from the inverses of their diagonal blocks; S1 is scratch
-    tri_join<T, true>(L.S2, [&](int a, int b) { return L.S4[a][b]; }, L.S1, fp);
-    tri_join<T, false>(L.S3, [&](int a, int b) { return L.S4[a][b]; }, L.S1, fp);
+    tri_join_both<T>(L.S2, [&](int a, int b) { return L.S4[a][b]; }, L.S3, [&](int a, int b) { return L.S4[a][b]; },
+                     L.S1, g, c);
     phase();
     // T = (U S) L^-T into S4 (through S1); U^-1 and T out
     frag_zero(f);
