@@ -266,14 +266,20 @@ __host__ __device__ __forceinline__ int tri_index(int i, int c) { return c * (c 
 // Exchange areas of the TSQR panel: values (one 8-byte word each) and the flags
 // that announce them.
 struct TsqrXch {
-  uint64_t* tri = nullptr;    // 2 kMaxPanelWgs x kTriEntries: the R of every unit of every tree level
+  uint64_t* tri = nullptr;    // 2 P x kTriEntries: the R of every unit of every tree level
   uint64_t* recon = nullptr;  // 2 NB^2: U^-1 and T from workgroup 0
-  uint64_t* gram = nullptr;   // (P + 1) x kTriEntries: Gram partials, then the sums
-  uint64_t* flags = nullptr;  // one per unit (2 kMaxPanelWgs), one for recon, 2 kMaxPanelWgs for the Gram sums
+  uint64_t* gram = nullptr;   // (P + 1) x NB^2: partial sums of the 64 x 64 reductions, then the sums
+  uint64_t* flags = nullptr;  // one per unit, one for the reconstruction, two per workgroup for the sums
   int chol = 1;               // try CholeskyQR2 first
 };
-constexpr int kTsqrUnits = 2 * kMaxPanelWgs;  // P + P/4 + P/16 + ... < 2 P
-constexpr int kTsqrFlags = kTsqrUnits + 1 + 2 * kMaxPanelWgs;
+// The streaming panel: 128 rows per workgroup (two 64-row chunks), so that
+// more compute units share each pass over the panel.
+constexpr int CQR_RPW = 128;
+constexpr int CQR_CHUNKS = CQR_RPW / 64;
+constexpr int CQR_RPT = CQR_RPW / PANEL_WAVES;  // rows per wave in its tall-skinny leaf
+constexpr int kMaxCqrWgs = static_cast<int>(kMaxRows / CQR_RPW);
+constexpr int kTsqrUnits = 2 * kMaxCqrWgs;  // P + P/4 + P/16 + ... < 2 P
+constexpr int kTsqrFlags = kTsqrUnits + 1 + 2 * kMaxCqrWgs;
 
 // Announced exchange: every thread writes its values with agent-scope stores
 // (write-through), waits for them to complete (s_waitcnt vmcnt(0)), and after a
@@ -723,8 +729,8 @@ __device__ __forceinline__ void tsqr_build_t(T (*Tm)[NB + 2], const T (*G)[NB + 
 // column), L.S1 the leaf's R (S1[i][c], i <= c, zero elsewhere), L.S4 its T
 // and L.tau its tau.  Wave 0 builds T column by column, one step behind; its
 // own rows leave the leaf first.
-template <class T>
-__device__ __forceinline__ void tsqr_leaf(T (&x)[RPT], int jbp, int lbase, int myrow0i, int g, int c,
+template <class T, int R>
+__device__ __forceinline__ void tsqr_leaf(T (&x)[R], int jbp, int lbase, int myrow0i, int g, int c,
                                  const TsqrLds<T>& L) {
   using V2 = typename Vec2<T>::type;
   c = opaque(c);
@@ -734,24 +740,24 @@ __device__ __forceinline__ void tsqr_leaf(T (&x)[RPT], int jbp, int lbase, int m
   }
   __syncthreads();
   T my_rinv = T(0);
-  constexpr int OWN_LD = RPT + 2;
+  constexpr int OWN_LD = R + 2;
   T* const own = &L.S2[0][0];
   for (int j = 0; j < jbp; ++j) {
     const int par = j & 1;
     T (*red)[NB] = par ? L.red1 : L.red0;
-    const int lo = min(max(lbase + j - myrow0i, -1), RPT);  // wave-uniform
-    const bool owner = lo >= 0 && lo < RPT;
-    const bool below = lo < RPT;
+    const int lo = min(max(lbase + j - myrow0i, -1), R);  // wave-uniform
+    const bool owner = lo >= 0 && lo < R;
+    const bool below = lo < R;
     const T* colp = &L.cb[g][0];
     if (lo < 0) {
       if (c == j) {
 #pragma unroll
-        for (int r = 0; r < RPT; r += 2) *reinterpret_cast<V2*>(&L.cb[g][r]) = Vec2<T>::make(x[r], x[r + 1]);
+        for (int r = 0; r < R; r += 2) *reinterpret_cast<V2*>(&L.cb[g][r]) = Vec2<T>::make(x[r], x[r + 1]);
       }
     } else if (owner) {
       T* mine_t = own + c * OWN_LD;
 #pragma unroll
-      for (int r = 0; r < RPT; r += 2) *reinterpret_cast<V2*>(mine_t + r) = Vec2<T>::make(x[r], x[r + 1]);
+      for (int r = 0; r < R; r += 2) *reinterpret_cast<V2*>(mine_t + r) = Vec2<T>::make(x[r], x[r + 1]);
       L.piv[par][c] = mine_t[lo];
       if (c == j)
         for (int r = 0; r <= lo; ++r) mine_t[r] = T(0);
@@ -761,7 +767,7 @@ __device__ __forceinline__ void tsqr_leaf(T (&x)[RPT], int jbp, int lbase, int m
     T qa[4] = {T(0), T(0), T(0), T(0)};
     if (below) {
 #pragma unroll
-      for (int r = 0; r < RPT; r += 2) {
+      for (int r = 0; r < R; r += 2) {
         const V2 xj = *reinterpret_cast<const V2*>(colp + r);
         qa[r & 2] += xj.x * x[r];
         qa[(r & 2) + 1] += xj.y * x[r + 1];
@@ -785,7 +791,7 @@ __device__ __forceinline__ void tsqr_leaf(T (&x)[RPT], int jbp, int lbase, int m
     const T coef = (c > j && t != T(0)) ? t * w * rinv : T(0);
     if (below) {
 #pragma unroll
-      for (int r = 0; r < RPT; r += 2) {
+      for (int r = 0; r < R; r += 2) {
         const V2 xj = *reinterpret_cast<const V2*>(colp + r);
         x[r] = fma(-coef, xj.x, x[r]);
         x[r + 1] = fma(-coef, xj.y, x[r + 1]);
@@ -797,7 +803,7 @@ __device__ __forceinline__ void tsqr_leaf(T (&x)[RPT], int jbp, int lbase, int m
   tsqr_build_t(L.S4, L.S3, L.tau, jbp, L.S2, g, c, fp);
   const int loc = lbase + c - myrow0i;
 #pragma unroll
-  for (int r = 0; r < RPT; ++r)
+  for (int r = 0; r < R; ++r)
     if (c < jbp && r > loc) x[r] *= my_rinv;
   __syncthreads();
 }
@@ -1488,50 +1494,77 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
 // The panel kernel the QR uses: one launch per block of up to 128 columns, two
 // 64-column parts, each factored without a device-wide step per column
 // (CholeskyQR2, or the tall-skinny QR when that is refused, then the rebuilt
-// Householder vectors).  The panel never lives in registers: every step
-// streams this workgroup's rows through LDS 64 rows at a time, from X (the
-// input, kept for the fallback) and the Y rows (the working copy, which ends
-// as the explicit reflectors).
+// Householder vectors).  The panel never lives in registers: each pass streams
+// this workgroup's rows (CQR_RPW of them) through LDS 64 rows at a time, the
+// next chunk's loads in flight while the matrix cores work on the current one.
 
 // Sum of a 64 x 64 matrix over the P workgroups of the launch, every workgroup
 // getting bitwise the same sum (one fixed order): this workgroup's term is in M
-// (LDS) on entry, the sum on return.  With sym only entries i <= j travel (the
-// rest is mirrored).  Each workgroup sums a slice of the entries over all
-// terms, then every workgroup gathers the slices (two announced exchanges).
-// False if a wait expired.
+// (LDS) on entry, the sum on return.  Each workgroup adds up a slice of the
+// entries over all terms, then every workgroup gathers the slices (two
+// announced exchanges).  False if a wait expired.
 template <class T>
-__device__ __forceinline__ bool allreduce64(T (*M)[NB + 2], bool sym, int P, int wg, const TsqrXch& xt,
-                                            uint32_t tag, unsigned* err, const PanelWait& pw) {
+__device__ __forceinline__ bool allreduce64(T (*M)[NB + 2], int P, int wg, const TsqrXch& xt, uint32_t tag,
+                                            unsigned* err, const PanelWait& pw) {
   if (P == 1) return true;
   const int tid = opaque(static_cast<int>(threadIdx.x));
   T* const part = reinterpret_cast<T*>(xt.gram);
   T* const sum = reinterpret_cast<T*>(xt.gram + static_cast<int64_t>(P) * NB * NB);
   uint64_t* const fa = xt.flags + kTsqrUnits + 1;
-  uint64_t* const fb = fa + kMaxPanelWgs;
-  for (int e = tid; e < NB * NB; e += PANEL_THREADS) {
-    const int i = e & (NB - 1), j = e / NB;
-    if (!sym || i <= j) store_agent(part + static_cast<int64_t>(wg) * NB * NB + e, M[i][j]);
-  }
+  uint64_t* const fb = fa + kMaxCqrWgs;
+  T* const mine = part + static_cast<int64_t>(wg) * NB * NB;
+  for (int e = tid; e < NB * NB; e += PANEL_THREADS) store_agent(mine + e, M[e & (NB - 1)][e / NB]);
   raise_flag(fa + wg, tag);
-  bool ok = static_cast<int>(threadIdx.x) >= P || await_flag(fa + threadIdx.x, tag + pw.skew, err, pw.spin_limit);
+  bool ok = tid >= P || await_flag(fa + tid, tag + pw.skew, err, pw.spin_limit);
   if (__syncthreads_or(ok ? 0 : 1)) return false;
-  const int e0 = NB * NB * wg / P, e1 = NB * NB * (wg + 1) / P;
-  for (int e = e0 + tid; e < e1; e += PANEL_THREADS) {
-    if (sym && (e & (NB - 1)) > e / NB) continue;
+  // this workgroup's slice [e0, e1): every term of it into M (free now), entry
+  // (e - e0) P + q, with the loads of a thread all in flight; then each sum in
+  // the order q = 0, 1, ...  (ne P <= NB^2 + P fits in M for P <= 128)
+  const int e0 = NB * NB * wg / P, e1 = NB * NB * (wg + 1) / P, ne = e1 - e0, nt = ne * P;
+  T* const flat = &M[0][0];
+  constexpr int U = 8;
+  for (int i0 = tid; i0 < nt; i0 += U * PANEL_THREADS) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * PANEL_THREADS;
+      v[u] = i < nt ? load_coherent(part + static_cast<int64_t>(i % P) * NB * NB + e0 + i / P) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * PANEL_THREADS;
+      if (i < nt) flat[i] = v[u];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < ne; t += PANEL_THREADS) {
     T a = T(0);
-    for (int q = 0; q < P; ++q) a += load_coherent(part + static_cast<int64_t>(q) * NB * NB + e);
-    store_agent(sum + e, a);
+    for (int q = 0; q < P; ++q) a += flat[t * P + q];
+    store_agent(sum + e0 + t, a);
   }
   raise_flag(fb + wg, tag);
-  ok = static_cast<int>(threadIdx.x) >= P || await_flag(fb + threadIdx.x, tag + pw.skew, err, pw.spin_limit);
+  ok = tid >= P || await_flag(fb + tid, tag + pw.skew, err, pw.spin_limit);
   if (__syncthreads_or(ok ? 0 : 1)) return false;
-  for (int e = tid; e < NB * NB; e += PANEL_THREADS) {
-    const int i = e & (NB - 1), j = e / NB;
-    M[i][j] = load_coherent(sum + ((sym && i > j) ? j + NB * i : e));
+  {
+    T v[NB * NB / PANEL_THREADS];
+#pragma unroll
+    for (int u = 0; u < NB * NB / PANEL_THREADS; ++u) v[u] = load_coherent(sum + tid + u * PANEL_THREADS);
+#pragma unroll
+    for (int u = 0; u < NB * NB / PANEL_THREADS; ++u) {
+      const int e = tid + u * PANEL_THREADS;
+      M[e & (NB - 1)][e / NB] = v[u];
+    }
   }
   __syncthreads();
   return true;
 }
+
+// A 64-row chunk of a column-major matrix in registers: thread t holds row
+// t & 63 of columns (t >> 6) + 8u.
+template <class T>
+struct ChunkRegs {
+  T v[64 * NB / PANEL_THREADS];
+};
 
 // Where this workgroup's rows of one part are and how to move them.
 template <class T>
@@ -1539,33 +1572,32 @@ struct CqrRows {
   int64_t row0, mp;  // first block row of the workgroup; rows of the block
   int lbase;         // first row of the part this workgroup holds (p0 in workgroup 0)
   int p0, jbp;       // the part's first pivot row and width
-  int kc;            // chunk of the workgroup's first 64 part rows (the pivot rows in workgroup 0)
-  __device__ __forceinline__ bool above(int k) const { return row0 + k * 64 + 64 <= lbase; }
-  // rows row0 + 64k .. of a column-major matrix (ld lds) into dst; 0 outside the part
-  // (lane indices through opaque(): the addresses are formed at each call, not
-  // hoisted out of the phases and held in registers or scratch)
-  __device__ __forceinline__ void in(T (*dst)[NB + 2], const T* src, int64_t lds, int k, bool coherent) const {
+  int kc;            // first chunk holding part rows (the pivot rows in workgroup 0)
+  // rows row0 + 64k .. of a column-major matrix (ld lds) into registers; 0 outside
+  // the part (lane indices through opaque(): the addresses are formed at each
+  // call, not hoisted out of the phases and held in registers or scratch)
+  __device__ __forceinline__ void load(ChunkRegs<T>& R, const T* src, int64_t lds, int k, bool coherent) const {
     const int r = opaque(threadIdx.x & 63), i0 = opaque(threadIdx.x >> 6);
     const int64_t gi = row0 + k * 64 + r;
     const bool rowok = gi < mp && gi >= lbase;
-    constexpr int YPT = 64 * NB / PANEL_THREADS;
-    T v[YPT];
 #pragma unroll
-    for (int u = 0; u < YPT; ++u) {
+    for (int u = 0; u < 64 * NB / PANEL_THREADS; ++u) {
       const int col = i0 + u * (PANEL_THREADS / 64);
       const T* p = src + gi + static_cast<int64_t>(col) * lds;
-      v[u] = (rowok && col < jbp) ? (coherent ? load_coherent(p) : *p) : T(0);
+      R.v[u] = (rowok && col < jbp) ? (coherent ? load_coherent(p) : *p) : T(0);
     }
+  }
+  __device__ __forceinline__ void put(T (*dst)[NB + 2], const ChunkRegs<T>& R) const {
+    const int r = threadIdx.x & 63, i0 = threadIdx.x >> 6;
 #pragma unroll
-    for (int u = 0; u < YPT; ++u) dst[r][i0 + u * (PANEL_THREADS / 64)] = v[u];
+    for (int u = 0; u < 64 * NB / PANEL_THREADS; ++u) dst[r][i0 + u * (PANEL_THREADS / 64)] = R.v[u];
   }
   __device__ __forceinline__ void out(const T (*sr)[NB + 2], T* dst, int64_t ldd, int k) const {
     const int r = opaque(threadIdx.x & 63), i0 = opaque(threadIdx.x >> 6);
     const int64_t gi = row0 + k * 64 + r;
     if (!(gi < mp && gi >= lbase)) return;
-    constexpr int YPT = 64 * NB / PANEL_THREADS;
 #pragma unroll
-    for (int u = 0; u < YPT; ++u) {
+    for (int u = 0; u < 64 * NB / PANEL_THREADS; ++u) {
       const int col = i0 + u * (PANEL_THREADS / 64);
       if (col < jbp) dst[gi + static_cast<int64_t>(col) * ldd] = sr[r][col];
     }
@@ -1576,10 +1608,12 @@ struct CqrRows {
 template <class T>
 __device__ __forceinline__ void cqr_rows_times(const CqrRows<T>& rw, T* Z, int64_t ldz, const T (*B)[NB + 2],
                                                T (*S)[NB + 2], const FragPos& fp) {
-  for (int k = 0; k < RPW / 64; ++k) {
-    if (rw.above(k)) continue;
-    rw.in(S, Z, ldz, k, false);
+  ChunkRegs<T> cur;
+  rw.load(cur, Z, ldz, rw.kc, false);
+  for (int k = rw.kc; k < CQR_CHUNKS; ++k) {
+    rw.put(S, cur);
     __syncthreads();
+    if (k + 1 < CQR_CHUNKS) rw.load(cur, Z, ldz, k + 1, false);
     Frag<T> f;
     frag_zero(f);
     frag_mma<T, false>(f, S, B, fp);
@@ -1591,12 +1625,40 @@ __device__ __forceinline__ void cqr_rows_times(const CqrRows<T>& rw, T* Z, int64
   }
 }
 
+// M (LDS) <- its upper triangle mirrored below the diagonal, identity outside
+// [0, jbp)^2.
+template <class T>
+__device__ __forceinline__ void sym_pad(T (*M)[NB + 2], int jbp) {
+  for (int e = opaque(static_cast<int>(threadIdx.x)); e < NB * NB; e += PANEL_THREADS) {
+    const int i = e & (NB - 1), j = e / NB;
+    if (i >= jbp || j >= jbp)
+      M[i][j] = (i == j) ? T(1) : T(0);
+    else if (i > j)
+      M[i][j] = M[j][i];
+  }
+  __syncthreads();
+}
+
 // One 64-column part.  On entry the part's columns are in Xp (rows of the
 // block, ld ldx; `coherent` when another kernel may have written them after
 // this one started).  On return Yp holds the explicit reflectors of this
 // workgroup's rows (1 on the diagonal, 0 above), Xp R on and above the
 // diagonal of the pivot rows and the reflectors below it, L.S4 the part's T
 // (workgroup 0, and every workgroup when all_t) and L.tau its tau.
+//
+// CholeskyQR2 (Yamamoto, Nakatsukasa, Yanagisawa, Fukaya 2015): G1 = X^T X
+// summed over the workgroups, G1 = R1^T R1, Q1 = X R1^-1 (into the Y rows) with
+// G2 = Q1^T Q1 formed in the same pass, G2 = R2^T R2, R = R2 R1; Q = Q1 R2^-1
+// is never stored: the reconstruction needs only its top rows, and the
+// reflectors below them are -Q U^-1 = -Q1 (R2^-1 U^-1).  Taken when both
+// factorizations have positive pivots, G2 is within 0.1 of I entrywise (the
+// first pass left Q1 well conditioned, the second restores orthogonality to
+// rounding level) and the part is not already upper triangular (where the
+// Householder form is exact).  Otherwise the tall-skinny QR: a Householder QR
+// of each workgroup's rows, a tree that stacks the R factors of up to 4 units
+// per level and factors the stack in every workgroup of the group, and
+// Q_w = Q_leaf M_w.  Either way workgroup 0 then factors S - Q_top = L U and
+// sends R2^-1 U^-1 (or U^-1) and T.
 template <class T>
 __device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, int g, int c, T* __restrict__ Xp,
                                          int64_t ldx, T* __restrict__ Yp, int64_t ldy, bool coherent,
@@ -1613,148 +1675,137 @@ __device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, in
   T* const ubuf = L.aux;          // pivots, then (at + NB) their reciprocals
   T* const sgn = L.aux + 2 * NB;  // signs of the reconstruction
   T* const dsq = L.aux + 3 * NB;  // square roots of the Cholesky pivots
-
-  // ---- working copy Xp -> Yp; is the part upper triangular already?
-  phase();
-  int below_nz = 0;
-  for (int k = 0; k < RPW / 64; ++k) {
-    if (rw.above(k)) continue;
-    const int r = opaque(threadIdx.x & 63), i0 = opaque(threadIdx.x >> 6);
-    const int64_t gi = rw.row0 + k * 64 + r;
-    if (gi < rw.mp && gi >= rw.lbase) {
-#pragma unroll
-      for (int u = 0; u < 64 * NB / PANEL_THREADS; ++u) {
-        const int col = i0 + u * (PANEL_THREADS / 64);
-        if (col < jbp) {
-          const T* p = Xp + gi + static_cast<int64_t>(col) * ldx;
-          const T v = coherent ? load_coherent(p) : *p;
-          Yp[gi + static_cast<int64_t>(col) * ldy] = v;
-          below_nz |= (gi > p0 + col && v != T(0)) ? 1 : 0;
-        }
-      }
-    }
-  }
-  // (also the barrier after the copy); every workgroup takes the answer of
-  // all of them, which travels with the first Gram sum
-  bool chol = use_chol && __syncthreads_or(below_nz);
-
-  // ---- CholeskyQR2
   Frag<T> f;
-  for (int pass = 0; pass < 2 && use_chol; ++pass) {
+  bool chol = use_chol;
+
+  // ---- G1 = X^T X over this workgroup's rows; is the part upper triangular already?
+  if (chol) {
     phase();
     frag_zero(f);
-    for (int k = 0; k < RPW / 64; ++k) {
-      if (rw.above(k)) continue;
-      rw.in(L.S1, Yp, ldy, k, false);
+    int below_nz = 0;
+    ChunkRegs<T> cur;
+    rw.load(cur, Xp, ldx, kc, coherent);
+    for (int k = kc; k < CQR_CHUNKS; ++k) {
+      {
+        const int r = threadIdx.x & 63, i0 = threadIdx.x >> 6;
+        const int64_t gi = rw.row0 + k * 64 + r;
+#pragma unroll
+        for (int u = 0; u < 64 * NB / PANEL_THREADS; ++u)
+          below_nz |= (gi > p0 + i0 + u * (PANEL_THREADS / 64) && cur.v[u] != T(0)) ? 1 : 0;
+      }
+      rw.put(L.S1, cur);
       __syncthreads();
+      if (k + 1 < CQR_CHUNKS) rw.load(cur, Xp, ldx, k + 1, coherent);
       frag_mma<T, true>(f, L.S1, L.S1, fp);
       __syncthreads();
     }
     frag_to_lds(f, L.S3, fp);
-    // the triangular test rides in entry (63, 0), below the diagonal (restored from (0, 63) below)
+    // the triangular test rides in entry (63, 0), below the diagonal (mirrored over afterwards)
+    const int any = __syncthreads_or(below_nz);
+    if (threadIdx.x == 0) L.S3[NB - 1][0] = any ? T(1) : T(0);
     __syncthreads();
-    if (pass == 0 && threadIdx.x == 0) L.S3[NB - 1][0] = chol ? T(1) : T(0);
+    if (!allreduce64(L.S3, P, wg, xt, tagG, err, pw)) return false;
+    chol = L.S3[NB - 1][0] != T(0);  // some workgroup holds a nonzero below the diagonal
     __syncthreads();
-    if (pass == 0 && P > 1) {
-      // entry (63, 0) is not among the symmetric ones: a full reduction for pass 0
-      if (!allreduce64(L.S3, false, P, wg, xt, tagG, err, pw)) return false;
-      chol = L.S3[NB - 1][0] != T(0);  // some workgroup saw a nonzero below the diagonal
-      for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
-        const int i = e & (NB - 1), j = e / NB;
-        if (i > j) L.S3[i][j] = L.S3[j][i];
-      }
-      __syncthreads();
-    } else if (pass == 1 && P > 1) {
-      if (!allreduce64(L.S3, true, P, wg, xt, tagG + 1, err, pw)) return false;
-    } else if (pass == 0) {
-      chol = L.S3[NB - 1][0] != T(0);
-      for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
-        const int i = e & (NB - 1), j = e / NB;
-        if (i > j) L.S3[i][j] = L.S3[j][i];
-      }
-      __syncthreads();
-    }
-    if (!chol) break;
-    // columns beyond the part: identity
-    for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
-      const int i = e & (NB - 1), j = e / NB;
-      if (i >= jbp || j >= jbp) L.S3[i][j] = (i == j) ? T(1) : T(0);
-    }
-    __syncthreads();
-    if (pass == 1) {
-      // the first pass must have left the rows nearly orthonormal
-      int far = 0;
-      for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
-        const T d = L.S3[e & (NB - 1)][e / NB] - ((e & (NB - 1)) == e / NB ? T(1) : T(0));
-        far |= !(d <= T(0.1) && d >= T(-0.1)) ? 1 : 0;  // also NaN
-      }
-      if (__syncthreads_or(far)) {
-        chol = false;
-        break;
-      }
-    }
+    sym_pad(L.S3, jbp);
+  }
+  // ---- G1 = L U, U = D R1 (no pivoting; every pivot must be positive)
+  if (chol) {
     phase();
-    blocked_lu(L.S3, false, ubuf, sgn, L.S2, L.S1, g, c);  // G = L U, U = D R (S4 keeps R1)
+    blocked_lu(L.S3, false, ubuf, sgn, L.S2, L.S1, g, c);
     int bad = 0;
     if (threadIdx.x < NB) {
       const T u = ubuf[threadIdx.x];
       bad = !(u > T(0)) ? 1 : 0;
       dsq[threadIdx.x] = sqrt(u);
     }
-    if (__syncthreads_or(bad)) {
-      chol = false;
-      break;
-    }
-    phase();
-    // R^-1 = U^-1 diag(sqrt u) into S2 (U^-1 from its diagonal blocks; S1 scratch)
-    tri_join<T, true>(L.S2, [&](int a, int b) { return L.S3[a][b]; }, L.S1, g, c);
-    for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) L.S2[e & (NB - 1)][e / NB] *= dsq[e / NB];
-    if (pass == 0) {
-      // R1 = diag(sqrt u)^-1 U, kept in S4
-      for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
-        const int i = e & (NB - 1), j = e / NB;
-        L.S4[i][j] = i <= j ? L.S3[i][j] / dsq[i] : T(0);
-      }
-      __syncthreads();
-    } else {
-      // R = R2 R1 into S3 (S1 is the chunk buffer below)
-      __syncthreads();
-      frag_zero(f);
-      frag_mma_f(f, [&](int i, int k) { return k >= i ? L.S3[i][k] / dsq[i] : T(0); },
-                 [&](int k, int j) { return L.S4[k][j]; }, fp, 0, NB);
-      __syncthreads();
-      frag_to_lds(f, L.S3, fp);
-      __syncthreads();
-    }
-    phase();
-    cqr_rows_times(rw, Yp, ldy, L.S2, L.S1, fp);  // rows <- rows R^-1
+    chol = !__syncthreads_or(bad);
   }
   if (chol) {
-    for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) L.S1[e & (NB - 1)][e / NB] = L.S3[e & (NB - 1)][e / NB];
+    phase();
+    // R1^-1 = U^-1 diag(sqrt u) into S2 (S1 scratch); R1 = diag(sqrt u)^-1 U into S4
+    tri_join<T, true>(L.S2, [&](int a, int b) { return L.S3[a][b]; }, L.S1, g, c);
+    for (int e = opaque(static_cast<int>(threadIdx.x)); e < NB * NB; e += PANEL_THREADS) {
+      const int i = e & (NB - 1), j = e / NB;
+      L.S2[i][j] *= dsq[j];
+      L.S4[i][j] = i <= j ? L.S3[i][j] / dsq[i] : T(0);
+    }
+    __syncthreads();
+    // ---- Q1 = X R1^-1 into the Y rows, and G2 = Q1^T Q1
+    phase();
+    Frag<T> g2;
+    frag_zero(g2);
+    ChunkRegs<T> cur;
+    rw.load(cur, Xp, ldx, kc, coherent);
+    for (int k = kc; k < CQR_CHUNKS; ++k) {
+      rw.put(L.S1, cur);
+      __syncthreads();
+      if (k + 1 < CQR_CHUNKS) rw.load(cur, Xp, ldx, k + 1, coherent);
+      frag_zero(f);
+      frag_mma<T, false>(f, L.S1, L.S2, fp);
+      __syncthreads();
+      frag_to_lds(f, L.S1, fp);
+      __syncthreads();
+      frag_mma<T, true>(g2, L.S1, L.S1, fp);
+      rw.out(L.S1, Yp, ldy, k);
+      __syncthreads();
+    }
+    frag_to_lds(g2, L.S3, fp);
+    __syncthreads();
+    if (!allreduce64(L.S3, P, wg, xt, tagG + 1, err, pw)) return false;
+    sym_pad(L.S3, jbp);
+    // the first pass must have left Q1 nearly orthonormal
+    int far = 0;
+    for (int e = opaque(static_cast<int>(threadIdx.x)); e < NB * NB; e += PANEL_THREADS) {
+      const T d = L.S3[e & (NB - 1)][e / NB] - ((e & (NB - 1)) == e / NB ? T(1) : T(0));
+      far |= !(d <= T(0.1) && d >= T(-0.1)) ? 1 : 0;  // also NaN
+    }
+    chol = !__syncthreads_or(far);
+  }
+  if (chol) {
+    phase();
+    blocked_lu(L.S3, false, ubuf, sgn, L.S2, L.S1, g, c);  // G2 = L U, U = D R2
+    int bad = 0;
+    if (threadIdx.x < NB) {
+      const T u = ubuf[threadIdx.x];
+      bad = !(u > T(0)) ? 1 : 0;
+      dsq[threadIdx.x] = sqrt(u);
+    }
+    chol = !__syncthreads_or(bad);
+  }
+  if (chol) {
+    phase();
+    // R2^-1 into S2; R = R2 R1 into S3
+    tri_join<T, true>(L.S2, [&](int a, int b) { return L.S3[a][b]; }, L.S1, g, c);
+    for (int e = opaque(static_cast<int>(threadIdx.x)); e < NB * NB; e += PANEL_THREADS) L.S2[e & (NB - 1)][e / NB] *= dsq[e / NB];
+    frag_zero(f);
+    frag_mma_f(f, [&](int i, int k) { return k >= i ? L.S3[i][k] / dsq[i] : T(0); },
+               [&](int k, int j) { return L.S4[k][j]; }, fp, 0, NB);
+    __syncthreads();
+    frag_to_lds(f, L.S3, fp);
     __syncthreads();
   } else {
     // ---- tall-skinny QR: the leaf needs the rows in registers (every row, from X)
     phase();
-    const int myrow0i = static_cast<int>(rw.row0) + g * RPT;
-    constexpr int WAVES_PER_CHUNK = 64 / RPT;
-    const int kw = g / WAVES_PER_CHUNK, r0w = (g % WAVES_PER_CHUNK) * RPT;
+    const int myrow0i = static_cast<int>(rw.row0) + g * CQR_RPT;
+    constexpr int WAVES_PER_CHUNK = 64 / CQR_RPT;
+    const int kw = g / WAVES_PER_CHUNK, r0w = (g % WAVES_PER_CHUNK) * CQR_RPT;
     {
-      T x[RPT];
+      T x[CQR_RPT];
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
+      for (int r = 0; r < CQR_RPT; ++r) {
         const int64_t gi = myrow0i + r;
         const T* p = Xp + gi + static_cast<int64_t>(c) * ldx;
         x[r] = (gi < rw.mp && gi >= rw.lbase && c < jbp) ? (coherent ? load_coherent(p) : *p) : T(0);
       }
-      tsqr_leaf(x, jbp, rw.lbase, myrow0i, g, c, L);
+      tsqr_leaf<T, CQR_RPT>(x, jbp, rw.lbase, myrow0i, g, c, L);
       const int loc = rw.lbase + c - myrow0i;  // local row of lane c's pivot in this wave
       if (P == 1) {
-        // one leaf: its reflectors are the panel's; Y explicit, R onto the pivot rows of X
-        for (int k = 0; k < RPW / 64; ++k) {
-          if (rw.above(k)) continue;
+        // one leaf: its reflectors are the part's; Y explicit, R onto the pivot rows of X
+        for (int k = kc; k < CQR_CHUNKS; ++k) {
           if (kw == k) {
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
+            for (int r = 0; r < CQR_RPT; ++r) {
               L.S2[r0w + r][c] = c < jbp ? (r > loc ? x[r] : (r == loc ? T(1) : T(0))) : T(0);
               const int row = myrow0i + r - p0;
               L.S3[r0w + r][c] = (row >= 0 && row < jbp && c >= row) ? L.S1[row][c] : x[r];
@@ -1772,18 +1823,19 @@ __device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, in
       // the leaf's explicit Q, Qt = [I; 0] - Y_w (T_w Y_w0^T), into the Y rows
       if (kw == kc) {
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) L.S2[r0w + r][c] = c < jbp ? (r > loc ? x[r] : (r == loc ? T(1) : T(0))) : T(0);
+        for (int r = 0; r < CQR_RPT; ++r)
+          L.S2[r0w + r][c] = c < jbp ? (r > loc ? x[r] : (r == loc ? T(1) : T(0))) : T(0);
       }
       __syncthreads();
       frag_zero(f);
       frag_mma<T, false, true>(f, L.S4, L.S2, fp);  // T_w Y_w0^T
       frag_to_lds(f, L.S3, fp);
-      for (int k = 0; k < RPW / 64; ++k) {
+      for (int k = kc; k < CQR_CHUNKS; ++k) {
         __syncthreads();
-        if (rw.above(k)) continue;
         if (kw == k) {
 #pragma unroll
-          for (int r = 0; r < RPT; ++r) L.S2[r0w + r][c] = c < jbp ? (r > loc ? x[r] : (r == loc ? T(1) : T(0))) : T(0);
+          for (int r = 0; r < CQR_RPT; ++r)
+            L.S2[r0w + r][c] = c < jbp ? (r > loc ? x[r] : (r == loc ? T(1) : T(0))) : T(0);
         }
         __syncthreads();
         frag_zero(f);
@@ -1829,68 +1881,89 @@ __device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, in
         span *= kTsqrFan;
       }
     }
-    // Q_w = Qt M into the Y rows; L.S1 holds the root's R
+    // Q_w = Qt M into the Y rows; the root's R from S1 into S3
     phase();
     frag_to_lds(fM, L.S2, fp);
+    for (int e = opaque(static_cast<int>(threadIdx.x)); e < NB * NB; e += PANEL_THREADS) L.S3[e & (NB - 1)][e / NB] = L.S1[e & (NB - 1)][e / NB];
     __syncthreads();
-    cqr_rows_times(rw, Yp, ldy, L.S2, L.S3, fp);
+    cqr_rows_times(rw, Yp, ldy, L.S2, L.S1, fp);
   }
-  // Q in the Y rows, R in S1 (up to the signs S)
+  // The Y rows hold Q1 (Q = Q1 R2^-1, R2^-1 in S2) or Q itself; R is in S3 (up to the signs S).
 
-  // ---- reconstruction: workgroup 0 factors S - Q1 = L U and sends U^-1 and T
+  // ---- reconstruction: workgroup 0 factors S - Q_top = L U, sends M = R2^-1 U^-1 (U^-1) and T
   phase();
   const int tid = opaque(static_cast<int>(threadIdx.x));
-  T* const xu = reinterpret_cast<T*>(xt.recon);  // U^-1 (NB^2), then T (NB^2), entry i + NB c
+  T* const xu = reinterpret_cast<T*>(xt.recon);  // M (NB^2), then T (NB^2), entry i + NB c
   uint64_t* const rflag = xt.flags + kTsqrUnits;
   if (wg == 0) {
-    rw.in(L.S4, Yp, ldy, kc, false);
+    Frag<T> fR2;
+    frag_zero(fR2);
+    {
+      ChunkRegs<T> cur;
+      rw.load(cur, Yp, ldy, kc, false);
+      rw.put(L.S4, cur);
+    }
     __syncthreads();
-    for (int e = tid; e < NB * NB; e += PANEL_THREADS) L.S4[e & (NB - 1)][e / NB] = -L.S4[e & (NB - 1)][e / NB];
+    frag_zero(f);
+    if (chol) {
+      frag_mma<T, false>(f, L.S4, L.S2, fp);  // Q_top = Q1_top R2^-1
+      frag_from_lds(fR2, L.S2, fp);
+    } else {
+      frag_from_lds(f, L.S4, fp);
+    }
+    frag_negate_plus_identity(f, fp, false);
     __syncthreads();
-    // S - Q1 = L U (blocked, in place on -Q1; S = diag(sgn) chosen during the
-    // elimination), inverses of the diagonal blocks of U and L in S2, S3
-    blocked_lu(L.S4, true, ubuf, sgn, L.S2, L.S3, g, c);
+    frag_to_lds(f, L.S1, fp);
+    // S - Q_top = L U in S1 (S diagonal, chosen during the elimination); inverses of
+    // the diagonal blocks of U and L in S2, S4
+    blocked_lu(L.S1, true, ubuf, sgn, L.S2, L.S4, g, c);
     phase();
     // the pivot rows: Y = L (unit lower), X = L below the diagonal and S R on and above it
     for (int e = tid; e < NB * NB; e += PANEL_THREADS) {
       const int i = e & (NB - 1), j = e / NB;
       const int64_t gi = p0 + i;
       if (gi < rw.mp && j < jbp) {
-        const T lij = L.S4[i][j];
+        const T lij = L.S1[i][j];
         Yp[gi + static_cast<int64_t>(j) * ldy] = i > j ? lij : (i == j ? T(1) : T(0));
-        Xp[gi + static_cast<int64_t>(j) * ldx] = i > j ? lij : sgn[i] * L.S1[i][j];
+        Xp[gi + static_cast<int64_t>(j) * ldx] = i > j ? lij : sgn[i] * L.S3[i][j];
       }
     }
     __syncthreads();
+    // U^-1 (S2) and L^-1 (S4) side by side; S3 is free: scratch
+    tri_join_both<T>(L.S2, [&](int a, int b) { return L.S1[a][b]; }, L.S4, [&](int a, int b) { return L.S1[a][b]; },
+                     L.S3, g, c);
     phase();
-    // U^-1 (S2) and L^-1 (S3) from the inverses of their diagonal blocks; S1 is scratch
-    tri_join_both<T>(L.S2, [&](int a, int b) { return L.S4[a][b]; }, L.S3, [&](int a, int b) { return L.S4[a][b]; },
-                     L.S1, g, c);
-    phase();
-    // T = (U S) L^-T into S4 (through S1); U^-1 and T out
+    if (chol) frag_to_lds(fR2, L.S3, fp);
+    __syncthreads();
+    // T = (U S) L^-T and M = R2^-1 U^-1
     frag_zero(f);
-    frag_mma_f(f, [&](int i, int k) { return k >= i ? L.S4[i][k] * sgn[k] : T(0); },
-               [&](int k, int j) { return L.S3[j][k]; }, fp, 0, NB);
-    frag_to_lds(f, L.S1, fp);
-    for (int e = tid; e < NB * NB; e += PANEL_THREADS) store_agent(xu + e, L.S2[e & (NB - 1)][e / NB]);
+    frag_mma_f(f, [&](int i, int k) { return k >= i ? L.S1[i][k] * sgn[k] : T(0); },
+               [&](int k, int j) { return L.S4[j][k]; }, fp, 0, NB);
+    Frag<T> fm;
+    if (chol) {
+      frag_zero(fm);
+      frag_mma<T, false>(fm, L.S3, L.S2, fp);
+    }
+    __syncthreads();
+    frag_to_lds(f, L.S4, fp);
+    if (chol) frag_to_lds(fm, L.S2, fp);
     __syncthreads();
     for (int e = tid; e < NB * NB; e += PANEL_THREADS) {
-      const T v = L.S1[e & (NB - 1)][e / NB];
-      L.S4[e & (NB - 1)][e / NB] = v;
-      store_agent(xu + NB * NB + e, v);
+      store_agent(xu + e, L.S2[e & (NB - 1)][e / NB]);
+      store_agent(xu + NB * NB + e, L.S4[e & (NB - 1)][e / NB]);
     }
     raise_flag(rflag, tagU);
   } else {
-    // U^-1 into S2, and T into S4 when every workgroup needs it
+    // M into S2, and T into S4 when every workgroup needs it
     const bool ok = await_flag(rflag, tagU + pw.skew, err, pw.spin_limit);
     const int nget = all_t ? 2 : 1;
     for (int hh = 0; hh < nget && ok; ++hh) {
       T (*dst)[NB + 2] = hh ? L.S4 : L.S2;
-      T v[8];
+      T v[NB * NB / PANEL_THREADS];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = load_coherent(xu + hh * NB * NB + tid + u * PANEL_THREADS);
+      for (int u = 0; u < NB * NB / PANEL_THREADS; ++u) v[u] = load_coherent(xu + hh * NB * NB + tid + u * PANEL_THREADS);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < NB * NB / PANEL_THREADS; ++u) {
         const int e = tid + u * PANEL_THREADS;
         dst[e & (NB - 1)][e / NB] = v[u];
       }
@@ -1899,21 +1972,26 @@ __device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, in
   }
   if (threadIdx.x < NB && (wg == 0 || all_t)) L.tau[threadIdx.x] = L.S4[threadIdx.x][threadIdx.x];
 
-  // ---- Y2 = -Q_w U^-1 below the pivot rows, into the Y rows and X
+  // ---- Y2 = -Q1 M below the pivot rows, into the Y rows and X
   phase();
-  for (int k = 0; k < RPW / 64; ++k) {
-    if (rw.above(k) || (wg == 0 && k == kc)) continue;  // workgroup-uniform
-    rw.in(L.S3, Yp, ldy, k, false);
-    __syncthreads();
-    frag_zero(f);
-    frag_mma<T, false>(f, L.S3, L.S2, fp);
-    frag_negate_plus_identity(f, fp, false);
-    __syncthreads();
-    frag_to_lds(f, L.S3, fp);
-    __syncthreads();
-    rw.out(L.S3, Yp, ldy, k);
-    rw.out(L.S3, Xp, ldx, k);
-    __syncthreads();
+  const int k1 = wg == 0 ? kc + 1 : kc;  // workgroup 0's chunk kc holds the pivot rows
+  if (k1 < CQR_CHUNKS) {
+    ChunkRegs<T> cur;
+    rw.load(cur, Yp, ldy, k1, false);
+    for (int k = k1; k < CQR_CHUNKS; ++k) {
+      rw.put(L.S1, cur);
+      __syncthreads();
+      if (k + 1 < CQR_CHUNKS) rw.load(cur, Yp, ldy, k + 1, false);
+      frag_zero(f);
+      frag_mma<T, false>(f, L.S1, L.S2, fp);
+      frag_negate_plus_identity(f, fp, false);
+      __syncthreads();
+      frag_to_lds(f, L.S1, fp);
+      __syncthreads();
+      rw.out(L.S1, Yp, ldy, k);
+      rw.out(L.S1, Xp, ldx, k);
+      __syncthreads();
+    }
   }
   return true;
 }
@@ -1921,7 +1999,7 @@ __device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, in
 // The block of columns [0, jb + jb2) (jb2 > 0: a second part of jb2 columns,
 // with the first part's reflectors applied to it in between and the joined T)
 // of rows [0, mp) at X: Householder vectors (explicit, into Y), T (into Tout,
-// ld ldt, from workgroup 0), tau; R in place in X.  P = ceil(mp / 256)
+// ld ldt, from workgroup 0), tau; R in place in X.  P = ceil(mp / CQR_RPW)
 // co-resident workgroups.  With wait_flag, the launch waits (bounded) for that
 // flag before reading its columns, which another stream updates.
 template <class T>
@@ -1946,7 +2024,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void cqr_panel_kernel(T* __restrict_
   const int P = gridDim.x, wg = blockIdx.x;
   int c = threadIdx.x & 63;
   const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t row0 = static_cast<int64_t>(wg) * RPW;
+  const int64_t row0 = static_cast<int64_t>(wg) * CQR_RPW;
   const bool two = jb2 > 0;
   FragPos fp{(g >> 1) * 16, (g & 1) * 32, c & 15, c >> 4};
   auto phase = [&]() {
@@ -2013,16 +2091,25 @@ __global__ __launch_bounds__(PANEL_THREADS) void cqr_panel_kernel(T* __restrict_
       // ---- the second part's columns C2 <- (I - Y1 T1^T Y1^T) C2: W = Y1^T C2 summed over the workgroups
       Frag<T> f;
       frag_zero(f);
-      for (int k = 0; k < RPW / 64; ++k) {
-        all.in(S1, Y, ldy, k, false);
-        rw2.in(S2, X2, ldx, k, waited);
-        __syncthreads();
-        frag_mma<T, true>(f, S1, S2, fp);
-        __syncthreads();
+      {
+        ChunkRegs<T> ya, ca;
+        all.load(ya, Y, ldy, 0, false);
+        rw2.load(ca, X2, ldx, 0, waited);
+        for (int k = 0; k < CQR_CHUNKS; ++k) {
+          all.put(S1, ya);
+          rw2.put(S2, ca);
+          __syncthreads();
+          if (k + 1 < CQR_CHUNKS) {
+            all.load(ya, Y, ldy, k + 1, false);
+            rw2.load(ca, X2, ldx, k + 1, waited);
+          }
+          frag_mma<T, true>(f, S1, S2, fp);
+          __syncthreads();
+        }
       }
       frag_to_lds(f, S3, fp);
       __syncthreads();
-      ok = allreduce64(S3, false, P, wg, xt, tagp + 5, err, pw);
+      ok = allreduce64(S3, P, wg, xt, tagp + 5, err, pw);
       if (!ok) break;
       phase();
       // W' = T1^T W (T1 in S4, every workgroup) into S2
@@ -2032,40 +2119,58 @@ __global__ __launch_bounds__(PANEL_THREADS) void cqr_panel_kernel(T* __restrict_
       frag_to_lds(f, S2, fp);
       __syncthreads();
       // C2 -= Y1 W', chunk by chunk, back into X
-      for (int k = 0; k < RPW / 64; ++k) {
-        all.in(S1, Y, ldy, k, false);
-        rw2.in(S3, X2, ldx, k, waited);
-        __syncthreads();
-        frag_from_lds(f, S3, fp);
-        Frag<T> g1;
-        frag_zero(g1);
-        frag_mma<T, false>(g1, S1, S2, fp);
+      {
+        ChunkRegs<T> ya, ca;
+        all.load(ya, Y, ldy, 0, false);
+        rw2.load(ca, X2, ldx, 0, waited);
+        for (int k = 0; k < CQR_CHUNKS; ++k) {
+          all.put(S1, ya);
+          rw2.put(S3, ca);
+          __syncthreads();
+          if (k + 1 < CQR_CHUNKS) {
+            all.load(ya, Y, ldy, k + 1, false);
+            rw2.load(ca, X2, ldx, k + 1, waited);
+          }
+          frag_from_lds(f, S3, fp);
+          Frag<T> g1;
+          frag_zero(g1);
+          frag_mma<T, false>(g1, S1, S2, fp);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          f.a0[v] -= g1.a0[v];
-          f.a1[v] -= g1.a1[v];
+          for (int v = 0; v < 4; ++v) {
+            f.a0[v] -= g1.a0[v];
+            f.a1[v] -= g1.a1[v];
+          }
+          __syncthreads();
+          frag_to_lds(f, S3, fp);
+          __syncthreads();
+          rw2.out(S3, X2, ldx, k);
+          __syncthreads();
         }
-        __syncthreads();
-        frag_to_lds(f, S3, fp);
-        __syncthreads();
-        rw2.out(S3, X2, ldx, k);
-        __syncthreads();
       }
     } else {
       // ---- T of the whole block: T12 = -T1 (Y1^T Y2) T2, S12 = Y1^T Y2 summed over the
       // workgroups (Y2 is zero above its part: rows from the part's first pivot row on)
       Frag<T> f;
       frag_zero(f);
-      for (int k = 0; k < RPW / 64; ++k) {
-        all.in(S1, Y, ldy, k, false);
-        rw.in(S2, Y2, ldy, k, false);
-        __syncthreads();
-        frag_mma<T, true>(f, S1, S2, fp);
-        __syncthreads();
+      {
+        ChunkRegs<T> ya, yb;
+        all.load(ya, Y, ldy, rw.kc, false);
+        rw.load(yb, Y2, ldy, rw.kc, false);
+        for (int k = rw.kc; k < CQR_CHUNKS; ++k) {
+          all.put(S1, ya);
+          rw.put(S2, yb);
+          __syncthreads();
+          if (k + 1 < CQR_CHUNKS) {
+            all.load(ya, Y, ldy, k + 1, false);
+            rw.load(yb, Y2, ldy, k + 1, false);
+          }
+          frag_mma<T, true>(f, S1, S2, fp);
+          __syncthreads();
+        }
       }
       frag_to_lds(f, S3, fp);
       __syncthreads();
-      ok = allreduce64(S3, false, P, wg, xt, tagp + 6, err, pw);
+      ok = allreduce64(S3, P, wg, xt, tagp + 6, err, pw);
       if (!ok) break;
       if (wg == 0) {
         phase();
@@ -2316,9 +2421,10 @@ struct QrSizes {
 };
 
 // Words of the exchange of the streaming panel: the units' R, U^-1 and T, the 64 x 64 sums, the flags.
-size_t tsqr_tri_words(int64_t m) { return static_cast<size_t>(2) * panel_wgs(m) * kTriEntries; }
+int cqr_wgs(int64_t m) { return static_cast<int>(ceil_div(m, CQR_RPW)); }
+size_t tsqr_tri_words(int64_t m) { return static_cast<size_t>(2) * cqr_wgs(m) * kTriEntries; }
 size_t tsqr_recon_words() { return static_cast<size_t>(2) * NB * NB; }
-size_t tsqr_gram_words(int64_t m) { return (static_cast<size_t>(panel_wgs(m)) + 1) * NB * NB; }
+size_t tsqr_gram_words(int64_t m) { return (static_cast<size_t>(cqr_wgs(m)) + 1) * NB * NB; }
 
 QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   QrSizes z;
@@ -2471,7 +2577,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     const int64_t mp = m - r0;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
     if (tsqr && join.Y1 == nullptr) {
-      cqr_panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
+      cqr_panel_kernel<T><<<static_cast<unsigned>(cqr_wgs(mp)), PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
                                                        w.tau + r0, Tp, NBO, panels * NB, err, zero_above, pwait,
                                                        jb2, wf, txch);
       URV_LAUNCHED("cqr_panel_kernel");
