@@ -127,6 +127,21 @@ int urv_dgemm(int32_t transA, int32_t transB, int64_t M, int64_t N, int64_t K,
               double beta, double* C, int64_t ldc, void* stream);
 
 /*
+ * urv_dgemm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, arithmetic and bitwise results, but the split-K partial
+ * sums live in a static 32 MiB device buffer that the library holds on every
+ * GPU it runs on until the process ends; this call allocates nothing.  Shapes
+ * whose partial sums would exceed 32 MiB return URV_EINVAL (message in
+ * urv_last_error) before any device work.  Every call on one GPU shares that
+ * buffer: calls that overlap on one GPU (different streams, or host threads,
+ * without ordering between them) race and give wrong results.
+ */
+int urv_dgemm_noalloc(int32_t transA, int32_t transB, int64_t M, int64_t N, int64_t K,
+                      double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                      double beta, double* C, int64_t ldc, void* stream);
+
+/*
  * Qpos: unpivoted blocked Householder QR of X (m x n, m >= n) with the
  * diagonal of R made non-negative (the Q-factors of Section 2.2 and eqs.
  * power / powerqr; the footnote on Haar matrices fixes the sign).  X is

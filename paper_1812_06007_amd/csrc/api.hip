@@ -421,6 +421,53 @@ int qr_entry(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, i
   if (e != hipSuccess && rc == URV_OK) rc = hip_status(e, "urv_qr_pos");
   return rc;
 }
+// Split-K scratch of urv_dgemm_noalloc: a file-scope device array, one copy on
+// every GPU the library runs on, held until the process ends.  Host code uses
+// the address hipGetSymbolAddress gives on each device (the array's name on
+// the host is a stand-in, not a device address).
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __attribute__((aligned(256))) double scratch[kStaticScratchBytes / sizeof(double)];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+double* scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up once per device.
+int static_scratch(double** out) {
+  int dev = 0;
+  URV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_last_error("urv_dgemm_noalloc: device index beyond the library's table");
+    return URV_ENOTSUP;
+  }
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    URV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = scratch_ptr[dev];
+  return URV_OK;
+}
+
+// Argument checks shared by urv_dgemm and urv_dgemm_noalloc.
+int dgemm_args(const char* who, int64_t M, int64_t N, int64_t K, int32_t transA, int32_t transB, double alpha,
+               const double* A, int64_t lda, const double* B, int64_t ldb, const double* C, int64_t ldc) {
+  if (M < 0 || N < 0 || K < 0) {
+    set_last_error(std::string(who) + ": negative size");
+    return URV_EINVAL;
+  }
+  const int64_t arows = transA ? K : M, brows = transB ? N : K;
+  if (lda < std::max<int64_t>(arows, 1) || ldb < std::max<int64_t>(brows, 1) ||
+      ldc < std::max<int64_t>(M, 1)) {
+    set_last_error(std::string(who) + ": leading dimension smaller than the row count");
+    return URV_EINVAL;
+  }
+  if (M > 0 && N > 0 && (!C || (K > 0 && alpha != 0.0 && (!A || !B)))) {
+    set_last_error(std::string(who) + ": null pointer");
+    return URV_EINVAL;
+  }
+  return URV_OK;
+}
 }  // namespace
 }  // namespace urv
 
@@ -476,21 +523,8 @@ int urv_dgemm(int32_t transA, int32_t transB, int64_t M, int64_t N, int64_t K, d
               const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
               int64_t ldc, void* stream) {
   clear_last_error();
-  if (M < 0 || N < 0 || K < 0) {
-    set_last_error("urv_dgemm: negative size");
-    return URV_EINVAL;
-  }
-  const int64_t arows = transA ? K : M, brows = transB ? N : K;
-  if (lda < std::max<int64_t>(arows, 1) || ldb < std::max<int64_t>(brows, 1) ||
-      ldc < std::max<int64_t>(M, 1)) {
-    set_last_error("urv_dgemm: leading dimension smaller than the row count");
-    return URV_EINVAL;
-  }
+  URV_TRY(dgemm_args("urv_dgemm", M, N, K, transA, transB, alpha, A, lda, B, ldb, C, ldc));
   if (M == 0 || N == 0) return URV_OK;
-  if (!C || (K > 0 && alpha != 0.0 && (!A || !B))) {
-    set_last_error("urv_dgemm: null pointer");
-    return URV_EINVAL;
-  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t we = dgemm_work_elems(M, N, K);
   double* work = nullptr;
@@ -501,6 +535,25 @@ int urv_dgemm(int32_t transA, int32_t transB, int64_t M, int64_t N, int64_t K, d
     if (e != hipSuccess && rc == URV_OK) rc = hip_status(e, "urv_dgemm");
   }
   return rc;
+}
+
+int urv_dgemm_noalloc(int32_t transA, int32_t transB, int64_t M, int64_t N, int64_t K, double alpha,
+                      const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                      int64_t ldc, void* stream) {
+  clear_last_error();
+  URV_TRY(dgemm_args("urv_dgemm_noalloc", M, N, K, transA, transB, alpha, A, lda, B, ldb, C, ldc));
+  if (M == 0 || N == 0) return URV_OK;
+  const size_t we = dgemm_work_elems(M, N, K);
+  if (we * sizeof(double) > kStaticScratchBytes) {
+    set_last_error("urv_dgemm_noalloc: this shape's split-K partial sums need " +
+                   std::to_string(we * sizeof(double)) + " bytes, more than the " +
+                   std::to_string(kStaticScratchBytes) + "-byte static scratch");
+    return URV_EINVAL;
+  }
+  double* work = nullptr;
+  if (we) URV_TRY(static_scratch(&work));
+  return dgemm(transA != 0, transB != 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work, we,
+               static_cast<hipStream_t>(stream));
 }
 
 int urv_qr_pos(double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq, double* R,

@@ -62,7 +62,7 @@ class UrvGradOpts(ctypes.Structure):
 TAPE_MODES = {"all": 0, "v": 1, "none": 2}
 
 EXPORTS = ["urv_opts_init", "urv_factor_ex", "urv_factor", "urv_workspace_size", "urv_gaussian",
-           "urv_dgemm", "urv_qr_pos", "urv_qr_pos_f32", "urv_metrics", "urv_strerror", "urv_last_error",
+           "urv_dgemm", "urv_dgemm_noalloc", "urv_qr_pos", "urv_qr_pos_f32", "urv_metrics", "urv_strerror", "urv_last_error",
            "urv_grad_opts_init", "urv_tape_bytes", "urv_grad_workspace_size", "urv_factor_tape",
            "urv_factor_backward", "urv_qr_adjoint", "urv_truncation_loss",
            "urv_batch_create", "urv_batch_set_buffers", "urv_batch_set_config", "urv_batch_get_config",
@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
     L.urv_workspace_size.restype = SZ
     L.urv_gaussian.argtypes = [P, I64, I64, I64, U64, U32, I32, P]
     L.urv_dgemm.argtypes = [I32, I32, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P]
+    L.urv_dgemm_noalloc.argtypes = [I32, I32, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P]
     L.urv_qr_pos.argtypes = [P, I64, I64, I64, P, I64, P, I64, P]
     L.urv_qr_pos_f32.argtypes = [P, I64, I64, I64, P, I64, P, I64, P]
     L.urv_metrics.argtypes = [P, I64, I64, P, P, P, P, P, P]
@@ -123,7 +124,7 @@ def lib() -> ctypes.CDLL:
     L.urv_max_rows.restype = I64
     L.urv_batch_destroy.argtypes = [P]
     L.urv_batch_destroy.restype = None
-    for name in ("urv_factor_ex", "urv_factor", "urv_gaussian", "urv_dgemm", "urv_qr_pos", "urv_qr_pos_f32",
+    for name in ("urv_factor_ex", "urv_factor", "urv_gaussian", "urv_dgemm", "urv_dgemm_noalloc", "urv_qr_pos", "urv_qr_pos_f32",
                  "urv_metrics", "urv_factor_tape", "urv_factor_backward", "urv_qr_adjoint",
                  "urv_truncation_loss", "urv_batch_create", "urv_batch_set_buffers", "urv_batch_set_config",
                  "urv_batch_get_config", "urv_batch_autotune", "urv_batch_run", "urv_batch_run_graph",
@@ -265,8 +266,10 @@ def gaussian(rows: int, cols: int, seed: int, stream_id: int = 2, dtype=None, de
     return G
 
 
-def dgemm(A, B, transA: bool = False, transB: bool = False, alpha: float = 1.0, beta: float = 0.0, C=None):
-    """C = alpha op(A) op(B) + beta C in FP64 (C column-major, written in place if given)."""
+def dgemm(A, B, transA: bool = False, transB: bool = False, alpha: float = 1.0, beta: float = 0.0, C=None,
+          noalloc: bool = False):
+    """C = alpha op(A) op(B) + beta C in FP64 (C column-major, written in place if given).
+    noalloc=True calls urv_dgemm_noalloc (split-K partials in the library's static buffer)."""
     A, lda = _colmajor(A)
     B, ldb = _colmajor(B)
     M = A.shape[1] if transA else A.shape[0]
@@ -280,8 +283,9 @@ def dgemm(A, B, transA: bool = False, transB: bool = False, alpha: float = 1.0, 
     elif C.stride(0) != 1 and C.shape[0] > 1:
         raise ValueError("C must be column-major")
     ldc = max(C.stride(1), M, 1) if N > 1 else max(M, 1)
-    _check(lib().urv_dgemm(int(transA), int(transB), M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta,
-                           _ptr(C), ldc, _stream_ptr()))
+    fn = lib().urv_dgemm_noalloc if noalloc else lib().urv_dgemm
+    _check(fn(int(transA), int(transB), M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta, _ptr(C), ldc,
+              _stream_ptr()))
     return C
 
 

@@ -228,3 +228,15 @@ def test_batch_calls_reject_a_null_plan():
     assert L.urv_batch_status(None, None) == urv.URV_EINVAL
     assert L.urv_batch_set_buffers(None, None, None, None, None) == urv.URV_EINVAL
     L.urv_batch_destroy(None)
+
+
+def test_dgemm_noalloc_rejects_shapes_beyond_its_static_scratch():
+    L = urv.lib()
+    # 256 x 256 output tiles (4) with a long sum: 64 splits of 256 x 256 doubles = 32 MiB fits;
+    # 255 tiles of 128 x 128 with K = 3 * 256 split 3 ways need 3 * 255 * 16384 doubles = 100 MiB
+    rc = L.urv_dgemm_noalloc(0, 0, 128 * 15, 128 * 17, 768, 1.0, FAKE, 128 * 15, FAKE, 768, 0.0, FAKE, 128 * 15, None)
+    assert rc == -1
+    assert b"static scratch" in L.urv_last_error()
+    # bad arguments are rejected as by urv_dgemm
+    assert L.urv_dgemm_noalloc(0, 0, -1, 4, 4, 1.0, FAKE, 4, FAKE, 4, 0.0, FAKE, 4, None) == -1
+    assert L.urv_dgemm_noalloc(0, 0, 8, 4, 4, 1.0, FAKE, 7, FAKE, 4, 0.0, FAKE, 8, None) == -1
