@@ -16,7 +16,11 @@
  * checks run on the host before any device work, so a call that returns
  * URV_EINVAL has written nothing.  HIP failures return URV_EDEVICE; the text
  * of the last failure on the calling thread is in urv_last_error().
- * Non-finite inputs propagate (NaN in, NaN out).
+ * Non-finite inputs propagate (NaN in, NaN out) unless urv_factor_ex is asked
+ * to check them (URV_CHECK_FINITE).  The QR's panels wait on each other on the
+ * device with a bounded spin; an expired wait poisons the outputs with NaN and
+ * raises a per-device status word, which the blocking urv_factor reports and
+ * asynchronous callers read with urv_sync_status.
  */
 #ifndef URV_H
 #define URV_H
@@ -33,7 +37,8 @@ typedef enum {
   URV_EINVAL = -1,   /* bad argument: null pointer, size, leading dimension, enum, workspace */
   URV_ENOMEM = -2,   /* device allocation failed */
   URV_EDEVICE = -3,  /* HIP runtime error, or a device-side bounded wait expired */
-  URV_ENOTSUP = -4   /* valid but unsupported combination */
+  URV_ENOTSUP = -4,  /* valid but unsupported combination */
+  URV_ENONFINITE = -5 /* URV_CHECK_FINITE found a NaN or an infinity in A (nothing written) */
 } urv_status;
 
 /* When the power iteration re-orthonormalises (Section 3, paragraph after
@@ -44,8 +49,13 @@ typedef enum {
   URV_REORTH_NONE = 2  /* (A^T A)^q G then a single Qpos; only for small q and mild spectra */
 } urv_variant;
 
-/* Arithmetic of the factorisation.  A, U, R, V are FP64 in every mode of
- * urv_factor_ex; URV_FP32 is taken only by the derivative entry points below. */
+/* Arithmetic of the factorisation.  U, R, V are FP64 in every mode of
+ * urv_factor_ex (A is FP64, or FP32 with URV_A_FP32).  URV_FP32 is taken only
+ * by the derivative entry points below: urv_factor_ex returns URV_EINVAL for
+ * it, since its outputs are FP64 buffers and an all-FP32 factorisation would
+ * leave A = U R V^T at about 1e-6 -- the mixed modes already run the power
+ * iteration in 16/32 bits and keep the FP64 tail that makes the result exact
+ * to FP64 rounding. */
 typedef enum {
   URV_FP64 = 0,       /* everything in FP64 */
   URV_FP32 = 1,       /* everything in FP32 (derivative entry points only) */
@@ -55,11 +65,16 @@ typedef enum {
   URV_MIXED_FP16 = 3  /* as above with FP16 operands */
 } urv_precision;
 
+/* Bits of urv_opts.flags. */
+#define URV_CHECK_FINITE 1 /* scan A first; NaN or infinity -> URV_ENONFINITE (the call then waits for the scan) */
+#define URV_A_FP32 2       /* A points to FP32 values (the 16-bit casts of the mixed modes read them directly;
+                              the FP64 steps use their exact FP64 value) */
+
 typedef struct {
   int32_t variant;    /* urv_variant */
   int32_t precision;  /* urv_precision */
   int32_t orth_g;     /* nonzero: start the power iteration from Qpos(G) instead of G */
-  int32_t reserved;   /* must be 0 */
+  int32_t flags;      /* URV_CHECK_FINITE | URV_A_FP32; other bits must be 0 */
   int64_t lda, ldu, ldr, ldv; /* leading dimensions; 0 selects the packed value (m, m, p, n), p = min(m, n) */
   const double* G;    /* optional p x p starting matrix (device); NULL draws it from seed */
   int64_t ldg;        /* leading dimension of G; 0 = p */
@@ -73,8 +88,8 @@ typedef struct {
 void urv_opts_init(urv_opts* opts);
 
 /*
- * PowerURV (Section 3, eqs. power and powerqr).  A is m x n (read only);
- * p = min(m, n).  A Gaussian p x p G (eq. power) is drawn from seed (see
+ * PowerURV (Section 3, eqs. power and powerqr).  A is m x n (read only;
+ * FP64, or FP32 with URV_A_FP32 in opts->flags); p = min(m, n).  A Gaussian p x p G (eq. power) is drawn from seed (see
  * urv_gaussian, stream id 2) unless opts->G is given.  Then q >= 0 power
  * steps are taken on V (V starts as G, or Qpos(G) when q == 0 -- the DDH-URV
  * case of Section 2.2 -- or when orth_g is set), and the final step factors
@@ -88,10 +103,22 @@ void urv_opts_init(urv_opts* opts);
  * min(m, n) == 0 is a no-op returning URV_OK.  q < 0, ld < rows (ldr < p,
  * ldv < n, ldg < p), unknown enums, null pointers or a too-small workspace
  * give URV_EINVAL; max(m, n) beyond the panel kernel's rows, URV_ENOTSUP.
- * Asynchronous on opts->stream.
+ * With URV_CHECK_FINITE, a NaN or infinity in A gives URV_ENONFINITE and no
+ * output is written.  Asynchronous on opts->stream (except for that scan);
+ * an expired device-side wait is reported by urv_sync_status.  In the FP16
+ * mode each 16-bit operand is scaled by a power of two from its largest
+ * magnitude before the cast (exact, and Qpos is unchanged by it), so entries
+ * beyond FP16's range do not overflow.
  */
-int urv_factor_ex(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
+int urv_factor_ex(const void* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
                   double* U, double* R, double* V, const urv_opts* opts);
+
+/* Waits for the stream, then reports whether any factorisation or QR queued
+ * on the current device since the last report had a panel's bounded
+ * device-side wait expire (URV_EDEVICE, outputs of that call NaN) or not
+ * (URV_OK), and clears that state.  The state is per device, shared by every
+ * stream and thread.  Allocates nothing. */
+int urv_sync_status(void* stream);
 
 /* urv_factor_ex with default options (FULL, FP64, packed, default stream);
  * returns after the device work has finished. */

@@ -32,6 +32,7 @@ struct MixedWork {
   float* X32 = nullptr;  // m x n
   float* W32 = nullptr;  // m x n
   float* Y32 = nullptr;  // n x n
+  unsigned* amax = nullptr;  // max |x| words of the FP16 casts (A, V, right-hand side)
   QrWorkT<float> qr;
 };
 
@@ -69,6 +70,7 @@ void carve_factor(Arena& a, int64_t m, int64_t n, bool mixed, FactorWork& w) {
   x.X32 = a.take<float>(static_cast<size_t>(m) * n);
   x.W32 = a.take<float>(static_cast<size_t>(m) * n);
   x.Y32 = a.take<float>(static_cast<size_t>(n) * n);
+  x.amax = a.take<unsigned>(4);
   qr_work_carve(a, m, n, x.qr);
 }
 
@@ -106,19 +108,116 @@ void carve_wide(Arena& a, int64_t m, int64_t n, WideWork& x) {
   x.gw = a.take<double>(x.gw_elems);
 }
 
+// The parts of the workspace beyond the factorisation's own: the FP64 copy of
+// an FP32 A, and the word of the finiteness scan.
+struct ExtraWork {
+  double* A64 = nullptr;       // m x n (ld m), with URV_A_FP32
+  unsigned* nonfinite = nullptr;
+};
+
+void carve_extra(Arena& a, int64_t m, int64_t n, bool a32, ExtraWork& e) {
+  if (a32) e.A64 = a.take<double>(static_cast<size_t>(m) * n);
+  e.nonfinite = a.take<unsigned>(1);
+}
+
 // Workspace of urv_factor_ex for any shape.
-size_t work_bytes(int64_t m, int64_t n, bool mixed) {
-  if (m >= n) return factor_bytes(m, n, mixed);
+size_t work_bytes(int64_t m, int64_t n, bool mixed, bool a32) {
   Arena a;
   FactorWork w;
-  carve_factor(a, n, m, mixed, w);
-  WideWork x;
-  carve_wide(a, m, n, x);
+  if (m >= n) {
+    carve_factor(a, m, n, mixed, w);
+  } else {
+    carve_factor(a, n, m, mixed, w);
+    WideWork x;
+    carve_wide(a, m, n, x);
+  }
+  ExtraWork e;
+  carve_extra(a, m, n, a32, e);
   return a.used;
 }
 
+// *flag = 1 if src (rows x cols) holds a NaN or an infinity.  *flag must be 0 before.
+template <class S>
+__global__ __launch_bounds__(256) void nonfinite_kernel(const S* __restrict__ src, int64_t lds, int64_t rows,
+                                                        int64_t cols, unsigned* __restrict__ flag) {
+  int bad = 0;
+  const int64_t total = rows * cols;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const S v = src[idx % rows + (idx / rows) * lds];
+    bad |= !(v - v == v - v) ? 1 : 0;  // inf - inf and NaN - NaN are NaN
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 1u);
+}
 
-int validate_factor(const double* A, int64_t m, int64_t n, int32_t q, const double* U,
+__global__ void set_u32_kernel(unsigned* p, unsigned v) { *p = v; }
+
+// Folds the error flags of a factorisation or QR into the device's status word.
+__global__ void fold_status_kernel(unsigned* status, const unsigned* f1, const unsigned* f2) {
+  if ((f1 && *f1) || (f2 && *f2)) atomicOr(status, 1u);
+}
+
+// Per-device statics: the split-K scratch of urv_dgemm_noalloc and the status word
+// that urv_sync_status reads (file-scope device arrays, one copy on every GPU the
+// library runs on; host code uses the addresses hipGetSymbolAddress gives).
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __attribute__((aligned(256))) double scratch[kStaticScratchBytes / sizeof(double)];
+static __device__ __attribute__((aligned(256))) unsigned status_word[64];
+constexpr int kMaxDevices = 64;
+struct DeviceStatics {
+  double* scratch = nullptr;
+  unsigned* status = nullptr;
+};
+std::mutex statics_mu;
+DeviceStatics statics[kMaxDevices];
+
+// The current device's statics, looked up once per device.
+int device_statics(DeviceStatics* out) {
+  int dev = 0;
+  URV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_last_error("liburv: device index beyond the library's table");
+    return URV_ENOTSUP;
+  }
+  std::lock_guard<std::mutex> lock(statics_mu);
+  DeviceStatics& d = statics[dev];
+  if (!d.scratch) {
+    void* p = nullptr;
+    void* q = nullptr;
+    URV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    URV_HIP(hipGetSymbolAddress(&q, HIP_SYMBOL(status_word)));
+    d.scratch = static_cast<double*>(p);
+    d.status = static_cast<unsigned*>(q);
+  }
+  *out = d;
+  return URV_OK;
+}
+
+// Queues the fold of up to two error flags into the device's status word.
+int fold_status(const unsigned* f1, const unsigned* f2, hipStream_t s) {
+  DeviceStatics d;
+  URV_TRY(device_statics(&d));
+  fold_status_kernel<<<1, 1, 0, s>>>(d.status, f1, f2);
+  URV_LAUNCHED("fold_status_kernel");
+  return URV_OK;
+}
+
+// Waits for s, then reads and clears the device's status word.
+int sync_status(hipStream_t s, const char* who) {
+  DeviceStatics d;
+  URV_TRY(device_statics(&d));
+  URV_HIP(hipStreamSynchronize(s));
+  unsigned v = 0;
+  URV_HIP(hipMemcpy(&v, d.status, sizeof(v), hipMemcpyDeviceToHost));
+  if (v == 0) return URV_OK;
+  const unsigned zero = 0;
+  URV_HIP(hipMemcpy(d.status, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  set_last_error(std::string(who) + ": a panel's device-wide wait expired");
+  return URV_EDEVICE;
+}
+
+
+int validate_factor(const void* A, int64_t m, int64_t n, int32_t q, const double* U,
                     const double* R, const double* V, const urv_opts& o) {
   if (n < 0 || m < 0 || q < 0) {
     set_last_error("urv_factor: need m, n >= 0 and q >= 0");
@@ -132,8 +231,8 @@ int validate_factor(const double* A, int64_t m, int64_t n, int32_t q, const doub
     set_last_error("urv_factor: unknown precision");
     return URV_EINVAL;
   }
-  if (o.reserved != 0) {
-    set_last_error("urv_factor: reserved field must be 0");
+  if ((o.flags & ~(URV_CHECK_FINITE | URV_A_FP32)) != 0) {
+    set_last_error("urv_factor: unknown bits in flags");
     return URV_EINVAL;
   }
   const int64_t p = std::min(m, n);
@@ -153,7 +252,8 @@ int validate_factor(const double* A, int64_t m, int64_t n, int32_t q, const doub
     set_last_error("urv_factor: workspace_bytes given without a workspace");
     return URV_EINVAL;
   }
-  if (o.workspace != nullptr && o.workspace_bytes < work_bytes(m, n, o.precision != URV_FP64 && q > 0)) {
+  if (o.workspace != nullptr &&
+      o.workspace_bytes < work_bytes(m, n, o.precision != URV_FP64 && q > 0, (o.flags & URV_A_FP32) != 0)) {
     set_last_error("urv_factor: workspace too small (see urv_workspace_size)");
     return URV_EINVAL;
   }
@@ -244,17 +344,31 @@ int run_factor(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, 
 }
 
 // The power iteration in 16-bit products / FP32 QRs, then the FP64 tail.
-int run_factor_mixed(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, double* U,
-                     double* R, double* V, const urv_opts& o, const FactorWork& w, hipStream_t s) {
-  const int64_t lda = o.lda ? o.lda : m, ldu = o.ldu ? o.ldu : m;
+// A (FP64, ld lda) feeds the FP64 tail; the 16-bit casts read A32 (FP32, ld lda32)
+// when the caller's matrix is FP32, else A.  FP16 casts scale their source by a
+// power of two from its largest magnitude (FP16 overflows at 65504); BF16 has
+// FP32's range and casts unscaled.
+int run_factor_mixed(const double* A, int64_t lda, const float* A32, int64_t lda32, int64_t m, int64_t n,
+                     int32_t q, uint64_t seed, double* U, double* R, double* V, const urv_opts& o,
+                     const FactorWork& w, hipStream_t s) {
+  const int64_t ldu = o.ldu ? o.ldu : m;
   const int64_t ldr = o.ldr ? o.ldr : n, ldv = o.ldv ? o.ldv : n, ldg = o.ldg ? o.ldg : n;
   const bool full = o.variant == URV_REORTH_FULL, none = o.variant == URV_REORTH_NONE;
   const bool bf16 = o.precision == URV_MIXED_BF16;
   const MixedWork& x = w.mx;
   const int64_t ldv16 = lowp_ld(n);
+  unsigned* const amaxA = bf16 ? nullptr : x.amax;
+  unsigned* const amaxB = bf16 ? nullptr : x.amax + 1;
 
-  URV_TRY(to_lowp<double>(bf16, A, lda, m, n, x.A16, x.lda16, s));           // A^T W operand
-  URV_TRY(to_lowp_transposed(bf16, A, lda, m, n, x.At16, x.ldat16, s));      // A V operand
+  if (A32) {
+    if (amaxA) URV_TRY(absmax<float>(A32, lda32, m, n, amaxA, s));
+    URV_TRY(to_lowp<float>(bf16, A32, lda32, m, n, x.A16, x.lda16, s, amaxA));            // A^T W operand
+    URV_TRY(to_lowp_transposed<float>(bf16, A32, lda32, m, n, x.At16, x.ldat16, s, amaxA)); // A V operand
+  } else {
+    if (amaxA) URV_TRY(absmax<double>(A, lda, m, n, amaxA, s));
+    URV_TRY(to_lowp<double>(bf16, A, lda, m, n, x.A16, x.lda16, s, amaxA));
+    URV_TRY(to_lowp_transposed<double>(bf16, A, lda, m, n, x.At16, x.ldat16, s, amaxA));
+  }
   if (o.G)
     URV_TRY((convert<double, float>(o.G, ldg, n, n, x.V32, n, s)));
   else
@@ -264,14 +378,16 @@ int run_factor_mixed(const double* A, int64_t m, int64_t n, int32_t q, uint64_t 
     URV_TRY(qr_pos<float>(x.Y32, n, n, n, x.V32, n, nullptr, 0, x.qr, s));
   }
   for (int32_t t = 0; t < q; ++t) {
-    URV_TRY(to_lowp<float>(bf16, x.V32, n, n, n, x.B16, ldv16, s));
+    if (amaxB) URV_TRY(absmax<float>(x.V32, n, n, n, amaxB, s));
+    URV_TRY(to_lowp<float>(bf16, x.V32, n, n, n, x.B16, ldv16, s, amaxB));
     URV_TRY(gemm_lowp(bf16, m, n, n, 1.f, x.At16, x.ldat16, x.B16, ldv16, 0.f, x.X32, m, s));  // X = A V
     const float* rhs = x.X32;
     if (full) {
       URV_TRY(qr_pos<float>(x.X32, m, n, m, x.W32, m, nullptr, 0, x.qr, s));               // W = Qpos(X)
       rhs = x.W32;
     }
-    URV_TRY(to_lowp<float>(bf16, rhs, m, m, n, x.B16, x.lda16, s));
+    if (amaxB) URV_TRY(absmax<float>(rhs, m, m, n, amaxB, s));
+    URV_TRY(to_lowp<float>(bf16, rhs, m, m, n, x.B16, x.lda16, s, amaxB));
     float* out = none ? x.V32 : x.Y32;
     URV_TRY(gemm_lowp(bf16, n, n, m, 1.f, x.A16, x.lda16, x.B16, x.lda16, 0.f, out, n, s));   // A^T W
     if (!none) URV_TRY(qr_pos<float>(x.Y32, n, n, n, x.V32, n, nullptr, 0, x.qr, s));        // V = Qpos
@@ -301,7 +417,7 @@ int run_wide(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, do
   ob.ldu = n;
   ob.ldr = m;
   ob.ldv = ldu;
-  URV_TRY(mixed ? run_factor_mixed(x.B, n, m, q, seed, x.Ut, x.Rt, U, ob, w, s)
+  URV_TRY(mixed ? run_factor_mixed(x.B, n, nullptr, 0, n, m, q, seed, x.Ut, x.Rt, U, ob, w, s)
                 : run_factor(x.B, n, m, q, seed, x.Ut, x.Rt, U, ob, w, s));  // U = V_B
   URV_TRY(reverse_cols(x.Rt, m, m, m, x.RJ, m, s));
   URV_TRY(qr_pos<double>(x.RJ, m, m, m, x.Q2, m, x.R2, m, w.qr, s));     // Rt J = Q2 R2
@@ -310,18 +426,20 @@ int run_wide(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, do
   return transpose_reverse(x.R2, m, m, R, ldr, s);                           // R = J R2^T J
 }
 
-// Runs the factorisation; when check_flag, waits for the stream and reports a
-// panel wait that expired on the device.
-int factor_impl(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, double* U,
-                double* R, double* V, const urv_opts& o, bool check_flag) {
+// Runs the factorisation, then folds the panels' error flags into the device's
+// status word; when blocking, waits for the stream and reports (and clears) it.
+int factor_impl(const void* A, int64_t m, int64_t n, int32_t q, uint64_t seed, double* U, double* R, double* V,
+                const urv_opts& o, bool blocking) {
   clear_last_error();
   URV_TRY(validate_factor(A, m, n, q, U, R, V, o));
   if (std::min(m, n) == 0) return URV_OK;
   hipStream_t s = static_cast<hipStream_t>(o.stream);
   const bool mixed = o.precision != URV_FP64 && q > 0;
+  const bool a32 = (o.flags & URV_A_FP32) != 0;
   const bool wide = m < n;
   const int64_t mt = wide ? n : m, nt = wide ? m : n;  // the tall problem
-  const size_t need = work_bytes(m, n, mixed);
+  const int64_t lda = o.lda ? o.lda : m;
+  const size_t need = work_bytes(m, n, mixed, a32);
   Arena a;
   bool owned = false;
   if (o.workspace) {
@@ -343,30 +461,51 @@ int factor_impl(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
   carve_factor(a, mt, nt, mixed, w);
   WideWork x;
   if (wide) carve_wide(a, m, n, x);
-  int rc = a.overflow ? URV_EINVAL : qr_clear_error_flag(w.qr, nt, s);
+  ExtraWork ex;
+  carve_extra(a, m, n, a32, ex);
+  int rc = a.overflow ? URV_EINVAL : URV_OK;
+  if (rc == URV_OK && (o.flags & URV_CHECK_FINITE)) {
+    // scan A before any other work; the answer needs the host
+    set_u32_kernel<<<1, 1, 0, s>>>(ex.nonfinite, 0u);
+    rc = hip_status(hipGetLastError(), "set_u32_kernel");
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(ceil_div(m * n, 256), 2048));
+    if (rc == URV_OK) {
+      if (a32)
+        nonfinite_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float*>(A), lda, m, n, ex.nonfinite);
+      else
+        nonfinite_kernel<double><<<blocks, 256, 0, s>>>(static_cast<const double*>(A), lda, m, n, ex.nonfinite);
+      rc = hip_status(hipGetLastError(), "nonfinite_kernel");
+    }
+    unsigned bad = 0;
+    if (rc == URV_OK) rc = hip_status(hipMemcpyAsync(&bad, ex.nonfinite, sizeof(bad), hipMemcpyDeviceToHost, s),
+                                      "urv_factor: finiteness scan");
+    if (rc == URV_OK) rc = hip_status(hipStreamSynchronize(s), "urv_factor: finiteness scan");
+    if (rc == URV_OK && bad) {
+      set_last_error("urv_factor: A holds a NaN or an infinity");
+      rc = URV_ENONFINITE;
+    }
+  }
+  // an FP32 A: its FP64 value for every FP64 step (exact)
+  const double* A64 = static_cast<const double*>(A);
+  urv_opts o64 = o;
+  if (rc == URV_OK && a32) {
+    rc = convert<float, double>(static_cast<const float*>(A), lda, m, n, ex.A64, m, s);
+    A64 = ex.A64;
+    o64.lda = m;
+  }
+  if (rc == URV_OK) rc = qr_clear_error_flag(w.qr, nt, s);
   if (rc == URV_OK && mixed) rc = qr_clear_error_flag(w.mx.qr, nt, s);
   if (rc == URV_OK) {
     if (wide)
-      rc = run_wide(A, m, n, q, seed, U, R, V, o, w, x, mixed, s);
+      rc = run_wide(A64, m, n, q, seed, U, R, V, o64, w, x, mixed, s);
+    else if (mixed)
+      rc = run_factor_mixed(A64, o64.lda ? o64.lda : m, a32 ? static_cast<const float*>(A) : nullptr, lda, m, n, q,
+                            seed, U, R, V, o64, w, s);
     else
-      rc = mixed ? run_factor_mixed(A, m, n, q, seed, U, R, V, o, w, s)
-                 : run_factor(A, m, n, q, seed, U, R, V, o, w, s);
+      rc = run_factor(A64, m, n, q, seed, U, R, V, o64, w, s);
   }
-  if (rc == URV_OK && check_flag) {
-    unsigned flag = 0;
-    unsigned flag32 = 0;
-    if (hipMemcpyAsync(&flag, qr_error_flag(w.qr, nt), sizeof(flag), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        (mixed && hipMemcpyAsync(&flag32, qr_error_flag(w.mx.qr, nt), sizeof(flag32),
-                                 hipMemcpyDeviceToHost, s) != hipSuccess) ||
-        hipStreamSynchronize(s) != hipSuccess) {
-      rc = hip_status(hipGetLastError(), "urv_factor: synchronize");
-      if (rc == URV_OK) rc = URV_EDEVICE;
-    } else if (flag != 0 || flag32 != 0) {
-      set_last_error("urv_factor: a panel's device-wide wait expired");
-      rc = URV_EDEVICE;
-    }
-  }
+  if (rc == URV_OK) rc = fold_status(qr_error_flag(w.qr, nt), mixed ? qr_error_flag(w.mx.qr, nt) : nullptr, s);
+  if (rc == URV_OK && blocking) rc = sync_status(s, "urv_factor");
   if (owned) {
     const hipError_t e = hipFreeAsync(a.base, s);
     if (e != hipSuccess && rc == URV_OK) rc = hip_status(e, "urv_factor");
@@ -417,38 +556,11 @@ int qr_entry(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, i
   qr_work_carve(a, m, n, w);
   int rc = qr_clear_error_flag(w, n, s);
   if (rc == URV_OK) rc = qr_pos<T>(X, m, n, ldx, Q, ldq, R, ldr, w, s);
+  if (rc == URV_OK) rc = fold_status(qr_error_flag(w, n), nullptr, s);
   const hipError_t e = hipFreeAsync(p, s);
   if (e != hipSuccess && rc == URV_OK) rc = hip_status(e, "urv_qr_pos");
   return rc;
 }
-// Split-K scratch of urv_dgemm_noalloc: a file-scope device array, one copy on
-// every GPU the library runs on, held until the process ends.  Host code uses
-// the address hipGetSymbolAddress gives on each device (the array's name on
-// the host is a stand-in, not a device address).
-constexpr size_t kStaticScratchBytes = size_t(32) << 20;
-static __device__ __attribute__((aligned(256))) double scratch[kStaticScratchBytes / sizeof(double)];
-constexpr int kMaxDevices = 64;
-std::mutex scratch_mu;
-double* scratch_ptr[kMaxDevices] = {};
-
-// The current device's copy of `scratch`, looked up once per device.
-int static_scratch(double** out) {
-  int dev = 0;
-  URV_HIP(hipGetDevice(&dev));
-  if (dev < 0 || dev >= kMaxDevices) {
-    set_last_error("urv_dgemm_noalloc: device index beyond the library's table");
-    return URV_ENOTSUP;
-  }
-  std::lock_guard<std::mutex> lock(scratch_mu);
-  if (!scratch_ptr[dev]) {
-    void* p = nullptr;
-    URV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
-    scratch_ptr[dev] = static_cast<double*>(p);
-  }
-  *out = scratch_ptr[dev];
-  return URV_OK;
-}
-
 // Argument checks shared by urv_dgemm and urv_dgemm_noalloc.
 int dgemm_args(const char* who, int64_t M, int64_t N, int64_t K, int32_t transA, int32_t transB, double alpha,
                const double* A, int64_t lda, const double* B, int64_t ldb, const double* C, int64_t ldc) {
@@ -482,7 +594,7 @@ void urv_opts_init(urv_opts* o) {
   o->precision = URV_FP64;
 }
 
-int urv_factor_ex(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, double* U,
+int urv_factor_ex(const void* A, int64_t m, int64_t n, int32_t q, uint64_t seed, double* U,
                   double* R, double* V, const urv_opts* opts) {
   urv_opts o;
   urv_opts_init(&o);
@@ -500,7 +612,12 @@ int urv_factor(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, 
 size_t urv_workspace_size(int64_t m, int64_t n, int32_t q, const urv_opts* opts) {
   if (m <= 0 || n <= 0 || q < 0) return 0;
   const bool mixed = opts && opts->precision != URV_FP64 && q > 0;
-  return work_bytes(m, n, mixed);
+  return work_bytes(m, n, mixed, opts && (opts->flags & URV_A_FP32) != 0);
+}
+
+int urv_sync_status(void* stream) {
+  clear_last_error();
+  return sync_status(static_cast<hipStream_t>(stream), "urv_sync_status");
 }
 
 int urv_gaussian(void* G, int64_t rows, int64_t cols, int64_t ld, uint64_t seed,
@@ -551,7 +668,11 @@ int urv_dgemm_noalloc(int32_t transA, int32_t transB, int64_t M, int64_t N, int6
     return URV_EINVAL;
   }
   double* work = nullptr;
-  if (we) URV_TRY(static_scratch(&work));
+  if (we) {
+    DeviceStatics d;
+    URV_TRY(device_statics(&d));
+    work = d.scratch;
+  }
   return dgemm(transA != 0, transB != 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work, we,
                static_cast<hipStream_t>(stream));
 }
@@ -585,6 +706,7 @@ const char* urv_strerror(int code) {
     case URV_ENOMEM: return "device memory allocation failed";
     case URV_EDEVICE: return "device (HIP) error";
     case URV_ENOTSUP: return "unsupported argument combination";
+    case URV_ENONFINITE: return "non-finite input";
     default: return "unknown status";
   }
 }

@@ -216,13 +216,19 @@ int64_t lowp_ld(int64_t rows);
 // B (K x N), column-major, leading dimensions multiples of 32 with zero padding below K.
 int gemm_lowp(bool bf16, int64_t M, int64_t N, int64_t K, float alpha, const void* A, int64_t lda,
               const void* B, int64_t ldb, float beta, float* C, int64_t ldc, hipStream_t s);
-// dst (ldd x cols, 16-bit, RNE) = src (rows x cols), zero in rows [rows, ldd).
+// dst (ldd x cols, 16-bit, RNE) = c src (rows x cols), zero in rows [rows, ldd).  c = 1
+// without amax; with amax (device word from absmax), the power of two that brings
+// max |src| into [2^13, 2^14) (exact; Qpos is unchanged by positive scaling).
 template <class S>
 int to_lowp(bool bf16, const S* src, int64_t lds, int64_t rows, int64_t cols, void* dst, int64_t ldd,
-            hipStream_t s);
-// dst (ldd x rows, 16-bit) = src^T for src rows x cols (FP64), zero in rows [cols, ldd).
-int to_lowp_transposed(bool bf16, const double* src, int64_t lds, int64_t rows, int64_t cols,
-                       void* dst, int64_t ldd, hipStream_t s);
+            hipStream_t s, const unsigned* amax = nullptr);
+// dst (ldd x rows, 16-bit) = c src^T for src rows x cols, zero in rows [cols, ldd).
+template <class S>
+int to_lowp_transposed(bool bf16, const S* src, int64_t lds, int64_t rows, int64_t cols, void* dst, int64_t ldd,
+                       hipStream_t s, const unsigned* amax = nullptr);
+// *amax (device) = bits of max |src| as FP32.
+template <class S>
+int absmax(const S* src, int64_t lds, int64_t rows, int64_t cols, unsigned* amax, hipStream_t s);
 template <class S, class D>
 int convert(const S* src, int64_t lds, int64_t rows, int64_t cols, D* dst, int64_t ldd, hipStream_t s);
 int copy_matrix_f32(const float* src, int64_t lds, float* dst, int64_t ldd, int64_t rows, int64_t cols,

@@ -140,34 +140,52 @@ __global__ __launch_bounds__(256) void gemm_lowp_kernel(int64_t M, int64_t N, in
 }
 
 // dst (rows_pad x cols, ld ldd) = 16-bit RNE rounding of src (rows x cols), zero in rows >= rows.
+// The power of two by which a cast scales its source: with amax (the bits of
+// max |x| over the source, from absmax_kernel) set, 2^(14 - e) for max |x| in
+// [2^(e-1), 2^e), so the largest magnitude lands in [2^13, 2^14) and FP16's
+// range (65504) leaves room; 1 when amax is null, zero or not finite.
+// Scaling by a power of two is exact, and Qpos(c X) = Qpos(X) for c > 0, so no
+// scale is ever undone.
+__device__ inline float cast_scale(const unsigned* amax) {
+  if (amax == nullptr) return 1.f;
+  const float mx = __uint_as_float(*amax);
+  if (!(mx > 0.f) || !(mx <= 3.4e38f)) return 1.f;
+  int e = 0;
+  (void)frexpf(mx, &e);
+  return ldexpf(1.f, 14 - e);
+}
+
+// dst (ldd x cols, 16-bit, RNE) = scale * src (rows x cols), zero in rows [rows, ldd).
 template <bool BF16, class S>
 __global__ void to_lowp_kernel(const S* __restrict__ src, int64_t lds, int64_t rows, int64_t cols,
-                               void* __restrict__ dstv, int64_t ldd) {
+                               void* __restrict__ dstv, int64_t ldd, const unsigned* __restrict__ amax) {
   using E = typename Lowp<BF16>::elem;
   E* dst = static_cast<E*>(dstv);
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx >= ldd * cols) return;
+  const float sc = cast_scale(amax);
   const int64_t i = idx % ldd, j = idx / ldd;
-  const float v = (i < rows) ? static_cast<float>(src[i + j * lds]) : 0.f;
+  const float v = (i < rows) ? static_cast<float>(src[i + j * lds]) * sc : 0.f;
   dst[i + j * ldd] = static_cast<E>(v);
 }
 
-// dst = 16-bit rounding of src^T: src rows x cols (ld lds), dst cols x rows (ld ldd, padded
+// dst = 16-bit rounding of scale * src^T: src rows x cols (ld lds), dst cols x rows (ld ldd, padded
 // with zeros in rows >= cols), through 32 x 32 LDS tiles so both sides are coalesced.
-template <bool BF16>
-__global__ __launch_bounds__(256) void to_lowp_transposed_kernel(const double* __restrict__ src,
+template <bool BF16, class S>
+__global__ __launch_bounds__(256) void to_lowp_transposed_kernel(const S* __restrict__ src,
                                                                   int64_t lds, int64_t rows,
                                                                   int64_t cols, void* __restrict__ dstv,
-                                                                  int64_t ldd) {
+                                                                  int64_t ldd, const unsigned* __restrict__ amax) {
   using E = typename Lowp<BF16>::elem;
   E* dst = static_cast<E*>(dstv);
   __shared__ float tile[32][33];
+  const float sc = cast_scale(amax);
   const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 32;  // src row block
   const int64_t j0 = static_cast<int64_t>(blockIdx.y) * 32;  // src column block
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;    // 32 x 8
   for (int y = ty; y < 32; y += 8) {
     const int64_t i = i0 + tx, j = j0 + y;
-    tile[y][tx] = (i < rows && j < cols) ? static_cast<float>(src[i + j * lds]) : 0.f;
+    tile[y][tx] = (i < rows && j < cols) ? static_cast<float>(src[i + j * lds]) * sc : 0.f;
   }
   __syncthreads();
   for (int y = ty; y < 32; y += 8) {
@@ -175,6 +193,32 @@ __global__ __launch_bounds__(256) void to_lowp_transposed_kernel(const double* _
     if (di < ldd && dj < rows) dst[di + dj * ldd] = static_cast<E>(tile[tx][y]);
   }
 }
+
+// *amax = the bits of max |x| over src (rows x cols), as an FP32 value (NaN wins):
+// non-negative floats order like their bits, so an integer maximum serves.
+// *amax must be 0 before the launch (zero_u32_kernel).
+template <class S>
+__global__ __launch_bounds__(256) void absmax_kernel(const S* __restrict__ src, int64_t lds, int64_t rows,
+                                                     int64_t cols, unsigned* __restrict__ amax) {
+  __shared__ unsigned red[256];
+  unsigned mx = 0;
+  const int64_t total = rows * cols;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t i = idx % rows, j = idx / rows;
+    const unsigned b = __float_as_uint(fabsf(static_cast<float>(src[i + j * lds])));
+    mx = b > mx ? b : mx;
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (static_cast<int>(threadIdx.x) < h && red[threadIdx.x + h] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(amax, red[0]);
+}
+
+__global__ void zero_u32_kernel(unsigned* p) { *p = 0u; }
 
 template <class S, class D>
 __global__ void convert_kernel(const S* __restrict__ src, int64_t lds, int64_t rows, int64_t cols,
@@ -208,31 +252,51 @@ int gemm_lowp(bool bf16, int64_t M, int64_t N, int64_t K, float alpha, const voi
 
 template <class S>
 int to_lowp(bool bf16, const S* src, int64_t lds, int64_t rows, int64_t cols, void* dst, int64_t ldd,
-            hipStream_t s) {
+            hipStream_t s, const unsigned* amax) {
   if (rows == 0 || cols == 0) return URV_OK;
   const unsigned blocks = static_cast<unsigned>(ceil_div(ldd * cols, 256));
   if (bf16)
-    to_lowp_kernel<true, S><<<blocks, 256, 0, s>>>(src, lds, rows, cols, dst, ldd);
+    to_lowp_kernel<true, S><<<blocks, 256, 0, s>>>(src, lds, rows, cols, dst, ldd, amax);
   else
-    to_lowp_kernel<false, S><<<blocks, 256, 0, s>>>(src, lds, rows, cols, dst, ldd);
+    to_lowp_kernel<false, S><<<blocks, 256, 0, s>>>(src, lds, rows, cols, dst, ldd, amax);
   URV_LAUNCHED("to_lowp_kernel");
   return URV_OK;
 }
-template int to_lowp<double>(bool, const double*, int64_t, int64_t, int64_t, void*, int64_t, hipStream_t);
-template int to_lowp<float>(bool, const float*, int64_t, int64_t, int64_t, void*, int64_t, hipStream_t);
+template int to_lowp<double>(bool, const double*, int64_t, int64_t, int64_t, void*, int64_t, hipStream_t,
+                             const unsigned*);
+template int to_lowp<float>(bool, const float*, int64_t, int64_t, int64_t, void*, int64_t, hipStream_t,
+                            const unsigned*);
 
-int to_lowp_transposed(bool bf16, const double* src, int64_t lds, int64_t rows, int64_t cols,
-                       void* dst, int64_t ldd, hipStream_t s) {
+template <class S>
+int to_lowp_transposed(bool bf16, const S* src, int64_t lds, int64_t rows, int64_t cols, void* dst, int64_t ldd,
+                       hipStream_t s, const unsigned* amax) {
   if (rows == 0 || cols == 0) return URV_OK;
   // cover dst rows [0, ldd) (zero padding included) and dst columns [0, rows)
   const dim3 grid(static_cast<unsigned>(ceil_div(rows, 32)), static_cast<unsigned>(ceil_div(ldd, 32)));
   if (bf16)
-    to_lowp_transposed_kernel<true><<<grid, 256, 0, s>>>(src, lds, rows, cols, dst, ldd);
+    to_lowp_transposed_kernel<true, S><<<grid, 256, 0, s>>>(src, lds, rows, cols, dst, ldd, amax);
   else
-    to_lowp_transposed_kernel<false><<<grid, 256, 0, s>>>(src, lds, rows, cols, dst, ldd);
+    to_lowp_transposed_kernel<false, S><<<grid, 256, 0, s>>>(src, lds, rows, cols, dst, ldd, amax);
   URV_LAUNCHED("to_lowp_transposed_kernel");
   return URV_OK;
 }
+template int to_lowp_transposed<double>(bool, const double*, int64_t, int64_t, int64_t, void*, int64_t,
+                                        hipStream_t, const unsigned*);
+template int to_lowp_transposed<float>(bool, const float*, int64_t, int64_t, int64_t, void*, int64_t, hipStream_t,
+                                       const unsigned*);
+
+template <class S>
+int absmax(const S* src, int64_t lds, int64_t rows, int64_t cols, unsigned* amax, hipStream_t s) {
+  zero_u32_kernel<<<1, 1, 0, s>>>(amax);
+  URV_LAUNCHED("zero_u32_kernel");
+  if (rows == 0 || cols == 0) return URV_OK;
+  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(ceil_div(rows * cols, 256), 1024));
+  absmax_kernel<S><<<blocks, 256, 0, s>>>(src, lds, rows, cols, amax);
+  URV_LAUNCHED("absmax_kernel");
+  return URV_OK;
+}
+template int absmax<double>(const double*, int64_t, int64_t, int64_t, unsigned*, hipStream_t);
+template int absmax<float>(const float*, int64_t, int64_t, int64_t, unsigned*, hipStream_t);
 
 template <class S, class D>
 int convert(const S* src, int64_t lds, int64_t rows, int64_t cols, D* dst, int64_t ldd, hipStream_t s) {

@@ -17,7 +17,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liburv.so")
 
-URV_OK, URV_EINVAL, URV_ENOMEM, URV_EDEVICE, URV_ENOTSUP = 0, -1, -2, -3, -4
+URV_OK, URV_EINVAL, URV_ENOMEM, URV_EDEVICE, URV_ENOTSUP, URV_ENONFINITE = 0, -1, -2, -3, -4, -5
+URV_CHECK_FINITE, URV_A_FP32 = 1, 2
 VARIANTS = {"full": 0, "half": 1, "none": 2}
 PRECISIONS = {"fp64": 0, "mixed_bf16": 2, "mixed_fp16": 3}
 
@@ -34,7 +35,7 @@ class UrvOpts(ctypes.Structure):
         ("variant", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("orth_g", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
         ("lda", ctypes.c_int64),
         ("ldu", ctypes.c_int64),
         ("ldr", ctypes.c_int64),
@@ -61,7 +62,7 @@ class UrvGradOpts(ctypes.Structure):
 
 TAPE_MODES = {"all": 0, "v": 1, "none": 2}
 
-EXPORTS = ["urv_opts_init", "urv_factor_ex", "urv_factor", "urv_workspace_size", "urv_gaussian",
+EXPORTS = ["urv_opts_init", "urv_factor_ex", "urv_sync_status", "urv_factor", "urv_workspace_size", "urv_gaussian",
            "urv_dgemm", "urv_dgemm_noalloc", "urv_qr_pos", "urv_qr_pos_f32", "urv_metrics", "urv_strerror", "urv_last_error",
            "urv_grad_opts_init", "urv_tape_bytes", "urv_grad_workspace_size", "urv_factor_tape",
            "urv_factor_backward", "urv_qr_adjoint", "urv_truncation_loss",
@@ -87,6 +88,7 @@ def lib() -> ctypes.CDLL:
     L.urv_opts_init.restype = None
     L.urv_factor_ex.argtypes = [P, I64, I64, I32, U64, P, P, P, ctypes.POINTER(UrvOpts)]
     L.urv_factor.argtypes = [P, I64, I64, I32, U64, P, P, P]
+    L.urv_sync_status.argtypes = [P]
     L.urv_workspace_size.argtypes = [I64, I64, I32, ctypes.POINTER(UrvOpts)]
     L.urv_workspace_size.restype = SZ
     L.urv_gaussian.argtypes = [P, I64, I64, I64, U64, U32, I32, P]
@@ -128,7 +130,7 @@ def lib() -> ctypes.CDLL:
                  "urv_metrics", "urv_factor_tape", "urv_factor_backward", "urv_qr_adjoint",
                  "urv_truncation_loss", "urv_batch_create", "urv_batch_set_buffers", "urv_batch_set_config",
                  "urv_batch_get_config", "urv_batch_autotune", "urv_batch_run", "urv_batch_run_graph",
-                 "urv_batch_status"):
+                 "urv_batch_status", "urv_sync_status"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -200,25 +202,32 @@ def max_rows() -> int:
     return int(lib().urv_max_rows())
 
 
-def workspace_size(m: int, n: int, q: int = 0, variant: str = "full", precision: str = "fp64") -> int:
+def workspace_size(m: int, n: int, q: int = 0, variant: str = "full", precision: str = "fp64",
+                   a_fp32: bool = False) -> int:
     o = UrvOpts()
     lib().urv_opts_init(ctypes.byref(o))
     o.variant = VARIANTS[variant]
     o.precision = PRECISIONS[precision]
+    o.flags = URV_A_FP32 if a_fp32 else 0
     return int(lib().urv_workspace_size(m, n, q, ctypes.byref(o)))
 
 
 def factor(A, q: int, seed: int = 0, variant: str = "full", precision: str = "fp64", G=None,
-           orth_g: bool = False, workspace=None, out=None):
+           orth_g: bool = False, workspace=None, out=None, check_finite: bool = False, check: bool = True):
     """PowerURV A = U R V^T (Section 3).  Returns (U, R, V) as column-major FP64 tensors:
     U m x p, R p x p, V n x p with p = min(m, n) (m < n: a ULV of A^T, transposed).
 
-    Asynchronous on the current stream.  ``workspace`` may be a uint8 CUDA
-    tensor of at least ``workspace_size(...)`` bytes; ``out`` may be a
-    (U, R, V) triple of column-major tensors to write into.
+    A may be FP64 or FP32 (an FP32 A is passed as is: URV_A_FP32).  ``workspace``
+    may be a uint8 CUDA tensor of at least ``workspace_size(...)`` bytes; ``out``
+    may be a (U, R, V) triple of column-major tensors to write into.
+    ``check_finite`` rejects a NaN or infinity in A (UrvError URV_ENONFINITE).
+    With ``check`` (default) the call waits for the stream and raises UrvError
+    (URV_EDEVICE) if a panel's device-side wait expired; with check=False it is
+    asynchronous on the current stream and ``sync_status()`` reports that later.
     """
     torch = _torch()
-    A, lda = _colmajor(A)
+    a32 = isinstance(A, torch.Tensor) and A.dtype == torch.float32
+    A, lda = _colmajor(A, dtype=torch.float32 if a32 else None)
     m, n = A.shape
     p = min(m, n)
     if out is None:
@@ -232,6 +241,7 @@ def factor(A, q: int, seed: int = 0, variant: str = "full", precision: str = "fp
     o.variant = VARIANTS[variant]
     o.precision = PRECISIONS[precision]
     o.orth_g = int(bool(orth_g))
+    o.flags = (URV_CHECK_FINITE if check_finite else 0) | (URV_A_FP32 if a32 else 0)
     o.lda = lda
     o.ldu = max(U.stride(1), m) if p > 1 else max(m, 1)
     o.ldr = max(R.stride(1), p) if p > 1 else max(p, 1)
@@ -253,7 +263,15 @@ def factor(A, q: int, seed: int = 0, variant: str = "full", precision: str = "fp
         if t.stride(0) != 1 and t.shape[0] > 1:
             raise ValueError("outputs must be column-major")
     _check(lib().urv_factor_ex(_ptr(A), m, n, q, seed & (2**64 - 1), _ptr(U), _ptr(R), _ptr(V), ctypes.byref(o)))
+    if check:
+        sync_status()
     return U, R, V
+
+
+def sync_status() -> None:
+    """Waits for the current stream; raises UrvError (URV_EDEVICE) if a factorisation or
+    QR queued since the last check had a panel's device-side wait expire."""
+    _check(lib().urv_sync_status(_stream_ptr()))
 
 
 def gaussian(rows: int, cols: int, seed: int, stream_id: int = 2, dtype=None, device=None):
@@ -289,9 +307,10 @@ def dgemm(A, B, transA: bool = False, transB: bool = False, alpha: float = 1.0, 
     return C
 
 
-def qr_pos(X, want_q: bool = True, want_r: bool = True, fp32: bool = False):
+def qr_pos(X, want_q: bool = True, want_r: bool = True, fp32: bool = False, check: bool = True):
     """Blocked Householder QR with diag(R) >= 0 (FP64, or FP32 with fp32=True).
-    Returns (Q, R) (None where not wanted)."""
+    Returns (Q, R) (None where not wanted).  With ``check`` (default) waits for the
+    stream and raises UrvError if a panel's device-side wait expired."""
     torch = _torch()
     dt = torch.float32 if fp32 else torch.float64
     Xw = empty_colmajor(*X.shape, dtype=dt, device=X.device)
@@ -301,6 +320,8 @@ def qr_pos(X, want_q: bool = True, want_r: bool = True, fp32: bool = False):
     R = empty_colmajor(n, n, dtype=dt, device=X.device) if want_r else None
     fn = lib().urv_qr_pos_f32 if fp32 else lib().urv_qr_pos
     _check(fn(_ptr(Xw), m, n, max(m, 1), _ptr(Q), max(m, 1), _ptr(R), max(n, 1), _stream_ptr()))
+    if check:
+        sync_status()
     return Q, R
 
 

@@ -38,7 +38,7 @@ def test_opts_struct_matches_header_layout():
     assert ctypes.sizeof(urv.UrvOpts) == 4 * 4 + 8 * 4 + 8 + 8 + 8 + 8 + 8
     o = urv.UrvOpts()
     urv.lib().urv_opts_init(ctypes.byref(o))
-    assert (o.variant, o.precision, o.orth_g, o.reserved, o.lda, o.G, o.stream, o.workspace) == (
+    assert (o.variant, o.precision, o.orth_g, o.flags, o.lda, o.G, o.stream, o.workspace) == (
         0, 0, 0, 0, 0, None, None, None)
 
 
@@ -68,8 +68,8 @@ def _factor(m, n, q, ptrs=True, **fields):
     (3, 5, 1, {"ldr": 2}),              # m < n: R is m x m
     (5, 3, -1, {}),                     # q < 0
     (5, 3, 1, {"variant": 3}),          # unknown variant
-    (5, 3, 1, {"precision": 1}),        # unknown precision
-    (5, 3, 1, {"reserved": 7}),
+    (5, 3, 1, {"precision": 1}),        # URV_FP32: not a mode of urv_factor_ex
+    (5, 3, 1, {"flags": 4}),           # unknown flag bit
     (5, 3, 1, {"lda": 4}),              # ld < rows
     (5, 3, 1, {"ldu": 2}),
     (5, 3, 1, {"ldr": 2}),
@@ -95,6 +95,20 @@ def test_factor_empty_is_noop():
 
 def test_too_many_rows_is_unsupported():
     assert _factor(1 << 20, 8, 1) == urv.URV_ENOTSUP
+
+
+def test_fp32_a_adds_its_fp64_copy_to_the_workspace():
+    base = urv.workspace_size(1000, 500, 2, precision="mixed_bf16")
+    a32 = urv.workspace_size(1000, 500, 2, precision="mixed_bf16", a_fp32=True)
+    assert a32 - base >= 1000 * 500 * 8
+    # a workspace sized without the copy is too small for an FP32 A
+    rc = _factor(1000, 500, 2, precision=2, flags=urv.URV_A_FP32, workspace=0x2000, workspace_bytes=base)
+    assert rc == urv.URV_EINVAL
+
+
+def test_status_codes_have_text():
+    L = urv.lib()
+    assert L.urv_strerror(urv.URV_ENONFINITE) == b"non-finite input"
 
 
 def test_workspace_size_monotone():

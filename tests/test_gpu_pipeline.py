@@ -120,3 +120,68 @@ def test_expired_panel_wait_is_reported_and_recovered(urv, monkeypatch):
     na = np.linalg.norm(A)
     assert np.all(np.isfinite(R))
     assert np.linalg.norm(A - U @ R @ V.T) <= 1e-13 * na
+
+
+def test_async_expiry_is_reported_by_sync_status(urv, monkeypatch):
+    """urv_factor_ex and urv_qr_pos are asynchronous: an expired panel wait reaches the caller
+    through urv_sync_status, which the Python calls check by default."""
+    import torch
+
+    announce("expired wait, async")
+    m, n = 600, 300
+    A = to_gpu(gen.spectral_matrix(m, n, gen.spectrum("geometric8", n), seed=78))
+    urv.sync_status()  # nothing pending
+    monkeypatch.setenv("URV_PANEL_EXPIRE_TEST", "1")
+    U, R, V = urv.factor(A, 1, seed=5, check=False)  # returns before the device work ends
+    with pytest.raises(urv.UrvError) as ei:
+        urv.sync_status()
+    assert ei.value.status == urv.URV_EDEVICE
+    assert torch.isnan(R).any()
+    urv.sync_status()  # reported once, then clear
+    with pytest.raises(urv.UrvError):
+        urv.factor(A, 1, seed=5)  # check=True waits and raises
+    with pytest.raises(urv.UrvError):
+        urv.qr_pos(A)
+    monkeypatch.delenv("URV_PANEL_EXPIRE_TEST")
+    urv.sync_status()
+    U, R, V = urv.factor(A, 1, seed=5)
+    assert torch.isfinite(R).all()
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), -float("inf")])
+def test_check_finite_rejects_before_writing(urv, bad):
+    import torch
+
+    announce("check_finite", bad)
+    m, n = 300, 200
+    A = gen.spectral_matrix(m, n, gen.spectrum("geometric8", n), seed=3)
+    A[17, 123] = bad
+    Ad = to_gpu(A)
+    outs = tuple(urv.empty_colmajor(r, c).fill_(7.0) for r, c in ((m, n), (n, n), (n, n)))
+    with pytest.raises(urv.UrvError) as ei:
+        urv.factor(Ad, 1, seed=2, check_finite=True, out=outs)
+    assert ei.value.status == urv.URV_ENONFINITE
+    for t in outs:
+        assert bool((t == 7.0).all())
+    # the same matrix, FP32, and without the check: NaN propagates, no error
+    A32 = Ad.float()
+    with pytest.raises(urv.UrvError):
+        urv.factor(A32, 1, seed=2, check_finite=True)
+    A[17, 123] = 0.5
+    U, R, V = urv.factor(to_gpu(A), 1, seed=2, check_finite=True)
+    assert torch.isfinite(R).all()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_bf16", "mixed_fp16"])
+def test_fp32_a_equals_its_fp64_value(urv, prec):
+    """An FP32 A gives bitwise the results of the FP64 matrix holding the same values: the
+    16-bit casts round the same numbers and every FP64 step sees the exact values."""
+    announce("fp32 A", prec)
+    m, n = 700, 300
+    A = gen.spectral_matrix(m, n, gen.spectrum("geometric8", n), seed=4).astype(np.float32)
+    A32 = to_gpu(A.astype(np.float64)).float()
+    A64 = to_gpu(A.astype(np.float64))
+    got = [to_np(t) for t in urv.factor(A32, 2, seed=9, precision=prec, variant="half")]
+    ref = [to_np(t) for t in urv.factor(A64, 2, seed=9, precision=prec, variant="half")]
+    for g, r in zip(got, ref):
+        np.testing.assert_array_equal(g, r)

@@ -264,3 +264,27 @@ def test_mixed_precision_against_fp64_oracle(urv, orc, prec, variant):
     print("[mixed] %s %s: max ek ratio (ek >= 5%% ||A||) %.4f, ||R-R64||/||A|| %.3e"
           % (prec, variant, ratio.max(), np.linalg.norm(R - Ro) / na))
     assert ratio.max() <= 1.25
+
+
+@pytest.mark.parametrize("variant", ["full", "half", "none"])
+def test_fp16_large_entries_scaled_not_overflowed(urv, orc, variant):
+    """||A|| ~ 1e6, entries far beyond FP16's 65504: the FP16 casts scale each operand by a
+    power of two (exact; Qpos is scale invariant), so the result matches the BF16 mode and the
+    FP64 oracle's rank-k errors as it does at unit scale."""
+    announce("fp16 scaled", variant)
+    m, n = 800, 400
+    sigma = 1e6 * np.exp(-8.0 * np.arange(1, n + 1) / n)
+    A = gen.noisy_spectral_matrix(m, n, sigma, seed=21, noise_var=1e-6)
+    G = gen.gaussian(n, n, 3)
+    q = 1 if variant == "none" else 2
+    U, R, V = _gpu_factor(urv, A, q, G=to_gpu(G), precision="mixed_fp16", variant=variant)
+    assert np.all(np.isfinite(R))
+    met = _assert_invariants(urv, A, (U, R, V), 1e-10)
+    assert met["recon"] <= 1e-12
+    Uo, Ro, Vo = orc.urv(A, q, G=G, variant="full")
+    eko = orc.metrics(A, Uo, Ro, Vo)["ek"]
+    na = np.linalg.norm(A)
+    sel = eko >= 0.05 * na
+    ratio = met["ek"][sel] / eko[sel]
+    print("[fp16 scaled] %s: max ek ratio %.4f" % (variant, ratio.max()))
+    assert ratio.max() <= 1.25
