@@ -168,7 +168,8 @@ struct SideStream {
   hipStream_t stream3 = nullptr;  // reflectors applied to the targets of a QR
   hipStream_t stream4 = nullptr;  // bulk of the trailing updates
   hipEvent_t ev_next = nullptr;
-  hipEvent_t ev_fact = nullptr;
+  hipEvent_t ev_fact = nullptr;   // block factored (even blocks)
+  hipEvent_t ev_fact2 = nullptr;  // block factored (odd blocks)
   hipEvent_t ev_tgt = nullptr;
   hipEvent_t ev_near = nullptr;
   hipEvent_t ev_bulk = nullptr;

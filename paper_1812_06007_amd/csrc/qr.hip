@@ -270,6 +270,8 @@ struct TsqrXch {
   uint64_t* recon = nullptr;  // 2 NB^2: U^-1 and T from workgroup 0
   uint64_t* gram = nullptr;   // (P + 1) x NB^2: partial sums of the 64 x 64 reductions, then the sums
   uint64_t* flags = nullptr;  // one per unit, one for the reconstruction, two per workgroup for the sums
+  uint64_t* upd = nullptr;    // (P + 1) x 4 NB^2: partial sums of the previous block's update, then the sums
+  uint64_t* uflags = nullptr; // two per workgroup, for that sum
   int chol = 1;               // try CholeskyQR2 first
 };
 // The streaming panel: 128 rows per workgroup (two 64-row chunks), so that
@@ -277,7 +279,8 @@ struct TsqrXch {
 constexpr int CQR_RPW = 128;
 constexpr int CQR_CHUNKS = CQR_RPW / 64;
 constexpr int CQR_RPT = CQR_RPW / PANEL_WAVES;  // rows per wave in its tall-skinny leaf
-constexpr int kMaxCqrWgs = static_cast<int>(kMaxRows / CQR_RPW);
+// (+1: the rows above a panel that first applies the previous block's reflectors)
+constexpr int kMaxCqrWgs = static_cast<int>(kMaxRows / CQR_RPW) + 1;
 constexpr int kTsqrUnits = 2 * kMaxCqrWgs;  // P + P/4 + P/16 + ... < 2 P
 constexpr int kTsqrFlags = kTsqrUnits + 1 + 2 * kMaxCqrWgs;
 
@@ -1498,65 +1501,78 @@ __global__ __launch_bounds__(PANEL_THREADS) void panel_kernel(T* __restrict__ X,
 // this workgroup's rows (CQR_RPW of them) through LDS 64 rows at a time, the
 // next chunk's loads in flight while the matrix cores work on the current one.
 
-// Sum of a 64 x 64 matrix over the P workgroups of the launch, every workgroup
-// getting bitwise the same sum (one fixed order): this workgroup's term is in M
-// (LDS) on entry, the sum on return.  Each workgroup adds up a slice of the
-// entries over all terms, then every workgroup gathers the slices (two
-// announced exchanges).  False if a wait expired.
-template <class T>
-__device__ __forceinline__ bool allreduce64(T (*M)[NB + 2], int P, int wg, const TsqrXch& xt, uint32_t tag,
-                                            unsigned* err, const PanelWait& pw) {
+// Sum of N 64 x 64 matrices over the P workgroups of the launch, every
+// workgroup getting bitwise the same sums (one fixed order): this workgroup's
+// terms are in M[0..N) (LDS) on entry, the sums on return.  Each workgroup adds
+// up a slice of the entries over all terms (staged in M, which is free once the
+// terms are published: its N 64 x 66 arrays hold any slice's P terms for
+// P <= 128 N), then every workgroup gathers the slices: two announced
+// exchanges through part (P x N NB^2 words) and sum (N NB^2), flagged in fa and
+// fb.  False if a wait expired.
+template <class T, int N>
+__device__ __forceinline__ bool allreduce_n(T (*const (&M)[N])[NB + 2], int P, int wg, T* part, T* sum, uint64_t* fa,
+                                            uint64_t* fb, uint32_t tag, unsigned* err, const PanelWait& pw) {
   if (P == 1) return true;
+  constexpr int E = N * NB * NB, BLK = NB * (NB + 2);
   const int tid = opaque(static_cast<int>(threadIdx.x));
-  T* const part = reinterpret_cast<T*>(xt.gram);
-  T* const sum = reinterpret_cast<T*>(xt.gram + static_cast<int64_t>(P) * NB * NB);
-  uint64_t* const fa = xt.flags + kTsqrUnits + 1;
-  uint64_t* const fb = fa + kMaxCqrWgs;
-  T* const mine = part + static_cast<int64_t>(wg) * NB * NB;
-  for (int e = tid; e < NB * NB; e += PANEL_THREADS) store_agent(mine + e, M[e & (NB - 1)][e / NB]);
+  T* const mine = part + static_cast<int64_t>(wg) * E;
+  for (int e = tid; e < E; e += PANEL_THREADS) {
+    const int b = e / (NB * NB), r = e % (NB * NB);
+    store_agent(mine + e, M[b][r & (NB - 1)][r / NB]);
+  }
   raise_flag(fa + wg, tag);
   bool ok = tid >= P || await_flag(fa + tid, tag + pw.skew, err, pw.spin_limit);
   if (__syncthreads_or(ok ? 0 : 1)) return false;
-  // this workgroup's slice [e0, e1): every term of it into M (free now), entry
-  // (e - e0) P + q, with the loads of a thread all in flight; then each sum in
-  // the order q = 0, 1, ...  (ne P <= NB^2 + P fits in M for P <= 128)
-  const int e0 = NB * NB * wg / P, e1 = NB * NB * (wg + 1) / P, ne = e1 - e0, nt = ne * P;
-  T* const flat = &M[0][0];
+  // this workgroup's slice [e0, e1): every term of it into M, entry (e - e0) P + q, with the
+  // loads of a thread all in flight; then each sum in the order q = 0, 1, ...
+  const int e0 = E * wg / P, e1 = E * (wg + 1) / P, ne = e1 - e0, nt = ne * P;
+  auto flat = [&](int f) -> T& { return (&M[f / BLK][0][0])[f % BLK]; };
   constexpr int U = 8;
   for (int i0 = tid; i0 < nt; i0 += U * PANEL_THREADS) {
     T v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = i0 + u * PANEL_THREADS;
-      v[u] = i < nt ? load_coherent(part + static_cast<int64_t>(i % P) * NB * NB + e0 + i / P) : T(0);
+      v[u] = i < nt ? load_coherent(part + static_cast<int64_t>(i % P) * E + e0 + i / P) : T(0);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = i0 + u * PANEL_THREADS;
-      if (i < nt) flat[i] = v[u];
+      if (i < nt) flat(i) = v[u];
     }
   }
   __syncthreads();
   for (int t = tid; t < ne; t += PANEL_THREADS) {
     T a = T(0);
-    for (int q = 0; q < P; ++q) a += flat[t * P + q];
+    for (int q = 0; q < P; ++q) a += flat(t * P + q);
     store_agent(sum + e0 + t, a);
   }
   raise_flag(fb + wg, tag);
   ok = tid >= P || await_flag(fb + tid, tag + pw.skew, err, pw.spin_limit);
   if (__syncthreads_or(ok ? 0 : 1)) return false;
-  {
+  for (int e00 = 0; e00 < E; e00 += NB * NB) {
     T v[NB * NB / PANEL_THREADS];
 #pragma unroll
-    for (int u = 0; u < NB * NB / PANEL_THREADS; ++u) v[u] = load_coherent(sum + tid + u * PANEL_THREADS);
+    for (int u = 0; u < NB * NB / PANEL_THREADS; ++u) v[u] = load_coherent(sum + e00 + tid + u * PANEL_THREADS);
 #pragma unroll
     for (int u = 0; u < NB * NB / PANEL_THREADS; ++u) {
-      const int e = tid + u * PANEL_THREADS;
-      M[e & (NB - 1)][e / NB] = v[u];
+      const int r = tid + u * PANEL_THREADS;
+      M[e00 / (NB * NB)][r & (NB - 1)][r / NB] = v[u];
     }
   }
   __syncthreads();
   return true;
+}
+
+// One 64 x 64 matrix summed over the workgroups (the factorisation's exchanges).
+template <class T>
+__device__ __forceinline__ bool allreduce64(T (*M)[NB + 2], int P, int wg, const TsqrXch& xt, uint32_t tag,
+                                            unsigned* err, const PanelWait& pw) {
+  T (*const blocks[1])[NB + 2] = {M};
+  uint64_t* const fa = xt.flags + kTsqrUnits + 1;
+  return allreduce_n<T, 1>(blocks, P, wg, reinterpret_cast<T*>(xt.gram),
+                           reinterpret_cast<T*>(xt.gram + static_cast<int64_t>(P) * NB * NB), fa, fa + kMaxCqrWgs, tag,
+                           err, pw);
 }
 
 // A 64-row chunk of a column-major matrix in registers: thread t holds row
@@ -1996,19 +2012,208 @@ __device__ __forceinline__ bool cqr_part(const CqrRows<T>& rw, int P, int wg, in
   return true;
 }
 
+// f <-> rows [r0, r0 + 64) of a column-major matrix (ld ld), in the fragment
+// layout; entries at rows >= mrows or columns >= ncols read as 0 and are not
+// written.  Each wave's 16 x 32 block covers whole 128-byte lines of 16 rows.
+template <class T>
+__device__ __forceinline__ void frag_load_global(Frag<T>& f, const T* src, int64_t ld, int64_t r0, int64_t mrows,
+                                                 int ncols, const FragPos& p, bool coherent) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t gi = r0 + p.ib + PanelMma<T>::row(p.lk, v);
+    const int j0 = p.cb0 + p.l16, j1 = j0 + 16;
+    const T* q0 = src + gi + static_cast<int64_t>(j0) * ld;
+    const T* q1 = src + gi + static_cast<int64_t>(j1) * ld;
+    f.a0[v] = (gi < mrows && j0 < ncols) ? (coherent ? load_coherent(q0) : *q0) : T(0);
+    f.a1[v] = (gi < mrows && j1 < ncols) ? (coherent ? load_coherent(q1) : *q1) : T(0);
+  }
+}
+template <class T>
+__device__ __forceinline__ void frag_store_global(const Frag<T>& f, T* dst, int64_t ld, int64_t r0, int64_t mrows,
+                                                  int ncols, const FragPos& p) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t gi = r0 + p.ib + PanelMma<T>::row(p.lk, v);
+    const int j0 = p.cb0 + p.l16, j1 = j0 + 16;
+    if (gi < mrows && j0 < ncols) dst[gi + static_cast<int64_t>(j0) * ld] = f.a0[v];
+    if (gi < mrows && j1 < ncols) dst[gi + static_cast<int64_t>(j1) * ld] = f.a1[v];
+  }
+}
+// S = the 64 x 64 block of a column-major matrix at src (ld ld).
+template <class T>
+__device__ __forceinline__ void block_to_lds(T (*S)[NB + 2], const T* src, int64_t ld) {
+  const int tid = opaque(static_cast<int>(threadIdx.x));
+  T v[NB * NB / PANEL_THREADS];
+#pragma unroll
+  for (int u = 0; u < NB * NB / PANEL_THREADS; ++u) {
+    const int e = tid + u * PANEL_THREADS;
+    v[u] = src[(e & (NB - 1)) + static_cast<int64_t>(e / NB) * ld];
+  }
+#pragma unroll
+  for (int u = 0; u < NB * NB / PANEL_THREADS; ++u) {
+    const int e = tid + u * PANEL_THREADS;
+    S[e & (NB - 1)][e / NB] = v[u];
+  }
+}
+
+// The previous 128-column block's reflectors applied to this launch's columns
+// (the look-ahead update of the blocked QR, Section 2.2), by every workgroup on
+// its own rows: C <- (I - Yp Tp Yp^T)^T C = C - Yp (Tp^T (Yp^T C)), with
+// W = Yp^T C (128 x 128) summed over the workgroups.  C is X's columns [0, nc1)
+// and [NB, NB + nc2) over rows [0, mp) (kernel rows: row 0 is the previous
+// block's first pivot row); Yp the previous block's explicit reflectors at the
+// same rows (ld ldy, 128 columns), Tp its 128 x 128 T (ld ldt).  False if a
+// wait expired.
+template <class T>
+__device__ __forceinline__ bool prev_update(T* __restrict__ X, int64_t ldx, int64_t mp, int nc1, int nc2,
+                                            const T* __restrict__ Yp, int64_t ldy, const T* __restrict__ Tp, int ldt,
+                                            int P, int wg, int g, int c, const TsqrXch& xt, uint32_t tag,
+                                            unsigned* err, const PanelWait& pw, bool coherent, const TsqrLds<T>& L) {
+  FragPos fp{(g >> 1) * 16, (g & 1) * 32, c & 15, c >> 4};
+  const int64_t row0 = static_cast<int64_t>(wg) * CQR_RPW;
+  CqrRows<T> yr;
+  yr.row0 = row0;
+  yr.mp = mp;
+  yr.lbase = static_cast<int>(row0);
+  yr.p0 = 0;
+  yr.jbp = NB;
+  yr.kc = 0;
+  CqrRows<T> c1 = yr, c2 = yr;
+  c1.jbp = nc1;
+  c2.jbp = nc2;
+  const T* Yh = Yp + static_cast<int64_t>(NB) * ldy;
+  T* X2 = X + static_cast<int64_t>(NB) * ldx;
+  // ---- W = Yp^T C over this workgroup's rows, four 64 x 64 blocks W_ab = Yp_a^T C_b
+  {
+    Frag<T> w00, w01, w10, w11;
+    frag_zero(w00);
+    frag_zero(w01);
+    frag_zero(w10);
+    frag_zero(w11);
+    ChunkRegs<T> ya, yb, ca, cb;
+    yr.load(ya, Yp, ldy, 0, false);
+    yr.load(yb, Yh, ldy, 0, false);
+    c1.load(ca, X, ldx, 0, coherent);
+    c2.load(cb, X2, ldx, 0, coherent);
+    for (int k = 0; k < CQR_CHUNKS; ++k) {
+      yr.put(L.S1, ya);
+      yr.put(L.S2, yb);
+      yr.put(L.S3, ca);
+      yr.put(L.S4, cb);
+      __syncthreads();
+      if (k + 1 < CQR_CHUNKS) {
+        yr.load(ya, Yp, ldy, k + 1, false);
+        yr.load(yb, Yh, ldy, k + 1, false);
+        c1.load(ca, X, ldx, k + 1, coherent);
+        c2.load(cb, X2, ldx, k + 1, coherent);
+      }
+      frag_mma<T, true>(w00, L.S1, L.S3, fp);
+      frag_mma<T, true>(w01, L.S1, L.S4, fp);
+      frag_mma<T, true>(w10, L.S2, L.S3, fp);
+      frag_mma<T, true>(w11, L.S2, L.S4, fp);
+      __syncthreads();
+    }
+    frag_to_lds(w00, L.S1, fp);
+    frag_to_lds(w01, L.S2, fp);
+    frag_to_lds(w10, L.S3, fp);
+    frag_to_lds(w11, L.S4, fp);
+    __syncthreads();
+  }
+  {
+    T (*const blocks[4])[NB + 2] = {L.S1, L.S2, L.S3, L.S4};
+    T* const part = reinterpret_cast<T*>(xt.upd);
+    if (!allreduce_n<T, 4>(blocks, P, wg, part, part + static_cast<int64_t>(P) * 4 * NB * NB, xt.uflags,
+                           xt.uflags + kMaxCqrWgs, tag, err, pw))
+      return false;
+  }
+  // ---- W' = Tp^T W: W'_0b = T00^T W_0b, W'_1b = T01^T W_0b + T11^T W_1b (S1 = W00, S2 = W01,
+  // S3 = W10, S4 = W11 on entry; the T blocks pass through S2 and S4)
+  Frag<T> f00, f01, f10, f11, g01, g11;
+  frag_from_lds(g01, L.S2, fp);
+  frag_from_lds(g11, L.S4, fp);
+  __syncthreads();
+  const T* T00 = Tp;
+  const T* T01 = Tp + static_cast<int64_t>(NB) * ldt;
+  const T* T11 = Tp + NB + static_cast<int64_t>(NB) * ldt;
+  block_to_lds(L.S2, T01, ldt);
+  block_to_lds(L.S4, T11, ldt);
+  __syncthreads();
+  frag_zero(f10);
+  frag_mma<T, true>(f10, L.S2, L.S1, fp);
+  frag_mma<T, true>(f10, L.S4, L.S3, fp);
+  __syncthreads();
+  block_to_lds(L.S2, T00, ldt);
+  __syncthreads();
+  frag_zero(f00);
+  frag_mma<T, true>(f00, L.S2, L.S1, fp);
+  __syncthreads();
+  frag_to_lds(g01, L.S1, fp);
+  frag_to_lds(g11, L.S3, fp);
+  block_to_lds(L.S2, T01, ldt);
+  block_to_lds(L.S4, T11, ldt);
+  __syncthreads();
+  frag_zero(f11);
+  frag_mma<T, true>(f11, L.S2, L.S1, fp);
+  frag_mma<T, true>(f11, L.S4, L.S3, fp);
+  __syncthreads();
+  block_to_lds(L.S2, T00, ldt);
+  __syncthreads();
+  frag_zero(f01);
+  frag_mma<T, true>(f01, L.S2, L.S1, fp);
+  __syncthreads();
+  // ---- C_b -= Yp_0 W'_0b + Yp_1 W'_1b, one half of C at a time (W' in S1, S2; Yp chunks in S3, S4)
+  for (int b = 0; b < 2; ++b) {
+    const int ncb = b ? nc2 : nc1;
+    T* Cb = b ? X2 : X;
+    frag_to_lds(b ? f01 : f00, L.S1, fp);
+    frag_to_lds(b ? f11 : f10, L.S2, fp);
+    ChunkRegs<T> ya, yb;
+    yr.load(ya, Yp, ldy, 0, false);
+    yr.load(yb, Yh, ldy, 0, false);
+    for (int k = 0; k < CQR_CHUNKS; ++k) {
+      yr.put(L.S3, ya);
+      yr.put(L.S4, yb);
+      __syncthreads();
+      if (k + 1 < CQR_CHUNKS) {
+        yr.load(ya, Yp, ldy, k + 1, false);
+        yr.load(yb, Yh, ldy, k + 1, false);
+      }
+      Frag<T> fc, fy;
+      frag_load_global(fc, Cb, ldx, row0 + 64 * k, mp, ncb, fp, coherent);
+      frag_zero(fy);
+      frag_mma<T, false>(fy, L.S3, L.S1, fp);
+      frag_mma<T, false>(fy, L.S4, L.S2, fp);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        fc.a0[v] -= fy.a0[v];
+        fc.a1[v] -= fy.a1[v];
+      }
+      frag_store_global(fc, Cb, ldx, row0 + 64 * k, mp, ncb, fp);
+      __syncthreads();
+    }
+  }
+  return true;
+}
+
 // The block of columns [0, jb + jb2) (jb2 > 0: a second part of jb2 columns,
 // with the first part's reflectors applied to it in between and the joined T)
-// of rows [0, mp) at X: Householder vectors (explicit, into Y), T (into Tout,
-// ld ldt, from workgroup 0), tau; R in place in X.  P = ceil(mp / CQR_RPW)
-// co-resident workgroups.  With wait_flag, the launch waits (bounded) for that
-// flag before reading its columns, which another stream updates.
+// of rows [ext, mp) at X: Householder vectors (explicit, into Y), T (into Tout,
+// ld ldt, from the workgroup holding the pivot rows), tau; R in place in X.
+// Rows are kernel rows: with ext = CQR_RPW, rows [0, ext) are the previous
+// block's pivot rows, and the launch first applies that block's reflectors
+// (Yprev, Tprev) to its columns over rows [0, mp); workgroup 0 holds those
+// rows and leaves after that update.  P = ceil(mp / CQR_RPW) co-resident
+// workgroups.  With wait_flag, the launch waits (bounded) for that flag before
+// reading its columns, which another stream updates.
 template <class T>
 __global__ __launch_bounds__(PANEL_THREADS) void cqr_panel_kernel(T* __restrict__ X, int64_t ldx, int64_t mp, int jb,
                                                                  T* __restrict__ Y, int64_t ldy, T* __restrict__ tau,
                                                                  T* __restrict__ Tout, int ldt, uint32_t tag0,
                                                                  unsigned* __restrict__ err, int zero_above,
                                                                  PanelWait pw, int jb2,
-                                                                 const unsigned* __restrict__ wait_flag, TsqrXch xt) {
+                                                                 const unsigned* __restrict__ wait_flag, TsqrXch xt,
+                                                                 const T* __restrict__ Yprev,
+                                                                 const T* __restrict__ Tprev, int ext) {
   __shared__ __attribute__((aligned(16))) T S1[NB][NB + 2];
   __shared__ __attribute__((aligned(16))) T S2[NB][NB + 2];
   __shared__ __attribute__((aligned(16))) T S3[NB][NB + 2];
@@ -2026,6 +2231,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void cqr_panel_kernel(T* __restrict_
   const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t row0 = static_cast<int64_t>(wg) * CQR_RPW;
   const bool two = jb2 > 0;
+  const int pwg = ext / CQR_RPW;  // the workgroup of the pivot rows
   FragPos fp{(g >> 1) * 16, (g & 1) * 32, c & 15, c >> 4};
   auto phase = [&]() {
     c = opaque(c);
@@ -2039,6 +2245,11 @@ __global__ __launch_bounds__(PANEL_THREADS) void cqr_panel_kernel(T* __restrict_
     if (threadIdx.x == 0) ok = wait_flag_geq(wait_flag, 1u, err, pw.spin_limit);
     ok = !__syncthreads_or(ok ? 0 : 1);
   }
+  if (ext > 0 && ok) {
+    ok = prev_update(X, ldx, mp, jb, jb2, Yprev, ldy, Tprev, ldt, P, wg, g, c, xt, tag0 + 7, err, pw, waited, L);
+    phase();
+  }
+  if (wg < pwg) return;  // rows above the block: only the previous block's update
   for (int part = 0; part < (two ? 2 : 1); ++part) {
     phase();
     const int p0 = part * NB;
@@ -2050,12 +2261,12 @@ __global__ __launch_bounds__(PANEL_THREADS) void cqr_panel_kernel(T* __restrict_
     CqrRows<T> rw;
     rw.row0 = row0;
     rw.mp = mp;
-    rw.lbase = wg == 0 ? p0 : static_cast<int>(row0);
-    rw.p0 = p0;
+    rw.lbase = wg == pwg ? ext + p0 : static_cast<int>(row0);
+    rw.p0 = ext + p0;
     rw.jbp = jbp;
     rw.kc = (rw.lbase - static_cast<int>(row0)) / 64;
     // part 0 reads columns another kernel may have just written; part 1 reads this kernel's own
-    ok = ok && cqr_part(rw, P, wg, g, c, Xp, ldx, Yp, ldy, waited && part == 0, xt, tagp, err, pw, two,
+    ok = ok && cqr_part(rw, P - pwg, wg - pwg, g, c, Xp, ldx, Yp, ldy, waited && part == 0, xt, tagp, err, pw, two,
                         xt.chol != 0, L);
     if (!ok) {
       // A device-side wait gave up: poison T and tau so that the failure is visible.
@@ -2063,19 +2274,21 @@ __global__ __launch_bounds__(PANEL_THREADS) void cqr_panel_kernel(T* __restrict_
       for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) S4[e & (NB - 1)][e / NB] = static_cast<T>(__builtin_nan(""));
     }
     __syncthreads();
-    if (wg == 0) {
+    if (wg == pwg) {
       for (int e = threadIdx.x; e < NB * NB; e += PANEL_THREADS) {
         const int i = e % NB, k = e / NB;
         if (i < jbp && k < jbp) Tp[i + static_cast<int64_t>(k) * ldt] = S4[i][k];
       }
       if (threadIdx.x < jbp) tau[p0 + threadIdx.x] = tau_sh[threadIdx.x];
-      // Y is zero in the zero_above rows above the panel (an earlier panel of the same block)
+      // Y is zero in the zero_above rows above the block's first pivot row (an earlier
+      // panel of the same block pair)
+      T* Yf = Yp + ext;
       for (int e = threadIdx.x; e < zero_above * jbp; e += PANEL_THREADS)
-        Yp[(e % zero_above) - zero_above + static_cast<int64_t>(e / zero_above) * ldy] = T(0);
+        Yf[(e % zero_above) - zero_above + static_cast<int64_t>(e / zero_above) * ldy] = T(0);
       // and in the rows of the first part above the second
       if (part == 1)
         for (int e = threadIdx.x; e < NB * jbp; e += PANEL_THREADS)
-          Yp[(e % NB) + static_cast<int64_t>(e / NB) * ldy] = T(0);
+          Yf[(e % NB) + static_cast<int64_t>(e / NB) * ldy] = T(0);
     }
     if (!two || !ok) break;
     phase();
@@ -2109,7 +2322,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void cqr_panel_kernel(T* __restrict_
       }
       frag_to_lds(f, S3, fp);
       __syncthreads();
-      ok = allreduce64(S3, P, wg, xt, tagp + 5, err, pw);
+      ok = allreduce64(S3, P - pwg, wg - pwg, xt, tagp + 5, err, pw);
       if (!ok) break;
       phase();
       // W' = T1^T W (T1 in S4, every workgroup) into S2
@@ -2170,9 +2383,9 @@ __global__ __launch_bounds__(PANEL_THREADS) void cqr_panel_kernel(T* __restrict_
       }
       frag_to_lds(f, S3, fp);
       __syncthreads();
-      ok = allreduce64(S3, P, wg, xt, tagp + 6, err, pw);
+      ok = allreduce64(S3, P - pwg, wg - pwg, xt, tagp + 6, err, pw);
       if (!ok) break;
-      if (wg == 0) {
+      if (wg == pwg) {
         phase();
         // S12 T2 (T2 in S4) into S2, T1 (from Tout) into S1, T12 = -T1 (S12 T2)
         frag_zero(f);
@@ -2360,9 +2573,17 @@ bool panel_fused() {
 }
 
 // Whether a block's factorisation is queued ahead of the update of its columns
-// and waits for it on the device (URV_PANEL_EARLY=0 orders them on one stream, for tuning).
-bool panel_early() {
+// and waits for it on the device (URV_PANEL_EARLY=0 orders them through the
+// streams, for tuning).  `fallback` when the variable is unset.
+bool panel_early(bool fallback) {
   const char* e = std::getenv("URV_PANEL_EARLY");
+  return e ? std::atoi(e) != 0 : fallback;
+}
+
+// Whether a block's panel launch applies the previous block's reflectors to its
+// columns first (URV_PANEL_PREV=0 leaves that to an update on the caller's stream).
+bool panel_prev() {
+  const char* e = std::getenv("URV_PANEL_PREV");
   return !(e && std::atoi(e) == 0);
 }
 
@@ -2425,6 +2646,8 @@ int cqr_wgs(int64_t m) { return static_cast<int>(ceil_div(m, CQR_RPW)); }
 size_t tsqr_tri_words(int64_t m) { return static_cast<size_t>(2) * cqr_wgs(m) * kTriEntries; }
 size_t tsqr_recon_words() { return static_cast<size_t>(2) * NB * NB; }
 size_t tsqr_gram_words(int64_t m) { return (static_cast<size_t>(cqr_wgs(m)) + 1) * NB * NB; }
+// the previous block's update: rows from one block above the panel
+size_t tsqr_upd_words(int64_t m) { return (static_cast<size_t>(cqr_wgs(m + NB2)) + 1) * 4 * NB * NB; }
 
 QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   QrSizes z;
@@ -2435,7 +2658,8 @@ QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   z.w = static_cast<size_t>(NBO) * n;
   z.xch = 2 * (static_cast<size_t>(panel_wgs(m)) + 1) * NB * 2;
   z.jxch = (static_cast<size_t>(panel_wgs(m)) + 1) * kJoinEntries * 2;
-  z.txch = tsqr_tri_words(m) + tsqr_recon_words() + tsqr_gram_words(m) + kTsqrFlags;
+  z.txch = tsqr_tri_words(m + NB2) + tsqr_recon_words() + tsqr_gram_words(m + NB2) + kTsqrFlags + tsqr_upd_words(m) +
+           2 * kMaxCqrWgs;
   z.sync = nblocks + 2;
   size_t gw = 0, gwb = 0, gwf = 0, gwn = 0;
   for (const int64_t nbo : {static_cast<int64_t>(NB2), static_cast<int64_t>(NBO)}) {
@@ -2554,10 +2778,12 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   }
   TsqrXch txch;
   txch.tri = w.txch;
-  txch.recon = txch.tri + tsqr_tri_words(m);
+  txch.recon = txch.tri + tsqr_tri_words(m + NB2);
   txch.gram = txch.recon + tsqr_recon_words();
   txch.chol = panel_chol() ? 1 : 0;
-  txch.flags = txch.gram + tsqr_gram_words(m);
+  txch.flags = txch.gram + tsqr_gram_words(m + NB2);
+  txch.upd = txch.flags + kTsqrFlags;
+  txch.uflags = txch.upd + tsqr_upd_words(m);
   // per-block flags: "the columns of the block at column b * NB are up to date"
   unsigned* ready = w.sync;
   fill_u32_kernel<<<static_cast<unsigned>(ceil_div(nblocks, 256)), 256, 0, s>>>(ready, nblocks, 0u);
@@ -2572,14 +2798,20 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   const bool fused = panel_fused();
 
   uint32_t panels = 0;  // panel launches so far: exchange tags stay distinct
+  // prev_j0 >= 0: the launch first applies the 128-column block at prev_j0
+  // (= r0 - NB2) to its columns (the streaming panel only).
   auto panel = [&](int64_t r0, int jbp, T* Tp, int zero_above, const PanelJoin<T>& join, int jb2,
-                   const unsigned* wf) -> int {
+                   const unsigned* wf, int64_t prev_j0 = -1) -> int {
     const int64_t mp = m - r0;
     const unsigned P = static_cast<unsigned>(panel_wgs(mp));
     if (tsqr && join.Y1 == nullptr) {
-      cqr_panel_kernel<T><<<static_cast<unsigned>(cqr_wgs(mp)), PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
-                                                       w.tau + r0, Tp, NBO, panels * NB, err, zero_above, pwait,
-                                                       jb2, wf, txch);
+      const int ext = prev_j0 >= 0 ? static_cast<int>(r0 - prev_j0) : 0;
+      const int64_t k0 = r0 - ext;  // the launch's kernel row 0
+      const T* Yprev = prev_j0 >= 0 ? w.Y + prev_j0 + prev_j0 * m : nullptr;
+      const T* Tprev = prev_j0 >= 0 ? w.Tm + prev_j0 * NBO : nullptr;
+      cqr_panel_kernel<T><<<static_cast<unsigned>(cqr_wgs(mp + ext)), PANEL_THREADS, 0, s2>>>(
+          X + k0 + r0 * ldx, ldx, mp + ext, jbp, w.Y + k0 + r0 * m, m, w.tau + r0, Tp, NBO, panels * NB, err,
+          zero_above, pwait, jb2, wf, txch, Yprev, Tprev, ext);
       URV_LAUNCHED("cqr_panel_kernel");
     } else {
       panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
@@ -2593,7 +2825,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   // Householder vectors, tau and T (at Tp, ld NBO) of the sub-block of width
   // jbs at row/column r0 of the outer block starting at j0, on the side stream;
   // with wf, its first launch waits for that flag before reading its columns.
-  auto factor_sub = [&](int64_t j0, int64_t r0, int jbs, T* Tp, const unsigned* wf) -> int {
+  auto factor_sub = [&](int64_t j0, int64_t r0, int jbs, T* Tp, const unsigned* wf, int64_t prev_j0 = -1) -> int {
     const int jb1 = std::min(jbs, NB), jb2 = jbs - jb1;
     const int64_t mp = m - r0;
     T* Yb = w.Y + r0 + r0 * m;
@@ -2602,9 +2834,9 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       PanelJoin<T> bufs;
       bufs.ps = w.jxch;
       bufs.sums = w.jxch + w.jxch_words - 2 * kJoinEntries;
-      return panel(r0, jb1, Tp, static_cast<int>(r0 - j0), bufs, jb2, wf);
+      return panel(r0, jb1, Tp, static_cast<int>(r0 - j0), bufs, jb2, wf, prev_j0);
     }
-    URV_TRY(panel(r0, jb1, Tp, static_cast<int>(r0 - j0), PanelJoin<T>{}, 0, wf));
+    URV_TRY(panel(r0, jb1, Tp, static_cast<int>(r0 - j0), PanelJoin<T>{}, 0, wf, jb2 > 0 ? -1 : prev_j0));
     if (jb2 > 0) {
       // first panel's reflectors applied to the second panel's columns:
       // C2 -= Y1 (T1^T (Y1^T C2)), the reduction of Y1^T C2 fused with T1^T
@@ -2640,7 +2872,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   };
   // The outer block at column j0: sub-blocks A and B, B updated by A in
   // between, and T = [[T_A, -T_A (Y_A^T Y_B) T_B], [0, T_B]].
-  auto factor_block = [&](int64_t j0, const unsigned* wf) -> int {
+  auto factor_block = [&](int64_t j0, const unsigned* wf, int64_t prev_j0 = -1) -> int {
     const int jbo = static_cast<int>(std::min<int64_t>(nbo, n - j0));
     const int ja = std::min(jbo, NB2), jbb = jbo - ja;
     const int64_t mp = m - j0;
@@ -2648,7 +2880,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     // Y is kept zero above the diagonal back to the start of the pair of
     // 128-column blocks, so that the targets can take a pair at once
     const int64_t jz = j0 - (j0 / NB2 % 2) * NB2;
-    URV_TRY(factor_sub(jz, j0, ja, Tb, wf));
+    URV_TRY(factor_sub(jz, j0, ja, Tb, wf, prev_j0));
     if (jbb > 0) {
       const T* Ya = w.Y + j0 + j0 * m;
       T* CB = X + j0 + (j0 + ja) * ldx;
@@ -2759,27 +2991,48 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   // queued before the factorisation that waits for it, so the two can share a
   // hardware queue.  With URV_PANEL_EARLY=0, s2 updates the next block's
   // columns itself, between the factorisations.
-  const bool early = panel_early();
+  // each block's factorisation applies the previous block to its own columns (the
+  // streaming panel with both parts in one launch; URV_PANEL_PREV=0 turns it off)
+  const bool prev_fused = tsqr && fused && nbo == NB2 && panel_prev();
+  // Queued early, a launch would hold its compute units spinning while the updates it
+  // waits for still run (measured slower with the previous block fused); the separate
+  // near update is faster queued early.
+  const bool early = panel_early(!prev_fused);
   const int64_t lag = target_lag();
   int64_t tgt_next = 0;  // first block whose targets are not yet queued
   URV_HIP(hipEventRecord(side.ev_next, s));      // the cleared flags and slots
   URV_HIP(hipStreamWaitEvent(s2, side.ev_next, 0));
   if (ntargets > 0) URV_HIP(hipStreamWaitEvent(s3, side.ev_next, 0));  // targets written before the call
+  // "block j is factored": two events, by the parity of j, so that block j's event is
+  // still the one recorded for it while block j + 1 is queued
+  const hipEvent_t ev_fact[2] = {side.ev_fact, side.ev_fact2};
   URV_TRY(factor_block(0, nullptr));
-  URV_HIP(hipEventRecord(side.ev_fact, s2));
+  URV_HIP(hipEventRecord(ev_fact[0], s2));
   bool near_pending = false, bulk_pending = false;
   for (int64_t j0 = 0; j0 < n; j0 += nbo) {
-    URV_HIP(hipStreamWaitEvent(s, side.ev_fact, 0));  // block j0 is factored
+    const int par = static_cast<int>((j0 / nbo) & 1);
+    URV_HIP(hipStreamWaitEvent(s, ev_fact[par], 0));  // block j0 is factored
     const int64_t j1 = j0 + nbo;
     if (ntargets > 0) {
       // blocks up to j0 - lag now; at the last block, all that are left
       const int64_t upto = j1 >= n ? j0 : j0 - lag * nbo;
-      if (tgt_next <= upto) URV_HIP(hipStreamWaitEvent(s3, side.ev_fact, 0));
+      if (tgt_next <= upto) URV_HIP(hipStreamWaitEvent(s3, ev_fact[par], 0));
       for (; tgt_next <= upto; tgt_next += nbo) URV_TRY(apply_targets(tgt_next));
     }
     if (j1 >= n) break;
     const int64_t nn = std::min<int64_t>(nbo, n - j1);
-    if (early) {
+    if (prev_fused) {
+      // block j1's factorisation applies block j0 to its columns itself; the earlier blocks'
+      // shares came from s and s4, announced by block j1's flag (none before block 2), or,
+      // with URV_PANEL_EARLY=0, by the event after them on s (the launch then takes its
+      // compute units only once its columns are ready)
+      if (early || j0 == 0) {
+        URV_TRY(factor_block(j1, j0 > 0 ? ready + j1 / NB : nullptr, j0));
+      } else {
+        URV_HIP(hipStreamWaitEvent(s2, side.ev_near, 0));
+        URV_TRY(factor_block(j1, nullptr, j0));
+      }
+    } else if (early) {
       // block j1's columns on s (after the previous block's share, also on s), its flag,
       // then its factorisation on s2
       URV_TRY(apply_block(j0, j1, nn, kOnCallerStream));
@@ -2792,19 +3045,26 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       URV_TRY(apply_block(j0, j1, nn, kOnPanelStream));
       URV_TRY(factor_block(j1, nullptr));
     }
-    URV_HIP(hipEventRecord(side.ev_fact, s2));
+    URV_HIP(hipEventRecord(ev_fact[par ^ 1], s2));
     const int64_t j2 = j1 + nn;
     if (j2 >= n) continue;
     // the block after next, which needs the previous bulk update first
     const int64_t nn2 = std::min<int64_t>(nbo, n - j2);
     if (bulk_pending) URV_HIP(hipStreamWaitEvent(s, side.ev_bulk, 0));
     URV_TRY(apply_block(j0, j2, nn2, kOnCallerStream));
+    if (prev_fused) {
+      // block j2's columns now hold every share but block j1's, which its factorisation applies
+      signal_kernel<<<1, 64, 0, s>>>(ready + j2 / NB, 1u);
+      URV_LAUNCHED("signal_kernel");
+    }
     URV_HIP(hipEventRecord(side.ev_near, s));
     near_pending = true;
     const int64_t j3 = j2 + nn2;
     if (j3 >= n) continue;
-    URV_HIP(hipStreamWaitEvent(s4, side.ev_near, 0));
-    URV_TRY(apply_block(j0, j3, n - j3, kOnBulkStream));  // the rest, beside the chain
+    // the rest, beside the chain: needs block j0's reflectors only (its columns are not the
+    // near updates', and the previous bulk update is ahead of it on s4)
+    URV_HIP(hipStreamWaitEvent(s4, ev_fact[par], 0));
+    URV_TRY(apply_block(j0, j3, n - j3, kOnBulkStream));
     URV_HIP(hipEventRecord(side.ev_bulk, s4));
     bulk_pending = true;
   }

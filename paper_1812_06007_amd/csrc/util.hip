@@ -152,10 +152,11 @@ int side_stream(SideStream* out) {
   if (e.stream == nullptr) {
     hipStream_t st[3];
     for (auto& x : st) URV_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-    hipEvent_t ev[6];
+    hipEvent_t ev[7];
     for (auto& x : ev) URV_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
     e.ev_next = ev[0];
     e.ev_fact = ev[1];
+    e.ev_fact2 = ev[6];
     e.ev_tgt = ev[2];
     e.ev_near = ev[3];
     e.ev_bulk = ev[4];

@@ -63,8 +63,13 @@ def _parity(urv, orc, m, n, q, seed):
     {"URV_TARGET_LAG": "1000"},
     {"URV_QR_BLOCK": "256", "URV_PANEL_FUSED": "0", "URV_PANEL_JOIN": "0", "URV_TARGET_PAIRS": "0",
      "URV_PANEL_EARLY": "0", "URV_TARGET_LAG": "1"},
+    {"URV_PANEL_EARLY": "1"},
+    {"URV_PANEL_PREV": "0"},
+    {"URV_PANEL_PREV": "0", "URV_PANEL_EARLY": "0"},
+    {"URV_PANEL_CHOL": "0"},
+    {"URV_PANEL_TSQR": "0"},
 ], ids=["block256", "no_pairs", "separate_panels", "no_join", "in_order", "targets_at_once", "targets_at_end",
-        "all_off"])
+        "all_off", "prev_flag_wait", "no_prev", "no_prev_in_order", "tall_skinny_only", "per_column_panel"])
 @pytest.mark.parametrize("m,n", [(400, 400), (700, 520), (300, 197)])
 def test_schedule_variants_match_oracle(urv, orc, monkeypatch, env, m, n):
     announce("schedule", env, m, n)
