@@ -5,9 +5,11 @@
 A step is one whole factorisation A = U R V^T (Gaussian draw, q power steps,
 final QR) of the 8000 x 8000 FP64 matrix A = Q1 diag(1/j^2) Q2^T with Haar
 Q1, Q2, inputs and workspace resident in HBM.  The printed JSON line carries
-TFLOP/s at the executed operation count (standard LAPACK counts, explicit Q
-included), the reconstruction error, the MFMA roofline of the dominant
-kernel (the FP64 GEMM A V, timed with HIP events on the stream it runs on),
+TFLOP/s at the standard operation count (LAPACK counts of the products,
+factorisations and explicit U and V; the executed count beside it), the
+reconstruction error, the MFMA roofline of the dominant kernel (the library's
+FP64 launches timed live with HIP events on the streams they run on, during
+the timed steps; the A V GEMM alone beside it),
 the mixed-precision forms (BF16 / FP16 power steps) against plain FP64 on the
 same input and on the 16000 x 8000 noisy exp(-j/800) matrix, the
 differentiation workload (forward, truncation loss and reverse sweep of a
@@ -63,22 +65,39 @@ def gemm_traffic(m: int, n: int):
 
 
 
-def executed_flops(m: int, n: int, q: int, variant: str, orth_g: bool = False) -> float:
-    """Standard operation counts: GEMM 2mn^2 each; QR with explicit Q of an
-    m x n matrix 2(2mn^2 - 2/3 n^3) (factor + form Q); n x n QR (8/3) n^3."""
+def standard_flops(m: int, n: int, q: int, variant: str, orth_g: bool = False) -> float:
+    """Standard (LAPACK) operation count of the algorithm as the driver runs it: every
+    product with A or A^T 2 m n^2 (2q + 1 of them), every Householder factorisation or
+    explicit-Q formation of an m x n matrix 2 m n^2 - 2/3 n^3 (n x n: 4/3 n^3).
+    Factorisations: FULL q (X, m x n) + q (A^T W, n x n), HALF q (n x n), NONE one n x n
+    (q > 0), plus Qpos(G) when q == 0 or orth_g, plus the final A V = U R; explicit Q:
+    V (n x n) and U (m x n).  FULL, q = 2, m = n: 58/3 n^3."""
     m, n = float(m), float(n)
     gemm = (2 * q + 1) * 2 * m * n * n
-    qr_mn = 2 * (2 * m * n * n - 2.0 / 3.0 * n ** 3)
-    qr_nn = 8.0 / 3.0 * n ** 3
+    f_mn = 2 * m * n * n - 2.0 / 3.0 * n ** 3
+    f_nn = 4.0 / 3.0 * n ** 3
     if variant == "full":
-        qr = (q + 1) * qr_mn + q * qr_nn
+        fact = q * (f_mn + f_nn) + f_mn
     elif variant == "half":
-        qr = qr_mn + q * qr_nn
+        fact = q * f_nn + f_mn
     else:
-        qr = qr_mn + (qr_nn if q > 0 else 0.0)
+        fact = (f_nn if q > 0 else 0.0) + f_mn
     if q == 0 or orth_g:
-        qr += qr_nn
-    return gemm + qr
+        fact += f_nn
+    return gemm + fact + f_nn + f_mn
+
+
+def executed_flops(m: int, n: int, q: int, variant: str, orth_g: bool = False) -> float:
+    """What the driver executes: the standard count, except that V, and U when m == n, are
+    formed by applying the reflectors to an identity (Z <- Z Q, 4 z m n - 2 z n^2 with z the
+    rows of Z: 2 n^3 for n x n) rather than by the structured formation (4/3 n^3).  The
+    products A^T W and A V of FULL are applied to A^T and A as targets of the QRs at the
+    cost of the products they replace."""
+    m_, n_ = float(m), float(n)
+    extra = 2.0 * n_ ** 3 - 4.0 / 3.0 * n_ ** 3  # V
+    if m == n:
+        extra += 2.0 * n_ ** 3 - 4.0 / 3.0 * n_ ** 3  # U
+    return standard_flops(m, n, q, variant, orth_g) + extra
 
 
 def paper_flops(m: int, n: int, q: int) -> float:
@@ -99,7 +118,7 @@ def cpu_baseline(q: int, variant: str, sample_n: int) -> dict:
     t0 = time.perf_counter()
     oracle.urv(A, q, seed=1812, variant=variant)
     dt = time.perf_counter() - t0
-    fl = executed_flops(sample_n, sample_n, q, variant)
+    fl = standard_flops(sample_n, sample_n, q, variant)
     cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)) or 1)
     return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
             "sample": "oracle PowerURV %s q=%d on %dx%d, sigma_j=1/j^2: %.2f s for %.3e flop"
@@ -117,7 +136,7 @@ def grad_flops(m: int, n: int, q: int, k: int, variant: str = "full") -> dict:
     Qb^T Q, Q S (2mn^2 each) and the solve with R^T (mn^2); with an R
     adjoint R Rb^T adds 2n^3."""
     m, n, k = float(m), float(n), float(k)
-    fwd = executed_flops(m, n, q, variant)
+    fwd = standard_flops(m, n, q, variant)
     loss = 4 * m * n * n + 2 * k * n * n + 8 * m * n * k
     bwd = 5 * m * n * n + 2 * n ** 3 + 4 * m * n * n          # final QR adjoint, Xb V^T, A^T Xb
     per = 5 * n ** 3 + 8 * m * n * n + (5 * m * n * n if variant == "full" else 0.0)
@@ -236,7 +255,7 @@ def bench_batched(steps: int, warmup: int, oracle_sample: int) -> dict:
     e1.record(stream)
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / steps
-    fl = sum(executed_flops(m, n, q, "full") for m, n in zip(ms, ns))
+    fl = sum(standard_flops(m, n, q, "full") for m, n in zip(ms, ns))
     # the largest matrix alone, on one workgroup: the floor of a one-workgroup-per-matrix schedule
     big = int(np.argmax([m * n * n for m, n in zip(ms, ns)]))
     one = urv.BatchPlan([ms[big]], [ns[big]], q=q, seed=1812 + big)
@@ -269,7 +288,7 @@ def bench_batched(steps: int, warmup: int, oracle_sample: int) -> dict:
             A_np = A[i].t().contiguous().t().cpu().double().numpy()
             oracle.urv(A_np, q, seed=1812 + i)
         dt = time.perf_counter() - t0
-        fl_s = sum(executed_flops(ms[i], ns[i], q, "full") for i in idx)
+        fl_s = sum(standard_flops(ms[i], ns[i], q, "full") for i in idx)
         cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)) or 1)
         res["cpu_baseline"] = {"value": fl_s / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
                                "seconds": dt,
@@ -298,7 +317,7 @@ def bench_wide(q: int, variant: str, steps: int, warmup: int) -> dict:
     ms_t = time_factor(B, q, variant, "fp64", steps, warmup, out_t)
     met = urv.metrics(A, *out_w)
     # the tall problem of A^T, plus the m x m QR of its R with reversed columns and the n x m x m product
-    fl = executed_flops(n, m, q, variant) + 8.0 / 3.0 * m ** 3 + 2.0 * n * m * m
+    fl = standard_flops(n, m, q, variant) + 8.0 / 3.0 * m ** 3 + 2.0 * n * m * m
     return {"workload": "A 4000x8000 = (Q1 diag(1/j^2) Q2^T)^T, FP64 %s q=%d, against the tall 8000x4000 A^T"
                         % (variant.upper(), q),
             "ms": ms_w, "ms_tall_transpose": ms_t, "flops_executed": fl,
@@ -322,9 +341,10 @@ def time_factor(A, q: int, variant: str, precision: str, steps: int, warmup: int
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
-        urv.factor(A, q, seed=1812, variant=variant, precision=precision, workspace=ws, out=out)
+        urv.factor(A, q, seed=1812, variant=variant, precision=precision, workspace=ws, out=out, check=False)
     e1.record(stream)
     torch.cuda.synchronize()
+    urv.sync_status()
     return e0.elapsed_time(e1) / steps
 
 
@@ -375,6 +395,30 @@ def compare_precisions(A, q: int, variant: str, ms64: float, met64: dict, steps:
     return res
 
 
+KERNEL_NAMES = {
+    "panel": "cqr_panel_kernel<double> (128-column QR panel; applies the previous block first)",
+    "gemm_nn": "gemm_kernel<double,NN> (every FP64 NN launch: A V and the trailing updates)",
+    "gemm_tn": "gemm_kernel<double,TN> (every FP64 TN launch: Y^T C of the updates)",
+    "gemm_nt": "gemm_kernel<double,NT> (every FP64 NT launch: the reflectors applied to targets)",
+    "gemm_tt": "gemm_kernel<double,TT>",
+}
+
+
+def live_roofline(classes: dict, steps: int) -> dict:
+    """The dominant kernel of the timed steps (most summed time among the library's FP64
+    launch classes, timed live with HIP events on the streams they run on): its algorithmic
+    flops per launch over its mean launch time, against the FP64 MFMA peak."""
+    cls = max(classes, key=lambda c: classes[c]["ms"])
+    v = classes[cls]
+    n = max(v["launches"], 1)
+    launch_ms = v["ms"] / n
+    achieved = v["flops"] / n / (launch_ms * 1e-3) / 1e12 if launch_ms > 0 else 0.0
+    return {"bound": "mfma", "kernel": KERNEL_NAMES[cls], "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+            "launch_ms": launch_ms, "flop_per_launch": v["flops"] / n, "launches_per_step": v["launches"] / steps,
+            "ms_per_step": v["ms"] / steps}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,6 +446,8 @@ def main() -> int:
     ap.add_argument("--factor-only", action="store_true",
                     help="run only two factorisations of a Gaussian A of the bench's shape (for counter "
                          "collection: no input construction through torch) and exit")
+    ap.add_argument("--no-live-timing", action="store_true",
+                    help="do not bracket the library's launches with HIP events during the timed steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only plain 1 GiB device copies (counter calibration) and exit")
     ap.add_argument("--gemm-source-hash", action="store_true",
@@ -482,7 +528,8 @@ def main() -> int:
     torch.cuda.synchronize()
 
     def step():
-        urv.factor(A, q, seed=1812, variant=args.variant, workspace=ws, out=(U, R, V))
+        # asynchronous: the expired-wait status is read once after the timed steps
+        urv.factor(A, q, seed=1812, variant=args.variant, workspace=ws, out=(U, R, V), check=False)
 
     print("[bench] warmup %d" % args.warmup, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -507,10 +554,25 @@ def main() -> int:
     ms = e0.elapsed_time(e1) / args.steps
     bounds = [e0] + marks + [e1]
     step_ms = sorted(bounds[i].elapsed_time(bounds[i + 1]) for i in range(args.steps))
+    urv.sync_status()  # raises if a panel's device-side wait expired in the timed steps
+    classes = None
+    if not args.no_live_timing:
+        # The same steps again with every FP64 launch of the library bracketed by HIP events
+        # on the stream it runs on (the host-side event records slow a step by a few per
+        # cent, so `value` comes from the steps above): per-class time, launches, flops.
+        print("[bench] %d steps with launch timing" % args.steps, file=sys.stderr, flush=True)
+        urv.timing(True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        urv.timing(False)
+        urv.sync_status()
+        classes = {c: urv.timing_read(c) for c in urv.TIMED_CLASSES}
 
     met = urv.metrics(A, U, R, V)
+    fl_std = standard_flops(m, n, q, args.variant)
     fl = executed_flops(m, n, q, args.variant)
-    tflops = fl / (ms * 1e-3) / 1e12
+    tflops = fl_std / (ms * 1e-3) / 1e12
 
     # Dominant kernel: the FP64 MFMA GEMM X = A V (2 m n^2 flop per launch), timed alone on the
     # same stream with HIP events, same shapes and leading dimensions as inside the step.
@@ -585,7 +647,9 @@ def main() -> int:
         "config": {"workload": "PowerURV FP64 %s, A %dx%d = Q1 diag(1/j^2) Q2^T (Haar Q1, Q2), q=%d, G from seed 1812"
                                % (args.variant.upper(), m, n, q),
                    "m": m, "n": n, "q": q, "variant": args.variant, "precision": "fp64"},
+        "flops_standard": fl_std,
         "flops_executed": fl,
+        "tflops_executed": fl / (ms * 1e-3) / 1e12,
         "flops_paper_table1": paper_flops(m, n, q),
         "tflops_at_paper_count": paper_flops(m, n, q) / (ms * 1e-3) / 1e12,
         "frac_fp64_peak": tflops / FP64_MFMA_PEAK_TFLOPS,
@@ -596,10 +660,14 @@ def main() -> int:
         "step_ms": {"median": step_ms[len(step_ms) // 2] if len(step_ms) % 2 else
                     0.5 * (step_ms[len(step_ms) // 2 - 1] + step_ms[len(step_ms) // 2]),
                     "min": step_ms[0], "max": step_ms[-1]},
-        "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double,NN,128x128,4x4 waves> (X = A V)",
-                     "achieved": gemm_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": gemm_tf / FP64_MFMA_PEAK_TFLOPS, "traffic": gemm_traffic(m, n),
-                     "launch_ms": gemm_ms, "flop_per_launch": 2.0 * m * n * n},
+        "roofline": live_roofline(classes, args.steps) if classes else None,
+        "roofline_classes": None if not classes else
+        {c: dict(v, frac=(v["flops"] / (v["ms"] * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS) if v["ms"] else None,
+                 ms_per_step=v["ms"] / args.steps) for c, v in classes.items()},
+        "gemm_av": {"bound": "mfma", "kernel": "gemm_kernel<double,NN,128x128,4x4 waves> (X = A V alone)",
+                    "achieved": gemm_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": gemm_tf / FP64_MFMA_PEAK_TFLOPS, "traffic": gemm_traffic(m, n),
+                    "launch_ms": gemm_ms, "flop_per_launch": 2.0 * m * n * n},
         "mixed_vs_fp64": mixed,
         "m_lt_n": wide,
         "differentiation": grad,

@@ -113,6 +113,18 @@ void urv_opts_init(urv_opts* opts);
 int urv_factor_ex(const void* A, int64_t m, int64_t n, int32_t q, uint64_t seed,
                   double* U, double* R, double* V, const urv_opts* opts);
 
+/* Launch timing, for measurement (not in the paper).  urv_timing(1) clears the
+ * counts and starts bracketing the library's FP64 launches of each class with
+ * HIP events on the stream each runs on; urv_timing(0) stops.  After the
+ * caller has synchronised, urv_timing_read gives (HOST pointers) the summed
+ * elapsed milliseconds, the number of launches and their algorithmic flops:
+ * class 0 the QR panel kernel (Householder QR of its mp x jb panel, plus the
+ * previous block's two products 4 (mp + 128) 128 jb when it applies them),
+ * classes 1..4 the FP64 GEMM tiles NN, TN, NT, TT (2 M N K each).  Unknown
+ * class or null pointers: URV_EINVAL.  The registry is process-wide. */
+int urv_timing(int32_t enable);
+int urv_timing_read(int32_t cls, double* ms, int64_t* launches, double* flops);
+
 /* Waits for the stream, then reports whether any factorisation or QR queued
  * on the current device since the last report had a panel's bounded
  * device-side wait expire (URV_EDEVICE, outputs of that call NaN) or not

@@ -615,6 +615,13 @@ size_t urv_workspace_size(int64_t m, int64_t n, int32_t q, const urv_opts* opts)
   return work_bytes(m, n, mixed, opts && (opts->flags & URV_A_FP32) != 0);
 }
 
+int urv_timing(int32_t enable) { return timing_enable(enable != 0); }
+
+int urv_timing_read(int32_t cls, double* ms, int64_t* launches, double* flops) {
+  clear_last_error();
+  return timing_read(cls, ms, launches, flops);
+}
+
 int urv_sync_status(void* stream) {
   clear_last_error();
   return sync_status(static_cast<hipStream_t>(stream), "urv_sync_status");

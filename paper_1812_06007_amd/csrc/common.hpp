@@ -49,6 +49,18 @@ __device__ inline int xcd_tile_order(int b, int ntiles) {
 }
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// ---------------------------------------------------------------- launch timing
+// Host-side registry of HIP event pairs around the FP64 launches the bench
+// reports (off unless urv_timing(1) is called): each class accumulates the
+// elapsed time, the launch count and the algorithmic flops of its launches.
+enum TimedKernel { kTimedPanel = 0, kTimedGemmNN, kTimedGemmTN, kTimedGemmNT, kTimedGemmTT, kTimedClasses };
+// Records the start event on s; -1 when timing is off.
+int timing_begin(hipStream_t s);
+// Records the end event on s for the launch opened by token.
+void timing_end(int token, int cls, double flops, hipStream_t s);
+int timing_enable(bool on);
+int timing_read(int cls, double* ms, int64_t* launches, double* flops);
+
 // ---------------------------------------------------------------- workspace
 // Bump allocator over one caller- or library-provided device block.
 // With base == nullptr it only measures (used = bytes needed).

@@ -413,10 +413,13 @@ int gemm_partials(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A,
     p.k_chunk = ceil_div(ceil_div(K, cap), BK) * BK;
     p.splits = static_cast<int>(ceil_div(K, p.k_chunk));
   }
+  const int tok = sizeof(T) == 8 ? timing_begin(s) : -1;
   if (!ta && !tb) launch_tiles<T, false, false>(p, M, N, K, T(1), A, lda, B, ldb, T(0), nullptr, M, partial, s);
   else if (ta && !tb) launch_tiles<T, true, false>(p, M, N, K, T(1), A, lda, B, ldb, T(0), nullptr, M, partial, s);
   else if (!ta && tb) launch_tiles<T, false, true>(p, M, N, K, T(1), A, lda, B, ldb, T(0), nullptr, M, partial, s);
   else launch_tiles<T, true, true>(p, M, N, K, T(1), A, lda, B, ldb, T(0), nullptr, M, partial, s);
+  timing_end(tok, ta ? (tb ? kTimedGemmTT : kTimedGemmTN) : (tb ? kTimedGemmNT : kTimedGemmNN),
+             2.0 * static_cast<double>(M) * N * K, s);
   URV_LAUNCHED("gemm_kernel");
   *splits = p.splits;
   return URV_OK;
@@ -444,11 +447,14 @@ int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, const T* A,
     p.k_chunk = ceil_div(K, BK) * BK;
   }
   T* partial = p.splits > 1 ? work : nullptr;
+  const int tok = sizeof(T) == 8 ? timing_begin(s) : -1;
   if (!ta && !tb) launch_tiles<T, false, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
   else if (ta && !tb) launch_tiles<T, true, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
   else if (!ta && tb) launch_tiles<T, false, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
   else launch_tiles<T, true, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, s);
   URV_LAUNCHED("gemm_kernel");
+  timing_end(tok, ta ? (tb ? kTimedGemmTT : kTimedGemmTN) : (tb ? kTimedGemmNT : kTimedGemmNN),
+             2.0 * static_cast<double>(M) * N * K, s);
   if (partial) {
     const int64_t total = M * N;
     splitk_reduce_kernel<<<static_cast<unsigned>(ceil_div(total, 256)), 256, 0, s>>>(

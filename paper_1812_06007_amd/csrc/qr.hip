@@ -2809,10 +2809,16 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       const int64_t k0 = r0 - ext;  // the launch's kernel row 0
       const T* Yprev = prev_j0 >= 0 ? w.Y + prev_j0 + prev_j0 * m : nullptr;
       const T* Tprev = prev_j0 >= 0 ? w.Tm + prev_j0 * NBO : nullptr;
+      const int tok = sizeof(T) == 8 ? timing_begin(s2) : -1;
       cqr_panel_kernel<T><<<static_cast<unsigned>(cqr_wgs(mp + ext)), PANEL_THREADS, 0, s2>>>(
           X + k0 + r0 * ldx, ldx, mp + ext, jbp, w.Y + k0 + r0 * m, m, w.tau + r0, Tp, NBO, panels * NB, err,
           zero_above, pwait, jb2, wf, txch, Yprev, Tprev, ext);
       URV_LAUNCHED("cqr_panel_kernel");
+      // algorithmic flops: Householder QR of the mp x jt panel, and the previous block's
+      // W = Yp^T C and C -= Yp W' over its mp + ext rows
+      const double jt = jbp + jb2, mr = static_cast<double>(mp);
+      timing_end(tok, kTimedPanel,
+                 2.0 * mr * jt * jt - 2.0 / 3.0 * jt * jt * jt + (ext ? 4.0 * (mr + ext) * NB2 * jt : 0.0), s2);
     } else {
       panel_kernel<T><<<P, PANEL_THREADS, 0, s2>>>(X + r0 + r0 * ldx, ldx, mp, jbp, w.Y + r0 + r0 * m, m,
                                                    w.tau + r0, Tp, NBO, w.xch, panels * NB, err, zero_above, join,

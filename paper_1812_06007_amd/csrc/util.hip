@@ -136,6 +136,107 @@ int sumsq(const double* X, int64_t ld, int64_t rows, int64_t cols, double diag, 
 
 }  // namespace
 
+namespace {
+struct TimedLaunch {
+  hipEvent_t a = nullptr, b = nullptr;
+  int cls = -1;
+  double flops = 0;
+};
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<TimedLaunch> pending;
+  double ms[kTimedClasses] = {};
+  int64_t launches[kTimedClasses] = {};
+  double flops[kTimedClasses] = {};
+};
+Timing g_timing;
+
+hipEvent_t take_event() {
+  if (!g_timing.pool.empty()) {
+    hipEvent_t e = g_timing.pool.back();
+    g_timing.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Adds the completed launches to the totals (the caller has synchronised).
+void timing_resolve() {
+  std::vector<TimedLaunch> left;
+  for (TimedLaunch& t : g_timing.pending) {
+    float ms = 0.f;
+    if (t.cls >= 0 && t.a && t.b && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      g_timing.ms[t.cls] += ms;
+      g_timing.launches[t.cls] += 1;
+      g_timing.flops[t.cls] += t.flops;
+    } else if (t.cls >= 0) {
+      (void)hipGetLastError();  // not complete yet: keep it
+      left.push_back(t);
+      continue;
+    }
+    if (t.a) g_timing.pool.push_back(t.a);
+    if (t.b) g_timing.pool.push_back(t.b);
+  }
+  g_timing.pending.swap(left);
+}
+}  // namespace
+
+int timing_begin(hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_timing.mu);
+  if (!g_timing.on) return -1;
+  TimedLaunch t;
+  t.a = take_event();
+  if (!t.a || hipEventRecord(t.a, s) != hipSuccess) return -1;
+  g_timing.pending.push_back(t);
+  return static_cast<int>(g_timing.pending.size()) - 1;
+}
+
+void timing_end(int token, int cls, double flops, hipStream_t s) {
+  if (token < 0) return;
+  std::lock_guard<std::mutex> lock(g_timing.mu);
+  if (token >= static_cast<int>(g_timing.pending.size())) return;
+  TimedLaunch& t = g_timing.pending[token];
+  t.b = take_event();
+  if (!t.b || hipEventRecord(t.b, s) != hipSuccess) return;
+  t.cls = cls;
+  t.flops = flops;
+}
+
+int timing_enable(bool on) {
+  std::lock_guard<std::mutex> lock(g_timing.mu);
+  if (on) {
+    for (int c = 0; c < kTimedClasses; ++c) {
+      g_timing.ms[c] = 0;
+      g_timing.launches[c] = 0;
+      g_timing.flops[c] = 0;
+    }
+    for (TimedLaunch& t : g_timing.pending) {
+      if (t.a) g_timing.pool.push_back(t.a);
+      if (t.b) g_timing.pool.push_back(t.b);
+    }
+    g_timing.pending.clear();
+  }
+  g_timing.on = on;
+  return URV_OK;
+}
+
+int timing_read(int cls, double* ms, int64_t* launches, double* flops) {
+  if (cls < 0 || cls >= kTimedClasses || !ms || !launches || !flops) {
+    set_last_error("urv_timing_read: unknown class or null pointer");
+    return URV_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_timing.mu);
+  timing_resolve();
+  *ms = g_timing.ms[cls];
+  *launches = g_timing.launches[cls];
+  *flops = g_timing.flops[cls];
+  return URV_OK;
+}
+
 int side_stream(SideStream* out) {
   constexpr int kMaxDevices = 64;
   static std::mutex init_mu;

@@ -62,7 +62,7 @@ class UrvGradOpts(ctypes.Structure):
 
 TAPE_MODES = {"all": 0, "v": 1, "none": 2}
 
-EXPORTS = ["urv_opts_init", "urv_factor_ex", "urv_sync_status", "urv_factor", "urv_workspace_size", "urv_gaussian",
+EXPORTS = ["urv_opts_init", "urv_factor_ex", "urv_sync_status", "urv_timing", "urv_timing_read", "urv_factor", "urv_workspace_size", "urv_gaussian",
            "urv_dgemm", "urv_dgemm_noalloc", "urv_qr_pos", "urv_qr_pos_f32", "urv_metrics", "urv_strerror", "urv_last_error",
            "urv_grad_opts_init", "urv_tape_bytes", "urv_grad_workspace_size", "urv_factor_tape",
            "urv_factor_backward", "urv_qr_adjoint", "urv_truncation_loss",
@@ -89,6 +89,9 @@ def lib() -> ctypes.CDLL:
     L.urv_factor_ex.argtypes = [P, I64, I64, I32, U64, P, P, P, ctypes.POINTER(UrvOpts)]
     L.urv_factor.argtypes = [P, I64, I64, I32, U64, P, P, P]
     L.urv_sync_status.argtypes = [P]
+    L.urv_timing.argtypes = [I32]
+    L.urv_timing_read.argtypes = [I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_double)]
     L.urv_workspace_size.argtypes = [I64, I64, I32, ctypes.POINTER(UrvOpts)]
     L.urv_workspace_size.restype = SZ
     L.urv_gaussian.argtypes = [P, I64, I64, I64, U64, U32, I32, P]
@@ -130,7 +133,7 @@ def lib() -> ctypes.CDLL:
                  "urv_metrics", "urv_factor_tape", "urv_factor_backward", "urv_qr_adjoint",
                  "urv_truncation_loss", "urv_batch_create", "urv_batch_set_buffers", "urv_batch_set_config",
                  "urv_batch_get_config", "urv_batch_autotune", "urv_batch_run", "urv_batch_run_graph",
-                 "urv_batch_status", "urv_sync_status"):
+                 "urv_batch_status", "urv_sync_status", "urv_timing", "urv_timing_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -266,6 +269,21 @@ def factor(A, q: int, seed: int = 0, variant: str = "full", precision: str = "fp
     if check:
         sync_status()
     return U, R, V
+
+
+TIMED_CLASSES = {"panel": 0, "gemm_nn": 1, "gemm_tn": 2, "gemm_nt": 3, "gemm_tt": 4}
+
+
+def timing(enable: bool) -> None:
+    """Start (clearing the counts) or stop HIP-event timing of the library's FP64 launches."""
+    _check(lib().urv_timing(int(bool(enable))))
+
+
+def timing_read(cls: str) -> dict:
+    """Summed ms, launch count and algorithmic flops of one timed class (call after a sync)."""
+    ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib().urv_timing_read(TIMED_CLASSES[cls], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)))
+    return {"ms": ms.value, "launches": n.value, "flops": fl.value}
 
 
 def sync_status() -> None:

@@ -1,10 +1,13 @@
 """The benchmark's flop accounting and its one-GPU contract (CPU only).
 
-`value` is executed flops / time, so the counts are pinned here against
-independent figures: the standard LAPACK operation counts written out for
-the benchmark's shapes (GEMM 2mn^2; QR with explicit Q of an m x n matrix
-2(2mn^2 - (2/3)n^3); an n x n QR with Q (8/3)n^3), and the paper's Table 1
-count (leading order, GEMM term 2(2q+1)mn^2)."""
+`value` is standard flops / time, so the counts are pinned here against hand
+counts written as the list of operations the driver (run_factor) performs,
+with the standard LAPACK counts of each: a product with A or A^T 2mn^2; a
+Householder QR of an m x n matrix 2mn^2 - (2/3)n^3, and the same for forming
+its explicit Q; n x n: (4/3)n^3.  The executed count differs where V, and U
+when m == n, are formed by applying the reflectors to an identity (2n^3 each
+for n x n).  The paper's Table 1 count (leading order, GEMM term 2(2q+1)mn^2)
+is pinned too."""
 import importlib.util
 import os
 import subprocess
@@ -23,27 +26,56 @@ def bench():
     return mod
 
 
-@pytest.mark.parametrize("m,n,q,variant,expected", [
-    (8000, 8000, 2, "full", 1.1946666666666667e13),   # 5 GEMMs 5.12e12 + 3 m x n QRs 4.096e12 + 2 n x n 2.731e12
-    (8000, 8000, 2, "half", 9.216e12),
-    (8000, 8000, 1, "full", 7.168e12),
-    (8000, 8000, 1, "half", 5.802666666666667e12),
-    (8000, 8000, 0, "full", 3.754666666666667e12),     # A G, QR of A V, and Qpos(G)
-    (400, 400, 2, "full", 1.4933333333333333e9),
-    (400, 400, 2, "half", 1.152e9),
-    (4000, 4000, 2, "full", 1.4933333333333333e12),    # the Kahan case
-])
-def test_executed_flops(bench, m, n, q, variant, expected):
-    assert bench.executed_flops(m, n, q, variant) == pytest.approx(expected, rel=1e-12)
+def _ops(m, n):
+    prod = 2.0 * m * n * n
+    qr_mn = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+    qr_nn = 4.0 * n ** 3 / 3.0
+    return prod, qr_mn, qr_nn
 
 
-def test_executed_flops_by_hand(bench):
-    m, n, q = 16000, 8000, 2
-    gemm = 5 * 2 * m * n * n
-    qr_mn = 2 * (2 * m * n * n - 2 * n ** 3 / 3)
-    qr_nn = 8 * n ** 3 / 3
-    assert bench.executed_flops(m, n, q, "full") == pytest.approx(gemm + 3 * qr_mn + 2 * qr_nn, rel=1e-12)
-    assert bench.executed_flops(m, n, q, "half") == pytest.approx(gemm + qr_mn + 2 * qr_nn, rel=1e-12)
+def _calls(m, n, q, variant):
+    """The driver's operations in order (run_factor, final_qr)."""
+    prod, qr_mn, qr_nn = _ops(m, n)
+    calls = []
+    if variant == "none":
+        calls += [prod, prod] * q                     # (A^T A)^q G
+        calls += [qr_nn] if q > 0 else [qr_nn]        # V = Qpos((A^T A)^q G), or Qpos(G) when q == 0
+        calls += [prod]                               # X = A V
+    else:
+        calls += [qr_nn, prod] if q == 0 else [prod]  # q == 0: V = Qpos(G), X = A V; else X = A G
+        for _ in range(q):
+            if variant == "full":
+                calls += [qr_mn, prod]                # W = Qpos(X), A^T W
+            else:
+                calls += [prod]                       # A^T X
+            calls += [qr_nn, prod]                    # V = Qpos(.), X = A V
+    calls += [qr_nn]                                  # V formed
+    calls += [qr_mn, qr_mn]                           # A V = U R, U formed
+    return calls
+
+
+@pytest.mark.parametrize("m,n", [(8000, 8000), (16000, 8000), (400, 400), (1200, 600)])
+@pytest.mark.parametrize("q", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", ["full", "half", "none"])
+def test_standard_flops_by_call_list(bench, m, n, q, variant):
+    assert bench.standard_flops(m, n, q, variant) == pytest.approx(sum(_calls(m, n, q, variant)), rel=1e-12)
+
+
+def test_standard_flops_of_the_bench_config(bench):
+    n = 8000.0
+    assert bench.standard_flops(8000, 8000, 2, "full") == pytest.approx(58.0 / 3.0 * n ** 3, rel=1e-12)
+    assert bench.standard_flops(8000, 8000, 2, "half") == pytest.approx(50.0 / 3.0 * n ** 3, rel=1e-12)
+    assert bench.standard_flops(8000, 8000, 2, "full") == pytest.approx(9.898666666666667e12, rel=1e-12)
+
+
+@pytest.mark.parametrize("m,n,extra", [(8000, 8000, 2 * (2.0 - 4.0 / 3.0)), (16000, 8000, 2.0 - 4.0 / 3.0)])
+def test_executed_flops_identity_targets(bench, m, n, extra):
+    """V (and U when m == n) are formed as the reflectors applied to an identity: 2 n^3
+    instead of 4/3 n^3 each."""
+    for variant in ("full", "half"):
+        got = bench.executed_flops(m, n, 2, variant) - bench.standard_flops(m, n, 2, variant)
+        assert got == pytest.approx(extra * n ** 3, rel=1e-12)
+    assert bench.executed_flops(8000, 8000, 2, "full") == pytest.approx(62.0 / 3.0 * 8000.0 ** 3, rel=1e-12)
 
 
 @pytest.mark.parametrize("q,expected", [(0, 1.7066666666666667e12), (1, 5.12e12), (2, 8.533333333333333e12)])
