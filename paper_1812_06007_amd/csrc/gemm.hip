@@ -62,10 +62,16 @@ struct Mma<float> {
 };
 
 constexpr int BK = 32;
+__device__ inline int lrow0(int lane) { return lane & 15; }
 constexpr int PAD = 1;  // LDS row padding (elements): spreads transposed LDS writes over banks
 
-template <class T, bool TA, bool TB, int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(
+// BKT: the k-step (BK, or 16 for short sums, where the halved LDS lets two
+// workgroups share a CU and overlap one's prologue and epilogue with the
+// other's MFMAs).  kPreC: with beta != 0, C is loaded at the start, so its
+// latency hides behind the (short) k loop instead of following it.
+template <class T, bool TA, bool TB, int BM, int BN, int WGM, int WGN, int BKT = BK, bool kPreC = false>
+__global__ __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(BKT < BK ? 4 : 1))) void gemm_kernel(
     int64_t M, int64_t N, int64_t K, T alpha, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T beta, T* __restrict__ C, int64_t ldc,
     T* __restrict__ partial, int64_t k_chunk, int tiles_m, int tiles_n) {
@@ -73,9 +79,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(
   constexpr int NT = 64 * WGM * WGN;             // threads
   constexpr int WM = BM / WGM, WN = BN / WGN;    // wave tile
   constexpr int FM = WM / 16, FN = WN / 16;     // MFMA blocks per wave
-  constexpr int LA = BM * BK / NT, LB = BN * BK / NT;  // loads per thread per step
-  __shared__ T As[2][BK][BM + PAD];
-  __shared__ T Bs[2][BK][BN + PAD];
+  constexpr int LA = BM * BKT / NT, LB = BN * BKT / NT;  // loads per thread per step
+  __shared__ T As[2][BKT][BM + PAD];
+  __shared__ T Bs[2][BKT][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -96,7 +102,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(
 
   const int64_t kb = static_cast<int64_t>(blockIdx.y) * k_chunk;
   const int64_t ke = min(K, kb + k_chunk);
-  const int nk = static_cast<int>(ceil_div(ke - kb, BK));
+  const int nk = static_cast<int>(ceil_div(ke - kb, BKT));
 
   T ra[LA], rb[LB];
   static_assert(LA % 2 == 0 && LB % 2 == 0, "pairs of loads");
@@ -107,17 +113,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(
   // two elements are consecutive in memory (along the operand's contiguous index)
   auto a_idx = [&](int s, int& i, int& k) {
     const int e = 2 * (tid + NT * (s >> 1)) + (s & 1);
-    if (!TA) { i = e % BM; k = e / BM; } else { k = e % BK; i = e / BK; }
+    if (!TA) { i = e % BM; k = e / BM; } else { k = e % BKT; i = e / BKT; }
   };
   auto b_idx = [&](int s, int& j, int& k) {
     const int e = 2 * (tid + NT * (s >> 1)) + (s & 1);
-    if (TB) { j = e % BN; k = e / BN; } else { k = e % BK; j = e / BK; }
+    if (TB) { j = e % BN; k = e / BN; } else { k = e % BKT; j = e / BKT; }
   };
   using V2 = typename Vec2T<T>::type;
   const bool aligned = vec_ok;
   const bool full_mn = (m0 + BM <= M) && (n0 + BN <= N);
   auto load_global = [&](int64_t k0) {
-    if (aligned && full_mn && k0 + BK <= ke) {
+    if (aligned && full_mn && k0 + BKT <= ke) {
 #pragma unroll
       for (int s = 0; s < LA; s += 2) {
         int i, k;
@@ -182,15 +188,27 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(
     load_global(kb);
     store_lds(0);
   }
+  // C of a short sum: loaded now, its latency hidden behind the k loop
+  acc_t cpre[FM][FN];
+  const bool pre_c = kPreC && partial == nullptr && full_mn && beta != T(0);
+  if (pre_c) {
+    const T* cb = C + (m0 + wm * WM + lrow0(lane)) + (n0 + wn * WN) * ldc;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cpre[a][b][r] = cb[a * 16 + (b * 16 + Mma<T>::row(lane >> 4, r)) * ldc];
+  }
   __syncthreads();
 
   const int lrow = lane & 15;  // index within a 16-block
   const int lk = lane >> 4;    // k within a 4-step
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) load_global(kb + static_cast<int64_t>(kt + 1) * BK);
+    if (kt + 1 < nk) load_global(kb + static_cast<int64_t>(kt + 1) * BKT);
 #pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
+    for (int kk = 0; kk < BKT / 4; ++kk) {
       T fa[FM], fb[FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a) fa[a] = As[cur][kk * 4 + lk][wm * WM + a * 16 + lrow];
@@ -225,20 +243,29 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(
   if (full_mn) {
     T* cbase = C + (m0 + wm * WM + lrow) + (n0 + wn * WN) * ldc;
     if (beta != T(0)) {
-      acc_t cv[FM][FN];
+      // all of a group's loads of C before its stores; the short-sum variant (two
+      // workgroups per CU, half the registers) takes one row block of the wave at a time
+      constexpr int EG = (BKT < BK) ? 1 : FM;
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
+      for (int a0 = 0; a0 < FM; a0 += EG) {
+        acc_t cv[EG][FN];
 #pragma unroll
-        for (int b = 0; b < FN; ++b)
+        for (int a = 0; a < EG; ++a)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) cv[a][b][r] = cbase[a * 16 + (b * 16 + Mma<T>::row(lk, r)) * ldc];
+          for (int b = 0; b < FN; ++b)
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
+            for (int r = 0; r < 4; ++r)
+              cv[a][b][r] = pre_c ? cpre[a0 + a][b][r]
+                                  : cbase[(a0 + a) * 16 + (b * 16 + Mma<T>::row(lk, r)) * ldc];
 #pragma unroll
-        for (int b = 0; b < FN; ++b)
+        for (int a = 0; a < EG; ++a)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            cbase[a * 16 + (b * 16 + Mma<T>::row(lk, r)) * ldc] = alpha * acc[a][b][r] + beta * cv[a][b][r];
+          for (int b = 0; b < FN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              cbase[(a0 + a) * 16 + (b * 16 + Mma<T>::row(lk, r)) * ldc] =
+                  alpha * acc[a0 + a][b][r] + beta * cv[a][b][r];
+      }
     } else {
 #pragma unroll
       for (int a = 0; a < FM; ++a)
@@ -314,6 +341,7 @@ __global__ void scale_kernel(int64_t M, int64_t N, T beta, T* __restrict__ C,
 struct Plan {
   int bm, bn, wgm, wgn, tiles_m, tiles_n, splits;
   int64_t k_chunk;
+  bool short_k = false;  // 128 x 128 tiles, k-step 16, 8 waves (two workgroups per CU), C loaded first
 };
 
 Plan make_plan(int64_t M, int64_t N, int64_t K) {
@@ -349,6 +377,19 @@ Plan make_plan(int64_t M, int64_t N, int64_t K) {
   }
   p.k_chunk = ceil_div(ceil_div(K, p.splits), BK) * BK;
   if (K > 0) p.splits = static_cast<int>(ceil_div(K, p.k_chunk));
+  // Sums of at most 256 over many 128 x 128 tiles (the block-reflector updates): a
+  // workgroup's prologue and epilogue are as long as its k loop, so 128 x 64 tiles with
+  // a k-step of 16 (8 waves, 50 KB of LDS, at most 128 registers) let two workgroups
+  // share each CU, one's MFMAs covering the other's loads and stores of C
+  // (URV_GEMM_SHORTK=0: off, for tuning).
+  const char* sk = std::getenv("URV_GEMM_SHORTK");
+  p.short_k = K > 0 && K <= 256 && p.bm == 128 && p.bn == 128 && p.splits == 1 && !(sk && std::atoi(sk) == 0);
+  if (p.short_k) {
+    p.bn = 64;
+    p.wgm = 4;
+    p.wgn = 2;
+    p.tiles_n = static_cast<int>(ceil_div(N, 64));
+  }
   return p;
 }
 
@@ -357,6 +398,11 @@ void launch_tiles(const Plan& p, int64_t M, int64_t N, int64_t K, T alpha, const
                   int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc,
                   T* partial, hipStream_t s) {
   const dim3 grid(p.tiles_m * p.tiles_n, p.splits);
+  if (p.short_k) {
+    gemm_kernel<T, TA, TB, 128, 64, 4, 2, 16, false><<<grid, 64 * 8, 0, s>>>(
+        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, p.k_chunk, p.tiles_m, p.tiles_n);
+    return;
+  }
 #define URV_GEMM_CASE(TBM, TBN, GM, GN)                                                          \
   if (p.bm == TBM && p.bn == TBN && p.wgm == GM && p.wgn == GN) {                               \
     gemm_kernel<T, TA, TB, TBM, TBN, GM, GN><<<grid, 64 * GM * GN, 0, s>>>(                       \

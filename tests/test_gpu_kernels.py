@@ -46,7 +46,9 @@ def test_gaussian_layout(urv):
 
 # ---------------------------------------------------------------- GEMM
 SHAPES = [(1, 1, 1), (7, 5, 3), (64, 64, 64), (65, 129, 17), (128, 128, 128), (300, 200, 513),
-          (64, 300, 5000), (64, 64, 20000), (1, 700, 2049), (257, 1, 300)]
+          (64, 300, 5000), (64, 64, 20000), (1, 700, 2049), (257, 1, 300),
+          # short sums over >= 256 tiles of 128 x 128: the 128 x 64, k-step 16 variant (edge tiles in m and n)
+          (2100, 2050, 200), (2048, 2048, 128)]
 
 
 @pytest.mark.parametrize("ta", [False, True])
