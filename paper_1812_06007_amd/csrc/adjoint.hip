@@ -9,6 +9,11 @@
 // the published one (Walter & Lehmann 2018; Seeger et al. 2017):
 //   M = R Rb^T - Qb^T Q,   S = the symmetric matrix from M's lower triangle,
 //   Xb = (Qb + Q S) R^{-T}.
+// For square X (m = n) the last column of Qb + Q S is (I - Q Q^T) Qb(:,n) +
+// R(n,n) Q Rb(:,n), whose first term vanishes: Xb(:,n) = Q Rb(:,n) is set
+// directly and the solve starts from it.  The last pivot of a numerically
+// singular square iterate is rounding noise (it can be exactly zero), and the
+// quotient of two noise terms would otherwise enter every other column.
 // The reverse sweep visits the products in the opposite order: P = A B gives
 // Ab += Pb B^T, Bb = A^T Pb; P = A^T B gives Ab += B Pb^T, Bb = A Pb.
 //
@@ -62,11 +67,11 @@ __global__ void copyltu_kernel(T* __restrict__ M, int64_t n, int64_t ld) {
 // l >= j of X(:,l) R(j,l), so lane i takes its row's last unknown first and
 // removes it from the others: x_j = b_j / R(j,j), b_l -= x_j R(l,j) for l < j.
 // Past nb the block is padded with the identity so the loops have fixed trip
-// counts.
+// counts.  With last_given, column nb - 1 of B already holds its x.
 template <class T>
 __global__ __launch_bounds__(kTrsmThreads) void trsm_rt_block_kernel(T* __restrict__ B, int64_t ldb, int64_t m,
                                                                      int nb, const T* __restrict__ R,
-                                                                     int64_t ldr) {
+                                                                     int64_t ldr, int last_given) {
   __shared__ T Rs[kTrsmNB][kTrsmNB + 1];  // Rs[j][l] = R(l, j), column j contiguous
   for (int e = threadIdx.x; e < kTrsmNB * kTrsmNB; e += kTrsmThreads) {
     const int l = e % kTrsmNB, j = e / kTrsmNB;
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(kTrsmThreads) void trsm_rt_block_kernel(T* __restri
   for (int j = 0; j < kTrsmNB; ++j) b[j] = (j < nb) ? B[i + j * ldb] : T(0);
 #pragma unroll
   for (int j = kTrsmNB - 1; j >= 0; --j) {
-    const T x = b[j] / Rs[j][j];
+    const T x = (last_given && j == nb - 1) ? b[j] : b[j] / Rs[j][j];
     b[j] = x;
 #pragma unroll
     for (int l = 0; l < j; ++l) b[l] = fma(-x, Rs[j][l], b[l]);
@@ -256,20 +261,21 @@ int gemm_w(bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, const T* 
 
 // B (m x n, ldb) <- B R^{-T}, R upper triangular n x n.  The trailing block
 // is solved first; X2 R12^T is then removed from the leading columns by one
-// GEMM, and the leading block is solved.
+// GEMM, and the leading block is solved.  With last_given, B's last column
+// already holds its x (no division by R(n,n)).
 template <class T>
 int trsm_rt(T* B, int64_t ldb, int64_t m, int64_t n, const T* R, int64_t ldr, const GradWork<T>& w,
-            hipStream_t s) {
+            hipStream_t s, bool last_given = false) {
   if (m == 0 || n == 0) return URV_OK;
   if (n <= kTrsmNB) {
     trsm_rt_block_kernel<T><<<grid_for(m, kTrsmThreads), kTrsmThreads, 0, s>>>(B, ldb, m, static_cast<int>(n),
-                                                                               R, ldr);
+                                                                               R, ldr, last_given ? 1 : 0);
     URV_LAUNCHED("trsm_rt_block_kernel");
     return URV_OK;
   }
   const int64_t n1 = std::max<int64_t>(kTrsmNB, (n / 2) / kTrsmNB * kTrsmNB);
   T* B2 = B + n1 * ldb;
-  URV_TRY(trsm_rt<T>(B2, ldb, m, n - n1, R + n1 + n1 * ldr, ldr, w, s));            // X2 = B2 R22^{-T}
+  URV_TRY(trsm_rt<T>(B2, ldb, m, n - n1, R + n1 + n1 * ldr, ldr, w, s, last_given));  // X2 = B2 R22^{-T}
   URV_TRY(gemm_w<T>(false, true, m, n1, n - n1, T(-1), B2, ldb, R + n1 * ldr, ldr, T(1), B, ldb, w, s));  // B1 -= X2 R12^T
   return trsm_rt<T>(B, ldb, m, n1, R, ldr, w, s);                                  // X1 = B1 R11^{-T}
 }
@@ -285,7 +291,15 @@ int qr_adjoint(const T* Q, const T* R, int64_t m, int64_t n, const T* Qb, const 
   URV_LAUNCHED("copyltu_kernel");
   if (Qb) URV_TRY(copy2d<T>(Qb, m, Xb, m, m, n, s));
   URV_TRY(gemm_w<T>(false, false, m, n, n, T(1), Q, m, w.M, n, Qb ? T(1) : T(0), Xb, m, w, s));     // + Q S
-  return trsm_rt<T>(Xb, m, m, n, R, n, w, s);                                                     // R^{-T}
+  const bool square = m == n;
+  if (square) {  // Xb(:,n) = Q Rb(:,n): (I - Q Q^T) Qb(:,n) is zero for square Q
+    T* xl = Xb + (n - 1) * m;
+    if (Rb)
+      URV_TRY(gemm_w<T>(false, false, m, 1, n, T(1), Q, m, Rb + (n - 1) * n, n, T(0), xl, m, w, s));
+    else
+      URV_TRY(fill2d<T>(xl, m, m, 1, T(0), s));
+  }
+  return trsm_rt<T>(Xb, m, m, n, R, n, w, s, square);                                             // R^{-T}
 }
 
 // One power step from V_in: P (W_t or X_t), Rw (FULL), then V_out = Qpos(A^T P), Rv.

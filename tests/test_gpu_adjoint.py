@@ -80,6 +80,25 @@ def test_qr_adjoint_matches_oracle(urv, orc, dtype, shape, which):
     assert _rel(to_np(out), ref) <= TOL[(dtype, "qr")]
 
 
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [129, 64, 1])
+def test_qr_adjoint_square_zero_last_pivot(urv, orc, dtype, n):
+    # A numerically singular square X can leave R(n, n) = 0 exactly.  The
+    # adjoint then stays finite and equals the limit R(n, n) -> 0 of the
+    # oracle's: at R(n, n) = 1e-6 the oracle differs from that limit by terms
+    # of order 1e-6 (R(n, n) Rb) and 1e-16 / 1e-6 ((I - Q Q^T) Qb / R(n, n)).
+    announce("qr_adjoint zero pivot", dtype, n)
+    rng = gen.generator(n + 31, 7)
+    Q, R = orc.qr_pos(rng.standard_normal((n, n)))
+    dQ, dR = rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    Rz, Re = R.copy(), R.copy()
+    Rz[-1, -1], Re[-1, -1] = 0.0, 1e-6
+    ref = adjoint.qr_adjoint(Q, Re, dQ, dR)
+    out = to_np(urv.qr_adjoint(_dev(Q, dtype), _dev(Rz, dtype), _dev(dQ, dtype), _dev(dR, dtype)))
+    assert np.isfinite(out).all()
+    assert _rel(out, ref) <= (1e-5 if dtype == "fp64" else 1e-4)
+
 # ---------------------------------------------------------------- the chain
 def _inputs(kind, m, n, k, seed):
     if kind == "spike":

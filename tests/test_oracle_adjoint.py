@@ -83,6 +83,22 @@ def test_qr_adjoint_finite_differences(m, n):
     assert _rel(g, _fd_grad(f, X, 1e-6)) < 1e-7
 
 
+
+@pytest.mark.parametrize("n", [1, 6, 40])
+def test_qr_adjoint_square_last_column(n):
+    # Q of a square X does not depend on X's last column (it completes the
+    # others to an orthonormal basis) and R's last column is Q^T x_n, so the
+    # last column of the adjoint is Q Rb(:, n): (I - Q Q^T) Qb(:, n) = 0.
+    r = _rng(900 + n)
+    X = r.standard_normal((n, n))
+    Cq = r.standard_normal((n, n))
+    Cr = r.standard_normal((n, n))
+    Q, R = oracle.qr_pos(X)
+    g = adjoint.qr_adjoint(Q, R, Cq, Cr)
+    assert np.abs(g[:, -1] - Q @ np.triu(Cr)[:, -1]).max() <= 1e-12 * np.abs(g).max()
+    g0 = adjoint.qr_adjoint(Q, R, Cq, None)
+    assert np.abs(g0[:, -1]).max() <= 1e-12 * np.abs(g0).max()
+
 def _chain_fd_error(m, n, q, k, variant, seed):
     r = _rng(seed)
     A = r.standard_normal((m, n))
