@@ -141,6 +141,7 @@ struct QrWorkT {
   // updates of the next two column blocks (caller's stream)
   T* W1n = nullptr;         // 2 kPanelNB x 2 kPanelNB
   T* W2n = nullptr;         // 2 kPanelNB x 2 kPanelNB
+  T* Tq = nullptr;          // 4 kPanelNB x 4 kPanelNB: joined T of the block pair the updates apply
   T* gemm_work_n = nullptr;
   size_t gemm_work_n_elems = 0;
   // scratch of the block factorisations, which run on a second stream

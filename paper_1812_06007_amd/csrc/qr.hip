@@ -2506,33 +2506,58 @@ __global__ __launch_bounds__(1024) void t_join_kernel(T* __restrict__ Tb, int ld
 }
 
 // W2 = T^T W1 with W1 = sum_z P[z] (jb x N each, packed, z ascending) and T
-// upper triangular (ld ldt): the middle factor of (I - Y T^T Y^T) C, fused with
-// the split-K reduction of W1 = Y^T C.  Four columns per workgroup.
+// upper triangular (ld ldt; entries below its diagonal are not read): the
+// middle factor of (I - Y T^T Y^T) C, fused with the split-K reduction of
+// W1 = Y^T C.  A workgroup takes RT_CW columns: their W1 into LDS (each entry
+// summed over the splits in order), then T^T W1 on the matrix cores, T staged
+// through LDS RT_KC rows at a time; row blocks of T^T past a chunk's
+// diagonal skip it.  jb <= RT_JB (the widest outer block).
+constexpr int RT_CW = 32, RT_KC = 32, RT_JB = 4 * NB;
 template <class T>
 __global__ __launch_bounds__(256) void reduce_tmul_kernel(int jb, int64_t N, int splits, const T* __restrict__ P,
                                                           const T* __restrict__ Tm, int ldt, T* __restrict__ W2,
                                                           int64_t ldw2) {
-  constexpr int CW = 4;
-  __shared__ T w1[CW][4 * NB + 1];
-  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * CW;
-  const int cols = static_cast<int>(min<int64_t>(CW, N - c0));
+  __shared__ T w1[RT_JB][RT_CW + 1];  // W1(k, j)
+  __shared__ T ts[RT_KC][RT_JB + 1];  // T(k0 + r, i)
+  const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * RT_CW;
+  const int cols = static_cast<int>(min<int64_t>(RT_CW, N - c0));
+  const int jb16 = (jb + 15) & ~15;
   const int64_t slice = static_cast<int64_t>(jb) * N;
-  for (int e = threadIdx.x; e < jb * cols; e += blockDim.x) {
-    const int k = e % jb, jj = e / jb;
-    w1[jj][k] = sum_splits(P + (c0 + jj) * jb + k, splits, slice);
+  for (int e = tid; e < jb16 * RT_CW; e += 256) {
+    const int k = e % jb16, jj = e / jb16;
+    w1[k][jj] = (k < jb && jj < cols) ? sum_splits(P + (c0 + jj) * jb + k, splits, slice) : T(0);
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < jb * cols; e += blockDim.x) {
-    const int i = e % jb, jj = e / jb;
-    const T* tcol = Tm + static_cast<int64_t>(i) * ldt;
-    T a0 = 0, a1 = 0;
-    int k = 0;
-    for (; k + 1 <= i; k += 2) {
-      a0 += tcol[k] * w1[jj][k];
-      a1 += tcol[k + 1] * w1[jj][k + 1];
+  // tiles of the jb16 x RT_CW result: t = 2 (row block) + (column block), wave g takes t = g + 4q
+  constexpr int QMAX = 2 * RT_JB / 16 / 4;
+  const int ntiles = 2 * (jb16 / 16);
+  TileAcc<T> acc[QMAX];
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) tile_zero<T>(acc[q]);
+  for (int kc = 0; kc < jb16; kc += RT_KC) {
+    const int nk = min(RT_KC, jb16 - kc);
+    __syncthreads();  // w1 written (first chunk), or the previous chunk's products done
+    for (int e = tid; e < RT_KC * jb16; e += 256) {
+      const int r = e % RT_KC, i = e / RT_KC, k = kc + r;
+      ts[r][i] = (r < nk && k < jb && i < jb && k <= i) ? Tm[k + static_cast<int64_t>(i) * ldt] : T(0);
     }
-    if (k <= i) a0 += tcol[k] * w1[jj][k];
-    W2[i + (c0 + jj) * ldw2] = a0 + a1;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int t = g + 4 * q;
+      const int i0 = (t >> 1) * 16, j0 = (t & 1) * 16;
+      if (t < ntiles && kc <= i0 + 15)
+        tile_mm<T>(acc[q], [&](int i, int k) { return ts[k - kc][i]; }, [&](int k, int j) { return w1[k][j]; }, i0,
+                   j0, kc, nk, c);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const int t = g + 4 * q;
+    if (t < ntiles)
+      tile_each<T>(acc[q], (t >> 1) * 16, (t & 1) * 16, c, [&](int i, int j, T v) {
+        if (i < jb && j < cols) W2[i + (c0 + j) * ldw2] = v;
+      });
   }
 }
 
@@ -2602,6 +2627,15 @@ bool panel_chol() {
   return !(e && std::atoi(e) == 0);
 }
 
+// Whether the trailing updates apply pairs of 128-column blocks at once (k = 256) once
+// the pair's second block is factored (URV_BULK_PAIRS=1, for tuning).  Off: the pair's
+// update of the rest starts a block later and the chain waits for it (measured on
+// MI355X at n = 8000, q = 2: FULL 288 ms with pairs against 271, HALF 222 against 213).
+bool bulk_pairs() {
+  const char* e = std::getenv("URV_BULK_PAIRS");
+  return e && std::atoi(e) == 1;
+}
+
 // Whether targets take pairs of 128-column blocks (URV_TARGET_PAIRS=0 turns it off, for tuning).
 bool target_pairs() {
   const char* e = std::getenv("URV_TARGET_PAIRS");
@@ -2638,7 +2672,7 @@ PanelWait panel_wait() {
 }
 
 struct QrSizes {
-  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f, wn, gemm_work_n, tp, jxch, txch;
+  size_t y, t, tau, w, xch, sync, gemm_work, wb, gemm_work_b, wf, gemm_work_f, wn, gemm_work_n, tp, tq, jxch, txch;
 };
 
 // Words of the exchange of the streaming panel: the units' R, U^-1 and T, the 64 x 64 sums, the flags.
@@ -2682,6 +2716,14 @@ QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
       gw = std::max(gw, gemm_partials_elems(jb, std::max<int64_t>(nc - nn - nn2, 0), mp));
       gw = std::max(gw, gemm_work_elems(jb, nc - nn, mp));
       gw = std::max(gw, gemm_work_elems(jb, n - j0, mp));
+      if (nbo == NB2 && j0 >= NB2) {
+        // block j0 closes the pair that starts one block earlier: its joined T (S of the
+        // pair), the pair on block j0 + 2 (caller's stream) and on the rest (fourth stream)
+        const int64_t mpp = m - (j0 - NB2);
+        gwn = std::max(gwn, gemm_work_elems(NB2, NB2, mpp));
+        gwn = std::max(gwn, gemm_partials_elems(2 * NB2, nn2, mpp));
+        gw = std::max(gw, gemm_partials_elems(2 * NB2, std::max<int64_t>(nc - nn - nn2, 0), mpp));
+      }
       if (target_rows > 0) {
         gwf = std::max(gwf, gemm_work_elems(target_rows, jb, mp));
         gwf = std::max(gwf, gemm_work_elems(NB2, NB2, mp));  // S of a block pair
@@ -2695,6 +2737,7 @@ QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
   z.gemm_work_f = gwf;
   z.tp = target_rows > 0 ? static_cast<size_t>(NBO) * n : 0;
   z.wn = static_cast<size_t>(NBO) * NBO;
+  z.tq = static_cast<size_t>(NBO) * NBO;
   z.gemm_work_n = gwn;
   return z;
 }
@@ -2738,6 +2781,7 @@ void qr_work_carve(Arena& a, int64_t m, int64_t n, QrWorkT<T>& w, int64_t target
   w.Tp = a.take<T>(z.tp);
   w.W1n = a.take<T>(z.wn);
   w.W2n = a.take<T>(z.wn);
+  w.Tq = a.take<T>(z.tq);
   w.gemm_work_n = a.take<T>(z.gemm_work_n);
   w.gemm_work_n_elems = z.gemm_work_n;
 }
@@ -2850,7 +2894,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       int splits = 0;
       URV_TRY(gemm_partials<T>(true, false, jb1, jb2, mp, Yb, m, C2, ldx, w.gemm_work_b, w.gemm_work_b_elems,
                                &splits, s2));
-      reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(jb2, 4)), 256, 0, s2>>>(
+      reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(jb2, RT_CW)), 256, 0, s2>>>(
           jb1, jb2, splits, w.gemm_work_b, Tp, NBO, w.W2b, NBO);
       URV_LAUNCHED("reduce_tmul_kernel");
       URV_TRY(gemm<T>(false, false, mp, jb2, jb1, T(-1), Yb, m, w.W2b, NBO, T(1), C2, ldx, nullptr, 0, s2));
@@ -2893,7 +2937,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       int splits = 0;
       URV_TRY(gemm_partials<T>(true, false, ja, jbb, mp, Ya, m, CB, ldx, w.gemm_work_b, w.gemm_work_b_elems,
                                &splits, s2));
-      reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(jbb, 4)), 256, 0, s2>>>(
+      reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(jbb, RT_CW)), 256, 0, s2>>>(
           ja, jbb, splits, w.gemm_work_b, Tb, NBO, w.W2b, NBO);
       URV_LAUNCHED("reduce_tmul_kernel");
       URV_TRY(gemm<T>(false, false, mp, jbb, ja, T(-1), Ya, m, w.W2b, NBO, T(1), CB, ldx, nullptr, 0, s2));
@@ -2913,12 +2957,13 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   // column blocks on the caller's stream, the bulk on the fourth stream (own scratch each).
   const hipStream_t s4 = side.stream4;
   enum { kOnPanelStream, kOnCallerStream, kOnBulkStream };
-  auto apply_block = [&](int64_t j0, int64_t c0, int64_t nc, int where) -> int {
+  // With jbo > 0 the reflectors are the jbo columns from j0 with T at Tbo (ld NBO): a block pair.
+  auto apply_block = [&](int64_t j0, int64_t c0, int64_t nc, int where, int jbo = 0, const T* Tbo = nullptr) -> int {
     if (nc <= 0) return URV_OK;
-    const int jb = static_cast<int>(std::min<int64_t>(nbo, n - j0));
+    const int jb = jbo > 0 ? jbo : static_cast<int>(std::min<int64_t>(nbo, n - j0));
     const int64_t mp = m - j0;
     const T* Yb = w.Y + j0 + j0 * m;
-    const T* Tb = w.Tm + j0 * NBO;
+    const T* Tb = Tbo ? Tbo : w.Tm + j0 * NBO;
     T* Cb = X + j0 + c0 * ldx;
     const bool bulk = where == kOnBulkStream, panel_side = where == kOnPanelStream;
     const hipStream_t st = bulk ? s4 : (panel_side ? s2 : s);
@@ -2929,11 +2974,34 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     (void)W1;
     int splits = 0;
     URV_TRY(gemm_partials<T>(true, false, jb, nc, mp, Yb, m, Cb, ldx, gw, gwe, &splits, st));   // Y^T C
-    reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(nc, 4)), 256, 0, st>>>(jb, nc, splits, gw, Tb, NBO,
+    reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(nc, RT_CW)), 256, 0, st>>>(jb, nc, splits, gw, Tb, NBO,
                                                                                    W2, NBO);  // T^T (Y^T C)
     URV_LAUNCHED("reduce_tmul_kernel");
     URV_TRY(gemm<T>(false, false, mp, nc, jb, T(-1), Yb, m, W2, NBO, T(1), Cb, ldx, nullptr, 0, st));
     return URV_OK;
+  };
+
+  // Joined T of the 128-column blocks A at j0 and B at j0 + NB2 (B may be narrower):
+  // P = [[T_A, -T_A (Y_A^T Y_B) T_B], [0, T_B]] (ld NBO), on stream st with its own scratch.
+  // Y_B is zero in the rows of A, so S = Y_A^T Y_B runs over all rows from j0.
+  auto pair_t = [&](int64_t j0, T* P, T* W1, T* W2, T* gw, size_t gwe, hipStream_t st) -> int {
+    const int64_t jblk = j0 + NB2;
+    const int jbb = static_cast<int>(std::min<int64_t>(NB2, n - jblk));
+    const int64_t mp = m - j0;
+    const T* TA = w.Tm + j0 * NBO;
+    const T* TB = w.Tm + jblk * NBO;
+    const T* Ya = w.Y + j0 + j0 * m;
+    copy_block_kernel<T><<<static_cast<unsigned>(ceil_div(NB2 * NB2, 256)), 256, 0, st>>>(TA, NBO, P, NBO, NB2, NB2);
+    URV_LAUNCHED("copy_block_kernel");
+    copy_block_kernel<T><<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(jbb) * jbb, 256)), 256, 0, st>>>(
+        TB, NBO, P + NB2 + static_cast<int64_t>(NB2) * NBO, NBO, jbb, jbb);
+    URV_LAUNCHED("copy_block_kernel");
+    URV_TRY(gemm<T>(false, false, jbb, NB2, 0, T(0), P, NBO, P, NBO, T(0), P + NB2, NBO, nullptr, 0, st));
+    URV_TRY(gemm<T>(true, false, NB2, jbb, mp, T(1), Ya, m, Ya + static_cast<int64_t>(NB2) * m, m, T(0), W1, NB2,
+                    gw, gwe, st));                                                             // S = Y_A^T Y_B
+    URV_TRY(gemm<T>(false, false, NB2, jbb, jbb, T(1), W1, NB2, TB, NBO, T(0), W2, NB2, nullptr, 0, st));  // S T_B
+    return gemm<T>(false, false, NB2, jbb, NB2, T(-1), TA, NBO, W2, NB2, T(0), P + static_cast<int64_t>(NB2) * NBO,
+                   NBO, nullptr, 0, st);                                                       // -T_A S T_B
   };
 
   // Z <- Z (I - Y T Y^T) for the block at j0 and every target, on the third stream.
@@ -2950,26 +3018,9 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       if (!second && jblk + NB2 < n) return URV_OK;  // wait for the pair's second block
       if (second) {
         j0 = jblk - NB2;
-        const int jbb = static_cast<int>(std::min<int64_t>(NB2, n - jblk));
-        jb = NB2 + jbb;
-        const int64_t mp = m - j0;
+        jb = NB2 + static_cast<int>(std::min<int64_t>(NB2, n - jblk));
         T* P = w.Tp + j0 * NBO;
-        const T* TA = w.Tm + j0 * NBO;
-        const T* TB = w.Tm + jblk * NBO;
-        const T* Ya = w.Y + j0 + j0 * m;
-        copy_block_kernel<T><<<static_cast<unsigned>(ceil_div(NB2 * NB2, 256)), 256, 0, s3>>>(TA, NBO, P, NBO, NB2,
-                                                                                             NB2);
-        URV_LAUNCHED("copy_block_kernel");
-        copy_block_kernel<T><<<static_cast<unsigned>(ceil_div(static_cast<int64_t>(jbb) * jbb, 256)), 256, 0, s3>>>(
-            TB, NBO, P + NB2 + static_cast<int64_t>(NB2) * NBO, NBO, jbb, jbb);
-        URV_LAUNCHED("copy_block_kernel");
-        URV_TRY(gemm<T>(false, false, jbb, NB2, 0, T(0), P, NBO, P, NBO, T(0), P + NB2, NBO, nullptr, 0, s3));
-        URV_TRY(gemm<T>(true, false, NB2, jbb, mp, T(1), Ya, m, Ya + static_cast<int64_t>(NB2) * m, m, T(0), w.W1f,
-                        NB2, w.gemm_work_f, w.gemm_work_f_elems, s3));                           // S = Y_A^T Y_B
-        URV_TRY(gemm<T>(false, false, NB2, jbb, jbb, T(1), w.W1f, NB2, TB, NBO, T(0), w.W2f, NB2, nullptr, 0,
-                        s3));                                                                     // S T_B
-        URV_TRY(gemm<T>(false, false, NB2, jbb, NB2, T(-1), TA, NBO, w.W2f, NB2, T(0),
-                        P + static_cast<int64_t>(NB2) * NBO, NBO, nullptr, 0, s3));               // -T_A S T_B
+        URV_TRY(pair_t(j0, P, w.W1f, w.W2f, w.gemm_work_f, w.gemm_work_f_elems, s3));
         Tb = P;
       }
     }
@@ -3004,6 +3055,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   // waits for still run (measured slower with the previous block fused); the separate
   // near update is faster queued early.
   const bool early = panel_early(!prev_fused);
+  const bool pair_bulk = nbo == NB2 && bulk_pairs();
   const int64_t lag = target_lag();
   int64_t tgt_next = 0;  // first block whose targets are not yet queued
   URV_HIP(hipEventRecord(side.ev_next, s));      // the cleared flags and slots
@@ -3056,8 +3108,20 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     if (j2 >= n) continue;
     // the block after next, which needs the previous bulk update first
     const int64_t nn2 = std::min<int64_t>(nbo, n - j2);
+    // With block pairs, block j0 closes a pair when its index is odd: the pair (k = 256)
+    // goes to block j2 and, below, to the rest; a block that opens a pair updates only
+    // block j2 (it reaches the columns beyond with its pair).  Block j2 still gets the
+    // blocks in order: the previous pair's bulk update covers it and comes first.
+    const bool closes = pair_bulk && (j0 / NB2) % 2 == 1;
     if (bulk_pending) URV_HIP(hipStreamWaitEvent(s, side.ev_bulk, 0));
-    URV_TRY(apply_block(j0, j2, nn2, kOnCallerStream));
+    if (closes) {
+      // the pair's T (into Tq, which the previous pair's bulk update has finished reading)
+      URV_TRY(pair_t(j0 - NB2, w.Tq, w.W1n, w.W2n, w.gemm_work_n, w.gemm_work_n_elems, s));
+      URV_HIP(hipEventRecord(side.ev_pair, s));
+      URV_TRY(apply_block(j0 - NB2, j2, nn2, kOnCallerStream, 2 * NB2, w.Tq));
+    } else {
+      URV_TRY(apply_block(j0, j2, nn2, kOnCallerStream));
+    }
     if (prev_fused) {
       // block j2's columns now hold every share but block j1's, which its factorisation applies
       signal_kernel<<<1, 64, 0, s>>>(ready + j2 / NB, 1u);
@@ -3067,10 +3131,16 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     near_pending = true;
     const int64_t j3 = j2 + nn2;
     if (j3 >= n) continue;
+    if (pair_bulk && !closes) continue;  // block j1 closes the pair and has j2 + nn2 < n too
     // the rest, beside the chain: needs block j0's reflectors only (its columns are not the
-    // near updates', and the previous bulk update is ahead of it on s4)
-    URV_HIP(hipStreamWaitEvent(s4, ev_fact[par], 0));
-    URV_TRY(apply_block(j0, j3, n - j3, kOnBulkStream));
+    // near updates', and the previous bulk update is ahead of it on s4), or the pair's T
+    if (closes) {
+      URV_HIP(hipStreamWaitEvent(s4, side.ev_pair, 0));
+      URV_TRY(apply_block(j0 - NB2, j3, n - j3, kOnBulkStream, 2 * NB2, w.Tq));
+    } else {
+      URV_HIP(hipStreamWaitEvent(s4, ev_fact[par], 0));
+      URV_TRY(apply_block(j0, j3, n - j3, kOnBulkStream));
+    }
     URV_HIP(hipEventRecord(side.ev_bulk, s4));
     bulk_pending = true;
   }
