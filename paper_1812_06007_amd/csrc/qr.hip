@@ -2509,27 +2509,59 @@ __global__ __launch_bounds__(1024) void t_join_kernel(T* __restrict__ Tb, int ld
 // upper triangular (ld ldt; entries below its diagonal are not read): the
 // middle factor of (I - Y T^T Y^T) C, fused with the split-K reduction of
 // W1 = Y^T C.  A workgroup takes RT_CW columns: their W1 into LDS (each entry
-// summed over the splits in order), then T^T W1 on the matrix cores, T staged
-// through LDS RT_KC rows at a time; row blocks of T^T past a chunk's
-// diagonal skip it.  jb <= RT_JB (the widest outer block).
-constexpr int RT_CW = 32, RT_KC = 32, RT_JB = 4 * NB;
-template <class T>
+// summed over the splits in ascending order, a thread's entries of two splits
+// loaded together), then T^T W1 on the matrix cores, T staged through LDS
+// RT_KC rows at a time; row blocks of T^T past a chunk's diagonal skip it.
+// jb <= RJB (128, or 256 for the widest outer block).
+constexpr int RT_CW = 32, RT_KC = 32;
+template <class T, int RJB>
 __global__ __launch_bounds__(256) void reduce_tmul_kernel(int jb, int64_t N, int splits, const T* __restrict__ P,
                                                           const T* __restrict__ Tm, int ldt, T* __restrict__ W2,
                                                           int64_t ldw2) {
-  __shared__ T w1[RT_JB][RT_CW + 1];  // W1(k, j)
-  __shared__ T ts[RT_KC][RT_JB + 1];  // T(k0 + r, i)
+  __shared__ T w1[RJB][RT_CW + 1];  // W1(k, j)
+  __shared__ T ts[RT_KC][RJB + 1];  // T(k0 + r, i)
   const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
   const int64_t c0 = static_cast<int64_t>(blockIdx.x) * RT_CW;
   const int cols = static_cast<int>(min<int64_t>(RT_CW, N - c0));
   const int jb16 = (jb + 15) & ~15;
   const int64_t slice = static_cast<int64_t>(jb) * N;
-  for (int e = tid; e < jb16 * RT_CW; e += 256) {
-    const int k = e % jb16, jj = e / jb16;
-    w1[k][jj] = (k < jb && jj < cols) ? sum_splits(P + (c0 + jj) * jb + k, splits, slice) : T(0);
+  constexpr int EPT = RJB * RT_CW / 256;  // entries of W1 per thread
+  int64_t off[EPT];
+  bool live[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = tid + 256 * u, k = e % jb16, jj = e / jb16;
+    live[u] = e < jb16 * RT_CW && k < jb && jj < cols;
+    off[u] = (c0 + jj) * jb + k;
+  }
+  T sum[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) sum[u] = T(0);
+  int z = 0;
+  for (; z + 2 <= splits; z += 2) {
+    T v0[EPT], v1[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      v0[u] = live[u] ? P[z * slice + off[u]] : T(0);
+      v1[u] = live[u] ? P[(z + 1) * slice + off[u]] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      sum[u] += v0[u];
+      sum[u] += v1[u];
+    }
+  }
+  if (z < splits) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) sum[u] += live[u] ? P[z * slice + off[u]] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = tid + 256 * u;
+    if (e < jb16 * RT_CW) w1[e % jb16][e / jb16] = live[u] ? sum[u] : T(0);
   }
   // tiles of the jb16 x RT_CW result: t = 2 (row block) + (column block), wave g takes t = g + 4q
-  constexpr int QMAX = 2 * RT_JB / 16 / 4;
+  constexpr int QMAX = 2 * RJB / 16 / 4;
   const int ntiles = 2 * (jb16 / 16);
   TileAcc<T> acc[QMAX];
 #pragma unroll
@@ -2559,6 +2591,16 @@ __global__ __launch_bounds__(256) void reduce_tmul_kernel(int jb, int64_t N, int
         if (i < jb && j < cols) W2[i + (c0 + j) * ldw2] = v;
       });
   }
+}
+
+template <class T>
+void launch_reduce_tmul(int jb, int64_t N, int splits, const T* P, const T* Tm, int ldt, T* W2, int64_t ldw2,
+                        hipStream_t s) {
+  const unsigned grid = static_cast<unsigned>(ceil_div(N, RT_CW));
+  if (jb <= 128)
+    reduce_tmul_kernel<T, 128><<<grid, 256, 0, s>>>(jb, N, splits, P, Tm, ldt, W2, ldw2);
+  else
+    reduce_tmul_kernel<T, 256><<<grid, 256, 0, s>>>(jb, N, splits, P, Tm, ldt, W2, ldw2);
 }
 
 // dst (rows x cols, ld ldd) = src (ld lds).
@@ -2894,8 +2936,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       int splits = 0;
       URV_TRY(gemm_partials<T>(true, false, jb1, jb2, mp, Yb, m, C2, ldx, w.gemm_work_b, w.gemm_work_b_elems,
                                &splits, s2));
-      reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(jb2, RT_CW)), 256, 0, s2>>>(
-          jb1, jb2, splits, w.gemm_work_b, Tp, NBO, w.W2b, NBO);
+      launch_reduce_tmul<T>(jb1, jb2, splits, w.gemm_work_b, Tp, NBO, w.W2b, NBO, s2);
       URV_LAUNCHED("reduce_tmul_kernel");
       URV_TRY(gemm<T>(false, false, mp, jb2, jb1, T(-1), Yb, m, w.W2b, NBO, T(1), C2, ldx, nullptr, 0, s2));
       // the second panel (Y2 zero above it), then the joined T from S12 = Y1^T Y2:
@@ -2937,8 +2978,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
       int splits = 0;
       URV_TRY(gemm_partials<T>(true, false, ja, jbb, mp, Ya, m, CB, ldx, w.gemm_work_b, w.gemm_work_b_elems,
                                &splits, s2));
-      reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(jbb, RT_CW)), 256, 0, s2>>>(
-          ja, jbb, splits, w.gemm_work_b, Tb, NBO, w.W2b, NBO);
+      launch_reduce_tmul<T>(ja, jbb, splits, w.gemm_work_b, Tb, NBO, w.W2b, NBO, s2);
       URV_LAUNCHED("reduce_tmul_kernel");
       URV_TRY(gemm<T>(false, false, mp, jbb, ja, T(-1), Ya, m, w.W2b, NBO, T(1), CB, ldx, nullptr, 0, s2));
       T* TB = Tb + ja + static_cast<int64_t>(ja) * NBO;
@@ -2974,8 +3014,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     (void)W1;
     int splits = 0;
     URV_TRY(gemm_partials<T>(true, false, jb, nc, mp, Yb, m, Cb, ldx, gw, gwe, &splits, st));   // Y^T C
-    reduce_tmul_kernel<T><<<static_cast<unsigned>(ceil_div(nc, RT_CW)), 256, 0, st>>>(jb, nc, splits, gw, Tb, NBO,
-                                                                                   W2, NBO);  // T^T (Y^T C)
+    launch_reduce_tmul<T>(jb, nc, splits, gw, Tb, NBO, W2, NBO, st);  // T^T (Y^T C)
     URV_LAUNCHED("reduce_tmul_kernel");
     URV_TRY(gemm<T>(false, false, mp, nc, jb, T(-1), Yb, m, W2, NBO, T(1), Cb, ldx, nullptr, 0, st));
     return URV_OK;
