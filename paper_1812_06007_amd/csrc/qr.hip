@@ -2678,6 +2678,13 @@ bool bulk_pairs() {
   return e && std::atoi(e) == 1;
 }
 
+// Column blocks updated on the caller's stream ahead of the bulk update: the next
+// one or two (URV_LOOKAHEAD=1 or 2, for tuning).
+int lookahead() {
+  const char* e = std::getenv("URV_LOOKAHEAD");
+  return (e && std::atoi(e) == 1) ? 1 : 2;
+}
+
 // Whether targets take pairs of 128-column blocks (URV_TARGET_PAIRS=0 turns it off, for tuning).
 bool target_pairs() {
   const char* e = std::getenv("URV_TARGET_PAIRS");
@@ -2756,6 +2763,10 @@ QrSizes qr_sizes(int64_t m, int64_t n, int64_t target_rows) {
       gwn = std::max(gwn, gemm_partials_elems(jb, nn, mp));
       gwn = std::max(gwn, gemm_partials_elems(jb, nn2, mp));
       gw = std::max(gw, gemm_partials_elems(jb, std::max<int64_t>(nc - nn - nn2, 0), mp));
+      // two look-ahead blocks: the third column block on the caller's stream, the rest after it
+      const int64_t nn3 = std::min<int64_t>(nbo, std::max<int64_t>(nc - nn - nn2, 0));
+      gwn = std::max(gwn, gemm_partials_elems(jb, nn3, mp));
+      gw = std::max(gw, gemm_partials_elems(jb, std::max<int64_t>(nc - nn - nn2 - nn3, 0), mp));
       gw = std::max(gw, gemm_work_elems(jb, nc - nn, mp));
       gw = std::max(gw, gemm_work_elems(jb, n - j0, mp));
       if (nbo == NB2 && j0 >= NB2) {
@@ -3095,6 +3106,7 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   // near update is faster queued early.
   const bool early = panel_early(!prev_fused);
   const bool pair_bulk = nbo == NB2 && bulk_pairs();
+  const bool ahead2 = !pair_bulk && lookahead() == 2;
   const int64_t lag = target_lag();
   int64_t tgt_next = 0;  // first block whose targets are not yet queued
   URV_HIP(hipEventRecord(side.ev_next, s));      // the cleared flags and slots
@@ -3152,7 +3164,9 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     // block j2 (it reaches the columns beyond with its pair).  Block j2 still gets the
     // blocks in order: the previous pair's bulk update covers it and comes first.
     const bool closes = pair_bulk && (j0 / NB2) % 2 == 1;
-    if (bulk_pending) URV_HIP(hipStreamWaitEvent(s, side.ev_bulk, 0));
+    // With two look-ahead blocks, block j2's columns already waited for the bulk update
+    // that covers them, before block j0 - 1's update of them (stream order on s).
+    if (bulk_pending && !ahead2) URV_HIP(hipStreamWaitEvent(s, side.ev_bulk, 0));
     if (closes) {
       // the pair's T (into Tq, which the previous pair's bulk update has finished reading)
       URV_TRY(pair_t(j0 - NB2, w.Tq, w.W1n, w.W2n, w.gemm_work_n, w.gemm_work_n_elems, s));
@@ -3170,6 +3184,21 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     near_pending = true;
     const int64_t j3 = j2 + nn2;
     if (j3 >= n) continue;
+    if (ahead2) {
+      // the next column block too on s (after block j0 - 1's bulk update, which covers it),
+      // and the rest from j4 on s4: a block's columns wait for the bulk update four blocks
+      // back instead of three
+      const int64_t nn3 = std::min<int64_t>(nbo, n - j3);
+      if (bulk_pending) URV_HIP(hipStreamWaitEvent(s, side.ev_bulk, 0));
+      URV_TRY(apply_block(j0, j3, nn3, kOnCallerStream));
+      const int64_t j4 = j3 + nn3;
+      if (j4 >= n) continue;
+      URV_HIP(hipStreamWaitEvent(s4, ev_fact[par], 0));
+      URV_TRY(apply_block(j0, j4, n - j4, kOnBulkStream));
+      URV_HIP(hipEventRecord(side.ev_bulk, s4));
+      bulk_pending = true;
+      continue;
+    }
     if (pair_bulk && !closes) continue;  // block j1 closes the pair and has j2 + nn2 < n too
     // the rest, beside the chain: needs block j0's reflectors only (its columns are not the
     // near updates', and the previous bulk update is ahead of it on s4), or the pair's T
