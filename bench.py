@@ -34,16 +34,51 @@ if ROOT not in sys.path:
 METRIC = "PowerURV TFLOP/s & time (n=8000,q=2) mixed vs FP64; ||A−URV||/||A||"
 FP64_MFMA_PEAK_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_nn_av_8000_traffic.txt")
-GEMM_SOURCES = [os.path.join(ROOT, "paper_1812_06007_amd", "csrc", f) for f in ("gemm.hip", "common.hpp")]
+CLASS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "powerurv_fp64_8000_q2_traffic.txt")
+CSRC = os.path.join(ROOT, "paper_1812_06007_amd", "csrc")
+GEMM_SOURCES = [os.path.join(CSRC, f) for f in ("gemm.hip", "common.hpp")]
+# the factorisation's launches (their shapes and kernels) follow from these
+PIPELINE_SOURCES = [os.path.join(CSRC, f) for f in ("gemm.hip", "common.hpp", "qr.hip", "api.hip")]
+
+
+def source_hash(paths) -> str:
+    """sha256 over the given source files, in order."""
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def gemm_source_hash() -> str:
     """sha256 over the sources the GEMM kernel is built from."""
-    h = hashlib.sha256()
-    for path in GEMM_SOURCES:
-        with open(path, "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+    return source_hash(GEMM_SOURCES)
+
+
+def _summary_keys(path: str) -> dict:
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#") and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    return kv
+
+
+def class_traffic(cls: str, m: int, n: int, q: int, variant: str):
+    """HBM bytes per launch of a launch class of the FP64 factorisation, from the
+    committed rocprofv3 PMC summary (FETCH_SIZE + WRITE_SIZE per dispatch,
+    copy-calibrated, averaged over the class's dispatches of one factorisation), or
+    None when that summary is for another workload or for other sources."""
+    try:
+        kv = _summary_keys(CLASS_TRAFFIC_FILE)
+        if kv.get("pipeline_source_sha256") != source_hash(PIPELINE_SOURCES):
+            return None
+        if kv.get("workload") != "%dx%d q=%d %s" % (m, n, q, variant):
+            return None
+        return float(kv["bytes_per_launch." + cls])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def gemm_traffic(m: int, n: int):
@@ -51,12 +86,7 @@ def gemm_traffic(m: int, n: int):
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when that
     summary is for another shape or for an older gemm.hip."""
     try:
-        kv = {}
-        with open(TRAFFIC_FILE) as f:
-            for line in f:
-                if ":" in line and not line.startswith("#"):
-                    k, v = line.split(":", 1)
-                    kv[k.strip()] = v.strip()
+        kv = _summary_keys(TRAFFIC_FILE)
         if kv.get("gemm_source_sha256") != gemm_source_hash() or kv.get("shape") != "%dx%dx%d" % (m, n, n):
             return None
         return float(kv["hbm_bytes_per_launch"])
@@ -404,17 +434,18 @@ KERNEL_NAMES = {
 }
 
 
-def live_roofline(classes: dict, steps: int) -> dict:
+def live_roofline(classes: dict, steps: int, workload: tuple) -> dict:
     """The dominant kernel of the timed steps (most summed time among the library's FP64
     launch classes, timed live with HIP events on the streams they run on): its algorithmic
-    flops per launch over its mean launch time, against the FP64 MFMA peak."""
+    flops per launch over its mean launch time, against the FP64 MFMA peak; its HBM bytes
+    per launch from the committed counter summary (None if that is stale)."""
     cls = max(classes, key=lambda c: classes[c]["ms"])
     v = classes[cls]
     n = max(v["launches"], 1)
     launch_ms = v["ms"] / n
     achieved = v["flops"] / n / (launch_ms * 1e-3) / 1e12 if launch_ms > 0 else 0.0
     return {"bound": "mfma", "kernel": KERNEL_NAMES[cls], "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": class_traffic(cls, *workload),
             "launch_ms": launch_ms, "flop_per_launch": v["flops"] / n, "launches_per_step": v["launches"] / steps,
             "ms_per_step": v["ms"] / steps}
 
@@ -452,9 +483,14 @@ def main() -> int:
                     help="run only plain 1 GiB device copies (counter calibration) and exit")
     ap.add_argument("--gemm-source-hash", action="store_true",
                     help="print the hash the traffic summary is keyed on and exit")
+    ap.add_argument("--pipeline-source-hash", action="store_true",
+                    help="print the hash the per-class traffic summary is keyed on and exit")
     args = ap.parse_args()
     if args.gemm_source_hash:
         print(gemm_source_hash())
+        return 0
+    if args.pipeline_source_hash:
+        print(source_hash(PIPELINE_SOURCES))
         return 0
 
     if args.gpus != 1:
@@ -660,7 +696,7 @@ def main() -> int:
         "step_ms": {"median": step_ms[len(step_ms) // 2] if len(step_ms) % 2 else
                     0.5 * (step_ms[len(step_ms) // 2 - 1] + step_ms[len(step_ms) // 2]),
                     "min": step_ms[0], "max": step_ms[-1]},
-        "roofline": live_roofline(classes, args.steps) if classes else None,
+        "roofline": live_roofline(classes, args.steps, (m, n, q, args.variant)) if classes else None,
         "roofline_classes": None if not classes else
         {c: dict(v, frac=(v["flops"] / (v["ms"] * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS) if v["ms"] else None,
                  ms_per_step=v["ms"] / args.steps) for c, v in classes.items()},
