@@ -118,13 +118,14 @@ def standard_flops(m: int, n: int, q: int, variant: str, orth_g: bool = False) -
 
 
 def executed_flops(m: int, n: int, q: int, variant: str, orth_g: bool = False) -> float:
-    """What the driver executes: the standard count, except that V, and U when m == n, are
-    formed by applying the reflectors to an identity (Z <- Z Q, 4 z m n - 2 z n^2 with z the
-    rows of Z: 2 n^3 for n x n) rather than by the structured formation (4/3 n^3).  The
-    products A^T W and A V of FULL are applied to A^T and A as targets of the QRs at the
-    cost of the products they replace."""
-    m_, n_ = float(m), float(n)
-    extra = 2.0 * n_ ** 3 - 4.0 / 3.0 * n_ ** 3  # V
+    """What the driver executes: the standard count, except that U, when m == n, is formed
+    by applying the final QR's reflectors to an identity alongside it (Z <- Z Q,
+    4 z m n - 2 z n^2 with z the rows of Z: 2 n^3 for n x n) rather than by the structured
+    formation (4/3 n^3).  V is formed structurally from its QR's reflectors, beside the
+    final QR.  The products A^T W and A V of FULL are applied to A^T and A as targets of
+    the QRs at the cost of the products they replace."""
+    n_ = float(n)
+    extra = 0.0
     if m == n:
         extra += 2.0 * n_ ** 3 - 4.0 / 3.0 * n_ ** 3  # U
     return standard_flops(m, n, q, variant, orth_g) + extra

@@ -43,9 +43,17 @@ struct FactorWork {
   double* gemm_work = nullptr;
   size_t gemm_work_elems = 0;
   QrWork qr;
+  QrWork qr2;  // the final QR's, while V is formed from the reflectors left in qr
   bool mixed = false;
   MixedWork mx;
 };
+
+// Whether the explicit V is formed from its QR's reflectors beside the final QR
+// (URV_DEFER_V=0: as a product with I alongside its QR, for tuning).
+bool defer_v() {
+  const char* e = std::getenv("URV_DEFER_V");
+  return !(e && std::atoi(e) == 0);
+}
 
 size_t driver_gemm_work(int64_t m, int64_t n) {
   return std::max(dgemm_work_elems(m, n, n), dgemm_work_elems(n, n, m));
@@ -58,6 +66,7 @@ void carve_factor(Arena& a, int64_t m, int64_t n, bool mixed, FactorWork& w) {
   w.gemm_work_elems = driver_gemm_work(m, n);
   w.gemm_work = a.take<double>(w.gemm_work_elems);
   qr_work_carve(a, m, n, w.qr, m);
+  qr_work_carve(a, m, n, w.qr2, m);
   w.mixed = mixed;
   if (!mixed) return;
   MixedWork& x = w.mx;
@@ -153,8 +162,8 @@ __global__ __launch_bounds__(256) void nonfinite_kernel(const S* __restrict__ sr
 __global__ void set_u32_kernel(unsigned* p, unsigned v) { *p = v; }
 
 // Folds the error flags of a factorisation or QR into the device's status word.
-__global__ void fold_status_kernel(unsigned* status, const unsigned* f1, const unsigned* f2) {
-  if ((f1 && *f1) || (f2 && *f2)) atomicOr(status, 1u);
+__global__ void fold_status_kernel(unsigned* status, const unsigned* f1, const unsigned* f2, const unsigned* f3) {
+  if ((f1 && *f1) || (f2 && *f2) || (f3 && *f3)) atomicOr(status, 1u);
 }
 
 // Per-device statics: the split-K scratch of urv_dgemm_noalloc and the status word
@@ -194,10 +203,10 @@ int device_statics(DeviceStatics* out) {
 }
 
 // Queues the fold of up to two error flags into the device's status word.
-int fold_status(const unsigned* f1, const unsigned* f2, hipStream_t s) {
+int fold_status(const unsigned* f1, const unsigned* f2, hipStream_t s, const unsigned* f3 = nullptr) {
   DeviceStatics d;
   URV_TRY(device_statics(&d));
-  fold_status_kernel<<<1, 1, 0, s>>>(d.status, f1, f2);
+  fold_status_kernel<<<1, 1, 0, s>>>(d.status, f1, f2, f3);
   URV_LAUNCHED("fold_status_kernel");
   return URV_OK;
 }
@@ -273,22 +282,44 @@ int qpos_times_a(const double* A, int64_t lda, int64_t m, int64_t n, double* Y, 
   int nt = 0;
   URV_TRY(copy_matrix(A, lda, w.X, m, m, n, s));
   t[nt++] = QrTarget<double>{w.X, m, m};
-  if (want_v) {
+  const bool defer = want_v && defer_v();
+  if (want_v && !defer) {
     URV_TRY(set_identity<double>(V, n, n, ldv, s));
     t[nt++] = QrTarget<double>{V, n, ldv};
   }
-  return qr_pos<double>(Y, n, n, n, nullptr, 0, nullptr, 0, w.qr, s, t, nt);
+  URV_TRY(qr_pos<double>(Y, n, n, n, nullptr, 0, nullptr, 0, w.qr, s, t, nt));
+  if (!defer) return URV_OK;
+  // V from the reflectors, applied backward to [D; 0] (4/3 n^3 instead of the 2 n^3 of a
+  // target), on the targets' stream beside the final QR, which runs on w.qr2; final_qr
+  // joins it.  Y (the factored matrix, for D) and w.qr stay untouched until then.
+  SideStream side;
+  URV_TRY(side_stream(&side));
+  std::lock_guard<std::mutex> lock(*side.mu);
+  URV_HIP(hipEventRecord(side.ev_defer, s));
+  URV_HIP(hipStreamWaitEvent(side.stream3, side.ev_defer, 0));
+  return form_q<double>(Y, n, n, n, V, ldv, w.qr, side.stream3, true);
 }
 
 // The final step of eq. (powerqr): A V = U R with X = A V in w.X.
 int final_qr(int64_t m, int64_t n, double* U, int64_t ldu, double* R, int64_t ldr, const FactorWork& w,
              hipStream_t s) {
+  const bool defer = defer_v();
+  const QrWork& wq = defer ? w.qr2 : w.qr;
   if (m == n) {  // U formed from I alongside the factorisation
     URV_TRY(set_identity<double>(U, m, n, ldu, s));
     const QrTarget<double> t{U, m, ldu};
-    return qr_pos<double>(w.X, m, n, m, nullptr, 0, R, ldr, w.qr, s, &t, 1);
+    URV_TRY(qr_pos<double>(w.X, m, n, m, nullptr, 0, R, ldr, wq, s, &t, 1));
+  } else {
+    URV_TRY(qr_pos<double>(w.X, m, n, m, U, ldu, R, ldr, wq, s));
   }
-  return qr_pos<double>(w.X, m, n, m, U, ldu, R, ldr, w.qr, s);
+  if (!defer) return URV_OK;
+  // the V formed beside this QR (if any) is part of the result
+  SideStream side;
+  URV_TRY(side_stream(&side));
+  std::lock_guard<std::mutex> lock(*side.mu);
+  URV_HIP(hipEventRecord(side.ev_defer_done, side.stream3));
+  URV_HIP(hipStreamWaitEvent(s, side.ev_defer_done, 0));
+  return URV_OK;
 }
 
 int run_factor(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, double* U,
@@ -494,6 +525,7 @@ int factor_impl(const void* A, int64_t m, int64_t n, int32_t q, uint64_t seed, d
     o64.lda = m;
   }
   if (rc == URV_OK) rc = qr_clear_error_flag(w.qr, nt, s);
+  if (rc == URV_OK && w.qr2.Y) rc = qr_clear_error_flag(w.qr2, nt, s);
   if (rc == URV_OK && mixed) rc = qr_clear_error_flag(w.mx.qr, nt, s);
   if (rc == URV_OK) {
     if (wide)
@@ -504,7 +536,9 @@ int factor_impl(const void* A, int64_t m, int64_t n, int32_t q, uint64_t seed, d
     else
       rc = run_factor(A64, m, n, q, seed, U, R, V, o64, w, s);
   }
-  if (rc == URV_OK) rc = fold_status(qr_error_flag(w.qr, nt), mixed ? qr_error_flag(w.mx.qr, nt) : nullptr, s);
+  if (rc == URV_OK)
+    rc = fold_status(qr_error_flag(w.qr, nt), mixed ? qr_error_flag(w.mx.qr, nt) : nullptr, s,
+                     w.qr2.Y ? qr_error_flag(w.qr2, nt) : nullptr);
   if (rc == URV_OK && blocking) rc = sync_status(s, "urv_factor");
   if (owned) {
     const hipError_t e = hipFreeAsync(a.base, s);

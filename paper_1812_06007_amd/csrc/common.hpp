@@ -187,6 +187,8 @@ struct SideStream {
   hipEvent_t ev_near = nullptr;
   hipEvent_t ev_bulk = nullptr;
   hipEvent_t ev_pair = nullptr;
+  hipEvent_t ev_defer = nullptr;       // caller's stream -> stream3: work deferred beside the next QR
+  hipEvent_t ev_defer_done = nullptr;  // stream3 -> caller's stream
   std::mutex* mu = nullptr;
 };
 int side_stream(SideStream* out);
@@ -222,6 +224,15 @@ int scale_cols_sign(T* Z, int64_t rows, int64_t n, int64_t ldz, const T* X, int6
 template <class T>
 int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int64_t ldr,
            const QrWorkT<T>& w, hipStream_t s, const QrTarget<T>* targets = nullptr, int ntargets = 0);
+
+// Q = H_1 ... H_n [D; 0] (m x n, ld ldq), D = diag(sign(X(c,c))), from the reflectors
+// that the last qr_pos on w left there (X is that call's factored matrix): the blocks
+// applied backward, 2 m n^2 - 2/3 n^3 flops.  With pairs, 256-column pairs of blocks are
+// applied with the joined T that the call's target products formed (only valid after a
+// qr_pos with targets).  On stream s; w's scratch must be free.
+template <class T>
+int form_q(const T* X, int64_t ldx, int64_t m, int64_t n, T* Q, int64_t ldq, const QrWorkT<T>& w, hipStream_t s,
+           bool pairs);
 
 // ---------------------------------------------------------------- mixed precision
 // Leading dimension of a 16-bit operand with `rows` rows (multiple of 32).

@@ -3225,22 +3225,32 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     extract_r_kernel<T><<<static_cast<unsigned>(ceil_div(n * n, 256)), 256, 0, s>>>(X, ldx, n, R, ldr);
     URV_LAUNCHED("extract_r_kernel");
   }
-  if (Q) {
-    init_q_kernel<T><<<static_cast<unsigned>(ceil_div(m * n, 256)), 256, 0, s>>>(X, ldx, m, n, Q, ldq);
-    URV_LAUNCHED("init_q_kernel");
-    const int64_t nouter = ceil_div(n, nbo);
-    for (int64_t blk = nouter - 1; blk >= 0; --blk) {
-      const int64_t j0 = blk * nbo;
-      const int jb = static_cast<int>(std::min<int64_t>(nbo, n - j0));
-      const int64_t mp = m - j0, nq = n - j0;
-      const T* Yb = w.Y + j0 + j0 * m;
-      const T* Tb = w.Tm + j0 * NBO;
-      T* Qb = Q + j0 + j0 * ldq;
-      URV_TRY(gemm<T>(true, false, jb, nq, mp, T(1), Yb, m, Qb, ldq, T(0), w.W1, NBO, w.gemm_work,
-                      w.gemm_work_elems, s));
-      URV_TRY(gemm<T>(false, false, jb, nq, jb, T(1), Tb, NBO, w.W1, NBO, T(0), w.W2, NBO, nullptr, 0, s));
-      URV_TRY(gemm<T>(false, false, mp, nq, jb, T(-1), Yb, m, w.W2, NBO, T(1), Qb, ldq, nullptr, 0, s));
-    }
+  if (Q) URV_TRY(form_q<T>(X, ldx, m, n, Q, ldq, w, s, false));
+  return URV_OK;
+}
+
+template <class T>
+int form_q(const T* X, int64_t ldx, int64_t m, int64_t n, T* Q, int64_t ldq, const QrWorkT<T>& w, hipStream_t s,
+           bool pairs) {
+  if (n == 0) return URV_OK;
+  init_q_kernel<T><<<static_cast<unsigned>(ceil_div(m * n, 256)), 256, 0, s>>>(X, ldx, m, n, Q, ldq);
+  URV_LAUNCHED("init_q_kernel");
+  const int nbo = outer_block();
+  // pairs of 128-column blocks with the joined T the target products formed (a lone last
+  // block keeps its own T)
+  const int64_t step = (pairs && nbo == NB2 && target_pairs()) ? 2 * NB2 : nbo;
+  const int64_t nouter = ceil_div(n, step);
+  for (int64_t blk = nouter - 1; blk >= 0; --blk) {
+    const int64_t j0 = blk * step;
+    const int jb = static_cast<int>(std::min<int64_t>(step, n - j0));
+    const int64_t mp = m - j0, nq = n - j0;
+    const T* Yb = w.Y + j0 + j0 * m;
+    const T* Tb = (step > nbo && jb > NB2) ? w.Tp + j0 * NBO : w.Tm + j0 * NBO;
+    T* Qb = Q + j0 + j0 * ldq;
+    URV_TRY(gemm<T>(true, false, jb, nq, mp, T(1), Yb, m, Qb, ldq, T(0), w.W1, NBO, w.gemm_work,
+                    w.gemm_work_elems, s));
+    URV_TRY(gemm<T>(false, false, jb, nq, jb, T(1), Tb, NBO, w.W1, NBO, T(0), w.W2, NBO, nullptr, 0, s));
+    URV_TRY(gemm<T>(false, false, mp, nq, jb, T(-1), Yb, m, w.W2, NBO, T(1), Qb, ldq, nullptr, 0, s));
   }
   return URV_OK;
 }
@@ -3262,6 +3272,8 @@ int qr_clear_error_flag(const QrWorkT<T>& w, int64_t n, hipStream_t s) {
   template void qr_work_carve<T>(Arena&, int64_t, int64_t, QrWorkT<T>&, int64_t);            \
   template int qr_pos<T>(T*, int64_t, int64_t, int64_t, T*, int64_t, T*, int64_t,             \
                          const QrWorkT<T>&, hipStream_t, const QrTarget<T>*, int);            \
+  template int form_q<T>(const T*, int64_t, int64_t, int64_t, T*, int64_t, const QrWorkT<T>&, hipStream_t, \
+                         bool);                                                                \
   template unsigned* qr_error_flag<T>(const QrWorkT<T>&, int64_t);                          \
   template int qr_clear_error_flag<T>(const QrWorkT<T>&, int64_t, hipStream_t);
 URV_QR_INSTANTIATE(double)

@@ -253,8 +253,10 @@ int side_stream(SideStream* out) {
   if (e.stream == nullptr) {
     hipStream_t st[3];
     for (auto& x : st) URV_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-    hipEvent_t ev[7];
+    hipEvent_t ev[9];
     for (auto& x : ev) URV_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    e.ev_defer = ev[7];
+    e.ev_defer_done = ev[8];
     e.ev_next = ev[0];
     e.ev_fact = ev[1];
     e.ev_fact2 = ev[6];
