@@ -2696,11 +2696,12 @@ bool target_pairs() {
 // returns, while the trailing updates of the first blocks gate the chain: held
 // back, the target products leave the CUs to those updates while the trailing
 // matrix is large and run beside the later, lighter blocks.  Measured on
-// MI355X at n = 8000, q = 2: 343 ms with no lag, 335-334 ms with 10-14
-// blocks, 338 ms with 20 (the held-back products then outlast the chain).
+// MI355X at n = 8000, q = 2 (FP64 FULL / HALF, V formed beside the final QR):
+// lag 6: 261.0 / 204.0 ms, 12: 257.0 / 201.9, 18: 253.4-254.5 / 198.5-200.5,
+// 21: 254.2, 24: 256.1 / 200.1, 30: 262.6 / 203.8.
 int target_lag() {
   const char* e = std::getenv("URV_TARGET_LAG");
-  return e ? std::max(0, std::atoi(e)) : 12;
+  return e ? std::max(0, std::atoi(e)) : 18;
 }
 
 // Outer block width used by qr_pos: NB2 or NBO (URV_QR_BLOCK, for tuning).
