@@ -2678,11 +2678,14 @@ bool bulk_pairs() {
   return e && std::atoi(e) == 1;
 }
 
-// Column blocks updated on the caller's stream ahead of the bulk update: the next
-// one or two (URV_LOOKAHEAD=1 or 2, for tuning).
+// Column blocks updated on the caller's stream ahead of the bulk update (URV_LOOKAHEAD
+// 1 to 3, for tuning).  Measured on MI355X at n = 8000, q = 2 (FULL / HALF): one block
+// 266.1 / 210.6 ms, two 264.0 / 209.5 (later, with V formed beside the final QR:
+// 253.1 / 199.0), three 263.1-263.7 / 204.5 - the near updates on the caller's stream
+// then hold the chain back more than the bulk updates did.
 int lookahead() {
   const char* e = std::getenv("URV_LOOKAHEAD");
-  return (e && std::atoi(e) == 1) ? 1 : 2;
+  return e ? std::min(3, std::max(1, std::atoi(e))) : 2;
 }
 
 // Whether targets take pairs of 128-column blocks (URV_TARGET_PAIRS=0 turns it off, for tuning).
@@ -3107,7 +3110,8 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   // near update is faster queued early.
   const bool early = panel_early(!prev_fused);
   const bool pair_bulk = nbo == NB2 && bulk_pairs();
-  const bool ahead2 = !pair_bulk && lookahead() == 2;
+  const int ahead = pair_bulk ? 1 : lookahead();
+  const bool ahead2 = ahead >= 2;
   const int64_t lag = target_lag();
   int64_t tgt_next = 0;  // first block whose targets are not yet queued
   URV_HIP(hipEventRecord(side.ev_next, s));      // the cleared flags and slots
@@ -3186,16 +3190,19 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
     const int64_t j3 = j2 + nn2;
     if (j3 >= n) continue;
     if (ahead2) {
-      // the next column block too on s (after block j0 - 1's bulk update, which covers it),
-      // and the rest from j4 on s4: a block's columns wait for the bulk update four blocks
-      // back instead of three
-      const int64_t nn3 = std::min<int64_t>(nbo, n - j3);
-      if (bulk_pending) URV_HIP(hipStreamWaitEvent(s, side.ev_bulk, 0));
-      URV_TRY(apply_block(j0, j3, nn3, kOnCallerStream));
-      const int64_t j4 = j3 + nn3;
-      if (j4 >= n) continue;
+      // the next ahead - 1 column blocks too on s, the farthest after block j0 - 1's bulk
+      // update (which covers it; the nearer ones had that wait in earlier iterations), and
+      // the rest on s4: a block's columns wait for the bulk update ahead + 2 blocks back
+      int64_t jc = j3;
+      for (int e = 0; e < ahead - 1 && jc < n; ++e) {
+        const int64_t nc = std::min<int64_t>(nbo, n - jc);
+        if (e == ahead - 2 && bulk_pending) URV_HIP(hipStreamWaitEvent(s, side.ev_bulk, 0));
+        URV_TRY(apply_block(j0, jc, nc, kOnCallerStream));
+        jc += nc;
+      }
+      if (jc >= n) continue;
       URV_HIP(hipStreamWaitEvent(s4, ev_fact[par], 0));
-      URV_TRY(apply_block(j0, j4, n - j4, kOnBulkStream));
+      URV_TRY(apply_block(j0, jc, n - jc, kOnBulkStream));
       URV_HIP(hipEventRecord(side.ev_bulk, s4));
       bulk_pending = true;
       continue;

@@ -73,10 +73,11 @@ def _parity(urv, orc, m, n, q, seed):
     {"URV_LOOKAHEAD": "1"},
     {"URV_LOOKAHEAD": "1", "URV_PANEL_PREV": "0", "URV_PANEL_EARLY": "0"},
     {"URV_DEFER_V": "0"},
+    {"URV_LOOKAHEAD": "3"},
 ], ids=["block256", "no_pairs", "separate_panels", "no_join", "in_order", "targets_at_once", "targets_at_end",
         "all_off", "prev_flag_wait", "no_prev", "no_prev_in_order", "tall_skinny_only", "per_column_panel",
         "bulk_pairs", "bulk_pairs_no_prev", "lookahead1",
-        "lookahead1_no_prev_in_order", "v_as_target"])
+        "lookahead1_no_prev_in_order", "v_as_target", "lookahead3"])
 @pytest.mark.parametrize("m,n", [(400, 400), (700, 520), (300, 197), (1100, 900)])
 def test_schedule_variants_match_oracle(urv, orc, monkeypatch, env, m, n):
     announce("schedule", env, m, n)
