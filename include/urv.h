@@ -223,7 +223,9 @@ int urv_metrics(const double* A, int64_t m, int64_t n, const double* U, const do
  * All matrices are packed column-major device arrays (ld = rows) of the type
  * opts->precision selects: double (URV_FP64) or float (URV_FP32).  The
  * derivative exists where every QR of the chain has full column rank; where a
- * diagonal entry of an R is zero the outputs are not finite.  Every call is
+ * diagonal entry of an R is zero the outputs are not finite, except the last
+ * entry of a square QR's R: there the last column of Xb is Q Rb(:,n) exactly
+ * ((I - Q Q^T) Qb vanishes for square Q), with no division.  Every call is
  * asynchronous on opts->stream; a device-side wait of a QR that expired leaves
  * NaN in the outputs.  Argument errors return URV_EINVAL before any launch;
  * m beyond the QR panel's row limit returns URV_ENOTSUP.
@@ -279,7 +281,9 @@ int urv_factor_backward(const void* A, int64_t m, int64_t n, int32_t q, const vo
 /*
  * Adjoint of one QR X = Q R (Q m x n, R n x n upper, m >= n): dX = (dQ + Q S) R^{-T}
  * with S from the lower triangle of R dR^T - dQ^T Q.  dQ or dR may be NULL
- * (zero).  precision URV_FP64 or URV_FP32; asynchronous on stream.
+ * (zero).  For m == n the last column of dX is Q dR(:,n) (no division by
+ * R(n,n), which may then be zero).  precision URV_FP64 or URV_FP32;
+ * asynchronous on stream.
  */
 int urv_qr_adjoint(const void* Q, const void* R, int64_t m, int64_t n, const void* dQ, const void* dR,
                    void* dX, int32_t precision, void* stream);
