@@ -89,3 +89,18 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_class_traffic_follows_the_committed_summary(bench, tmp_path, monkeypatch):
+    """roofline.traffic comes from the committed PMC summary only while the factorisation's
+    sources hash to the value recorded there, and only for the workload it was taken on."""
+    src = tmp_path / "summary.txt"
+    h = bench.source_hash(bench.PIPELINE_SOURCES)
+    src.write_text("workload: 8000x8000 q=2 full\npipeline_source_sha256: %s\nbytes_per_launch.gemm_nn: 123\n" % h)
+    monkeypatch.setattr(bench, "CLASS_TRAFFIC_FILE", str(src))
+    assert bench.class_traffic("gemm_nn", 8000, 8000, 2, "full") == 123.0
+    assert bench.class_traffic("gemm_nn", 8000, 8000, 2, "half") is None
+    assert bench.class_traffic("gemm_tn", 8000, 8000, 2, "full") is None
+    src.write_text("workload: 8000x8000 q=2 full\npipeline_source_sha256: %s\nbytes_per_launch.gemm_nn: 123\n" % ("0" * 64))
+    assert bench.class_traffic("gemm_nn", 8000, 8000, 2, "full") is None
+
