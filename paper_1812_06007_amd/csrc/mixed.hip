@@ -39,21 +39,28 @@ struct Lowp<false> {
   }
 };
 
-constexpr int LBM = 128, LBN = 128, LBK = 32;
-constexpr int LPAD = 8;  // 16-byte row padding in LDS
+constexpr int LBK = 64;
+constexpr int LPAD = 8;  // 16-byte row padding in LDS: 144-byte rows, conflict-free 16-byte reads
 
 // v_mfma_f32_16x16x32_{bf16,f16}: lane l holds A(i = l%16, k = 8(l/16) + e), e = 0..7,
 // B(k = 8(l/16) + e, j = l%16); result entry r of lane l is D(4(l/16) + r, l%16).
 // The MFMA is fed (B fragment, A fragment), so lane l ends with C(m = l%16, n = 4(l/16)+r):
 // sixteen consecutive rows of C per column.
-template <bool BF16>
-__global__ __launch_bounds__(256) void gemm_lowp_kernel(int64_t M, int64_t N, int64_t K, float alpha,
-                                                        const void* __restrict__ Av, int64_t lda,
-                                                        const void* __restrict__ Bv, int64_t ldb,
-                                                        float beta, float* __restrict__ C,
-                                                        int64_t ldc, int tiles_m, int tiles_n) {
+// An LBM x LBN tile of C per workgroup of WGM x WGN waves, each wave a (LBM / WGM) x
+// (LBN / WGN) sub-tile: the larger the wave tile, the fewer LDS bytes per MFMA.
+template <bool BF16, int LBM, int LBN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_lowp_kernel(int64_t M, int64_t N, int64_t K, float alpha,
+                                                                  const void* __restrict__ Av, int64_t lda,
+                                                                  const void* __restrict__ Bv, int64_t ldb,
+                                                                  float beta, float* __restrict__ C,
+                                                                  int64_t ldc, int tiles_m, int tiles_n) {
   using E = typename Lowp<BF16>::elem;
   using V8 = typename Lowp<BF16>::vec8;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WTM = LBM / WGM, WTN = LBN / WGN;  // wave tile
+  constexpr int FA = WTM / 16, FB = WTN / 16;      // MFMA blocks per wave
+  constexpr int LA = LBM * LBK / 8 / NT, LB = LBN * LBK / 8 / NT;  // 16-byte chunks per thread and K step
+  static_assert(LA * NT * 8 == LBM * LBK && LB * NT * 8 == LBN * LBK, "whole chunks per thread");
   const E* A = static_cast<const E*>(Av);
   const E* B = static_cast<const E*>(Bv);
   __shared__ __attribute__((aligned(16))) E As[2][LBM][LBK + LPAD];
@@ -61,7 +68,7 @@ __global__ __launch_bounds__(256) void gemm_lowp_kernel(int64_t M, int64_t N, in
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
   const int ntiles = tiles_m * tiles_n;
   // XCD-contiguous ranges of the tile sequence, walked in groups of 8 tile rows
   const int wg = xcd_tile_order(static_cast<int>(blockIdx.x), ntiles);
@@ -72,34 +79,47 @@ __global__ __launch_bounds__(256) void gemm_lowp_kernel(int64_t M, int64_t N, in
   const int tn = (wg % (GROUP * tiles_n)) / gsize;
   const int64_t m0 = static_cast<int64_t>(tm) * LBM, n0 = static_cast<int64_t>(tn) * LBN;
   const int nk = static_cast<int>(ceil_div(K, LBK));
+  // K padded to a multiple of 32 with zeros: a 16-byte chunk lies wholly below kp or wholly
+  // at or above it, and the last K step of 64 may hold chunks past the padding (read as 0)
+  const int64_t kp = ceil_div(K, 32) * 32;
 
-  // each thread moves two 16-byte chunks of A and two of B per K step
-  uint4 ra[2], rb[2];
+  // each thread moves LA 16-byte chunks of A and LB of B per K step: 8 threads per
+  // 128-byte row segment
+  uint4 ra[LA], rb[LB];
   auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int q = tid + 256 * r;
-      const int row = q >> 2, ch = q & 3;
-      const int64_t gi = m0 + row, gj = n0 + row;
-      ra[r] = (gi < M) ? *reinterpret_cast<const uint4*>(A + gi * lda + k0 + 8 * ch) : make_uint4(0, 0, 0, 0);
-      rb[r] = (gj < N) ? *reinterpret_cast<const uint4*>(B + gj * ldb + k0 + 8 * ch) : make_uint4(0, 0, 0, 0);
+    for (int r = 0; r < LA; ++r) {
+      const int q = tid + NT * r;
+      const int row = q >> 3, ch = q & 7;
+      const int64_t gi = m0 + row, gk = k0 + 8 * ch;
+      ra[r] = (gi < M && gk < kp) ? *reinterpret_cast<const uint4*>(A + gi * lda + gk) : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int q = tid + NT * r;
+      const int row = q >> 3, ch = q & 7;
+      const int64_t gj = n0 + row, gk = k0 + 8 * ch;
+      rb[r] = (gj < N && gk < kp) ? *reinterpret_cast<const uint4*>(B + gj * ldb + gk) : make_uint4(0, 0, 0, 0);
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int q = tid + 256 * r;
-      const int row = q >> 2, ch = q & 3;
-      *reinterpret_cast<uint4*>(&As[buf][row][8 * ch]) = ra[r];
-      *reinterpret_cast<uint4*>(&Bs[buf][row][8 * ch]) = rb[r];
+    for (int r = 0; r < LA; ++r) {
+      const int q = tid + NT * r;
+      *reinterpret_cast<uint4*>(&As[buf][q >> 3][8 * (q & 7)]) = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int q = tid + NT * r;
+      *reinterpret_cast<uint4*>(&Bs[buf][q >> 3][8 * (q & 7)]) = rb[r];
     }
   };
 
-  f4 acc[4][4];
+  f4 acc[FA][FB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < FA; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < FB; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 
   if (nk > 0) {
     load(0);
@@ -110,27 +130,32 @@ __global__ __launch_bounds__(256) void gemm_lowp_kernel(int64_t M, int64_t N, in
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) load(static_cast<int64_t>(kt + 1) * LBK);
-    V8 fa[4], fb[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) fa[a] = *reinterpret_cast<const V8*>(&As[cur][wm * 64 + a * 16 + lrow][8 * lk]);
+    for (int kk = 0; kk < LBK / 32; ++kk) {
+      V8 fa[FA], fb[FB];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) fb[b] = *reinterpret_cast<const V8*>(&Bs[cur][wn * 64 + b * 16 + lrow][8 * lk]);
+      for (int a = 0; a < FA; ++a)
+        fa[a] = *reinterpret_cast<const V8*>(&As[cur][wm * WTM + a * 16 + lrow][32 * kk + 8 * lk]);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < FB; ++b)
+        fb[b] = *reinterpret_cast<const V8*>(&Bs[cur][wn * WTN + b * 16 + lrow][32 * kk + 8 * lk]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = Lowp<BF16>::mma(fb[b], fa[a], acc[a][b]);
+      for (int a = 0; a < FA; ++a)
+#pragma unroll
+        for (int b = 0; b < FB; ++b) acc[a][b] = Lowp<BF16>::mma(fb[b], fa[a], acc[a][b]);
+    }
     if (kt + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
 
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t gm = m0 + wm * 64 + a * 16 + lrow;
+  for (int a = 0; a < FA; ++a) {
+    const int64_t gm = m0 + wm * WTM + a * 16 + lrow;
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < FB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gn = n0 + wn * 64 + b * 16 + 4 * lk + r;
+        const int64_t gn = n0 + wn * WTN + b * 16 + 4 * lk + r;
         if (gm < M && gn < N) {
           float* c = C + gm + gn * ldc;
           *c = (beta == 0.f) ? alpha * acc[a][b][r] : alpha * acc[a][b][r] + beta * *c;
@@ -240,12 +265,30 @@ int gemm_lowp(bool bf16, int64_t M, int64_t N, int64_t K, float alpha, const voi
     set_last_error("gemm_lowp: 16-bit operands need padded leading dimensions");
     return URV_EINVAL;
   }
-  const int tiles_m = static_cast<int>(ceil_div(M, LBM)), tiles_n = static_cast<int>(ceil_div(N, LBN));
+  // 256 x 256 tiles (8 waves of 128 x 64: a third fewer LDS bytes per MFMA than 64 x 64
+  // wave tiles) when they still fill the 256 CUs, else 128 x 128 (URV_LOWP_TILE=128 or
+  // 256 forces one, for tuning)
+  int tb = ceil_div(M, 256) * ceil_div(N, 256) >= 256 ? 256 : 128;
+  if (const char* te = std::getenv("URV_LOWP_TILE")) {
+    if (std::atoi(te) == 128) tb = 128;
+    if (std::atoi(te) == 256) tb = 256;
+  }
+  const int tiles_m = static_cast<int>(ceil_div(M, tb)), tiles_n = static_cast<int>(ceil_div(N, tb));
   const dim3 grid(tiles_m * tiles_n);
-  if (bf16)
-    gemm_lowp_kernel<true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n);
-  else
-    gemm_lowp_kernel<false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, tiles_m, tiles_n);
+  if (tb == 256) {
+    if (bf16)
+      gemm_lowp_kernel<true, 256, 256, 2, 4><<<grid, 512, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                                  tiles_m, tiles_n);
+    else
+      gemm_lowp_kernel<false, 256, 256, 2, 4><<<grid, 512, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                                   tiles_m, tiles_n);
+  } else if (bf16) {
+    gemm_lowp_kernel<true, 128, 128, 2, 2><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                                tiles_m, tiles_n);
+  } else {
+    gemm_lowp_kernel<false, 128, 128, 2, 2><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                                 tiles_m, tiles_n);
+  }
   URV_LAUNCHED("gemm_lowp_kernel");
   return URV_OK;
 }

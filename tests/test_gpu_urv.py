@@ -237,13 +237,17 @@ def test_full_size_kahan_4000(urv):
 
 
 # ------------------------------------------------ mixed precision (BF16 / FP16 products, FP32 QR, FP64 tail)
+@pytest.mark.parametrize("tile", ["128", "256"])
 @pytest.mark.parametrize("prec", ["mixed_bf16", "mixed_fp16"])
 @pytest.mark.parametrize("variant", ["full", "half"])
-def test_mixed_precision_against_fp64_oracle(urv, orc, prec, variant):
+def test_mixed_precision_against_fp64_oracle(urv, orc, monkeypatch, prec, variant, tile):
     """Reconstruction and orthogonality stay at FP64 level (the FP64 re-orthonormalisation and
     tail); the rank-k errors stay close to the FP64 oracle's where sigma_k is well above the
-    16-bit rounding level, and never beat the Eckart-Young bound."""
-    announce("mixed", prec, variant)
+    16-bit rounding level, and never beat the Eckart-Young bound.  Both tile shapes of the
+    16-bit products (the 256 x 256 one is chosen by itself only for outputs of 256 such tiles)
+    run here, with ragged edges and a K that ends inside a K step."""
+    announce("mixed", prec, variant, tile)
+    monkeypatch.setenv("URV_LOWP_TILE", tile)
     m, n = 1200, 600
     sigma = np.exp(-10.0 * np.arange(1, n + 1) / n)  # the same decay range as exp(-j/800), j <= 8000
     A = gen.noisy_spectral_matrix(m, n, sigma, seed=7, noise_var=1e-6)
