@@ -384,8 +384,8 @@ def compare_precisions(A, q: int, variant: str, ms64: float, met64: dict, steps:
     """The mixed-precision forms against the FP64 run (time, reconstruction,
     orthogonality, rank-k errors and the diagonal of R) on the same A and G,
     for the variant timed and, with half_too, for HALF as well (one QR per
-    power step: the FULL mixed form runs six QRs, four of them FP32, against
-    five FP64 ones)."""
+    power step: at q = 2 the FULL mixed form runs five QRs, three of them FP32,
+    like the five FP64 ones)."""
     import numpy as np
     import torch
 

@@ -60,8 +60,8 @@ typedef enum {
   URV_FP64 = 0,       /* everything in FP64 */
   URV_FP32 = 1,       /* everything in FP32 (derivative entry points only) */
   URV_MIXED_BF16 = 2, /* power-step products on BF16 MFMA with FP32 accumulation, QR of the
-                         power iterates in FP32, V re-orthonormalised and the final
-                         A V = U R in FP64 */
+                         power iterates in FP32 except the last V = Qpos(Y), which is taken
+                         in FP64, as is the final A V = U R */
   URV_MIXED_FP16 = 3  /* as above with FP16 operands */
 } urv_precision;
 

@@ -421,14 +421,15 @@ int run_factor_mixed(const double* A, int64_t lda, const float* A32, int64_t lda
     URV_TRY(to_lowp<float>(bf16, rhs, m, m, n, x.B16, x.lda16, s, amaxB));
     float* out = none ? x.V32 : x.Y32;
     URV_TRY(gemm_lowp(bf16, n, n, m, 1.f, x.A16, x.lda16, x.B16, x.lda16, 0.f, out, n, s));   // A^T W
-    if (!none) URV_TRY(qr_pos<float>(x.Y32, n, n, n, x.V32, n, nullptr, 0, x.qr, s));        // V = Qpos
+    // V = Qpos(Y), in FP32 except after the last step: there the FP64 QR below takes Y
+    // itself, since Qpos(Qpos(Y)) = Qpos(Y)
+    if (!none && t + 1 < q) URV_TRY(qr_pos<float>(x.Y32, n, n, n, x.V32, n, nullptr, 0, x.qr, s));
   }
-  if (none && q > 0) {
-    URV_TRY(copy_matrix_f32(x.V32, n, x.Y32, n, n, n, s));
-    URV_TRY(qr_pos<float>(x.Y32, n, n, n, x.V32, n, nullptr, 0, x.qr, s));
-  }
-  // FP64 re-orthonormalisation of V (delivering X = A V alongside), then the FP64 tail A V = U R.
-  URV_TRY((convert<float, double>(x.V32, n, n, n, w.Xs, n, s)));
+  // The last V = Qpos(.) in FP64 (delivering X = A V alongside): of Y after a power step
+  // (FULL, HALF), of (A^T A)^q G (NONE), or of the starting V when q = 0; then the FP64
+  // tail A V = U R.
+  const float* vsrc = (q > 0 && !none) ? x.Y32 : x.V32;
+  URV_TRY((convert<float, double>(vsrc, n, n, n, w.Xs, n, s)));
   URV_TRY(qpos_times_a(A, lda, m, n, w.Xs, V, ldv, true, w, s));
   return final_qr(m, n, U, ldu, R, ldr, w, s);
 }
