@@ -42,6 +42,7 @@ constexpr int BT = 256;                  // threads per workgroup: 4 waves
 constexpr int RPT = 4;                   // panel rows per lane
 constexpr int kBatchMaxRows = BT * RPT;  // 1024
 constexpr int kNBMax = 32;               // widest panel
+constexpr int kLT = 2 * kNBMax;          // leading dimension of T and W: a pair of panels
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -58,9 +59,9 @@ struct BatchItem {
   float* Y = nullptr;        // n x n: A^T W, factored in place
   float* Vc = nullptr;       // n x n: the current V
   float* Vr = nullptr;       // m x n: explicit unit-lower reflectors of the current QR
-  float* T = nullptr;        // kNBMax x n: T of each panel
-  float* Wb = nullptr;       // kNBMax x n
-  float* W2b = nullptr;      // kNBMax x n
+  float* T = nullptr;        // kLT x n: T of each pair of panels
+  float* Wb = nullptr;       // kLT x n
+  float* W2b = nullptr;      // kLT x n
 };
 
 constexpr int GBK = 32;  // k step of the workgroup GEMM
@@ -73,6 +74,10 @@ struct Lds {
       float As[2][GBK][64 + 1];  // double-buffered tiles of the GEMM
       float Bs[2][GBK][64 + 1];
     } g;
+    struct {
+      float As[2][2 * GBK][64 + 1];  // the short GEMM's tiles: K <= 2 GBK in one step
+      float Bs[2][2 * GBK][64 + 1];
+    } g2;
     float red[kNBMax * RED_LD];
   } u;
   float part[kNBMax][PARTS + 1];
@@ -268,13 +273,13 @@ __device__ __noinline__ void wg_gemm_t(int M, int N, int K, float alpha, const f
   team_sync(tm);
 }
 
-template <bool TA, int BM>
+template <bool TA, int BM, int KS>
 __device__ __noinline__ void wg_gemm_short(int M, int N, int K, float alpha, const float* __restrict__ A, int lda,
                                           const float* __restrict__ B, int ldb, float beta, float* __restrict__ C,
                                           int ldc, Lds& s, Team& tm) {
   constexpr int FM = BM / 32;                  // 16-row MFMA blocks per wave
   constexpr int FN = 2;                        // 16-column MFMA blocks per wave
-  constexpr int LA = BM * GBK / BT, LB = 64 * GBK / BT;
+  constexpr int LA = BM * KS / BT, LB = 64 * KS / BT;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int lrow = lane & 15, lk = lane >> 4;
@@ -289,8 +294,8 @@ __device__ __noinline__ void wg_gemm_short(int M, int N, int K, float alpha, con
         i = qa % BM;
         k = qa / BM;
       } else {
-        k = qa % GBK;
-        i = qa / GBK;
+        k = qa % KS;
+        i = qa / KS;
       }
       const int gi = m0 + i, gk = k0 + k;
       float v = 0.f;
@@ -301,7 +306,7 @@ __device__ __noinline__ void wg_gemm_short(int M, int N, int K, float alpha, con
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
       const int qb = t + BT * r;
-      const int k = qb % GBK, j = qb / GBK;
+      const int k = qb % KS, j = qb / KS;
       const int gj = n0 + j, gk = k0 + k;
       rb[r] = (gj < N && gk < K) ? B[gk + static_cast<int64_t>(gj) * ldb] : 0.f;
     }
@@ -315,18 +320,18 @@ __device__ __noinline__ void wg_gemm_short(int M, int N, int K, float alpha, con
         i = qa % BM;
         k = qa / BM;
       } else {
-        k = qa % GBK;
-        i = qa / GBK;
+        k = qa % KS;
+        i = qa / KS;
       }
-      s.u.g.As[buf][k][i] = ra[r];
+      s.u.g2.As[buf][k][i] = ra[r];
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
       const int qb = t + BT * r;
-      s.u.g.Bs[buf][qb % GBK][qb / GBK] = rb[r];
+      s.u.g2.Bs[buf][qb % KS][qb / KS] = rb[r];
     }
   };
-  // K <= GBK: one k step per tile.  Tiles are taken in pairs, so the C values
+  // K <= KS: one k step per tile.  Tiles are taken in pairs, so the C values
   // of the next tile (for beta != 0) are loaded into the other register set
   // while the current tile computes and stores; A and B of the next tile are
   // in flight meanwhile too.
@@ -366,12 +371,12 @@ __device__ __noinline__ void wg_gemm_short(int M, int N, int K, float alpha, con
 #pragma unroll
       for (int b = 0; b < FN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kk = 0; kk < GBK / 4; ++kk) {
+    for (int kk = 0; kk < KS / 4; ++kk) {
       float fa[FM], fb[FN];
 #pragma unroll
-      for (int a = 0; a < FM; ++a) fa[a] = s.u.g.As[cur][kk * 4 + lk][wm * (BM / 2) + a * 16 + lrow];
+      for (int a = 0; a < FM; ++a) fa[a] = s.u.g2.As[cur][kk * 4 + lk][wm * (BM / 2) + a * 16 + lrow];
 #pragma unroll
-      for (int b = 0; b < FN; ++b) fb[b] = s.u.g.Bs[cur][kk * 4 + lk][wn * 32 + b * 16 + lrow];
+      for (int b = 0; b < FN; ++b) fb[b] = s.u.g2.Bs[cur][kk * 4 + lk][wn * 32 + b * 16 + lrow];
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -418,9 +423,14 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, float alpha, const 
                                         int ldc, Lds& s, Team& tm) {
   if (K <= GBK) {  // rank-GBK updates: latency hidden across tiles
     if (M <= 32)
-      wg_gemm_short<TA, 32>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
+      wg_gemm_short<TA, 32, GBK>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
     else
-      wg_gemm_short<TA, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
+      wg_gemm_short<TA, 64, GBK>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
+  } else if (K <= 2 * GBK) {  // the rank-2 NB updates of a pair of panels
+    if (M <= 32)
+      wg_gemm_short<TA, 32, 2 * GBK>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
+    else
+      wg_gemm_short<TA, 64, 2 * GBK>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
   } else if (M <= 32) {
     wg_gemm_t<TA, 32>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, tm);
   } else {
@@ -509,7 +519,7 @@ struct PanelColumns<NB, NB> {
 // Householder factorisation of the panel P (mp x jb, jb <= NB, top-left on the
 // diagonal) in registers: on return P holds R on and above the diagonal and
 // the reflectors below it, Vp the explicit unit-lower reflectors and Tp
-// (ld kNBMax) the upper triangular T with H_1 ... H_jb = I - V T V^T.
+// (ld kLT) the upper triangular T with H_1 ... H_jb = I - V T V^T.
 template <int NB>
 __device__ __forceinline__ void panel_factor(float* __restrict__ P, int ldp, int mp, int jb,
                                              float* __restrict__ Vp, int ldv, float* __restrict__ Tp, Lds& s) {
@@ -548,7 +558,7 @@ __device__ __forceinline__ void panel_factor(float* __restrict__ P, int ldp, int
         v = -s.tau[c] * acc;
       }
       s.trow[t][c] = v;
-      Tp[t + c * kNBMax] = v;
+      Tp[t + c * kLT] = v;
     }
   }
   __syncthreads();
@@ -562,36 +572,64 @@ __device__ __forceinline__ void qr_wg(float* X, int rows, int cols, int ldx, flo
                                       const BatchItem& it, Lds& s, Team& tm) {
   const int e0 = tm.member * BT + static_cast<int>(threadIdx.x), es = tm.size * BT;
   const int ldv = rows;
-  for (int j0 = 0; j0 < cols; j0 += NB) {
-    const int jb = min(NB, cols - j0), mp = rows - j0;
+  // Panels A and B of NB columns each form a pair whose joined T
+  // [[T_A, -T_A (V_A^T V_B) T_B], [0, T_B]] (ld kLT) lets the rest of the
+  // matrix, and later Q, take one rank-2NB update per pair instead of two
+  // rank-NB ones.  V_B is kept zero in the rows of A, so V_A and V_B form one
+  // unit-lower block from the pair's first row.
+  for (int j0 = 0; j0 < cols; j0 += 2 * NB) {
+    const int ja = min(NB, cols - j0), jbb = max(0, min(NB, cols - j0 - NB)), jb = ja + jbb;
+    const int mp = rows - j0;
     float* P = X + j0 + static_cast<int64_t>(j0) * ldx;
     float* Vp = it.Vr + j0 + static_cast<int64_t>(j0) * ldv;
-    float* Tp = it.T + static_cast<int64_t>(j0) * kNBMax;
-    if (tm.member == 0) panel_factor<NB>(P, ldx, mp, jb, Vp, ldv, Tp, s);
+    float* Tp = it.T + static_cast<int64_t>(j0) * kLT;
+    if (tm.member == 0) panel_factor<NB>(P, ldx, mp, ja, Vp, ldv, Tp, s);
     team_sync(tm);
+    if (jbb > 0) {
+      const int r1 = j0 + ja;
+      // B's columns: C_B -= V_A (T_A^T (V_A^T C_B))
+      float* CB = X + j0 + static_cast<int64_t>(r1) * ldx;
+      wg_gemm<true>(ja, jbb, mp, 1.f, Vp, ldv, CB, ldx, 0.f, it.Wb, kLT, s, tm);
+      wg_gemm<true>(ja, jbb, ja, 1.f, Tp, kLT, it.Wb, kLT, 0.f, it.W2b, kLT, s, tm);
+      wg_gemm<false>(mp, jbb, ja, -1.f, Vp, ldv, it.W2b, kLT, 1.f, CB, ldx, s, tm);
+      float* VB = it.Vr + j0 + static_cast<int64_t>(r1) * ldv;  // from the pair's first row
+      float* TB = Tp + ja + static_cast<int64_t>(ja) * kLT;
+      if (tm.member == 0) {
+        panel_factor<NB>(X + r1 + static_cast<int64_t>(r1) * ldx, ldx, rows - r1, jbb, VB + ja, ldv, TB, s);
+        for (int e = threadIdx.x; e < ja * jbb; e += BT) {
+          VB[e % ja + static_cast<int64_t>(e / ja) * ldv] = 0.f;  // V_B in the rows of A
+          Tp[ja + e % jbb + static_cast<int64_t>(e / jbb) * kLT] = 0.f;  // T's lower-left block
+        }
+      }
+      team_sync(tm);
+      // T_AB = -T_A (V_A^T V_B) T_B, V_B zero in the rows of A
+      wg_gemm<true>(ja, jbb, mp, 1.f, Vp, ldv, VB, ldv, 0.f, it.Wb, kLT, s, tm);
+      wg_gemm<false>(ja, jbb, jbb, 1.f, it.Wb, kLT, TB, kLT, 0.f, it.W2b, kLT, s, tm);
+      wg_gemm<false>(ja, jbb, ja, -1.f, Tp, kLT, it.W2b, kLT, 0.f, Tp + static_cast<int64_t>(ja) * kLT, kLT, s, tm);
+    }
     const int nrest = cols - j0 - jb;
     if (nrest > 0) {
       // C -= V (T^T (V^T C))
       float* C = X + j0 + static_cast<int64_t>(j0 + jb) * ldx;
-      wg_gemm<true>(jb, nrest, mp, 1.f, Vp, ldv, C, ldx, 0.f, it.Wb, kNBMax, s, tm);
-      wg_gemm<true>(jb, nrest, jb, 1.f, Tp, kNBMax, it.Wb, kNBMax, 0.f, it.W2b, kNBMax, s, tm);  // T^T W
-      wg_gemm<false>(mp, nrest, jb, -1.f, Vp, ldv, it.W2b, kNBMax, 1.f, C, ldx, s, tm);
+      wg_gemm<true>(jb, nrest, mp, 1.f, Vp, ldv, C, ldx, 0.f, it.Wb, kLT, s, tm);
+      wg_gemm<true>(jb, nrest, jb, 1.f, Tp, kLT, it.Wb, kLT, 0.f, it.W2b, kLT, s, tm);  // T^T W
+      wg_gemm<false>(mp, nrest, jb, -1.f, Vp, ldv, it.W2b, kLT, 1.f, C, ldx, s, tm);
     }
   }
-  // Q = H_1 ... H_k [I; 0], accumulated from the last block back
+  // Q = H_1 ... H_k [I; 0], accumulated from the last pair back
   for (int e = e0; e < rows * cols; e += es) {
     const int i = e % rows, j = e / rows;
     Q[i + static_cast<int64_t>(j) * ldq] = (i == j) ? 1.f : 0.f;
   }
   team_sync(tm);
-  for (int j0 = ((cols - 1) / NB) * NB; j0 >= 0; j0 -= NB) {
-    const int jb = min(NB, cols - j0), mp = rows - j0, nq = cols - j0;
+  for (int j0 = ((cols - 1) / (2 * NB)) * (2 * NB); j0 >= 0; j0 -= 2 * NB) {
+    const int jb = min(2 * NB, cols - j0), mp = rows - j0, nq = cols - j0;
     const float* Vp = it.Vr + j0 + static_cast<int64_t>(j0) * ldv;
-    const float* Tp = it.T + static_cast<int64_t>(j0) * kNBMax;
+    const float* Tp = it.T + static_cast<int64_t>(j0) * kLT;
     float* Qs = Q + j0 + static_cast<int64_t>(j0) * ldq;
-    wg_gemm<true>(jb, nq, mp, 1.f, Vp, ldv, Qs, ldq, 0.f, it.Wb, kNBMax, s, tm);
-    wg_gemm<false>(jb, nq, jb, 1.f, Tp, kNBMax, it.Wb, kNBMax, 0.f, it.W2b, kNBMax, s, tm);   // T W
-    wg_gemm<false>(mp, nq, jb, -1.f, Vp, ldv, it.W2b, kNBMax, 1.f, Qs, ldq, s, tm);
+    wg_gemm<true>(jb, nq, mp, 1.f, Vp, ldv, Qs, ldq, 0.f, it.Wb, kLT, s, tm);
+    wg_gemm<false>(jb, nq, jb, 1.f, Tp, kLT, it.Wb, kLT, 0.f, it.W2b, kLT, s, tm);   // T W
+    wg_gemm<false>(mp, nq, jb, -1.f, Vp, ldv, it.W2b, kLT, 1.f, Qs, ldq, s, tm);
   }
   // sign fix: Q(:,j) *= sgn(R(j,j)), R(j,:) = sgn(R(j,j)) R(j,:), sgn(0) = +1
   for (int e = e0; e < rows * cols; e += es) {
@@ -707,7 +745,7 @@ __global__ __launch_bounds__(BT) void batched_urv_kernel(const BatchItem* __rest
 
 size_t item_scratch_floats(int64_t m, int64_t n) {
   auto a = [](int64_t e) { return static_cast<int64_t>(align_up(static_cast<size_t>(e), 64)); };
-  return static_cast<size_t>(3 * a(m * n) + 2 * a(n * n) + 3 * a(kNBMax * n));
+  return static_cast<size_t>(3 * a(m * n) + 2 * a(n * n) + 3 * a(kLT * n));
 }
 
 struct DeviceQueue {
@@ -922,9 +960,9 @@ int urv_batch_create(int64_t count, const int64_t* m, const int64_t* n, int32_t 
     it.Vr = take(m[i] * n[i]);
     it.Y = take(n[i] * n[i]);
     it.Vc = take(n[i] * n[i]);
-    it.T = take(urv::kNBMax * n[i]);
-    it.Wb = take(urv::kNBMax * n[i]);
-    it.W2b = take(urv::kNBMax * n[i]);
+    it.T = take(urv::kLT * n[i]);
+    it.Wb = take(urv::kLT * n[i]);
+    it.W2b = take(urv::kLT * n[i]);
   }
   // largest first (LPT): cost ~ m n^2, ties by index
   p->order.resize(static_cast<size_t>(count));
