@@ -341,7 +341,7 @@ __global__ void scale_kernel(int64_t M, int64_t N, T beta, T* __restrict__ C,
 struct Plan {
   int bm, bn, wgm, wgn, tiles_m, tiles_n, splits;
   int64_t k_chunk;
-  bool short_k = false;  // 128 x 128 tiles, k-step 16, 8 waves (two workgroups per CU), C loaded first
+  bool short_k = false;  // 128 x 64 tiles, k-step 16, 8 waves (two workgroups per CU), C loaded first
 };
 
 Plan make_plan(int64_t M, int64_t N, int64_t K) {
@@ -399,8 +399,18 @@ void launch_tiles(const Plan& p, int64_t M, int64_t N, int64_t K, T alpha, const
                   T* partial, hipStream_t s) {
   const dim3 grid(p.tiles_m * p.tiles_n, p.splits);
   if (p.short_k) {
-    gemm_kernel<T, TA, TB, 128, 64, 4, 2, 16, false><<<grid, 64 * 8, 0, s>>>(
-        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, p.k_chunk, p.tiles_m, p.tiles_n);
+    // C loaded before the k loop (URV_GEMM_PREC=0: after it, for tuning); measured on
+    // MI355X in the FP64 factorisation at n = 8000: FULL 252.3-252.7 ms against 253.6-254.0
+    static const bool prec = [] {
+      const char* e = std::getenv("URV_GEMM_PREC");
+      return !(e && std::atoi(e) == 0);
+    }();
+    if (prec)
+      gemm_kernel<T, TA, TB, 128, 64, 4, 2, 16, true><<<grid, 64 * 8, 0, s>>>(
+          M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, p.k_chunk, p.tiles_m, p.tiles_n);
+    else
+      gemm_kernel<T, TA, TB, 128, 64, 4, 2, 16, false><<<grid, 64 * 8, 0, s>>>(
+          M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, partial, p.k_chunk, p.tiles_m, p.tiles_n);
     return;
   }
 #define URV_GEMM_CASE(TBM, TBN, GM, GN)                                                          \
