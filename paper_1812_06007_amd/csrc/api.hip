@@ -48,6 +48,25 @@ struct FactorWork {
   MixedWork mx;
 };
 
+// Whether the square FP32 QRs of the mixed form take their explicit Q as the reflectors
+// applied to I alongside the factorisation (2n^3, on the targets' stream, beside the chain)
+// rather than backward after it (4/3 n^3, after the chain; URV_MIXED_ITARGET=0, for tuning).
+// Measured on MI355X at n = 8000, q = 2, BF16: FULL 193.0-193.3 ms against 210.0-210.4.
+bool mixed_identity_target() {
+  const char* e = std::getenv("URV_MIXED_ITARGET");
+  return !(e && std::atoi(e) == 0);
+}
+
+// Qpos of the square or tall FP32 matrix X (rows x n, ld rows, overwritten) into Q (ld rows).
+int qpos_f32(float* X, int64_t rows, int64_t n, float* Q, const QrWorkT<float>& w, hipStream_t s) {
+  if (rows == n && mixed_identity_target()) {
+    URV_TRY(set_identity<float>(Q, rows, n, rows, s));
+    const QrTarget<float> t{Q, rows, rows};
+    return qr_pos<float>(X, rows, n, rows, nullptr, 0, nullptr, 0, w, s, &t, 1);
+  }
+  return qr_pos<float>(X, rows, n, rows, Q, rows, nullptr, 0, w, s);
+}
+
 // Whether the explicit V is formed from its QR's reflectors beside the final QR
 // (URV_DEFER_V=0: as a product with I alongside its QR, for tuning).
 bool defer_v() {
@@ -80,7 +99,7 @@ void carve_factor(Arena& a, int64_t m, int64_t n, bool mixed, FactorWork& w) {
   x.W32 = a.take<float>(static_cast<size_t>(m) * n);
   x.Y32 = a.take<float>(static_cast<size_t>(n) * n);
   x.amax = a.take<unsigned>(4);
-  qr_work_carve(a, m, n, x.qr);
+  qr_work_carve(a, m, n, x.qr, n);  // targets of n rows: the square QRs' explicit Q formed from I
 }
 
 size_t factor_bytes(int64_t m, int64_t n, bool mixed) {
@@ -406,7 +425,7 @@ int run_factor_mixed(const double* A, int64_t lda, const float* A32, int64_t lda
     URV_TRY(launch_gaussian(x.V32, n, n, n, seed, 2u, true, s));
   if (o.orth_g) {
     URV_TRY(copy_matrix_f32(x.V32, n, x.Y32, n, n, n, s));
-    URV_TRY(qr_pos<float>(x.Y32, n, n, n, x.V32, n, nullptr, 0, x.qr, s));
+    URV_TRY(qpos_f32(x.Y32, n, n, x.V32, x.qr, s));
   }
   for (int32_t t = 0; t < q; ++t) {
     if (amaxB) URV_TRY(absmax<float>(x.V32, n, n, n, amaxB, s));
@@ -414,7 +433,7 @@ int run_factor_mixed(const double* A, int64_t lda, const float* A32, int64_t lda
     URV_TRY(gemm_lowp(bf16, m, n, n, 1.f, x.At16, x.ldat16, x.B16, ldv16, 0.f, x.X32, m, s));  // X = A V
     const float* rhs = x.X32;
     if (full) {
-      URV_TRY(qr_pos<float>(x.X32, m, n, m, x.W32, m, nullptr, 0, x.qr, s));               // W = Qpos(X)
+      URV_TRY(qpos_f32(x.X32, m, n, x.W32, x.qr, s));                                      // W = Qpos(X)
       rhs = x.W32;
     }
     if (amaxB) URV_TRY(absmax<float>(rhs, m, m, n, amaxB, s));
@@ -423,7 +442,7 @@ int run_factor_mixed(const double* A, int64_t lda, const float* A32, int64_t lda
     URV_TRY(gemm_lowp(bf16, n, n, m, 1.f, x.A16, x.lda16, x.B16, x.lda16, 0.f, out, n, s));   // A^T W
     // V = Qpos(Y), in FP32 except after the last step: there the FP64 QR below takes Y
     // itself, since Qpos(Qpos(Y)) = Qpos(Y)
-    if (!none && t + 1 < q) URV_TRY(qr_pos<float>(x.Y32, n, n, n, x.V32, n, nullptr, 0, x.qr, s));
+    if (!none && t + 1 < q) URV_TRY(qpos_f32(x.Y32, n, n, x.V32, x.qr, s));
   }
   // The last V = Qpos(.) in FP64 (delivering X = A V alongside): of Y after a power step
   // (FULL, HALF), of (A^T A)^q G (NONE), or of the starting V when q = 0; then the FP64

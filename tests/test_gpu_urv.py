@@ -270,6 +270,31 @@ def test_mixed_precision_against_fp64_oracle(urv, orc, monkeypatch, prec, varian
     assert ratio.max() <= 1.25
 
 
+@pytest.mark.parametrize("itarget", ["1", "0"])
+@pytest.mark.parametrize("variant", ["full", "half"])
+def test_mixed_square_both_q_formations(urv, orc, monkeypatch, variant, itarget):
+    """A square A: the FP32 QRs of X and Y form their explicit Q from I alongside the
+    factorisation (the default) or backward after it; both meet the FP64 oracle as the tall
+    case does."""
+    announce("mixed square", variant, itarget)
+    monkeypatch.setenv("URV_MIXED_ITARGET", itarget)
+    n = 700
+    sigma = np.exp(-10.0 * np.arange(1, n + 1) / n)
+    A = gen.noisy_spectral_matrix(n, n, sigma, seed=17, noise_var=1e-6)
+    A = A.astype(np.float32).astype(np.float64)
+    G = gen.gaussian(n, n, 18)
+    U, R, V = _gpu_factor(urv, A, 2, G=to_gpu(G), precision="mixed_bf16", variant=variant)
+    met = _assert_invariants(urv, A, (U, R, V), 1e-10)
+    assert met["recon"] <= 1e-6
+    Uo, Ro, Vo = orc.urv(A, 2, G=G, variant="full")
+    eko = orc.metrics(A, Uo, Ro, Vo)["ek"]
+    na = np.linalg.norm(A)
+    sel = eko >= 0.05 * na
+    ratio = met["ek"][sel] / eko[sel]
+    print("[mixed square] %s itarget=%s: max ek ratio %.4f" % (variant, itarget, ratio.max()))
+    assert ratio.max() <= 1.25
+
+
 @pytest.mark.parametrize("variant", ["full", "half", "none"])
 def test_fp16_large_entries_scaled_not_overflowed(urv, orc, variant):
     """||A|| ~ 1e6, entries far beyond FP16's 65504: the FP16 casts scale each operand by a
