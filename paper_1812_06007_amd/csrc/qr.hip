@@ -2701,10 +2701,23 @@ bool target_pairs() {
 // matrix is large and run beside the later, lighter blocks.  Measured on
 // MI355X at n = 8000, q = 2 (FP64 FULL / HALF, V formed beside the final QR):
 // lag 6: 261.0 / 204.0 ms, 12: 257.0 / 201.9, 18: 253.4-254.5 / 198.5-200.5,
-// 21: 254.2, 24: 256.1 / 200.1, 30: 262.6 / 203.8.
-int target_lag() {
+// 21: 254.2, 24: 256.1 / 200.1, 30: 262.6 / 203.8.  Targets with more rows than the QR
+// has columns hold proportionally more work per block, and a tall QR's trailing matrix
+// stays tall to its last block, leaving little idle time to fill there: the lag shrinks
+// by n / target_rows and by n / m.  Measured on MI355X (alternating runs), FP64 FULL
+// q = 2 of a 4000 x 8000 A (its transpose factored): 120.1-120.2 ms against 124.7-125.1
+// with the first factor alone, which gave 124.8-125.3 against 128.7-128.8 with 18 on
+// another box; 8000 x 8000 unchanged, 16000 x 8000 within the noise (URV_TARGET_LAG=-1
+// keeps 18).
+int target_lag(int64_t m, int64_t n, int64_t target_rows) {
   const char* e = std::getenv("URV_TARGET_LAG");
-  return e ? std::max(0, std::atoi(e)) : 18;
+  const int v = e ? std::atoi(e) : -2;
+  if (v >= 0) return v;
+  if (v == -1) return 18;
+  double lag = 18.0;
+  if (target_rows > n) lag *= static_cast<double>(n) / target_rows;
+  if (m > n) lag *= static_cast<double>(n) / m;
+  return std::max(4, static_cast<int>(lag + 0.5));
 }
 
 // Outer block width used by qr_pos: NB2 or NBO (URV_QR_BLOCK, for tuning).
@@ -3112,7 +3125,9 @@ int qr_pos(T* X, int64_t m, int64_t n, int64_t ldx, T* Q, int64_t ldq, T* R, int
   const bool pair_bulk = nbo == NB2 && bulk_pairs();
   const int ahead = pair_bulk ? 1 : lookahead();
   const bool ahead2 = ahead >= 2;
-  const int64_t lag = target_lag();
+  int64_t target_rows_max = 0;
+  for (int i = 0; i < ntargets; ++i) target_rows_max = std::max<int64_t>(target_rows_max, targets[i].rows);
+  const int64_t lag = target_lag(m, n, target_rows_max);
   int64_t tgt_next = 0;  // first block whose targets are not yet queued
   URV_HIP(hipEventRecord(side.ev_next, s));      // the cleared flags and slots
   URV_HIP(hipStreamWaitEvent(s2, side.ev_next, 0));
