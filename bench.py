@@ -347,8 +347,9 @@ def bench_wide(q: int, variant: str, steps: int, warmup: int) -> dict:
     ms_w = time_factor(A, q, variant, "fp64", steps, warmup, out_w)
     ms_t = time_factor(B, q, variant, "fp64", steps, warmup, out_t)
     met = urv.metrics(A, *out_w)
-    # the tall problem of A^T, plus the m x m QR of its R with reversed columns and the n x m x m product
-    fl = standard_flops(n, m, q, variant) + 8.0 / 3.0 * m ** 3 + 2.0 * n * m * m
+    # the tall problem of A^T, plus the m x m QR of its R with reversed columns, whose reflectors
+    # are applied to the tall problem's n x m U (the cost of the n x m x m product)
+    fl = standard_flops(n, m, q, variant) + 4.0 / 3.0 * m ** 3 + 2.0 * n * m * m
     return {"workload": "A 4000x8000 = (Q1 diag(1/j^2) Q2^T)^T, FP64 %s q=%d, against the tall 8000x4000 A^T"
                         % (variant.upper(), q),
             "ms": ms_w, "ms_tall_transpose": ms_t, "flops_executed": fl,

@@ -471,6 +471,17 @@ int run_wide(const double* A, int64_t m, int64_t n, int32_t q, uint64_t seed, do
   URV_TRY(mixed ? run_factor_mixed(x.B, n, nullptr, 0, n, m, q, seed, x.Ut, x.Rt, U, ob, w, s)
                 : run_factor(x.B, n, m, q, seed, x.Ut, x.Rt, U, ob, w, s));  // U = V_B
   URV_TRY(reverse_cols(x.Rt, m, m, m, x.RJ, m, s));
+  const char* wt = std::getenv("URV_WIDE_TARGET");
+  if (!(wt && std::atoi(wt) == 0)) {
+    // Rt J = Q2 R2 with Q2's reflectors applied to Ut as they come: Ut <- Ut Q2, beside the
+    // chain, and Q2 never formed (URV_WIDE_TARGET=0: Q2 formed, then the product, for
+    // tuning).  Measured on MI355X at 4000 x 8000, FP64 FULL q = 2: 113.0-113.1 ms
+    // against 119.1-119.3.
+    const QrTarget<double> t{x.Ut, n, n};
+    URV_TRY(qr_pos<double>(x.RJ, m, m, m, nullptr, 0, x.R2, m, w.qr, s, &t, 1));
+    URV_TRY(reverse_cols(x.Ut, n, n, m, V, ldv, s));                        // V = Ut Q2 J
+    return transpose_reverse(x.R2, m, m, R, ldr, s);                        // R = J R2^T J
+  }
   URV_TRY(qr_pos<double>(x.RJ, m, m, m, x.Q2, m, x.R2, m, w.qr, s));     // Rt J = Q2 R2
   URV_TRY(dgemm(false, false, n, m, m, 1.0, x.Ut, n, x.Q2, m, 0.0, x.T, n, x.gw, x.gw_elems, s));
   URV_TRY(reverse_cols(x.T, n, n, m, V, ldv, s));                           // V = Ut Q2 J
