@@ -19,7 +19,7 @@
 //
 // Kernels: the products are the MFMA GEMM of gemm.hip; R^{-T} is a recursive
 // blocked solve whose off-diagonal blocks are GEMMs and whose 64-column
-// diagonal blocks are solved by trsm_rt_block_kernel (one row per lane, the
+// diagonal blocks are solved by trsm_rt_block_kernel (one wave per row, the
 // block of R in LDS); the QRs are qr_pos.  The tape keeps what the reverse
 // sweep reads (every Q and R of the power steps, or only the V's, or nothing,
 // in which case the sweep recomputes the V's from G).
@@ -32,7 +32,7 @@ namespace urv {
 namespace {
 
 constexpr int kTrsmNB = 64;       // columns of a diagonal block of the solve
-constexpr int kTrsmThreads = 128;  // rows per workgroup of the block solve
+constexpr int kTrsmThreads = 512;  // threads per workgroup of the block solve: 8 waves, a row each
 constexpr int kLossBlocks = 512;
 constexpr int kLossThreads = 256;
 
@@ -64,37 +64,49 @@ __global__ void copyltu_kernel(T* __restrict__ M, int64_t n, int64_t ld) {
 
 // X = B R^{-T} in place for one diagonal block: nb <= 64 columns of B (m rows)
 // and the nb x nb upper triangle of R.  Column j of X R^T is the sum over
-// l >= j of X(:,l) R(j,l), so lane i takes its row's last unknown first and
-// removes it from the others: x_j = b_j / R(j,j), b_l -= x_j R(l,j) for l < j.
-// Past nb the block is padded with the identity so the loops have fixed trip
-// counts.  With last_given, column nb - 1 of B already holds its x.
+// l >= j of X(:,l) R(j,l), so a row takes its last unknown first and removes
+// it from the others: x_j = b_j / R(j,j), b_l -= x_j R(l,j) for l < j.  One
+// wave per row, lane l holding b_l: each step broadcasts b_j from lane j and
+// every lane l < j updates at once, so a row costs nb dependent steps instead
+// of nb^2 / 2 (the arithmetic of every element, and its order, are those of a
+// row solved by one lane).  With last_given, column nb - 1 of B already holds its x.
+template <class T>
+__device__ inline T lane_value(T v, int j);
+template <>
+__device__ inline float lane_value<float>(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+template <>
+__device__ inline double lane_value<double>(double v, int j) {
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), j);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), j);
+  return __hiloint2double(hi, lo);
+}
+
 template <class T>
 __global__ __launch_bounds__(kTrsmThreads) void trsm_rt_block_kernel(T* __restrict__ B, int64_t ldb, int64_t m,
                                                                      int nb, const T* __restrict__ R,
                                                                      int64_t ldr, int last_given) {
-  __shared__ T Rs[kTrsmNB][kTrsmNB + 1];  // Rs[j][l] = R(l, j), column j contiguous
+  __shared__ T Rs[kTrsmNB][kTrsmNB + 1];  // Rs[j][l] = R(l, j): row j holds column j of R
   for (int e = threadIdx.x; e < kTrsmNB * kTrsmNB; e += kTrsmThreads) {
     const int l = e % kTrsmNB, j = e / kTrsmNB;
-    T v = (l == j) ? T(1) : T(0);
-    if (l < nb && j < nb) v = (l <= j) ? R[l + j * ldr] : T(0);
-    Rs[j][l] = v;
+    Rs[j][l] = (l < nb && j < nb && l <= j) ? R[l + j * ldr] : T(0);
   }
   __syncthreads();
-  const int64_t i = blockIdx.x * static_cast<int64_t>(kTrsmThreads) + threadIdx.x;
-  if (i >= m) return;
-  T b[kTrsmNB];
-#pragma unroll
-  for (int j = 0; j < kTrsmNB; ++j) b[j] = (j < nb) ? B[i + j * ldb] : T(0);
-#pragma unroll
-  for (int j = kTrsmNB - 1; j >= 0; --j) {
-    const T x = (last_given && j == nb - 1) ? b[j] : b[j] / Rs[j][j];
-    b[j] = x;
-#pragma unroll
-    for (int l = 0; l < j; ++l) b[l] = fma(-x, Rs[j][l], b[l]);
+  constexpr int kWaves = kTrsmThreads / 64;
+  const int l = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWaves + wave; i < m;
+       i += static_cast<int64_t>(gridDim.x) * kWaves) {
+    T b = (l < nb) ? B[i + l * ldb] : T(0);
+    for (int j = nb - 1; j >= 0; --j) {
+      const T bj = lane_value<T>(b, j);
+      const T x = (last_given && j == nb - 1) ? bj : bj / Rs[j][j];
+      if (l == j) b = x;
+      else if (l < j) b = fma(-x, Rs[j][l], b);
+    }
+    if (l < nb) B[i + l * ldb] = b;
   }
-#pragma unroll
-  for (int j = 0; j < kTrsmNB; ++j)
-    if (j < nb) B[i + j * ldb] = b[j];
 }
 
 // partial[b] = sum of E^2 over a fixed set of elements (in double); then one
@@ -268,8 +280,9 @@ int trsm_rt(T* B, int64_t ldb, int64_t m, int64_t n, const T* R, int64_t ldr, co
             hipStream_t s, bool last_given = false) {
   if (m == 0 || n == 0) return URV_OK;
   if (n <= kTrsmNB) {
-    trsm_rt_block_kernel<T><<<grid_for(m, kTrsmThreads), kTrsmThreads, 0, s>>>(B, ldb, m, static_cast<int>(n),
-                                                                               R, ldr, last_given ? 1 : 0);
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(ceil_div(m, kTrsmThreads / 64), 1024));
+    trsm_rt_block_kernel<T><<<blocks, kTrsmThreads, 0, s>>>(B, ldb, m, static_cast<int>(n), R, ldr,
+                                                              last_given ? 1 : 0);
     URV_LAUNCHED("trsm_rt_block_kernel");
     return URV_OK;
   }
